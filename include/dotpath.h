@@ -1,0 +1,236 @@
+/*
+ * dotpath: C ABI of the MI355X (gfx950) library for the hot path of randomized
+ * nonlinear inversion in diffuse optical tomography with random and optimized
+ * simultaneous sources and detectors (Aslan, de Sturler, Kilmer).
+ *
+ * Model (Section 2, eq. PDE at zero frequency):
+ *     -div(D grad eta) + mu(x; p) eta = g  on a box,
+ *     eta = 0 on Dirichlet faces, 0.25 eta + (D/2) d eta/d xi = 0 on Robin faces,
+ * discretized by a symmetric cell-centred finite-volume scheme on a uniform
+ * grid of spacing h = 1 / n_x (cells are cubes):
+ *     interior face       T = h^(d-2) 2 D_c D_c' / (D_c + D_c')
+ *     Dirichlet face      T = h^(d-2) 2 D_c
+ *     Robin face          T = h^(d-1) 2 D_c / (h + 4 D_c)
+ *     (A eta)_c = sum_faces T (eta_c - eta_nbr) + sum_bdry T eta_c + h^d mu_c eta_c.
+ * A is symmetric positive definite, so A^T = A.  Cells are numbered
+ * c = i + n_x (j + n_y k).  Absorption mu comes from the parametric level set
+ * (PaLS) phi = sum_j alpha_j psi(sqrt(beta_j^2 |x - chi_j|^2 + gamma^2)) with
+ * the Wendland psi_{2,1}(r) = (1-r)^4 (4r+1) and
+ * mu = mu_out + (mu_in - mu_out) H_eps(phi - c), where
+ * H_eps(s) = (1 + s/eps + sin(pi s/eps)/pi)/2 on |s| <= eps (0 below, 1 above).
+ *
+ * Conventions for every call:
+ *   - Pointers named *_dev are device pointers (hipMalloc'd or torch tensors),
+ *     pointers named *_host are host pointers.  Multi-column arrays are
+ *     column-major with leading dimension equal to the row count (an N x k
+ *     field block has element (c, j) at c + N j).  All floating point data is
+ *     IEEE binary64 unless stated.
+ *   - The caller owns every data buffer.  The library allocates device memory
+ *     only inside dot_build_operator (coefficients, level set, small state)
+ *     and dot_pals_mua (per-RBF cell lists); dot_solve_multi_rhs,
+ *     dot_jacobian and dot_grad_misfit use the caller's workspace.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Work is
+ *     enqueued on it; calls that return host values synchronize it.
+ *   - Arguments are validated on the host before any HIP call; on error the
+ *     call returns a negative code and dot_last_error() explains it.  Outputs
+ *     are undefined after an error.
+ *   - A handle is not thread-safe; separate handles are independent.
+ */
+#ifndef DOTPATH_H
+#define DOTPATH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DOT_ABI_VERSION 1
+
+/* return codes */
+#define DOT_OK 0
+#define DOT_NOT_CONVERGED 1   /* solve hit max_iter; outputs valid, info.relres filled */
+#define DOT_EINVAL (-1)       /* invalid argument */
+#define DOT_ENOMEM (-2)       /* workspace too small or device allocation failed */
+#define DOT_EHIP (-3)         /* HIP runtime error */
+#define DOT_EBREAKDOWN (-4)   /* CG breakdown: p^T A p <= 0 (operator not SPD) */
+#define DOT_ENONFINITE (-5)   /* NaN or Inf in the data */
+
+/* boundary codes per face */
+#define DOT_BC_DIRICHLET 0
+#define DOT_BC_ROBIN 1
+
+/* solve precision */
+#define DOT_FP64 0    /* Jacobi-PCG in binary64 */
+#define DOT_MIXED 1   /* binary32 Jacobi-PCG inside binary64 iterative refinement */
+
+/* Jacobian precision */
+#define DOT_JAC_FP64 0        /* binary64 products and sums */
+#define DOT_JAC_SPLIT_BF16 1  /* hi/lo bfloat16 operands, 3 MFMA products, fp32 accumulate */
+
+/* PaLS parameter activity bits */
+#define DOT_ACT_ALPHA 1u
+#define DOT_ACT_BETA 2u
+#define DOT_ACT_CHI 4u
+
+typedef struct dot_grid {
+  int dim;     /* 2 or 3 */
+  int n[3];    /* cells per axis (n[2] ignored when dim == 2) */
+  int bc[6];   /* faces -x,+x,-y,+y,-z,+z: DOT_BC_DIRICHLET or DOT_BC_ROBIN (z ignored in 2D) */
+} dot_grid;
+
+typedef struct dot_pals {
+  int m0;            /* number of RBFs; theta is m0 x (2 + dim), RBF-major [alpha, beta, chi] */
+  unsigned active;   /* DOT_ACT_* bits: which per-RBF parameters are unknowns */
+  double mu_in, mu_out, cutoff, eps, gamma;
+} dot_pals;
+
+typedef struct dot_solve_opts {
+  double rtol;        /* per-column target ||b - A x||_2 / ||b||_2 */
+  int max_iter;       /* FP64: CG iterations; MIXED: total inner iterations */
+  int precision;      /* DOT_FP64 or DOT_MIXED */
+  double inner_rtol;  /* MIXED: inner binary32 relative tolerance (e.g. 1e-4) */
+  int max_outer;      /* MIXED: maximum refinement steps */
+  int check_every;    /* iterations between host polls of the convergence count (>= 1) */
+} dot_solve_opts;
+
+typedef struct dot_solve_info {
+  int iters_max;      /* out: max over columns of (inner) iterations */
+  int outer;          /* out: refinement steps taken (MIXED), 0 for FP64 */
+  int32_t* iters_host;   /* in: NULL or host array [k]; out: iterations per column */
+  double* relres_host;   /* in: NULL or host array [k]; out: final true relative residual
+                            ||b - A x|| / ||b|| per column, recomputed in binary64 */
+} dot_solve_info;
+
+typedef struct dot_op dot_op;
+
+/* ABI version (DOT_ABI_VERSION). */
+int dot_abi_version(void);
+
+/* Thread-local description of the last error ("" if none). */
+const char* dot_last_error(void);
+
+/* Number of cells N of a grid descriptor, or -1 if it is invalid. */
+int64_t dot_grid_cells(const dot_grid* grid);
+
+/*
+ * PaLS field on a grid, without an operator (Section 2, PaLS definition and
+ * eq. absorption const): mua_dev[c] = mu(x_c; theta) at cell centres
+ * x_c = ((i + 1/2) h, ...).  If diff_dev is not NULL it also receives the
+ * diffusion coefficient D = 1 / (3 (mu + mus_prime)) of the diffusion
+ * approximation.  theta_dev: m0 x (2 + dim) device array, RBF-major.
+ */
+int dot_pals_field(const dot_grid* grid, const dot_pals* pals, const double* theta_dev,
+                   double mus_prime, double* mua_dev, double* diff_dev, void* stream);
+
+/*
+ * Build the frozen part of A from the diffusion coefficient D_dev[N] (the
+ * face coefficients T and the boundary diagonal).  The absorption starts at
+ * zero; set it with dot_pals_mua or dot_set_mua.  *out receives a handle that
+ * owns its device arrays; free it with dot_destroy_operator.
+ */
+int dot_build_operator(const dot_grid* grid, const double* D_dev, void* stream, dot_op** out);
+
+/* Free a handle (NULL is accepted).  Synchronizes the device. */
+int dot_destroy_operator(dot_op* op);
+
+/* Number of cells of the operator's grid. */
+int64_t dot_operator_cells(const dot_op* op);
+
+/* Set the absorption of A from an explicit field mua_dev[N] (diagonal h^d mu). */
+int dot_set_mua(dot_op* op, const double* mua_dev, void* stream);
+
+/*
+ * Set A(theta): evaluate the PaLS absorption at every cell, update the
+ * diagonal, and keep on the handle what dot_jacobian and dot_grad_misfit
+ * need at this theta (a copy of theta and the descriptor, the level set phi,
+ * and per-RBF lists of cells where d mu / d p is nonzero).  Allocates device
+ * memory for those lists when they grow.  If mua_dev is not NULL it receives
+ * mu.  Synchronizes the stream.
+ */
+int dot_pals_mua(dot_op* op, const dot_pals* pals, const double* theta_dev, double* mua_dev,
+                 void* stream);
+
+/* Y = A X for k columns (X_dev and Y_dev are N x k and must not overlap). */
+int dot_apply(dot_op* op, int k, const double* X_dev, double* Y_dev, void* stream);
+
+/*
+ * Simultaneous sources (Section 3.1, eq. Rw; Section 3.3): rhs_dev (N x k) =
+ * B W, i.e. column l is sum_i weights_dev[i + n_pts l] e_{cells_host[i]}.
+ * cells_host: n_pts cell indices in [0, N) (host array; repeated cells add).
+ * Used for C V with the detector cells and V.
+ */
+int dot_form_rhs(dot_op* op, int n_pts, const int32_t* cells_host, int k,
+                 const double* weights_dev, double* rhs_dev, void* stream);
+
+/* Workspace bytes for dot_solve_multi_rhs with k columns at the given precision. */
+size_t dot_solve_workspace_bytes(const dot_op* op, int k, int precision);
+
+/*
+ * Multi-right-hand-side solve A X = RHS (trans = 0) or A^T X = RHS (trans =
+ * 1; identical here since A is symmetric), Section 3.3: the forward fields
+ * z_i of A z_i = B w_i and the adjoint fields y_j of A^T y_j = C v_j.
+ * Jacobi-preconditioned CG from x0 = 0 per column until
+ * ||b - A x||_2 <= rtol ||b||_2; MIXED runs binary32 inner CG on the
+ * scaled residual inside binary64 refinement (residual b - A x, update
+ * x += d and the stopping test in binary64).
+ * rhs_dev, x_dev: N x k, must not overlap.  work_dev: >= the size from
+ * dot_solve_workspace_bytes, 256-byte aligned.  Synchronizes the stream.
+ * Returns DOT_OK, DOT_NOT_CONVERGED (outputs valid), or an error.
+ */
+int dot_solve_multi_rhs(dot_op* op, int trans, int k, const double* rhs_dev, double* x_dev,
+                        const dot_solve_opts* opts, void* work_dev, size_t work_bytes,
+                        dot_solve_info* info, void* stream);
+
+/*
+ * Sampled residual and misfit (Section 3.3, eq. EsTResidual; Thm 3.1):
+ * Rs_dev (l_d x l_s) = V^T (C^T U - DW), f = 1/2 ||Rs||_F^2 written to *f_host.
+ * det_host: n_d detector cells; U_dev: N x l_s forward fields; V_dev: n_d x l_d;
+ * DW_dev: n_d x l_s (data times W).  Synchronizes the stream.
+ */
+int dot_sampled_misfit(dot_op* op, int n_d, const int32_t* det_host, int l_s, const double* U_dev,
+                       int l_d, const double* V_dev, const double* DW_dev, double* Rs_dev,
+                       double* f_host, void* stream);
+
+/* Workspace bytes for dot_jacobian / dot_grad_misfit (after dot_pals_mua). */
+size_t dot_jacobian_workspace_bytes(const dot_op* op, int l_s, int l_d);
+
+/*
+ * Sampled Jacobian (Section 3.3, eq. Jacobian kth column, sign of eq.
+ * Jacobiancomp): Js_dev[(j + l_d i) + (l_s l_d) k] = -sum_c Z[c,j] U[c,i]
+ * h^d d mu_c / d p_k, for the parameters of the last dot_pals_mua call
+ * (n_p = m0 x number of active bits; parameter k = rbf * n_act + local
+ * index in the order alpha, beta, chi_1..chi_d).  Only cells where
+ * d mu / d p_k is nonzero are visited.  precision: DOT_JAC_FP64 or
+ * DOT_JAC_SPLIT_BF16.  U_dev: N x l_s, Z_dev: N x l_d.
+ */
+int dot_jacobian(dot_op* op, int l_s, const double* U_dev, int l_d, const double* Z_dev,
+                 int precision, double* Js_dev, void* work_dev, size_t work_bytes, void* stream);
+
+/*
+ * Gradient of f = 1/2 ||Rs||_F^2 (Section 3.1, eq. UnbiasedGrad):
+ * g_dev[k] = sum_{i,j} Rs[j,i] Js[j + l_d i, k]
+ *          = -sum_c h^d d mu_c/d p_k sum_i U[c,i] (Z Rs)[c,i],
+ * without forming Js.  Rs_dev: l_d x l_s.
+ */
+int dot_grad_misfit(dot_op* op, int l_s, const double* U_dev, int l_d, const double* Z_dev,
+                    const double* Rs_dev, double* g_dev, void* work_dev, size_t work_bytes,
+                    void* stream);
+
+/*
+ * Small dense binary64 helpers on the device, for the optimized
+ * sources/detectors (Section 3.2, Alg. 1) and the Gauss-Newton SVD.
+ *
+ * dot_gemm: C (m x n) = alpha op(A) op(B) + beta C, op = transpose if trans*
+ *   is nonzero; column-major with leading dimensions lda, ldb, ldc.
+ */
+int dot_gemm(int transa, int transb, int m, int n, int kdim, double alpha, const double* A_dev,
+             int lda, const double* B_dev, int ldb, double beta, double* C_dev, int ldc,
+             void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DOTPATH_H */

@@ -1,0 +1,298 @@
+"""Thin Python layer over the dotpath C ABI.
+
+Matrices are passed as torch tensors with their logical (rows, cols) shape;
+the ABI wants column-major device memory, which is what ``A.t().contiguous()``
+holds, so a field block U of logical shape (N, l) lives in memory as a
+contiguous (l, N) tensor and is returned as its transposed view.  torch
+supplies device memory and the current stream only: every arithmetic step
+runs in the HIP kernels of libdotpath.so.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import warnings
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from ._lib import check, lib
+
+__all__ = ["Grid", "Pals", "Operator", "SolveResult", "pals_field", "gemm", "colmajor",
+           "empty_colmajor"]
+
+
+def _stream() -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr())
+
+
+def _need_cuda_f64(t: torch.Tensor, name: str):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+        raise TypeError(f"{name} must be a float64 CUDA tensor")
+
+
+def colmajor(t: torch.Tensor, name: str = "array") -> torch.Tensor:
+    """Memory of a logical (rows, cols) matrix in column-major order: a contiguous
+    (cols, rows) tensor (no copy when t already is such a transposed view)."""
+    _need_cuda_f64(t, name)
+    if t.dim() == 1:
+        return t.contiguous()
+    return t.t().contiguous()
+
+
+def empty_colmajor(rows: int, cols: int, device) -> torch.Tensor:
+    """Storage for a column-major (rows, cols) matrix; returns the (rows, cols) view."""
+    return torch.empty((cols, rows), dtype=torch.float64, device=device).t()
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    w = torch.empty(max(int(nbytes), 256) + 256, dtype=torch.uint8, device=device)
+    off = (-w.data_ptr()) % 256
+    return w[off:off + max(int(nbytes), 256)]
+
+
+@dataclass(frozen=True)
+class Grid:
+    dim: int
+    n: tuple
+    bc: tuple
+
+    def c(self) -> L.DotGrid:
+        g = L.DotGrid()
+        g.dim = self.dim
+        n = list(self.n) + [1] * (3 - len(self.n))
+        for a in range(3):
+            g.n[a] = int(n[a])
+        bc = list(self.bc) + [0] * (6 - len(self.bc))
+        for f in range(6):
+            g.bc[f] = int(bc[f])
+        return g
+
+    @property
+    def N(self) -> int:
+        return int(np.prod(self.n))
+
+    @classmethod
+    def from_config(cls, cfg) -> "Grid":
+        return cls(dim=cfg.dim, n=tuple(cfg.n), bc=tuple(cfg.bc[: 2 * cfg.dim]))
+
+
+@dataclass(frozen=True)
+class Pals:
+    m0: int
+    active: int
+    mu_in: float
+    mu_out: float
+    cutoff: float
+    eps: float
+    gamma: float
+
+    def c(self) -> L.DotPals:
+        p = L.DotPals()
+        p.m0, p.active = int(self.m0), int(self.active)
+        p.mu_in, p.mu_out, p.cutoff, p.eps, p.gamma = (self.mu_in, self.mu_out, self.cutoff,
+                                                       self.eps, self.gamma)
+        return p
+
+    @classmethod
+    def from_config(cls, cfg) -> "Pals":
+        return cls(m0=cfg.m0, active=cfg.active, mu_in=cfg.mu_in, mu_out=cfg.mu_out,
+                   cutoff=cfg.cutoff, eps=cfg.eps, gamma=cfg.gamma)
+
+    def n_act(self, dim: int) -> int:
+        return ((self.active & 1) > 0) + ((self.active & 2) > 0) + (dim if self.active & 4 else 0)
+
+
+def pals_field(grid: Grid, pals: Pals, theta: torch.Tensor, mus_prime: float | None = None):
+    """mu(x_c; theta) on the grid, and D = 1/(3 (mu + mus')) when mus_prime is given."""
+    _need_cuda_f64(theta, "theta")
+    theta = theta.contiguous()
+    mua = torch.empty(grid.N, dtype=torch.float64, device=theta.device)
+    diff = torch.empty_like(mua) if mus_prime is not None else None
+    g, p = grid.c(), pals.c()
+    check(lib.dot_pals_field(C.byref(g), C.byref(p), _ptr(theta),
+                             float(mus_prime or 0.0), _ptr(mua),
+                             _ptr(diff) if diff is not None else None, _stream()),
+          "dot_pals_field")
+    return (mua, diff) if diff is not None else mua
+
+
+def gemm(A: torch.Tensor, B: torch.Tensor, transa: bool = False, transb: bool = False,
+         alpha: float = 1.0) -> torch.Tensor:
+    """alpha op(A) op(B) for logical matrices, computed by the library's FP64 kernel."""
+    Am, Bm = colmajor(A, "A"), colmajor(B, "B")
+    ar, ac = A.shape
+    br, bc = B.shape
+    m, kd = (ac, ar) if transa else (ar, ac)
+    kb, n = (bc, br) if transb else (br, bc)
+    if kd != kb:
+        raise ValueError("inner dimensions differ")
+    out = empty_colmajor(m, n, A.device)
+    check(lib.dot_gemm(int(transa), int(transb), m, n, kd, float(alpha), _ptr(Am), max(ar, 1),
+                       _ptr(Bm), max(br, 1), 0.0, _ptr(out), max(m, 1), _stream()), "dot_gemm")
+    return out
+
+
+@dataclass
+class SolveResult:
+    x: torch.Tensor          # logical (N, k) view of column-major storage
+    iters: np.ndarray        # per column
+    relres: np.ndarray       # true ||b - A x|| / ||b|| per column (binary64)
+    iters_max: int
+    outer: int
+    converged: bool
+
+
+class Operator:
+    """Handle over dot_op: A(p) on one grid, owned device arrays freed on close()."""
+
+    def __init__(self, grid: Grid, D: torch.Tensor):
+        _need_cuda_f64(D, "D")
+        if D.numel() != grid.N:
+            raise ValueError("D must have one value per cell")
+        self.grid = grid
+        self.device = D.device
+        self._handle = C.c_void_p()
+        g = grid.c()
+        check(lib.dot_build_operator(C.byref(g), _ptr(D.contiguous()), _stream(),
+                                     C.byref(self._handle)), "dot_build_operator")
+        self.pals = None
+
+    # ------------------------------------------------------------ lifetime
+    def close(self):
+        if self._handle:
+            lib.dot_destroy_operator(self._handle)
+            self._handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def N(self) -> int:
+        return self.grid.N
+
+    # ------------------------------------------------------------ operator
+    def set_mua(self, mua: torch.Tensor):
+        _need_cuda_f64(mua, "mua")
+        check(lib.dot_set_mua(self._handle, _ptr(mua.contiguous()), _stream()), "dot_set_mua")
+        self.pals = None
+
+    def pals_mua(self, pals: Pals, theta: torch.Tensor) -> torch.Tensor:
+        _need_cuda_f64(theta, "theta")
+        mua = torch.empty(self.N, dtype=torch.float64, device=self.device)
+        p = pals.c()
+        check(lib.dot_pals_mua(self._handle, C.byref(p), _ptr(theta.contiguous()), _ptr(mua),
+                               _stream()), "dot_pals_mua")
+        self.pals = pals
+        return mua
+
+    def apply(self, X: torch.Tensor) -> torch.Tensor:
+        X2 = X.reshape(-1, 1) if X.dim() == 1 else X
+        Xm = colmajor(X2, "X")
+        k = X2.shape[1]
+        Y = empty_colmajor(self.N, k, self.device)
+        check(lib.dot_apply(self._handle, k, _ptr(Xm), _ptr(Y), _stream()), "dot_apply")
+        return Y.reshape(-1) if X.dim() == 1 else Y
+
+    def form_rhs(self, cells, weights: torch.Tensor) -> torch.Tensor:
+        """B W: weights is (n_pts, k); returns the (N, k) right-hand side block."""
+        cells = np.ascontiguousarray(np.asarray(cells, dtype=np.int32))
+        Wm = colmajor(weights, "weights")
+        n_pts, k = weights.shape
+        if cells.size != n_pts:
+            raise ValueError("one cell per weight row")
+        rhs = empty_colmajor(self.N, k, self.device)
+        check(lib.dot_form_rhs(self._handle, n_pts, cells.ctypes.data_as(L._pi32), k, _ptr(Wm),
+                               _ptr(rhs), _stream()), "dot_form_rhs")
+        return rhs
+
+    def solve_workspace_bytes(self, k: int, precision: int) -> int:
+        return int(lib.dot_solve_workspace_bytes(self._handle, k, precision))
+
+    def solve(self, rhs: torch.Tensor, rtol: float = 1e-10, precision: int = L.DOT_FP64,
+              max_iter: int = 20000, inner_rtol: float = 1e-4, max_outer: int = 30,
+              check_every: int = 16, trans: int = 0, out: torch.Tensor | None = None,
+              work: torch.Tensor | None = None, warn: bool = True) -> SolveResult:
+        Bm = colmajor(rhs, "rhs")
+        k = rhs.shape[1]
+        x = out if out is not None else empty_colmajor(self.N, k, self.device)
+        nbytes = self.solve_workspace_bytes(k, precision)
+        if work is None or work.numel() < nbytes or work.data_ptr() % 256:
+            work = _workspace(nbytes, self.device)
+        opts = L.DotSolveOpts(rtol, max_iter, precision, inner_rtol, max_outer, check_every)
+        iters = np.zeros(k, dtype=np.int32)
+        rel = np.zeros(k, dtype=np.float64)
+        info = L.DotSolveInfo(0, 0, iters.ctypes.data_as(C.POINTER(C.c_int32)),
+                              rel.ctypes.data_as(C.POINTER(C.c_double)))
+        code = lib.dot_solve_multi_rhs(self._handle, trans, k, _ptr(Bm), _ptr(x), C.byref(opts),
+                                       _ptr(work), work.numel(), C.byref(info), _stream())
+        check(code, "dot_solve_multi_rhs")
+        if code == L.DOT_NOT_CONVERGED and warn:
+            warnings.warn(f"solve did not reach rtol={rtol}: max relres {rel.max():.3e}",
+                          L.NotConverged)
+        return SolveResult(x=x, iters=iters, relres=rel, iters_max=info.iters_max,
+                           outer=info.outer, converged=code == L.DOT_OK)
+
+    # ------------------------------------------------------------ estimators
+    def sampled_misfit(self, det_cells, U: torch.Tensor, V: torch.Tensor, DW: torch.Tensor):
+        """R_s = V^T (C^T U - D W) and f = 1/2 ||R_s||_F^2."""
+        det = np.ascontiguousarray(np.asarray(det_cells, dtype=np.int32))
+        Um, Vm, DWm = colmajor(U, "U"), colmajor(V, "V"), colmajor(DW, "DW")
+        n_d, l_d = V.shape
+        l_s = U.shape[1]
+        if DW.shape != (n_d, l_s) or det.size != n_d:
+            raise ValueError("shape mismatch in sampled_misfit")
+        Rs = empty_colmajor(l_d, l_s, self.device)
+        f = C.c_double(0.0)
+        check(lib.dot_sampled_misfit(self._handle, n_d, det.ctypes.data_as(L._pi32), l_s, _ptr(Um),
+                                     l_d, _ptr(Vm), _ptr(DWm), _ptr(Rs), C.byref(f), _stream()),
+              "dot_sampled_misfit")
+        return Rs, f.value
+
+    def jacobian_workspace_bytes(self, l_s: int, l_d: int) -> int:
+        return int(lib.dot_jacobian_workspace_bytes(self._handle, l_s, l_d))
+
+    def jacobian(self, U: torch.Tensor, Z: torch.Tensor, precision: int = L.DOT_JAC_FP64,
+                 work: torch.Tensor | None = None) -> torch.Tensor:
+        if self.pals is None:
+            raise RuntimeError("call pals_mua before jacobian")
+        Um, Zm = colmajor(U, "U"), colmajor(Z, "Z")
+        l_s, l_d = U.shape[1], Z.shape[1]
+        n_p = self.pals.m0 * self.pals.n_act(self.grid.dim)
+        Js = empty_colmajor(l_s * l_d, n_p, self.device)
+        nbytes = self.jacobian_workspace_bytes(l_s, l_d)
+        if work is None or work.numel() < nbytes or work.data_ptr() % 256:
+            work = _workspace(nbytes, self.device)
+        check(lib.dot_jacobian(self._handle, l_s, _ptr(Um), l_d, _ptr(Zm), precision, _ptr(Js),
+                               _ptr(work), work.numel(), _stream()), "dot_jacobian")
+        return Js
+
+    def grad_misfit(self, U: torch.Tensor, Z: torch.Tensor, Rs: torch.Tensor,
+                    work: torch.Tensor | None = None) -> torch.Tensor:
+        if self.pals is None:
+            raise RuntimeError("call pals_mua before grad_misfit")
+        Um, Zm, Rm = colmajor(U, "U"), colmajor(Z, "Z"), colmajor(Rs, "Rs")
+        l_s, l_d = U.shape[1], Z.shape[1]
+        n_p = self.pals.m0 * self.pals.n_act(self.grid.dim)
+        g = torch.empty(n_p, dtype=torch.float64, device=self.device)
+        nbytes = self.jacobian_workspace_bytes(l_s, l_d)
+        if work is None or work.numel() < nbytes or work.data_ptr() % 256:
+            work = _workspace(nbytes, self.device)
+        check(lib.dot_grad_misfit(self._handle, l_s, _ptr(Um), l_d, _ptr(Zm), _ptr(Rm), _ptr(g),
+                                  _ptr(work), work.numel(), _stream()), "dot_grad_misfit")
+        return g

@@ -1,0 +1,106 @@
+// Internal declarations shared by the dotpath HIP sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstddef>
+#include <cstdint>
+#include <cstdio>
+
+#include "../../include/dotpath.h"
+
+namespace dot {
+
+// ---------------------------------------------------------------- errors
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define DOT_FAIL(code, ...)          \
+  do {                               \
+    ::dot::set_error(__VA_ARGS__);   \
+    return (code);                   \
+  } while (0)
+
+#define DOT_HIP(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      ::dot::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                       __LINE__);                                                      \
+      return DOT_EHIP;                                                                 \
+    }                                                                                  \
+  } while (0)
+
+#define DOT_LAUNCH_CHECK() DOT_HIP(hipGetLastError())
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ---------------------------------------------------------------- handle
+struct GridDims {
+  int dim;
+  int nx, ny, nz;
+  int64_t nxy, N;
+  double h;
+  double hd;   // h^d (cell volume)
+};
+
+struct dot_state_arrays;
+
+}  // namespace dot
+
+struct dot_op {
+  dot::GridDims g;
+  int bc[6];
+  int device;
+  // binary64 operator (unscaled): face coefficients to the +axis neighbour
+  // (zero on the last layer), boundary diagonal b0, full diagonal.
+  double* cx = nullptr;
+  double* cy = nullptr;
+  double* cz = nullptr;
+  double* b0 = nullptr;
+  double* diag = nullptr;
+  // symmetric Jacobi scaling: sd = sqrt(diag); scaled coefficients
+  // T / (sd_c sd_c'), unit diagonal (binary64 and binary32 copies).
+  double* sd = nullptr;
+  double* sx = nullptr;
+  double* sy = nullptr;
+  double* sz = nullptr;
+  float* sx32 = nullptr;
+  float* sy32 = nullptr;
+  float* sz32 = nullptr;
+  // level-set state from the last dot_pals_mua call
+  double* phi = nullptr;
+  double* theta = nullptr;      // copy of theta (m0 x (2 + dim))
+  int64_t theta_cap = 0;
+  dot_pals pals{};
+  bool have_pals = false;
+  // per-RBF cell lists where d mu / d p is nonzero: cells sorted by RBF then
+  // cell index; rbf_start[m]..rbf_start[m+1]; chunk table for the contraction
+  int32_t* pair_cell = nullptr;
+  int64_t pair_cap = 0;
+  int64_t n_pairs = 0;
+  int64_t* rbf_start = nullptr;  // device, m0 + 1
+  int32_t* chunk_rbf = nullptr;  // device, per chunk: RBF index
+  int64_t* chunk_begin = nullptr;  // device, per chunk: first pair
+  int32_t* rbf_chunk0 = nullptr;   // device, m0 + 1: first chunk of each RBF
+  int64_t chunk_cap = 0;
+  int64_t n_chunks = 0;
+  int64_t rbf_cap = 0;
+  // small device/pinned staging
+  int32_t* cells_dev = nullptr;   // optode cells staging
+  int64_t cells_cap = 0;
+  double* small_dev = nullptr;    // small device scratch (scalars)
+  int32_t* pinned = nullptr;      // pinned host mailbox (counters/flags)
+  double* pinned_d = nullptr;     // pinned host doubles (misfit, small results)
+};
+
+namespace dot {
+
+int validate_grid(const dot_grid* g, GridDims* out, const char** why);
+int ensure_cells_dev(dot_op* op, int n, const int32_t* cells_host, hipStream_t s);
+
+constexpr int kWave = 64;
+
+}  // namespace dot

@@ -1,0 +1,615 @@
+// Operator construction, PaLS absorption, right-hand sides.
+//
+// Section 2 (eq. PDE, PaLS definition, eq. absorption const) and Section 3.1
+// (eq. Rw).  The finite-volume coefficients, the smoothed Heaviside and the
+// frozen diffusion follow the readings stated in include/dotpath.h.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "dot_internal.h"
+
+namespace dot {
+
+// ------------------------------------------------------------------ errors
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+void clear_error() { g_err[0] = '\0'; }
+
+int validate_grid(const dot_grid* g, GridDims* out, const char** why) {
+  if (!g) {
+    *why = "grid is NULL";
+    return DOT_EINVAL;
+  }
+  if (g->dim != 2 && g->dim != 3) {
+    *why = "grid.dim must be 2 or 3";
+    return DOT_EINVAL;
+  }
+  const int nz = g->dim == 3 ? g->n[2] : 1;
+  if (g->n[0] < 1 || g->n[1] < 1 || nz < 1) {
+    *why = "grid.n must be positive";
+    return DOT_EINVAL;
+  }
+  if (g->n[0] > (1 << 20) || g->n[1] > (1 << 20) || nz > (1 << 20)) {
+    *why = "grid.n too large";
+    return DOT_EINVAL;
+  }
+  const int64_t N = (int64_t)g->n[0] * g->n[1] * nz;
+  if (N > ((int64_t)1 << 31) - 1) {
+    *why = "grid has more than 2^31-1 cells";
+    return DOT_EINVAL;
+  }
+  for (int f = 0; f < 2 * g->dim; ++f) {
+    if (g->bc[f] != DOT_BC_DIRICHLET && g->bc[f] != DOT_BC_ROBIN) {
+      *why = "grid.bc entries must be DOT_BC_DIRICHLET or DOT_BC_ROBIN";
+      return DOT_EINVAL;
+    }
+  }
+  if (out) {
+    out->dim = g->dim;
+    out->nx = g->n[0];
+    out->ny = g->n[1];
+    out->nz = nz;
+    out->nxy = (int64_t)g->n[0] * g->n[1];
+    out->N = N;
+    out->h = 1.0 / g->n[0];
+    out->hd = g->dim == 3 ? out->h * out->h * out->h : out->h * out->h;
+  }
+  return DOT_OK;
+}
+
+static int validate_pals(const dot_pals* p, int dim) {
+  if (!p) DOT_FAIL(DOT_EINVAL, "pals is NULL");
+  if (p->m0 < 1 || p->m0 > (1 << 20)) DOT_FAIL(DOT_EINVAL, "pals.m0 must be in [1, 2^20]");
+  if ((p->active & ~7u) != 0 || p->active == 0)
+    DOT_FAIL(DOT_EINVAL, "pals.active must be a nonzero combination of DOT_ACT_* bits");
+  if (!(p->eps > 0.0) || !std::isfinite(p->eps)) DOT_FAIL(DOT_EINVAL, "pals.eps must be > 0");
+  if (!(p->gamma >= 0.0) || !(p->gamma < 1.0)) DOT_FAIL(DOT_EINVAL, "pals.gamma must be in [0, 1)");
+  if (!std::isfinite(p->mu_in) || !std::isfinite(p->mu_out) || !std::isfinite(p->cutoff))
+    DOT_FAIL(DOT_EINVAL, "pals constants must be finite");
+  (void)dim;
+  return DOT_OK;
+}
+
+int ensure_cells_dev(dot_op* op, int n, const int32_t* cells_host, hipStream_t s) {
+  if (n > op->cells_cap) {
+    if (op->cells_dev) DOT_HIP(hipFree(op->cells_dev));
+    op->cells_dev = nullptr;
+    int64_t cap = std::max<int64_t>(n, 1024);
+    DOT_HIP(hipMalloc(&op->cells_dev, cap * sizeof(int32_t)));
+    op->cells_cap = cap;
+  }
+  DOT_HIP(hipMemcpyAsync(op->cells_dev, cells_host, (size_t)n * sizeof(int32_t),
+                         hipMemcpyHostToDevice, s));
+  return DOT_OK;
+}
+
+// ------------------------------------------------------------------ PaLS
+struct PalsK {
+  double mu_in, mu_out, cutoff, eps, gamma;
+  int m0, dim, stride;  // stride = 2 + dim
+};
+
+__device__ __forceinline__ double wendland(double r) {
+  if (r >= 1.0) return 0.0;
+  const double o = 1.0 - r;
+  const double o2 = o * o;
+  return o2 * o2 * (4.0 * r + 1.0);
+}
+
+__device__ __forceinline__ double heaviside_eps(double s, double eps) {
+  if (s < -eps) return 0.0;
+  if (s > eps) return 1.0;
+  return 0.5 * (1.0 + s / eps + sin(M_PI * s / eps) / M_PI);
+}
+
+// Block-wide exclusive prefix sum of a 0/1 flag over 256 threads; returns the
+// position and sets *total.  Order follows threadIdx.x, so compaction is
+// deterministic.
+__device__ __forceinline__ int block_scan_flag256(int flag, int* s_wave, int* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const unsigned long long bal = __ballot(flag);
+  const int before = __popcll(bal & ((1ull << lane) - 1ull));
+  if (lane == 0) s_wave[wave] = __popcll(bal);
+  __syncthreads();
+  int off = 0, tot = 0;
+  for (int w = 0; w < 4; ++w) {
+    if (w < wave) off += s_wave[w];
+    tot += s_wave[w];
+  }
+  *total = tot;
+  return off + before;
+}
+
+// One block of 256 threads per cell tile (8x8x4 in 3D, 16x16 in 2D).  RBFs are
+// culled against the tile's bounding box in chunks of 256, compacted in RBF
+// order, and summed in that order at each cell centre.
+__global__ __launch_bounds__(256) void pals_field_kernel(GridDims g, PalsK p,
+                                                         const double* __restrict__ theta,
+                                                         double mus_prime, double* __restrict__ mua,
+                                                         double* __restrict__ diff,
+                                                         double* __restrict__ phi_out) {
+  __shared__ int s_wave[4];
+  __shared__ int s_list[256];
+  const bool d3 = g.dim == 3;
+  const int TX = d3 ? 8 : 16, TY = d3 ? 8 : 16, TZ = d3 ? 4 : 1;
+  const int tiles_x = (g.nx + TX - 1) / TX, tiles_y = (g.ny + TY - 1) / TY;
+  const int tile = blockIdx.x;
+  const int bx = tile % tiles_x, by = (tile / tiles_x) % tiles_y, bz = tile / (tiles_x * tiles_y);
+  const int t = threadIdx.x;
+  const int lx = t % TX, ly = (t / TX) % TY, lz = t / (TX * TY);
+  const int x = bx * TX + lx, y = by * TY + ly, z = bz * TZ + lz;
+  const bool inside = x < g.nx && y < g.ny && z < g.nz;
+  const double h = g.h;
+  const double xc0 = (x + 0.5) * h, xc1 = (y + 0.5) * h, xc2 = (z + 0.5) * h;
+  // tile bounding box of cell centres
+  const double lo0 = (bx * TX + 0.5) * h, hi0 = (min(g.nx, bx * TX + TX) - 0.5) * h;
+  const double lo1 = (by * TY + 0.5) * h, hi1 = (min(g.ny, by * TY + TY) - 0.5) * h;
+  const double lo2 = (bz * TZ + 0.5) * h, hi2 = (min(g.nz, bz * TZ + TZ) - 0.5) * h;
+  const double g2 = p.gamma * p.gamma;
+  double phi = 0.0;
+  for (int base = 0; base < p.m0; base += 256) {
+    const int j = base + t;
+    int flag = 0;
+    if (j < p.m0) {
+      const double* th = theta + (int64_t)j * p.stride;
+      const double beta = th[1];
+      double d0 = fmax(0.0, fmax(lo0 - th[2], th[2] - hi0));
+      double d1 = fmax(0.0, fmax(lo1 - th[3], th[3] - hi1));
+      double dist2 = d0 * d0 + d1 * d1;
+      if (d3) {
+        double d2 = fmax(0.0, fmax(lo2 - th[4], th[4] - hi2));
+        dist2 += d2 * d2;
+      }
+      // conservative: every cell in the box has rho >= dist
+      flag = (beta * beta * dist2 + g2 < 1.0) ? 1 : 0;
+    }
+    int total;
+    const int pos = block_scan_flag256(flag, s_wave, &total);
+    if (flag) s_list[pos] = j;
+    __syncthreads();
+    if (inside) {
+      for (int q = 0; q < total; ++q) {
+        const double* th = theta + (int64_t)s_list[q] * p.stride;
+        const double alpha = th[0], beta = th[1];
+        const double e0 = xc0 - th[2], e1 = xc1 - th[3];
+        double rho2 = e0 * e0 + e1 * e1;
+        if (d3) {
+          const double e2 = xc2 - th[4];
+          rho2 += e2 * e2;
+        }
+        const double r = sqrt(beta * beta * rho2 + g2);
+        phi += alpha * wendland(r);
+      }
+    }
+    __syncthreads();
+  }
+  if (!inside) return;
+  const int64_t c = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+  const double H = heaviside_eps(phi - p.cutoff, p.eps);
+  const double mu = p.mu_in * H + p.mu_out * (1.0 - H);
+  if (mua) mua[c] = mu;
+  if (diff) diff[c] = 1.0 / (3.0 * (mu + mus_prime));
+  if (phi_out) phi_out[c] = phi;
+}
+
+static int launch_pals(const GridDims& g, const dot_pals* pals, const double* theta,
+                       double mus_prime, double* mua, double* diff, double* phi, hipStream_t s) {
+  PalsK p{pals->mu_in, pals->mu_out, pals->cutoff, pals->eps, pals->gamma, pals->m0, g.dim,
+          2 + g.dim};
+  int64_t tiles;
+  if (g.dim == 3)
+    tiles = (int64_t)((g.nx + 7) / 8) * ((g.ny + 7) / 8) * ((g.nz + 3) / 4);
+  else
+    tiles = (int64_t)((g.nx + 15) / 16) * ((g.ny + 15) / 16);
+  hipLaunchKernelGGL(pals_field_kernel, dim3((unsigned)tiles), dim3(256), 0, s, g, p, theta,
+                     mus_prime, mua, diff, phi);
+  DOT_LAUNCH_CHECK();
+  return DOT_OK;
+}
+
+// ------------------------------------------------------------------ operator
+__device__ __forceinline__ double bdry_T(int code, double Dc, double h, int d) {
+  const double hd2 = d == 3 ? h : 1.0;       // h^(d-2)
+  const double hd1 = d == 3 ? h * h : h;     // h^(d-1)
+  if (code == DOT_BC_DIRICHLET) return hd2 * 2.0 * Dc;
+  return hd1 * 2.0 * Dc / (h + 4.0 * Dc);
+}
+
+struct BC6 {
+  int f[6];
+};
+
+__global__ void build_coef_kernel(GridDims g, BC6 bc, const double* __restrict__ D,
+                                  double* __restrict__ cx, double* __restrict__ cy,
+                                  double* __restrict__ cz, double* __restrict__ b0) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= g.N) return;
+  const int x = (int)(c % g.nx);
+  const int y = (int)((c / g.nx) % g.ny);
+  const int z = (int)(c / g.nxy);
+  const int d = g.dim;
+  const double hd2 = d == 3 ? g.h : 1.0;
+  const double Dc = D[c];
+  double tx = 0.0, ty = 0.0, tz = 0.0;
+  if (x + 1 < g.nx) {
+    const double Dn = D[c + 1];
+    tx = hd2 * 2.0 * Dc * Dn / (Dc + Dn);
+  }
+  if (y + 1 < g.ny) {
+    const double Dn = D[c + g.nx];
+    ty = hd2 * 2.0 * Dc * Dn / (Dc + Dn);
+  }
+  if (d == 3 && z + 1 < g.nz) {
+    const double Dn = D[c + g.nxy];
+    tz = hd2 * 2.0 * Dc * Dn / (Dc + Dn);
+  }
+  double bb = 0.0;
+  if (x == 0) bb += bdry_T(bc.f[0], Dc, g.h, d);
+  if (x == g.nx - 1) bb += bdry_T(bc.f[1], Dc, g.h, d);
+  if (y == 0) bb += bdry_T(bc.f[2], Dc, g.h, d);
+  if (y == g.ny - 1) bb += bdry_T(bc.f[3], Dc, g.h, d);
+  if (d == 3) {
+    if (z == 0) bb += bdry_T(bc.f[4], Dc, g.h, d);
+    if (z == g.nz - 1) bb += bdry_T(bc.f[5], Dc, g.h, d);
+  }
+  cx[c] = tx;
+  cy[c] = ty;
+  cz[c] = tz;
+  b0[c] = bb;
+}
+
+// diag = b0 + sum of the face coefficients + h^d mu;  sd = sqrt(diag)
+__global__ void diag_kernel(GridDims g, const double* __restrict__ cx, const double* __restrict__ cy,
+                            const double* __restrict__ cz, const double* __restrict__ b0,
+                            const double* __restrict__ mua, double* __restrict__ diag,
+                            double* __restrict__ sd) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= g.N) return;
+  const int x = (int)(c % g.nx);
+  const int y = (int)((c / g.nx) % g.ny);
+  const int z = (int)(c / g.nxy);
+  double s = b0[c] + (mua ? g.hd * mua[c] : 0.0);
+  s += cx[c];
+  if (x > 0) s += cx[c - 1];
+  s += cy[c];
+  if (y > 0) s += cy[c - g.nx];
+  if (g.dim == 3) {
+    s += cz[c];
+    if (z > 0) s += cz[c - g.nxy];
+  }
+  diag[c] = s;
+  sd[c] = sqrt(s);
+}
+
+__global__ void scale_kernel(GridDims g, const double* __restrict__ cx, const double* __restrict__ cy,
+                             const double* __restrict__ cz, const double* __restrict__ sd,
+                             double* __restrict__ sx, double* __restrict__ sy,
+                             double* __restrict__ sz, float* __restrict__ sx32,
+                             float* __restrict__ sy32, float* __restrict__ sz32) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= g.N) return;
+  const int x = (int)(c % g.nx);
+  const int y = (int)((c / g.nx) % g.ny);
+  const int z = (int)(c / g.nxy);
+  const double s0 = sd[c];
+  const double vx = (x + 1 < g.nx) ? cx[c] / (s0 * sd[c + 1]) : 0.0;
+  const double vy = (y + 1 < g.ny) ? cy[c] / (s0 * sd[c + g.nx]) : 0.0;
+  const double vz = (g.dim == 3 && z + 1 < g.nz) ? cz[c] / (s0 * sd[c + g.nxy]) : 0.0;
+  sx[c] = vx;
+  sy[c] = vy;
+  sz[c] = vz;
+  sx32[c] = (float)vx;
+  sy32[c] = (float)vy;
+  sz32[c] = (float)vz;
+}
+
+static unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+static int refresh_diag(dot_op* op, const double* mua, hipStream_t s) {
+  const GridDims& g = op->g;
+  hipLaunchKernelGGL(diag_kernel, dim3(nblk(g.N, 256)), dim3(256), 0, s, g, op->cx, op->cy,
+                     op->cz, op->b0, mua, op->diag, op->sd);
+  DOT_LAUNCH_CHECK();
+  hipLaunchKernelGGL(scale_kernel, dim3(nblk(g.N, 256)), dim3(256), 0, s, g, op->cx, op->cy,
+                     op->cz, op->sd, op->sx, op->sy, op->sz, op->sx32, op->sy32, op->sz32);
+  DOT_LAUNCH_CHECK();
+  return DOT_OK;
+}
+
+// ------------------------------------------------------------------ RBF cell lists
+// For RBF m, the cells inside its support (r < 1) and inside the Heaviside band
+// (|phi - c| <= eps): exactly the cells where some d mu / d p_k of that RBF can
+// be nonzero.  Enumerated over the support's bounding box in increasing cell
+// index, one block per RBF.
+struct BoxK {
+  int lo[3], ext[3];
+};
+
+__device__ __forceinline__ void rbf_box(const GridDims& g, const double* th, double gamma, int* lo,
+                                        int* ext) {
+  const double beta = th[1];
+  const double R = sqrt(fmax(0.0, 1.0 - gamma * gamma)) / beta;
+  const int n[3] = {g.nx, g.ny, g.nz};
+  for (int a = 0; a < 3; ++a) {
+    if (a >= g.dim) {
+      lo[a] = 0;
+      ext[a] = 1;
+      continue;
+    }
+    double a0 = (th[2 + a] - R) / g.h - 0.5;
+    double a1 = (th[2 + a] + R) / g.h - 0.5;
+    int i0 = (int)ceil(fmax(a0, -1.0));
+    int i1 = (int)floor(fmin(a1, (double)n[a]));
+    i0 = max(i0, 0);
+    i1 = min(i1, n[a] - 1);
+    lo[a] = i0;
+    ext[a] = max(0, i1 - i0 + 1);
+  }
+}
+
+template <bool kFill>
+__global__ __launch_bounds__(256) void rbf_cells_kernel(GridDims g, PalsK p,
+                                                        const double* __restrict__ theta,
+                                                        const double* __restrict__ phi,
+                                                        int64_t* __restrict__ counts,
+                                                        const int64_t* __restrict__ start,
+                                                        int32_t* __restrict__ cells) {
+  __shared__ int s_wave[4];
+  const int m = blockIdx.x;
+  const double* th = theta + (int64_t)m * p.stride;
+  int lo[3], ext[3];
+  rbf_box(g, th, p.gamma, lo, ext);
+  const int64_t box = (int64_t)ext[0] * ext[1] * ext[2];
+  const double beta = th[1], g2 = p.gamma * p.gamma;
+  int64_t total = 0;
+  int64_t out = kFill ? start[m] : 0;
+  for (int64_t base = 0; base < box; base += 256) {
+    const int64_t q = base + threadIdx.x;
+    int flag = 0;
+    int64_t c = 0;
+    if (q < box) {
+      const int ix = (int)(q % ext[0]);
+      const int iy = (int)((q / ext[0]) % ext[1]);
+      const int iz = (int)(q / ((int64_t)ext[0] * ext[1]));
+      const int x = lo[0] + ix, y = lo[1] + iy, z = lo[2] + iz;
+      c = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+      const double e0 = (x + 0.5) * g.h - th[2], e1 = (y + 0.5) * g.h - th[3];
+      double rho2 = e0 * e0 + e1 * e1;
+      if (g.dim == 3) {
+        const double e2 = (z + 0.5) * g.h - th[4];
+        rho2 += e2 * e2;
+      }
+      const double r = sqrt(beta * beta * rho2 + g2);
+      const double s = phi[c] - p.cutoff;
+      flag = (r < 1.0 && fabs(s) <= p.eps) ? 1 : 0;
+    }
+    int tot;
+    const int pos = block_scan_flag256(flag, s_wave, &tot);
+    if (kFill && flag) cells[out + pos] = (int32_t)c;
+    out += tot;
+    total += tot;
+    __syncthreads();
+  }
+  if (!kFill && threadIdx.x == 0) counts[m] = total;
+}
+
+}  // namespace dot
+
+using namespace dot;
+
+// ====================================================================== ABI
+extern "C" {
+
+int dot_abi_version(void) { return DOT_ABI_VERSION; }
+
+const char* dot_last_error(void) { return dot::g_err; }
+
+int64_t dot_grid_cells(const dot_grid* grid) {
+  GridDims g;
+  const char* why = "";
+  if (validate_grid(grid, &g, &why) != DOT_OK) return -1;
+  return g.N;
+}
+
+int dot_pals_field(const dot_grid* grid, const dot_pals* pals, const double* theta_dev,
+                   double mus_prime, double* mua_dev, double* diff_dev, void* stream) {
+  clear_error();
+  GridDims g;
+  const char* why = "";
+  if (validate_grid(grid, &g, &why) != DOT_OK) DOT_FAIL(DOT_EINVAL, "%s", why);
+  int rc = validate_pals(pals, g.dim);
+  if (rc) return rc;
+  if (!theta_dev) DOT_FAIL(DOT_EINVAL, "theta_dev is NULL");
+  if (!mua_dev) DOT_FAIL(DOT_EINVAL, "mua_dev is NULL");
+  if (diff_dev && !(mus_prime >= 0.0)) DOT_FAIL(DOT_EINVAL, "mus_prime must be >= 0");
+  return launch_pals(g, pals, theta_dev, mus_prime, mua_dev, diff_dev, nullptr,
+                     as_stream(stream));
+}
+
+int dot_build_operator(const dot_grid* grid, const double* D_dev, void* stream, dot_op** out) {
+  clear_error();
+  GridDims g;
+  const char* why = "";
+  if (validate_grid(grid, &g, &why) != DOT_OK) DOT_FAIL(DOT_EINVAL, "%s", why);
+  if (!D_dev) DOT_FAIL(DOT_EINVAL, "D_dev is NULL");
+  if (!out) DOT_FAIL(DOT_EINVAL, "out is NULL");
+  *out = nullptr;
+  hipStream_t s = as_stream(stream);
+  dot_op* op = new dot_op();
+  op->g = g;
+  for (int f = 0; f < 6; ++f) op->bc[f] = (f < 2 * g.dim) ? grid->bc[f] : DOT_BC_DIRICHLET;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  op->device = dev;
+  const size_t n8 = (size_t)g.N * sizeof(double), n4 = (size_t)g.N * sizeof(float);
+  double** d64[] = {&op->cx, &op->cy, &op->cz, &op->b0, &op->diag, &op->sd,
+                    &op->sx, &op->sy, &op->sz, &op->phi};
+  float** d32[] = {&op->sx32, &op->sy32, &op->sz32};
+  for (double** p : d64)
+    if (e == hipSuccess) e = hipMalloc(p, n8);
+  for (float** p : d32)
+    if (e == hipSuccess) e = hipMalloc(p, n4);
+  if (e == hipSuccess) e = hipMalloc(&op->small_dev, 64 * sizeof(double));
+  if (e == hipSuccess) e = hipHostMalloc(&op->pinned, 64 * sizeof(int32_t), hipHostMallocDefault);
+  if (e == hipSuccess)
+    e = hipHostMalloc(&op->pinned_d, 64 * sizeof(double), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    set_error("device allocation failed: %s", hipGetErrorString(e));
+    dot_destroy_operator(op);
+    return e == hipErrorOutOfMemory ? DOT_ENOMEM : DOT_EHIP;
+  }
+  BC6 bc;
+  for (int f = 0; f < 6; ++f) bc.f[f] = op->bc[f];
+  hipLaunchKernelGGL(build_coef_kernel, dim3(nblk(g.N, 256)), dim3(256), 0, s, g, bc, D_dev,
+                     op->cx, op->cy, op->cz, op->b0);
+  int rc = DOT_OK;
+  e = hipGetLastError();
+  if (e == hipSuccess) rc = refresh_diag(op, nullptr, s);
+  if (e != hipSuccess || rc != DOT_OK) {
+    if (e != hipSuccess) set_error("build_coef_kernel: %s", hipGetErrorString(e));
+    dot_destroy_operator(op);
+    return DOT_EHIP;
+  }
+  *out = op;
+  return DOT_OK;
+}
+
+int dot_destroy_operator(dot_op* op) {
+  if (!op) return DOT_OK;
+  (void)hipDeviceSynchronize();
+  void* ptrs[] = {op->cx,        op->cy,         op->cz,          op->b0,        op->diag,
+                  op->sd,        op->sx,         op->sy,          op->sz,        op->sx32,
+                  op->sy32,      op->sz32,       op->phi,         op->theta,     op->pair_cell,
+                  op->rbf_start, op->chunk_rbf,  op->chunk_begin, op->rbf_chunk0, op->cells_dev,  op->small_dev};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (op->pinned) (void)hipHostFree(op->pinned);
+  if (op->pinned_d) (void)hipHostFree(op->pinned_d);
+  delete op;
+  return DOT_OK;
+}
+
+int64_t dot_operator_cells(const dot_op* op) { return op ? op->g.N : -1; }
+
+int dot_set_mua(dot_op* op, const double* mua_dev, void* stream) {
+  clear_error();
+  if (!op) DOT_FAIL(DOT_EINVAL, "op is NULL");
+  if (!mua_dev) DOT_FAIL(DOT_EINVAL, "mua_dev is NULL");
+  op->have_pals = false;
+  return refresh_diag(op, mua_dev, as_stream(stream));
+}
+
+int dot_pals_mua(dot_op* op, const dot_pals* pals, const double* theta_dev, double* mua_dev,
+                 void* stream) {
+  clear_error();
+  if (!op) DOT_FAIL(DOT_EINVAL, "op is NULL");
+  int rc = validate_pals(pals, op->g.dim);
+  if (rc) return rc;
+  if (!theta_dev) DOT_FAIL(DOT_EINVAL, "theta_dev is NULL");
+  hipStream_t s = as_stream(stream);
+  const GridDims& g = op->g;
+  const int m0 = pals->m0, stride = 2 + g.dim;
+  // keep a copy of theta
+  if ((int64_t)m0 * stride > op->theta_cap) {
+    if (op->theta) DOT_HIP(hipFree(op->theta));
+    op->theta = nullptr;
+    op->theta_cap = 0;
+    DOT_HIP(hipMalloc(&op->theta, (size_t)m0 * stride * sizeof(double)));
+    op->theta_cap = (int64_t)m0 * stride;
+  }
+  DOT_HIP(hipMemcpyAsync(op->theta, theta_dev, (size_t)m0 * stride * sizeof(double),
+                         hipMemcpyDeviceToDevice, s));
+  // mu and phi, then the diagonal.  Without a caller buffer, mu is written
+  // into the diagonal array itself: diag_kernel reads mu[c] and writes
+  // diag[c] from the same thread, so the update is safe in place.
+  double* tmp_mu = mua_dev ? mua_dev : op->diag;
+  rc = launch_pals(g, pals, op->theta, 0.0, tmp_mu, nullptr, op->phi, s);
+  if (rc) return rc;
+  rc = refresh_diag(op, tmp_mu, s);
+  if (rc) return rc;
+  // per-RBF cell lists
+  if (m0 + 1 > op->rbf_cap) {
+    if (op->rbf_start) DOT_HIP(hipFree(op->rbf_start));
+    if (op->rbf_chunk0) DOT_HIP(hipFree(op->rbf_chunk0));
+    op->rbf_start = nullptr;
+    op->rbf_chunk0 = nullptr;
+    op->rbf_cap = 0;
+    DOT_HIP(hipMalloc(&op->rbf_start, (size_t)(m0 + 1) * sizeof(int64_t)));
+    DOT_HIP(hipMalloc(&op->rbf_chunk0, (size_t)(m0 + 1) * sizeof(int32_t)));
+    op->rbf_cap = m0 + 1;
+  }
+  PalsK p{pals->mu_in, pals->mu_out, pals->cutoff, pals->eps, pals->gamma, m0, g.dim, stride};
+  hipLaunchKernelGGL(rbf_cells_kernel<false>, dim3(m0), dim3(256), 0, s, g, p, op->theta, op->phi,
+                     op->rbf_start, nullptr, nullptr);
+  DOT_LAUNCH_CHECK();
+  std::vector<int64_t> counts(m0 + 1, 0);
+  DOT_HIP(hipMemcpyAsync(counts.data(), op->rbf_start, (size_t)m0 * sizeof(int64_t),
+                         hipMemcpyDeviceToHost, s));
+  DOT_HIP(hipStreamSynchronize(s));
+  std::vector<int64_t> start(m0 + 1, 0);
+  for (int m = 0; m < m0; ++m) start[m + 1] = start[m] + counts[m];
+  const int64_t total = start[m0];
+  // chunk table: each RBF's list split into chunks of at most kPairChunk cells
+  const int64_t kPairChunk = 2048;
+  std::vector<int32_t> chunk_rbf;
+  std::vector<int64_t> chunk_begin;
+  std::vector<int32_t> rbf_chunk0(m0 + 1, 0);
+  for (int m = 0; m < m0; ++m) {
+    rbf_chunk0[m] = (int32_t)chunk_rbf.size();
+    for (int64_t b = start[m]; b < start[m + 1]; b += kPairChunk) {
+      chunk_rbf.push_back(m);
+      chunk_begin.push_back(b);
+    }
+  }
+  rbf_chunk0[m0] = (int32_t)chunk_rbf.size();
+  const int64_t nch = (int64_t)chunk_rbf.size();
+  if (std::max<int64_t>(total, 1) > op->pair_cap) {
+    if (op->pair_cell) DOT_HIP(hipFree(op->pair_cell));
+    op->pair_cell = nullptr;
+    op->pair_cap = 0;
+    const int64_t cap = std::max<int64_t>(total + total / 8, 1024);
+    DOT_HIP(hipMalloc(&op->pair_cell, (size_t)cap * sizeof(int32_t)));
+    op->pair_cap = cap;
+  }
+  if (std::max<int64_t>(nch, 1) > op->chunk_cap) {
+    if (op->chunk_rbf) DOT_HIP(hipFree(op->chunk_rbf));
+    if (op->chunk_begin) DOT_HIP(hipFree(op->chunk_begin));
+    op->chunk_rbf = nullptr;
+    op->chunk_begin = nullptr;
+    op->chunk_cap = 0;
+    const int64_t cap = std::max<int64_t>(nch + nch / 8, 256);
+    DOT_HIP(hipMalloc(&op->chunk_rbf, (size_t)cap * sizeof(int32_t)));
+    DOT_HIP(hipMalloc(&op->chunk_begin, (size_t)(cap + 1) * sizeof(int64_t)));
+    op->chunk_cap = cap;
+  }
+  chunk_begin.push_back(total);
+  DOT_HIP(hipMemcpyAsync(op->rbf_start, start.data(), (size_t)(m0 + 1) * sizeof(int64_t),
+                         hipMemcpyHostToDevice, s));
+  DOT_HIP(hipMemcpyAsync(op->rbf_chunk0, rbf_chunk0.data(), (size_t)(m0 + 1) * sizeof(int32_t),
+                         hipMemcpyHostToDevice, s));
+  if (nch > 0) {
+    DOT_HIP(hipMemcpyAsync(op->chunk_rbf, chunk_rbf.data(), (size_t)nch * sizeof(int32_t),
+                           hipMemcpyHostToDevice, s));
+  }
+  DOT_HIP(hipMemcpyAsync(op->chunk_begin, chunk_begin.data(), (size_t)(nch + 1) * sizeof(int64_t),
+                         hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(rbf_cells_kernel<true>, dim3(m0), dim3(256), 0, s, g, p, op->theta, op->phi,
+                     nullptr, op->rbf_start, op->pair_cell);
+  DOT_LAUNCH_CHECK();
+  // the host vectors above are read by the asynchronous copies: wait for them
+  DOT_HIP(hipStreamSynchronize(s));
+  op->n_pairs = total;
+  op->n_chunks = nch;
+  op->pals = *pals;
+  op->have_pals = true;
+  return DOT_OK;
+}
+
+}  // extern "C"

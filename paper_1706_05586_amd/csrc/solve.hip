@@ -1,0 +1,888 @@
+// Multi-right-hand-side solves with the matrix-free 7-point (5-point in 2D)
+// operator: the forward solves A z_i = B w_i and the adjoint solves
+// A^T y_j = C v_j of Section 3.3 (A is symmetric here).
+//
+// Method: Jacobi-preconditioned CG from x0 = 0.  With S = diag(A)^{1/2} the
+// iteration is carried out on the symmetrically scaled system
+// (S^-1 A S^-1) x^ = S^-1 b (unit diagonal), whose CG iterates are those of
+// Jacobi-PCG on A with x = S^-1 x^.  Each iteration is two stencil sweeps:
+//   pass 1: p = r + beta p_old (formed on the fly at the halo too), q = A^ p,
+//           partial sums of p.q; p written to the other buffer
+//   pass 2: q = A^ p recomputed, x += alpha p, r -= alpha q, partial sums of
+//           r.r and |S r|^2 (the unscaled residual norm)
+// so the vector traffic is 8 streams per column per iteration.  Per-column
+// alpha, beta, norms and the convergence mask live on the device; the host
+// polls the number of active columns every few iterations.
+//
+// Mixed precision: binary32 PCG on A^ d = r / |r| inside binary64 iterative
+// refinement (binary64 residual b^ - A^ x^, update x^ += |r| d, stopping
+// test on the binary64 residual).
+//
+// Kernel layout for gfx950: a block is a 64 x 8 tile in (x, y) (one wave per
+// x row) marching through a chunk of z planes; z neighbours stay in
+// registers, x/y neighbours come from an LDS plane with a one-cell halo.  A
+// block processes a group of RG columns so each coefficient is loaded once
+// per cell per group.  Blocks are renumbered so that each of the 8 XCDs
+// gets a contiguous run of tiles (halo reuse in its L2).  Reductions are
+// deterministic: wave shuffles, then LDS in fixed order, then per-block
+// partials summed in fixed order by a one-block finalize kernel.
+#include <algorithm>
+#include <vector>
+
+#include "dot_internal.h"
+
+namespace dot {
+
+constexpr int TX = 64;
+constexpr int TY = 8;
+constexpr int NT = TX * TY;
+constexpr int RG = 4;
+constexpr int NHALO = 2 * TX + 2 * TY;
+
+enum SweepMode { M_APPLY = 0, M_TRUE = 1, M_PCG1 = 2, M_PCG2 = 3, M_RESID = 4 };
+enum EltMode { E_INIT = 0, E_INNER_INIT = 1, E_FOLD = 2, E_UNSCALE = 3 };
+enum FinMode {
+  F_INIT = 0,        // bnorm, rho, active (fp64 PCG)
+  F_INIT_IR = 1,     // bnorm, scale = |b^|, active (mixed)
+  F_ALPHA = 2,       // alpha = rho / p.q
+  F_BETA = 3,        // fp64 PCG: relres, convergence, beta
+  F_RHO_INNER = 4,   // inner: rho = r32.r32, inner_active = active
+  F_BETA_INNER = 5,  // inner: convergence at inner_rtol, beta
+  F_OUTER = 6,       // mixed: true relres, active, scale
+  F_TRUE = 7         // final true relres
+};
+
+enum { FLAG_BREAKDOWN = 1, FLAG_NONFINITE = 2 };
+
+struct Geom {
+  int nx, ny, nz;
+  int64_t nxy, N;
+  int tiles_x, ntiles, zc, nzc, ngrp, k;
+  int nblk_col;  // ntiles * nzc
+  int nblocks;   // ntiles * nzc * ngrp
+};
+
+struct ColState {
+  double* rho;
+  double* alpha;
+  double* beta;
+  double* bnorm;
+  double* relres;
+  double* scale;
+  int* active;        // outer activity (fp64: CG activity)
+  int* inner_active;  // mixed: inner activity
+  int* iters;         // fp64: CG iterations; mixed: total inner iterations
+  int* flags;         // per column FLAG_*
+  int* counters;      // [0] = number of active columns after the last finalize
+};
+
+template <typename T>
+struct SweepArgs {
+  Geom G;
+  const T* cx;
+  const T* cy;
+  const T* cz;
+  const double* diag;  // unscaled diagonal (APPLY/TRUE); unit diagonal otherwise
+  const double* sd;    // sqrt(diag)
+  const int* active;   // per column, NULL = all
+  const double* coef;  // beta (PCG1), alpha (PCG2)
+  int first;           // PCG1: first iteration, p_old ignored
+  const T* in0;        // APPLY/TRUE: x; PCG1: r; PCG2: p; RESID: x^
+  const T* in1;        // PCG1: p_old
+  const double* b;     // TRUE/RESID: right-hand side
+  T* out0;             // APPLY: y; PCG1: p_new; PCG2: x (in place); RESID: r64
+  T* out1;             // PCG2: r (in place)
+  double* partial;     // [2][k][nblk_col]
+};
+
+__device__ __forceinline__ int remap_block(int L, int total) {
+  const int per = total >> 3, rem = total & 7;
+  const int xcd = L & 7, idx = L >> 3;
+  return xcd * per + min(xcd, rem) + idx;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Block reduction of acc[RG][2] over NT threads into the per-block partial
+// slots.  Deterministic: fixed shuffle tree, then waves summed in order.
+__device__ __forceinline__ void block_partials(double (&acc)[RG][2], const Geom& G, int grp,
+                                               int slot, double* partial) {
+  __shared__ double red[TY][RG][2];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int r = 0; r < RG; ++r) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const double v = wave_sum(acc[r][a]);
+      if (lane == 0) red[wave][r][a] = v;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < RG * 2) {
+    const int r = threadIdx.x >> 1, a = threadIdx.x & 1;
+    const int j = grp * RG + r;
+    if (j < G.k) {
+      double s = 0.0;
+      for (int w = 0; w < TY; ++w) s += red[w][r][a];
+      partial[((int64_t)a * G.k + j) * G.nblk_col + slot] = s;
+    }
+  }
+}
+
+template <int MODE, typename T>
+__global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs<T> a) {
+  __shared__ T sm[RG][TY + 2][TX + 2];
+  const Geom& G = a.G;
+  const int logical = remap_block((int)blockIdx.x, G.nblocks);
+  const int tile = logical % G.ntiles;
+  const int rest = logical / G.ntiles;
+  const int zci = rest % G.nzc;
+  const int grp = rest / G.nzc;
+  const int slot = tile + G.ntiles * zci;
+  const int x0 = (tile % G.tiles_x) * TX, y0 = (tile / G.tiles_x) * TY;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int x = x0 + tx, y = y0 + ty;
+  const bool in = x < G.nx && y < G.ny;
+  const int z0 = zci * G.zc, z1 = min(G.nz, z0 + G.zc);
+
+  bool act[RG];
+  int col[RG];
+  double cf[RG];
+  bool any = false;
+#pragma unroll
+  for (int r = 0; r < RG; ++r) {
+    const int j = grp * RG + r;
+    col[r] = j;
+    act[r] = j < G.k && (a.active == nullptr || a.active[j] != 0);
+    cf[r] = (act[r] && a.coef) ? a.coef[j] : 0.0;
+    any |= act[r];
+  }
+  if (!any) return;  // uniform over the block
+
+  auto stage = [&](int64_t c, int r) -> T {
+    const int64_t o = c + G.N * (int64_t)col[r];
+    if constexpr (MODE == M_PCG1) {
+      T v = a.in0[o];
+      if (!a.first) v += (T)cf[r] * a.in1[o];
+      return v;
+    } else {
+      return a.in0[o];
+    }
+  };
+
+  // halo slot owned by this thread (if any)
+  int hx = -1, hy = -1, hsy = 0, hsx = 0;
+  if (threadIdx.x < NHALO) {
+    const int s = threadIdx.x;
+    if (s < TX) {
+      hx = x0 + s; hy = y0 - 1; hsy = 0; hsx = s + 1;
+    } else if (s < 2 * TX) {
+      hx = x0 + s - TX; hy = y0 + TY; hsy = TY + 1; hsx = s - TX + 1;
+    } else if (s < 2 * TX + TY) {
+      hx = x0 - 1; hy = y0 + s - 2 * TX; hsy = s - 2 * TX + 1; hsx = 0;
+    } else {
+      hx = x0 + TX; hy = y0 + s - 2 * TX - TY; hsy = s - 2 * TX - TY + 1; hsx = TX + 1;
+    }
+  }
+  const bool hin = hx >= 0 && hx < G.nx && hy >= 0 && hy < G.ny;
+  const int64_t hbase = hin ? (hx + (int64_t)G.nx * hy) : 0;
+  const int64_t base = in ? (x + (int64_t)G.nx * y) : 0;
+
+  T vm[RG], vc[RG], vp[RG];
+  double acc[RG][2];
+#pragma unroll
+  for (int r = 0; r < RG; ++r) {
+    acc[r][0] = acc[r][1] = 0.0;
+    vm[r] = vc[r] = vp[r] = T(0);
+    if (in && act[r]) {
+      if (z0 > 0) vm[r] = stage(base + (int64_t)(z0 - 1) * G.nxy, r);
+      vc[r] = stage(base + (int64_t)z0 * G.nxy, r);
+    }
+  }
+  T cD = T(0);
+  if (in && z0 > 0) cD = a.cz[base + (int64_t)(z0 - 1) * G.nxy];
+
+  for (int z = z0; z < z1; ++z) {
+    const int64_t c = base + (int64_t)z * G.nxy;
+    const bool has_up = z + 1 < G.nz;
+#pragma unroll
+    for (int r = 0; r < RG; ++r) {
+      vp[r] = (in && act[r] && has_up) ? stage(c + G.nxy, r) : T(0);
+      sm[r][ty + 1][tx + 1] = vc[r];
+    }
+    if (threadIdx.x < NHALO) {
+      const int64_t hc = hbase + (int64_t)z * G.nxy;
+#pragma unroll
+      for (int r = 0; r < RG; ++r) sm[r][hsy][hsx] = (hin && act[r]) ? stage(hc, r) : T(0);
+    }
+    __syncthreads();
+    if (in) {
+      const T cE = a.cx[c];
+      const T cW = x > 0 ? a.cx[c - 1] : T(0);
+      const T cN = a.cy[c];
+      const T cS = y > 0 ? a.cy[c - G.nx] : T(0);
+      const T cU = a.cz[c];
+      T dd = T(1);
+      if constexpr (MODE == M_APPLY || MODE == M_TRUE) dd = (T)a.diag[c];
+#pragma unroll
+      for (int r = 0; r < RG; ++r) {
+        if (!act[r]) continue;
+        const T vW = sm[r][ty + 1][tx], vE = sm[r][ty + 1][tx + 2];
+        const T vS = sm[r][ty][tx + 1], vN = sm[r][ty + 2][tx + 1];
+        const T Av = dd * vc[r] - cW * vW - cE * vE - cS * vS - cN * vN - cD * vm[r] - cU * vp[r];
+        const int64_t o = c + G.N * (int64_t)col[r];
+        if constexpr (MODE == M_APPLY) {
+          a.out0[o] = Av;
+        } else if constexpr (MODE == M_TRUE) {
+          const double rr = a.b[o] - (double)Av;
+          acc[r][0] += rr * rr;
+        } else if constexpr (MODE == M_PCG1) {
+          a.out0[o] = vc[r];
+          acc[r][0] += (double)vc[r] * (double)Av;
+        } else if constexpr (MODE == M_PCG2) {
+          const T al = (T)cf[r];
+          const T xn = a.out0[o] + al * vc[r];
+          const T rn = a.out1[o] - al * Av;
+          a.out0[o] = xn;
+          a.out1[o] = rn;
+          const double rd = (double)rn;
+          acc[r][0] += rd * rd;
+          if (a.sd) {
+            const double t = a.sd[c] * rd;
+            acc[r][1] += t * t;
+          }
+        } else if constexpr (MODE == M_RESID) {
+          const double s = a.sd[c];
+          const double rr = a.b[o] / s - (double)Av;
+          a.out0[o] = (T)rr;
+          acc[r][0] += rr * rr;
+          const double t = s * rr;
+          acc[r][1] += t * t;
+        }
+      }
+      cD = cU;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RG; ++r) {
+      vm[r] = vc[r];
+      vc[r] = vp[r];
+    }
+  }
+  if constexpr (MODE != M_APPLY) block_partials(acc, G, grp, slot, a.partial);
+}
+
+// Elementwise passes on the same block decomposition (same partial slots).
+struct EltArgs {
+  Geom G;
+  const double* sd;
+  const int* active;    // columns to process
+  const double* scale;  // per column scale
+  const double* b;      // INIT: rhs
+  double* xh;           // x^ (binary64)
+  double* r64;          // binary64 residual
+  float* r32;           // inner residual
+  float* d32;           // inner correction
+  double* partial;
+};
+
+template <int MODE>
+__global__ __launch_bounds__(NT) void elt_kernel(EltArgs a) {
+  const Geom& G = a.G;
+  const int logical = remap_block((int)blockIdx.x, G.nblocks);
+  const int tile = logical % G.ntiles;
+  const int rest = logical / G.ntiles;
+  const int zci = rest % G.nzc;
+  const int grp = rest / G.nzc;
+  const int slot = tile + G.ntiles * zci;
+  const int x = (tile % G.tiles_x) * TX + (threadIdx.x & 63);
+  const int y = (tile / G.tiles_x) * TY + (threadIdx.x >> 6);
+  const bool in = x < G.nx && y < G.ny;
+  const int z0 = zci * G.zc, z1 = min(G.nz, z0 + G.zc);
+  bool act[RG];
+  int col[RG];
+  double sc[RG];
+  bool any = false;
+#pragma unroll
+  for (int r = 0; r < RG; ++r) {
+    const int j = grp * RG + r;
+    col[r] = j;
+    act[r] = j < G.k && (a.active == nullptr || a.active[j] != 0);
+    sc[r] = (act[r] && a.scale) ? a.scale[j] : 0.0;
+    any |= act[r];
+  }
+  if (!any) return;
+  double acc[RG][2];
+#pragma unroll
+  for (int r = 0; r < RG; ++r) acc[r][0] = acc[r][1] = 0.0;
+  if (in) {
+    const int64_t base = x + (int64_t)G.nx * y;
+    for (int z = z0; z < z1; ++z) {
+      const int64_t c = base + (int64_t)z * G.nxy;
+#pragma unroll
+      for (int r = 0; r < RG; ++r) {
+        if (!act[r]) continue;
+        const int64_t o = c + G.N * (int64_t)col[r];
+        if constexpr (MODE == E_INIT) {
+          const double bv = a.b[o];
+          const double rv = bv / a.sd[c];
+          a.xh[o] = 0.0;
+          a.r64[o] = rv;
+          acc[r][0] += rv * rv;
+          acc[r][1] += bv * bv;
+        } else if constexpr (MODE == E_INNER_INIT) {
+          const float rv = (float)(a.r64[o] / sc[r]);
+          a.r32[o] = rv;
+          a.d32[o] = 0.0f;
+          acc[r][0] += (double)rv * (double)rv;
+        } else if constexpr (MODE == E_FOLD) {
+          a.xh[o] += sc[r] * (double)a.d32[o];
+        } else if constexpr (MODE == E_UNSCALE) {
+          a.xh[o] = a.xh[o] / a.sd[c];
+        }
+      }
+    }
+  }
+  if constexpr (MODE == E_INIT || MODE == E_INNER_INIT) block_partials(acc, G, grp, slot, a.partial);
+}
+
+// One block: sum per-block partials in fixed order and update per-column state.
+struct FinArgs {
+  int mode;
+  int k, nblk;
+  const double* partial;
+  ColState st;
+  double rtol, inner_rtol;
+};
+
+__global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
+  __shared__ double red[256];
+  __shared__ double tot[2];
+  const ColState& st = a.st;
+  for (int j = 0; j < a.k; ++j) {
+    bool live;
+    if (a.mode == F_INIT || a.mode == F_INIT_IR || a.mode == F_TRUE || a.mode == F_RHO_INNER)
+      live = true;
+    else if (a.mode == F_ALPHA)
+      live = (st.inner_active ? st.inner_active[j] : st.active[j]) != 0;
+    else if (a.mode == F_BETA_INNER)
+      live = st.inner_active[j] != 0;
+    else
+      live = st.active[j] != 0;
+    if (a.mode == F_RHO_INNER && st.active[j] == 0) {
+      // not refined in this outer step: keep it out of the inner solve
+      if (threadIdx.x == 0) st.inner_active[j] = 0;
+      live = false;
+    }
+    if (!live) continue;  // uniform: j and state are the same for every thread
+    for (int acc = 0; acc < 2; ++acc) {
+      const double* p = a.partial + ((int64_t)acc * a.k + j) * a.nblk;
+      double s = 0.0;
+      for (int i = threadIdx.x; i < a.nblk; i += 256) s += p[i];
+      red[threadIdx.x] = s;
+      __syncthreads();
+      for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) tot[acc] = red[0];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      const double s0 = tot[0], s1 = tot[1];
+      switch (a.mode) {
+        case F_INIT: {
+          const double bn = sqrt(s1);
+          st.bnorm[j] = bn;
+          st.rho[j] = s0;
+          st.iters[j] = 0;
+          st.beta[j] = 0.0;
+          st.flags[j] = 0;
+          if (!isfinite(s0) || !isfinite(s1)) {
+            st.flags[j] |= FLAG_NONFINITE;
+            st.active[j] = 0;
+            st.relres[j] = NAN;
+          } else {
+            st.active[j] = bn > 0.0 ? 1 : 0;
+            st.relres[j] = bn > 0.0 ? 1.0 : 0.0;
+          }
+          break;
+        }
+        case F_INIT_IR: {
+          const double bn = sqrt(s1);
+          st.bnorm[j] = bn;
+          st.scale[j] = sqrt(s0);
+          st.iters[j] = 0;
+          st.flags[j] = 0;
+          if (st.inner_active) st.inner_active[j] = 0;
+          if (!isfinite(s0) || !isfinite(s1)) {
+            st.flags[j] |= FLAG_NONFINITE;
+            st.active[j] = 0;
+            st.relres[j] = NAN;
+          } else {
+            st.active[j] = bn > 0.0 ? 1 : 0;
+            st.relres[j] = bn > 0.0 ? 1.0 : 0.0;
+          }
+          break;
+        }
+        case F_ALPHA: {
+          if (!(s0 > 0.0) || !isfinite(s0)) {
+            st.flags[j] |= isfinite(s0) ? FLAG_BREAKDOWN : FLAG_NONFINITE;
+            st.alpha[j] = 0.0;
+            if (st.inner_active) st.inner_active[j] = 0;
+            st.active[j] = 0;
+          } else {
+            st.alpha[j] = st.rho[j] / s0;
+          }
+          break;
+        }
+        case F_BETA: {
+          st.iters[j] += 1;
+          const double rel = sqrt(s1) / st.bnorm[j];
+          st.relres[j] = rel;
+          if (!isfinite(s0) || !isfinite(s1)) {
+            st.flags[j] |= FLAG_NONFINITE;
+            st.active[j] = 0;
+          } else if (rel <= a.rtol) {
+            st.active[j] = 0;
+          } else {
+            st.beta[j] = s0 / st.rho[j];
+            st.rho[j] = s0;
+          }
+          break;
+        }
+        case F_RHO_INNER: {
+          st.rho[j] = s0;
+          st.beta[j] = 0.0;
+          st.inner_active[j] = (s0 > 0.0 && isfinite(s0)) ? 1 : 0;
+          break;
+        }
+        case F_BETA_INNER: {
+          st.iters[j] += 1;
+          if (!isfinite(s0)) {
+            st.flags[j] |= FLAG_NONFINITE;
+            st.inner_active[j] = 0;
+            st.active[j] = 0;
+          } else if (sqrt(s0) <= a.inner_rtol) {
+            st.inner_active[j] = 0;
+          } else {
+            st.beta[j] = s0 / st.rho[j];
+            st.rho[j] = s0;
+          }
+          break;
+        }
+        case F_OUTER: {
+          const double rel = sqrt(s1) / st.bnorm[j];
+          st.relres[j] = rel;
+          st.scale[j] = sqrt(s0);
+          if (!isfinite(s0) || !isfinite(s1)) {
+            st.flags[j] |= FLAG_NONFINITE;
+            st.active[j] = 0;
+          } else if (rel <= a.rtol || !(s0 > 0.0)) {
+            st.active[j] = 0;
+          }
+          break;
+        }
+        case F_TRUE: {
+          const double bn = st.bnorm[j];
+          st.relres[j] = bn > 0.0 ? sqrt(s0) / bn : sqrt(s0);
+          break;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // number of still-active columns (inner activity for the inner finalizers)
+  if (threadIdx.x == 0) {
+    int n = 0;
+    const bool inner = (a.mode == F_BETA_INNER || a.mode == F_RHO_INNER ||
+                        (a.mode == F_ALPHA && st.inner_active));
+    for (int j = 0; j < a.k; ++j) n += inner ? (st.inner_active[j] != 0) : (st.active[j] != 0);
+    st.counters[0] = n;
+  }
+}
+
+// ---------------------------------------------------------------- host side
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+static Geom make_geom(const GridDims& g, int k) {
+  Geom G;
+  G.nx = g.nx;
+  G.ny = g.ny;
+  G.nz = g.nz;
+  G.nxy = g.nxy;
+  G.N = g.N;
+  G.k = k;
+  G.tiles_x = (g.nx + TX - 1) / TX;
+  const int tiles_y = (g.ny + TY - 1) / TY;
+  G.ntiles = G.tiles_x * tiles_y;
+  G.ngrp = (k + RG - 1) / RG;
+  // z chunk: aim for >= 2048 blocks, chunks of at least 8 planes
+  const int64_t want = 2048;
+  const int64_t per_z = (int64_t)G.ntiles * G.ngrp;
+  int nzc = (int)std::min<int64_t>(g.nz, std::max<int64_t>(1, (want + per_z - 1) / per_z));
+  int zc = (g.nz + nzc - 1) / nzc;
+  zc = std::max(zc, std::min(8, g.nz));
+  G.zc = zc;
+  G.nzc = (g.nz + zc - 1) / zc;
+  G.nblk_col = G.ntiles * G.nzc;
+  G.nblocks = G.nblk_col * G.ngrp;
+  return G;
+}
+
+struct Workspace {
+  double* r64;
+  double* p64[2];
+  float* r32;
+  float* p32[2];
+  float* d32;
+  double* partial;
+  ColState st;
+  size_t bytes;
+};
+
+static size_t layout_workspace(const Geom& G, int precision, char* base, Workspace* w) {
+  const size_t Nk = (size_t)G.N * G.k;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off += align256(bytes);
+    return p;
+  };
+  Workspace ws{};
+  if (precision == DOT_FP64) {
+    ws.r64 = (double*)take(Nk * 8);
+    ws.p64[0] = (double*)take(Nk * 8);
+    ws.p64[1] = (double*)take(Nk * 8);
+  } else {
+    ws.r64 = (double*)take(Nk * 8);
+    ws.r32 = (float*)take(Nk * 4);
+    ws.p32[0] = (float*)take(Nk * 4);
+    ws.p32[1] = (float*)take(Nk * 4);
+    ws.d32 = (float*)take(Nk * 4);
+  }
+  ws.partial = (double*)take((size_t)2 * G.k * G.nblk_col * 8);
+  const size_t k = (size_t)G.k;
+  ws.st.rho = (double*)take(k * 8);
+  ws.st.alpha = (double*)take(k * 8);
+  ws.st.beta = (double*)take(k * 8);
+  ws.st.bnorm = (double*)take(k * 8);
+  ws.st.relres = (double*)take(k * 8);
+  ws.st.scale = (double*)take(k * 8);
+  ws.st.active = (int*)take(k * 4);
+  ws.st.inner_active = (int*)take(k * 4);
+  ws.st.iters = (int*)take(k * 4);
+  ws.st.flags = (int*)take(k * 4);
+  ws.st.counters = (int*)take(64);
+  ws.bytes = off;
+  if (w) *w = ws;
+  return off;
+}
+
+template <int MODE, typename T>
+static int launch_sweep(const SweepArgs<T>& a, hipStream_t s) {
+  hipLaunchKernelGGL((sweep_kernel<MODE, T>), dim3(a.G.nblocks), dim3(NT), 0, s, a);
+  DOT_LAUNCH_CHECK();
+  return DOT_OK;
+}
+
+template <int MODE>
+static int launch_elt(const EltArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((elt_kernel<MODE>), dim3(a.G.nblocks), dim3(NT), 0, s, a);
+  DOT_LAUNCH_CHECK();
+  return DOT_OK;
+}
+
+static int launch_fin(int mode, const Geom& G, const Workspace& ws, double rtol, double inner_rtol,
+                      hipStream_t s) {
+  FinArgs f;
+  f.mode = mode;
+  f.k = G.k;
+  f.nblk = G.nblk_col;
+  f.partial = ws.partial;
+  f.st = ws.st;
+  f.rtol = rtol;
+  f.inner_rtol = inner_rtol;
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, f);
+  DOT_LAUNCH_CHECK();
+  return DOT_OK;
+}
+
+static int poll_active(dot_op* op, const Workspace& ws, hipStream_t s, int* n) {
+  DOT_HIP(hipMemcpyAsync(op->pinned, ws.st.counters, sizeof(int), hipMemcpyDeviceToHost, s));
+  DOT_HIP(hipStreamSynchronize(s));
+  *n = op->pinned[0];
+  return DOT_OK;
+}
+
+#define DOT_TRY(...)                 \
+  do {                               \
+    int rc_ = (__VA_ARGS__);         \
+    if (rc_ != DOT_OK) return rc_;   \
+  } while (0)
+
+static SweepArgs<double> base_args64(dot_op* op, const Geom& G) {
+  SweepArgs<double> a{};
+  a.G = G;
+  a.cx = op->sx;
+  a.cy = op->sy;
+  a.cz = op->sz;
+  a.sd = op->sd;
+  return a;
+}
+
+static SweepArgs<float> base_args32(dot_op* op, const Geom& G) {
+  SweepArgs<float> a{};
+  a.G = G;
+  a.cx = op->sx32;
+  a.cy = op->sy32;
+  a.cz = op->sz32;
+  a.sd = nullptr;
+  return a;
+}
+
+static int finish_true(dot_op* op, const Geom& G, const Workspace& ws, const double* rhs,
+                       double* x, hipStream_t s) {
+  EltArgs e{};
+  e.G = G;
+  e.sd = op->sd;
+  e.xh = x;
+  DOT_TRY(launch_elt<E_UNSCALE>(e, s));
+  SweepArgs<double> t{};
+  t.G = G;
+  t.cx = op->cx;
+  t.cy = op->cy;
+  t.cz = op->cz;
+  t.diag = op->diag;
+  t.in0 = x;
+  t.b = rhs;
+  t.partial = ws.partial;
+  DOT_TRY(launch_sweep<M_TRUE, double>(t, s));
+  DOT_TRY(launch_fin(F_TRUE, G, ws, 0.0, 0.0, s));
+  return DOT_OK;
+}
+
+static int solve_fp64(dot_op* op, const Geom& G, const Workspace& ws, const double* rhs, double* x,
+                      const dot_solve_opts& o, hipStream_t s, int* iters_done) {
+  EltArgs e{};
+  e.G = G;
+  e.sd = op->sd;
+  e.b = rhs;
+  e.xh = x;
+  e.r64 = ws.r64;
+  e.partial = ws.partial;
+  DOT_TRY(launch_elt<E_INIT>(e, s));
+  DOT_TRY(launch_fin(F_INIT, G, ws, o.rtol, 0.0, s));
+  int n_active = 0;
+  DOT_TRY(poll_active(op, ws, s, &n_active));
+  int it = 0;
+  int cur = 0;
+  while (n_active > 0 && it < o.max_iter) {
+    SweepArgs<double> p1 = base_args64(op, G);
+    p1.active = ws.st.active;
+    p1.coef = ws.st.beta;
+    p1.first = it == 0;
+    p1.in0 = ws.r64;
+    p1.in1 = ws.p64[cur];
+    p1.out0 = ws.p64[cur ^ 1];
+    p1.partial = ws.partial;
+    DOT_TRY(launch_sweep<M_PCG1, double>(p1, s));
+    DOT_TRY(launch_fin(F_ALPHA, G, ws, o.rtol, 0.0, s));
+    cur ^= 1;
+    SweepArgs<double> p2 = base_args64(op, G);
+    p2.active = ws.st.active;
+    p2.coef = ws.st.alpha;
+    p2.in0 = ws.p64[cur];
+    p2.out0 = x;
+    p2.out1 = ws.r64;
+    p2.partial = ws.partial;
+    DOT_TRY(launch_sweep<M_PCG2, double>(p2, s));
+    DOT_TRY(launch_fin(F_BETA, G, ws, o.rtol, 0.0, s));
+    ++it;
+    if (it % o.check_every == 0 || it == o.max_iter) DOT_TRY(poll_active(op, ws, s, &n_active));
+  }
+  *iters_done = it;
+  return finish_true(op, G, ws, rhs, x, s);
+}
+
+static int solve_mixed(dot_op* op, const Geom& G, const Workspace& ws, const double* rhs,
+                       double* x, const dot_solve_opts& o, hipStream_t s, int* iters_done,
+                       int* outer_done) {
+  EltArgs e{};
+  e.G = G;
+  e.sd = op->sd;
+  e.b = rhs;
+  e.xh = x;
+  e.r64 = ws.r64;
+  e.r32 = ws.r32;
+  e.d32 = ws.d32;
+  e.partial = ws.partial;
+  DOT_TRY(launch_elt<E_INIT>(e, s));
+  DOT_TRY(launch_fin(F_INIT_IR, G, ws, o.rtol, o.inner_rtol, s));
+  int n_active = 0;
+  DOT_TRY(poll_active(op, ws, s, &n_active));
+  int total_inner = 0, outer = 0;
+  while (n_active > 0 && outer < o.max_outer && total_inner < o.max_iter) {
+    // inner right-hand side r32 = r64 / |r64|, correction d32 = 0
+    EltArgs ei = e;
+    ei.active = ws.st.active;
+    ei.scale = ws.st.scale;
+    DOT_TRY(launch_elt<E_INNER_INIT>(ei, s));
+    DOT_TRY(launch_fin(F_RHO_INNER, G, ws, o.rtol, o.inner_rtol, s));
+    int n_inner = n_active;
+    int it = 0, cur = 0;
+    while (n_inner > 0 && total_inner + it < o.max_iter) {
+      SweepArgs<float> p1 = base_args32(op, G);
+      p1.active = ws.st.inner_active;
+      p1.coef = ws.st.beta;
+      p1.first = it == 0;
+      p1.in0 = ws.r32;
+      p1.in1 = ws.p32[cur];
+      p1.out0 = ws.p32[cur ^ 1];
+      p1.partial = ws.partial;
+      DOT_TRY(launch_sweep<M_PCG1, float>(p1, s));
+      DOT_TRY(launch_fin(F_ALPHA, G, ws, o.rtol, o.inner_rtol, s));
+      cur ^= 1;
+      SweepArgs<float> p2 = base_args32(op, G);
+      p2.active = ws.st.inner_active;
+      p2.coef = ws.st.alpha;
+      p2.in0 = ws.p32[cur];
+      p2.out0 = ws.d32;
+      p2.out1 = ws.r32;
+      p2.partial = ws.partial;
+      DOT_TRY(launch_sweep<M_PCG2, float>(p2, s));
+      DOT_TRY(launch_fin(F_BETA_INNER, G, ws, o.rtol, o.inner_rtol, s));
+      ++it;
+      if (it % o.check_every == 0) DOT_TRY(poll_active(op, ws, s, &n_inner));
+    }
+    total_inner += it;
+    ++outer;
+    // x^ += |r| d for the columns that were refined
+    EltArgs ef = e;
+    ef.active = ws.st.active;
+    ef.scale = ws.st.scale;
+    DOT_TRY(launch_elt<E_FOLD>(ef, s));
+    // binary64 residual r64 = b^ - A^ x^ and the stopping test
+    SweepArgs<double> rs = base_args64(op, G);
+    rs.active = ws.st.active;
+    rs.in0 = x;
+    rs.b = rhs;
+    rs.out0 = ws.r64;
+    rs.partial = ws.partial;
+    DOT_TRY(launch_sweep<M_RESID, double>(rs, s));
+    DOT_TRY(launch_fin(F_OUTER, G, ws, o.rtol, o.inner_rtol, s));
+    DOT_TRY(poll_active(op, ws, s, &n_active));
+  }
+  *iters_done = total_inner;
+  *outer_done = outer;
+  return finish_true(op, G, ws, rhs, x, s);
+}
+
+}  // namespace dot
+
+using namespace dot;
+
+extern "C" {
+
+size_t dot_solve_workspace_bytes(const dot_op* op, int k, int precision) {
+  if (!op || k < 1 || (precision != DOT_FP64 && precision != DOT_MIXED)) return 0;
+  Geom G = make_geom(op->g, k);
+  return layout_workspace(G, precision, nullptr, nullptr);
+}
+
+int dot_apply(dot_op* op, int k, const double* X_dev, double* Y_dev, void* stream) {
+  clear_error();
+  if (!op) DOT_FAIL(DOT_EINVAL, "op is NULL");
+  if (k < 1) DOT_FAIL(DOT_EINVAL, "k must be >= 1");
+  if (!X_dev || !Y_dev) DOT_FAIL(DOT_EINVAL, "X_dev/Y_dev is NULL");
+  const size_t bytes = (size_t)op->g.N * k * sizeof(double);
+  const char* xa = (const char*)X_dev;
+  const char* ya = (const char*)Y_dev;
+  if (xa < ya + bytes && ya < xa + bytes) DOT_FAIL(DOT_EINVAL, "X_dev and Y_dev overlap");
+  Geom G = make_geom(op->g, k);
+  SweepArgs<double> a{};
+  a.G = G;
+  a.cx = op->cx;
+  a.cy = op->cy;
+  a.cz = op->cz;
+  a.diag = op->diag;
+  a.in0 = X_dev;
+  a.out0 = Y_dev;
+  return launch_sweep<M_APPLY, double>(a, as_stream(stream));
+}
+
+int dot_solve_multi_rhs(dot_op* op, int trans, int k, const double* rhs_dev, double* x_dev,
+                        const dot_solve_opts* opts, void* work_dev, size_t work_bytes,
+                        dot_solve_info* info, void* stream) {
+  clear_error();
+  if (!op) DOT_FAIL(DOT_EINVAL, "op is NULL");
+  if (trans != 0 && trans != 1) DOT_FAIL(DOT_EINVAL, "trans must be 0 or 1");
+  if (k < 1) DOT_FAIL(DOT_EINVAL, "k must be >= 1");
+  if (!rhs_dev || !x_dev) DOT_FAIL(DOT_EINVAL, "rhs_dev/x_dev is NULL");
+  if (!opts) DOT_FAIL(DOT_EINVAL, "opts is NULL");
+  if (opts->precision != DOT_FP64 && opts->precision != DOT_MIXED)
+    DOT_FAIL(DOT_EINVAL, "opts.precision must be DOT_FP64 or DOT_MIXED");
+  if (!(opts->rtol > 0.0) || !(opts->rtol < 1.0)) DOT_FAIL(DOT_EINVAL, "opts.rtol must be in (0, 1)");
+  if (opts->max_iter < 1) DOT_FAIL(DOT_EINVAL, "opts.max_iter must be >= 1");
+  if (opts->check_every < 1) DOT_FAIL(DOT_EINVAL, "opts.check_every must be >= 1");
+  if (opts->precision == DOT_MIXED) {
+    if (!(opts->inner_rtol > 0.0) || !(opts->inner_rtol < 1.0))
+      DOT_FAIL(DOT_EINVAL, "opts.inner_rtol must be in (0, 1)");
+    if (opts->max_outer < 1) DOT_FAIL(DOT_EINVAL, "opts.max_outer must be >= 1");
+  }
+  const size_t bytes = (size_t)op->g.N * k * sizeof(double);
+  const char* ra = (const char*)rhs_dev;
+  const char* xa = (const char*)x_dev;
+  if (ra < xa + bytes && xa < ra + bytes) DOT_FAIL(DOT_EINVAL, "rhs_dev and x_dev overlap");
+  Geom G = make_geom(op->g, k);
+  const size_t need = layout_workspace(G, opts->precision, nullptr, nullptr);
+  if (!work_dev || work_bytes < need)
+    DOT_FAIL(DOT_ENOMEM, "workspace too small: need %zu bytes, got %zu", need, work_bytes);
+  if (((uintptr_t)work_dev & 255) != 0) DOT_FAIL(DOT_EINVAL, "work_dev must be 256-byte aligned");
+  const char* wa = (const char*)work_dev;
+  if ((wa < xa + bytes && xa < wa + need) || (wa < ra + bytes && ra < wa + need))
+    DOT_FAIL(DOT_EINVAL, "workspace overlaps rhs_dev or x_dev");
+  Workspace ws;
+  layout_workspace(G, opts->precision, (char*)work_dev, &ws);
+  if (opts->precision == DOT_FP64) ws.st.inner_active = nullptr;
+  hipStream_t s = as_stream(stream);
+  int iters = 0, outer = 0;
+  int rc = opts->precision == DOT_FP64 ? solve_fp64(op, G, ws, rhs_dev, x_dev, *opts, s, &iters)
+                                       : solve_mixed(op, G, ws, rhs_dev, x_dev, *opts, s, &iters, &outer);
+  if (rc != DOT_OK) return rc;
+  // per-column results
+  std::vector<int> it_col(k), flags(k), act(k);
+  std::vector<double> rel(k);
+  DOT_HIP(hipMemcpyAsync(it_col.data(), ws.st.iters, k * sizeof(int), hipMemcpyDeviceToHost, s));
+  DOT_HIP(hipMemcpyAsync(flags.data(), ws.st.flags, k * sizeof(int), hipMemcpyDeviceToHost, s));
+  DOT_HIP(hipMemcpyAsync(rel.data(), ws.st.relres, k * sizeof(double), hipMemcpyDeviceToHost, s));
+  DOT_HIP(hipStreamSynchronize(s));
+  int imax = 0, fl = 0;
+  bool conv = true;
+  for (int j = 0; j < k; ++j) {
+    imax = std::max(imax, it_col[j]);
+    fl |= flags[j];
+    if (!(rel[j] <= opts->rtol)) conv = false;
+  }
+  if (info) {
+    info->iters_max = imax;
+    info->outer = outer;
+    if (info->iters_host)
+      for (int j = 0; j < k; ++j) info->iters_host[j] = it_col[j];
+    if (info->relres_host)
+      for (int j = 0; j < k; ++j) info->relres_host[j] = rel[j];
+  }
+  if (fl & FLAG_NONFINITE) DOT_FAIL(DOT_ENONFINITE, "non-finite values in the solve");
+  if (fl & FLAG_BREAKDOWN) DOT_FAIL(DOT_EBREAKDOWN, "CG breakdown: p^T A p <= 0");
+  if (!conv) {
+    set_error("not converged: max relres above rtol after %d iterations", iters);
+    return DOT_NOT_CONVERGED;
+  }
+  return DOT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,275 @@
+"""GPU parity: every ABI call against the CPU oracle on the same seeded inputs.
+
+Grids are ragged against the kernels' 64 x 8 tiles and z chunks (37x29,
+19x13x11, 24^3, 70x33x17, 32^2).  Tolerances:
+  * PaLS mu and D, stencil apply: 1e-13 relative (binary64 rounding only);
+  * RHS scatter: exact;
+  * FP64 solve: true relative residual, recomputed by the oracle's CSR
+    matrix, at most the requested rtol (1e-12) times 1.5 (the final true
+    residual is not the recursive one); iteration counts within 3% of the
+    oracle's Jacobi-PCG; bitwise reproducible;
+  * mixed solve: true relative residual <= rtol;
+  * misfit, Jacobian (given identical fields), gradient: 1e-12 relative.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import synthetic
+from oracle import discretization as odisc
+from oracle import estimators as oest
+from oracle import problem as oprob
+from oracle import solvers as osol
+
+pytestmark = pytest.mark.gpu
+
+NAMES = ["t2d", "t3d", "t3d_b", "t3d_c", "C1"]
+
+
+@pytest.fixture(scope="module")
+def dotlib():
+    import paper_1706_05586_amd as dl
+    assert torch.cuda.is_available()
+    return dl
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return torch.device("cuda:0")
+
+
+_CACHE = {}
+
+
+def case(name):
+    if name in _CACHE:
+        return _CACHE[name]
+    wl = synthetic.make_workload(synthetic.get_config(name))
+    prob = oprob.build(wl)
+    if name == "C1":   # the 2D workload uses every source and detector (W = V = I)
+        W, V = np.eye(len(wl.src_cells)), np.eye(len(wl.det_cells))
+    else:
+        W, V = oest.sample_matrix(wl.w_signs), oest.sample_matrix(wl.v_signs)
+    data = oprob.synthetic_data(prob, wl)
+    ref = oprob.evaluate(prob, wl, wl.theta_ref, W, V, data)
+    _CACHE[name] = (wl, prob, W, V, data, ref)
+    return _CACHE[name]
+
+
+def gpu_operator(dl, dev, wl, D=None):
+    cfg = wl.cfg
+    grid, pals = dl.Grid.from_config(cfg), dl.Pals.from_config(cfg)
+    th = torch.tensor(wl.theta_ref, device=dev)
+    if D is None:
+        _, D = dl.pals_field(grid, pals, th, cfg.mus_prime)
+    op = dl.Operator(grid, D)
+    return op, grid, pals, th
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_pals_field_matches_oracle(dotlib, dev, name):
+    wl, prob, *_ = case(name)
+    cfg = wl.cfg
+    grid, pals = dotlib.Grid.from_config(cfg), dotlib.Pals.from_config(cfg)
+    mua, D = dotlib.pals_field(grid, pals, torch.tensor(wl.theta_ref, device=dev), cfg.mus_prime)
+    mu_ref = prob.mua(wl.theta_ref)
+    assert np.max(np.abs(mua.cpu().numpy() - mu_ref)) <= 1e-13 * np.max(mu_ref)
+    assert np.max(np.abs(D.cpu().numpy() - prob.D)) <= 1e-13 * np.max(prob.D)
+    # the workload really has an anomaly band
+    assert mu_ref.max() > cfg.mu_out * 1.5 or name == "t3d_c"
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_apply_matches_oracle_csr(dotlib, dev, name):
+    wl, prob, *_ = case(name)
+    Dt = torch.tensor(prob.D, device=dev)
+    op, grid, pals, th = gpu_operator(dotlib, dev, wl, D=Dt)
+    with op:
+        rng = np.random.default_rng(7)
+        X = rng.standard_normal((prob.N, 5))
+        # explicit mu
+        mu = prob.mua(wl.theta_ref)
+        op.set_mua(torch.tensor(mu, device=dev))
+        Y = op.apply(torch.tensor(X, device=dev)).cpu().numpy()
+        A = odisc.assemble(prob.n, prob.bc, prob.D, mu)
+        Yr = A @ X
+        assert np.linalg.norm(Y - Yr) <= 1e-13 * np.linalg.norm(Yr)
+        # PaLS-driven mu at theta_ref
+        op.pals_mua(pals, th)
+        Y2 = op.apply(torch.tensor(X, device=dev)).cpu().numpy()
+        assert np.linalg.norm(Y2 - Yr) <= 1e-13 * np.linalg.norm(Yr)
+
+
+@pytest.mark.parametrize("name", ["t3d", "t2d"])
+def test_form_rhs_exact(dotlib, dev, name):
+    wl, prob, W, V, data, ref = case(name)
+    op, *_ = gpu_operator(dotlib, dev, wl)
+    with op:
+        BW = op.form_rhs(wl.src_cells, torch.tensor(W, device=dev)).cpu().numpy()
+        assert np.array_equal(BW, ref["BW"])
+        # repeated cells add up
+        cells = np.array([3, 3, 5], dtype=np.int32)
+        w = np.array([[1.0, 2.0], [0.5, -1.0], [4.0, 0.0]])
+        R = op.form_rhs(cells, torch.tensor(w, device=dev)).cpu().numpy()
+        assert R[3, 0] == 1.5 and R[3, 1] == 1.0 and R[5, 0] == 4.0 and np.count_nonzero(R) == 3
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_solve_fp64_matches_oracle(dotlib, dev, name):
+    wl, prob, W, V, data, ref = case(name)
+    op, grid, pals, th = gpu_operator(dotlib, dev, wl)
+    with op:
+        op.pals_mua(pals, th)
+        rhs = np.hstack([ref["BW"], ref["CV"]])
+        res = op.solve(torch.tensor(rhs, device=dev), rtol=1e-12, precision=dotlib.DOT_FP64)
+        X = res.x.cpu().numpy()
+    assert res.converged
+    true_rel = osol.relative_residuals(ref["A"], X, rhs)
+    assert np.all(true_rel <= 1.5e-12), true_rel.max()
+    assert np.allclose(true_rel, res.relres, rtol=1e-3, atol=1e-15)
+    Xd = np.hstack([ref["U"], ref["Z"]])
+    assert np.linalg.norm(X - Xd) <= 1e-8 * np.linalg.norm(Xd)
+    # iteration counts follow the oracle's Jacobi-PCG
+    _, its, _ = osol.pcg_jacobi_multi(ref["A"], rhs, 1e-12)
+    assert np.all(np.abs(res.iters - its) <= np.maximum(2, 0.03 * its)), (res.iters, its)
+
+
+@pytest.mark.parametrize("name", ["t3d_b", "t3d_c", "t2d"])
+def test_solve_mixed_reaches_fp64_accuracy(dotlib, dev, name):
+    wl, prob, W, V, data, ref = case(name)
+    op, grid, pals, th = gpu_operator(dotlib, dev, wl)
+    with op:
+        op.pals_mua(pals, th)
+        rhs = np.hstack([ref["BW"], ref["CV"]])
+        res = op.solve(torch.tensor(rhs, device=dev), rtol=1e-10, precision=dotlib.DOT_MIXED,
+                       inner_rtol=1e-4)
+        X = res.x.cpu().numpy()
+    assert res.converged and res.outer >= 2
+    true_rel = osol.relative_residuals(ref["A"], X, rhs)
+    assert np.all(true_rel <= 1e-10), true_rel.max()
+    Xd = np.hstack([ref["U"], ref["Z"]])
+    assert np.linalg.norm(X - Xd) <= 1e-6 * np.linalg.norm(Xd)
+
+
+def test_solve_bitwise_deterministic(dotlib, dev):
+    wl, prob, W, V, data, ref = case("t3d_c")
+    op, grid, pals, th = gpu_operator(dotlib, dev, wl)
+    with op:
+        op.pals_mua(pals, th)
+        rhs = torch.tensor(np.hstack([ref["BW"], ref["CV"]]), device=dev)
+        for prec in (dotlib.DOT_FP64, dotlib.DOT_MIXED):
+            a = op.solve(rhs, rtol=1e-10, precision=prec)
+            b = op.solve(rhs, rtol=1e-10, precision=prec)
+            assert torch.equal(a.x, b.x)
+            assert np.array_equal(a.iters, b.iters)
+
+
+def test_solve_edge_cases(dotlib, dev):
+    wl, prob, W, V, data, ref = case("t3d")
+    op, grid, pals, th = gpu_operator(dotlib, dev, wl)
+    with op:
+        op.pals_mua(pals, th)
+        # single column, and a zero column among others
+        rhs = np.zeros((prob.N, 3))
+        rhs[:, 0] = ref["BW"][:, 0]
+        rhs[:, 2] = ref["CV"][:, 1]
+        res = op.solve(torch.tensor(rhs, device=dev), rtol=1e-12)
+        X = res.x.cpu().numpy()
+        assert res.converged and np.all(X[:, 1] == 0.0) and res.iters[1] == 0
+        assert res.relres[1] == 0.0
+        one = op.solve(torch.tensor(rhs[:, :1].copy(), device=dev), rtol=1e-12)
+        assert np.array_equal(one.x.cpu().numpy()[:, 0], X[:, 0])
+        # iteration cap: outputs valid, status "not converged"
+        with pytest.warns(dotlib.NotConverged):
+            capped = op.solve(torch.tensor(rhs, device=dev), rtol=1e-12, max_iter=3)
+        assert not capped.converged and capped.iters_max == 3
+        # non-finite data is reported
+        bad = rhs.copy()
+        bad[5, 0] = np.nan
+        with pytest.raises(dotlib.DotError) as ei:
+            op.solve(torch.tensor(bad, device=dev), rtol=1e-12)
+        assert ei.value.code == -5
+
+
+def test_indefinite_operator_reports_breakdown(dotlib, dev):
+    wl, prob, W, V, data, ref = case("t3d")
+    op, grid, pals, th = gpu_operator(dotlib, dev, wl)
+    with op:
+        # a strongly negative absorption in the interior makes A indefinite
+        # while keeping its diagonal positive
+        mu = np.full(prob.N, 0.01)
+        h = prob.h
+        x = prob.x
+        centre = np.all(np.abs(x - x.mean(axis=0)) < 0.2, axis=1)
+        diag_pos = 2.0 * 3 * h * prob.D.min() / h ** 3 * 0.9
+        mu[centre] = -diag_pos
+        op.set_mua(torch.tensor(mu, device=dev))
+        A = odisc.assemble(prob.n, prob.bc, prob.D, mu)
+        assert A.diagonal().min() > 0
+        rng = np.random.default_rng(3)
+        b = rng.standard_normal((prob.N, 2))
+        with pytest.raises(dotlib.DotError) as ei:
+            op.solve(torch.tensor(b, device=dev), rtol=1e-12, max_iter=5000)
+        assert ei.value.code == -4
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_sampled_misfit_matches_oracle(dotlib, dev, name):
+    wl, prob, W, V, data, ref = case(name)
+    op, *_ = gpu_operator(dotlib, dev, wl)
+    with op:
+        U = torch.tensor(ref["U"], device=dev)
+        Rs, f = op.sampled_misfit(wl.det_cells, U, torch.tensor(V, device=dev),
+                                  torch.tensor(data @ W, device=dev))
+    assert np.linalg.norm(Rs.cpu().numpy() - ref["Rs"]) <= 1e-12 * np.linalg.norm(ref["Rs"])
+    assert f == pytest.approx(ref["f"], rel=1e-12)
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_jacobian_fp64_matches_oracle(dotlib, dev, name):
+    wl, prob, W, V, data, ref = case(name)
+    op, grid, pals, th = gpu_operator(dotlib, dev, wl)
+    with op:
+        op.pals_mua(pals, th)
+        Js = op.jacobian(torch.tensor(ref["U"], device=dev), torch.tensor(ref["Z"], device=dev),
+                         dotlib.DOT_JAC_FP64).cpu().numpy()
+    Jr = ref["Js"]
+    assert Js.shape == Jr.shape
+    assert np.linalg.norm(Jr) > 0
+    assert np.linalg.norm(Js - Jr) <= 1e-12 * np.linalg.norm(Jr)
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_gradient_matches_oracle(dotlib, dev, name):
+    wl, prob, W, V, data, ref = case(name)
+    op, grid, pals, th = gpu_operator(dotlib, dev, wl)
+    with op:
+        op.pals_mua(pals, th)
+        g = op.grad_misfit(torch.tensor(ref["U"], device=dev), torch.tensor(ref["Z"], device=dev),
+                           torch.tensor(ref["Rs"], device=dev)).cpu().numpy()
+    assert np.linalg.norm(g - ref["g"]) <= 1e-12 * np.linalg.norm(ref["g"])
+
+
+def test_reciprocity_on_gpu(dotlib, dev):
+    """Co-located optodes and A = A^T: the GPU measurement matrix is symmetric."""
+    wl, prob, W, V, data, ref = case("C1")
+    op, grid, pals, th = gpu_operator(dotlib, dev, wl)
+    with op:
+        op.pals_mua(pals, th)
+        B = op.form_rhs(wl.src_cells, torch.eye(16, dtype=torch.float64, device=dev))
+        X = op.solve(B, rtol=1e-13).x.cpu().numpy()
+    M = X[wl.det_cells, :]
+    assert np.linalg.norm(M - M.T) <= 1e-11 * np.linalg.norm(M)
+
+
+def test_gemm_matches_numpy(dotlib, dev):
+    rng = np.random.default_rng(9)
+    for (m, k, n) in [(7, 5, 3), (40, 300, 33), (17, 1, 19)]:
+        A, B = rng.standard_normal((m, k)), rng.standard_normal((k, n))
+        for ta in (False, True):
+            for tb in (False, True):
+                Aa = A.T.copy() if ta else A
+                Bb = B.T.copy() if tb else B
+                C = dotlib.gemm(torch.tensor(Aa, device=dev), torch.tensor(Bb, device=dev), ta, tb)
+                assert np.allclose(C.cpu().numpy(), A @ B, rtol=1e-13, atol=1e-13)
