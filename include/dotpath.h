@@ -86,18 +86,22 @@ typedef struct dot_pals {
   double mu_in, mu_out, cutoff, eps, gamma;
 } dot_pals;
 
+/* most columns one solve call accepts */
+#define DOT_MAX_COLUMNS 4096
+
 typedef struct dot_solve_opts {
   double rtol;        /* per-column target ||b - A x||_2 / ||b||_2 */
-  int max_iter;       /* FP64: CG iterations; MIXED: total inner iterations */
+  int max_iter;       /* CG iterations (binary32 iterations for DOT_MIXED) */
   int precision;      /* DOT_FP64 or DOT_MIXED */
-  double inner_rtol;  /* MIXED: inner binary32 relative tolerance (e.g. 1e-4) */
-  int max_outer;      /* MIXED: maximum refinement steps */
-  int check_every;    /* iterations between host polls of the convergence count (>= 1) */
+  double inner_rtol;  /* DOT_MIXED: factor by which the binary32 residual of a column must
+                         drop before its correction is folded into x in binary64 and its
+                         residual is replaced by the binary64 b - A x (e.g. 0.1) */
+  int check_every;    /* iterations between host polls of the column flags (>= 1) */
 } dot_solve_opts;
 
 typedef struct dot_solve_info {
-  int iters_max;      /* out: max over columns of (inner) iterations */
-  int outer;          /* out: refinement steps taken (MIXED), 0 for FP64 */
+  int iters_max;      /* out: max over columns of CG iterations */
+  int outer;          /* out: binary64 residual updates (DOT_MIXED), 0 for DOT_FP64 */
   int32_t* iters_host;   /* in: NULL or host array [k]; out: iterations per column */
   double* relres_host;   /* in: NULL or host array [k]; out: final true relative residual
                             ||b - A x|| / ||b|| per column, recomputed in binary64 */
@@ -172,9 +176,12 @@ size_t dot_solve_workspace_bytes(const dot_op* op, int k, int precision);
  * 1; identical here since A is symmetric), Section 3.3: the forward fields
  * z_i of A z_i = B w_i and the adjoint fields y_j of A^T y_j = C v_j.
  * Jacobi-preconditioned CG from x0 = 0 per column until
- * ||b - A x||_2 <= rtol ||b||_2; MIXED runs binary32 inner CG on the
- * scaled residual inside binary64 refinement (residual b - A x, update
- * x += d and the stopping test in binary64).
+ * ||b - A x||_2 <= rtol ||b||_2.  DOT_MIXED runs the CG recurrences (stencil,
+ * vectors) in binary32 inside binary64 iterative refinement: the binary32
+ * correction is folded into x in binary64, and the residual b - A x is
+ * recomputed in binary64 and replaces the binary32 one whenever the latter
+ * has dropped by inner_rtol (the search direction is kept); convergence is
+ * decided on the binary64 residual.
  * rhs_dev, x_dev: N x k, must not overlap.  work_dev: >= the size from
  * dot_solve_workspace_bytes, 256-byte aligned.  Synchronizes the stream.
  * Returns DOT_OK, DOT_NOT_CONVERGED (outputs valid), or an error.
@@ -217,6 +224,25 @@ int dot_jacobian(dot_op* op, int l_s, const double* U_dev, int l_d, const double
 int dot_grad_misfit(dot_op* op, int l_s, const double* U_dev, int l_d, const double* Z_dev,
                     const double* Rs_dev, double* g_dev, void* work_dev, size_t work_bytes,
                     void* stream);
+
+/*
+ * Kernel timing with HIP events on the caller's stream (off by default).
+ * dot_profile_enable(op, 1) resets and starts timing of the solver sweeps
+ * and the contraction; dot_profile_read returns, for one kernel kind, the
+ * summed event time (ms), the number of launches and the sum over launches
+ * of the number of active columns each launch processed (a contraction
+ * launch counts 1).  Reading synchronizes the device.
+ */
+#define DOT_PROF_PCG1_FP64 0   /* CG pass 1 (p = r + beta p, A p, p.Ap), binary64 */
+#define DOT_PROF_PCG2_FP64 1   /* CG pass 2 (A p, x += alpha p, r -= alpha A p, norms) */
+#define DOT_PROF_PCG1_FP32 2
+#define DOT_PROF_PCG2_FP32 3
+#define DOT_PROF_RESID 4       /* binary64 residual of the refinement */
+#define DOT_PROF_JACOBIAN 5    /* Jacobian contraction */
+#define DOT_PROF_KINDS 8
+int dot_profile_enable(dot_op* op, int enable);
+int dot_profile_read(dot_op* op, int kind, double* ms_total, int64_t* launches,
+                     int64_t* column_sweeps);
 
 /*
  * Small dense binary64 helpers on the device, for the optimized

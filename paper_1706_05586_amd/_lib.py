@@ -29,6 +29,13 @@ DOT_JAC_SPLIT_BF16 = 1
 DOT_ACT_ALPHA = 1
 DOT_ACT_BETA = 2
 DOT_ACT_CHI = 4
+DOT_MAX_COLUMNS = 4096
+DOT_PROF_PCG1_FP64 = 0
+DOT_PROF_PCG2_FP64 = 1
+DOT_PROF_PCG1_FP32 = 2
+DOT_PROF_PCG2_FP32 = 3
+DOT_PROF_RESID = 4
+DOT_PROF_JACOBIAN = 5
 
 
 class DotGrid(C.Structure):
@@ -43,7 +50,7 @@ class DotPals(C.Structure):
 
 class DotSolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int), ("precision", C.c_int),
-                ("inner_rtol", C.c_double), ("max_outer", C.c_int), ("check_every", C.c_int)]
+                ("inner_rtol", C.c_double), ("check_every", C.c_int)]
 
 
 class DotSolveInfo(C.Structure):
@@ -80,6 +87,9 @@ SIGNATURES = {
     "dot_jacobian": (_i, [_vp, _i, _vp, _i, _vp, _i, _vp, _vp, _sz, _vp]),
     "dot_grad_misfit": (_i, [_vp, _i, _vp, _i, _vp, _vp, _vp, _vp, _sz, _vp]),
     "dot_gemm": (_i, [_i, _i, _i, _i, _i, _d, _vp, _i, _vp, _i, _d, _vp, _i, _vp]),
+    "dot_profile_enable": (_i, [_vp, _i]),
+    "dot_profile_read": (_i, [_vp, _i, C.POINTER(C.c_double), C.POINTER(_i64),
+                              C.POINTER(_i64)]),
 }
 
 

@@ -209,14 +209,20 @@ class Operator:
         check(lib.dot_apply(self._handle, k, _ptr(Xm), _ptr(Y), _stream()), "dot_apply")
         return Y.reshape(-1) if X.dim() == 1 else Y
 
-    def form_rhs(self, cells, weights: torch.Tensor) -> torch.Tensor:
-        """B W: weights is (n_pts, k); returns the (N, k) right-hand side block."""
+    def form_rhs(self, cells, weights: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """B W: weights is (n_pts, k); returns the (N, k) right-hand side block.
+        ``out`` may be a column slice of a larger column-major block."""
         cells = np.ascontiguousarray(np.asarray(cells, dtype=np.int32))
         Wm = colmajor(weights, "weights")
         n_pts, k = weights.shape
         if cells.size != n_pts:
             raise ValueError("one cell per weight row")
-        rhs = empty_colmajor(self.N, k, self.device)
+        if out is not None:
+            if out.shape != (self.N, k) or not out.t().is_contiguous() or out.dtype != torch.float64:
+                raise ValueError("out must be a column-major (N, k) float64 block")
+            rhs = out
+        else:
+            rhs = empty_colmajor(self.N, k, self.device)
         check(lib.dot_form_rhs(self._handle, n_pts, cells.ctypes.data_as(L._pi32), k, _ptr(Wm),
                                _ptr(rhs), _stream()), "dot_form_rhs")
         return rhs
@@ -225,8 +231,8 @@ class Operator:
         return int(lib.dot_solve_workspace_bytes(self._handle, k, precision))
 
     def solve(self, rhs: torch.Tensor, rtol: float = 1e-10, precision: int = L.DOT_FP64,
-              max_iter: int = 20000, inner_rtol: float = 1e-4, max_outer: int = 30,
-              check_every: int = 16, trans: int = 0, out: torch.Tensor | None = None,
+              max_iter: int = 20000, inner_rtol: float = 0.1,
+              check_every: int = 8, trans: int = 0, out: torch.Tensor | None = None,
               work: torch.Tensor | None = None, warn: bool = True) -> SolveResult:
         Bm = colmajor(rhs, "rhs")
         k = rhs.shape[1]
@@ -234,7 +240,7 @@ class Operator:
         nbytes = self.solve_workspace_bytes(k, precision)
         if work is None or work.numel() < nbytes or work.data_ptr() % 256:
             work = _workspace(nbytes, self.device)
-        opts = L.DotSolveOpts(rtol, max_iter, precision, inner_rtol, max_outer, check_every)
+        opts = L.DotSolveOpts(rtol, max_iter, precision, inner_rtol, check_every)
         iters = np.zeros(k, dtype=np.int32)
         rel = np.zeros(k, dtype=np.float64)
         info = L.DotSolveInfo(0, 0, iters.ctypes.data_as(C.POINTER(C.c_int32)),
@@ -247,6 +253,17 @@ class Operator:
                           L.NotConverged)
         return SolveResult(x=x, iters=iters, relres=rel, iters_max=info.iters_max,
                            outer=info.outer, converged=code == L.DOT_OK)
+
+    # ------------------------------------------------------------ profiling
+    def profile_enable(self, on: bool = True):
+        check(lib.dot_profile_enable(self._handle, int(on)), "dot_profile_enable")
+
+    def profile_read(self, kind: int):
+        """(summed event ms, launches, sum over launches of active columns)."""
+        ms, n, cols = C.c_double(), C.c_int64(), C.c_int64()
+        check(lib.dot_profile_read(self._handle, kind, C.byref(ms), C.byref(n), C.byref(cols)),
+              "dot_profile_read")
+        return ms.value, n.value, cols.value
 
     # ------------------------------------------------------------ estimators
     def sampled_misfit(self, det_cells, U: torch.Tensor, V: torch.Tensor, DW: torch.Tensor):

@@ -8,6 +8,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <cstdio>
+#include <vector>
 
 #include "../../include/dotpath.h"
 
@@ -92,6 +93,7 @@ struct dot_op {
   int32_t* cells_dev = nullptr;   // optode cells staging
   int64_t cells_cap = 0;
   double* small_dev = nullptr;    // small device scratch (scalars)
+  void* prof = nullptr;           // kernel timing state (solve.hip)
   int32_t* pinned = nullptr;      // pinned host mailbox (counters/flags)
   double* pinned_d = nullptr;     // pinned host doubles (misfit, small results)
 };
@@ -99,6 +101,11 @@ struct dot_op {
 namespace dot {
 
 int validate_grid(const dot_grid* g, GridDims* out, const char** why);
+void destroy_profile(dot_op* op);
+int profile_begin(dot_op* op, int kind, hipStream_t s, hipEvent_t* e0, hipEvent_t* e1,
+                  unsigned long long** cols);
+int profile_end(dot_op* op, int kind, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+constexpr int kPinnedInts = 2 * DOT_MAX_COLUMNS + 64;
 int ensure_cells_dev(dot_op* op, int n, const int32_t* cells_host, hipStream_t s);
 
 constexpr int kWave = 64;

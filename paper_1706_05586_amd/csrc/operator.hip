@@ -457,7 +457,7 @@ int dot_build_operator(const dot_grid* grid, const double* D_dev, void* stream, 
   for (float** p : d32)
     if (e == hipSuccess) e = hipMalloc(p, n4);
   if (e == hipSuccess) e = hipMalloc(&op->small_dev, 64 * sizeof(double));
-  if (e == hipSuccess) e = hipHostMalloc(&op->pinned, 64 * sizeof(int32_t), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc(&op->pinned, kPinnedInts * sizeof(int32_t), hipHostMallocDefault);
   if (e == hipSuccess)
     e = hipHostMalloc(&op->pinned_d, 64 * sizeof(double), hipHostMallocDefault);
   if (e != hipSuccess) {
@@ -484,6 +484,7 @@ int dot_build_operator(const dot_grid* grid, const double* D_dev, void* stream, 
 int dot_destroy_operator(dot_op* op) {
   if (!op) return DOT_OK;
   (void)hipDeviceSynchronize();
+  destroy_profile(op);
   void* ptrs[] = {op->cx,        op->cy,         op->cz,          op->b0,        op->diag,
                   op->sd,        op->sx,         op->sy,          op->sz,        op->sx32,
                   op->sy32,      op->sz32,       op->phi,         op->theta,     op->pair_cell,

@@ -40,19 +40,24 @@ constexpr int RG = 4;
 constexpr int NHALO = 2 * TX + 2 * TY;
 
 enum SweepMode { M_APPLY = 0, M_TRUE = 1, M_PCG1 = 2, M_PCG2 = 3, M_RESID = 4 };
-enum EltMode { E_INIT = 0, E_INNER_INIT = 1, E_FOLD = 2, E_UNSCALE = 3 };
+enum EltMode { E_INIT = 0, E_REPLACE = 1, E_FOLD = 2, E_UNSCALE = 3 };
 enum FinMode {
-  F_INIT = 0,        // bnorm, rho, active (fp64 PCG)
-  F_INIT_IR = 1,     // bnorm, scale = |b^|, active (mixed)
-  F_ALPHA = 2,       // alpha = rho / p.q
-  F_BETA = 3,        // fp64 PCG: relres, convergence, beta
-  F_RHO_INNER = 4,   // inner: rho = r32.r32, inner_active = active
-  F_BETA_INNER = 5,  // inner: convergence at inner_rtol, beta
-  F_OUTER = 6,       // mixed: true relres, active, scale
-  F_TRUE = 7         // final true relres
+  F_INIT = 0,      // bnorm, rho, scale = |b^|, activity
+  F_ALPHA = 1,     // alpha = rho / p.q
+  F_BETA = 2,      // binary64 PCG: relres, convergence, beta
+  F_BETA_RU = 3,   // binary32 CG: beta, reliable-update schedule
+  F_RESID = 4,     // true binary64 residual: convergence
+  F_REPLACE = 5,   // residual replaced: rho, beta
+  F_TRUE = 6       // final true relres
 };
 
 enum { FLAG_BREAKDOWN = 1, FLAG_NONFINITE = 2 };
+
+#define DOT_TRY(...)               \
+  do {                             \
+    int rc_ = (__VA_ARGS__);       \
+    if (rc_ != DOT_OK) return rc_; \
+  } while (0)
 
 struct Geom {
   int nx, ny, nz;
@@ -63,17 +68,18 @@ struct Geom {
 };
 
 struct ColState {
-  double* rho;
+  double* rho;       // r.z of the current iteration
+  double* rho_prev;  // r.z of the previous iteration (reliable updates)
   double* alpha;
   double* beta;
-  double* bnorm;
-  double* relres;
-  double* scale;
-  int* active;        // outer activity (fp64: CG activity)
-  int* inner_active;  // mixed: inner activity
-  int* iters;         // fp64: CG iterations; mixed: total inner iterations
-  int* flags;         // per column FLAG_*
-  int* counters;      // [0] = number of active columns after the last finalize
+  double* bnorm;     // ||b||_2
+  double* relres;    // last relative residual (estimate or true)
+  double* scale;     // binary32 scaling of the residual (||b^||)
+  double* rmax;      // largest binary32 residual norm since the last update
+  int* active;       // column still iterating
+  int* upd;          // reliable update due
+  int* iters;        // iterations per column
+  int* flags;        // FLAG_* per column
 };
 
 template <typename T>
@@ -93,6 +99,7 @@ struct SweepArgs {
   T* out0;             // APPLY: y; PCG1: p_new; PCG2: x (in place); RESID: r64
   T* out1;             // PCG2: r (in place)
   double* partial;     // [2][k][nblk_col]
+  unsigned long long* prof_cols;  // optional: sum of active columns over launches
 };
 
 __device__ __forceinline__ int remap_block(int L, int total) {
@@ -135,7 +142,10 @@ __device__ __forceinline__ void block_partials(double (&acc)[RG][2], const Geom&
 
 template <int MODE, typename T>
 __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs<T> a) {
-  __shared__ T sm[RG][TY + 2][TX + 2];
+  // two LDS planes: plane z is written to sm[(z - z0) & 1] while the other
+  // buffer may still be read by slower waves of plane z - 1, so one barrier
+  // per plane suffices
+  __shared__ T sm[2][RG][TY + 2][TX + 2];
   const Geom& G = a.G;
   const int logical = remap_block((int)blockIdx.x, G.nblocks);
   const int tile = logical % G.ntiles;
@@ -162,6 +172,12 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs<T> a) {
     any |= act[r];
   }
   if (!any) return;  // uniform over the block
+  if (a.prof_cols && tile == 0 && zci == 0 && threadIdx.x == 0) {
+    int n = 0;
+#pragma unroll
+    for (int r = 0; r < RG; ++r) n += act[r] ? 1 : 0;
+    atomicAdd(a.prof_cols, (unsigned long long)n);
+  }
 
   auto stage = [&](int64_t c, int r) -> T {
     const int64_t o = c + G.N * (int64_t)col[r];
@@ -176,7 +192,8 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs<T> a) {
 
   // halo slot owned by this thread (if any)
   int hx = -1, hy = -1, hsy = 0, hsx = 0;
-  if (threadIdx.x < NHALO) {
+  const bool hthread = threadIdx.x < NHALO;
+  if (hthread) {
     const int s = threadIdx.x;
     if (s < TX) {
       hx = x0 + s; hy = y0 - 1; hsy = 0; hsx = s + 1;
@@ -192,81 +209,100 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs<T> a) {
   const int64_t hbase = hin ? (hx + (int64_t)G.nx * hy) : 0;
   const int64_t base = in ? (x + (int64_t)G.nx * y) : 0;
 
-  T vm[RG], vc[RG], vp[RG];
+  T vm[RG], vc[RG], vp[RG], hv[RG];
   double acc[RG][2];
 #pragma unroll
   for (int r = 0; r < RG; ++r) {
     acc[r][0] = acc[r][1] = 0.0;
-    vm[r] = vc[r] = vp[r] = T(0);
+    vm[r] = vc[r] = vp[r] = hv[r] = T(0);
     if (in && act[r]) {
       if (z0 > 0) vm[r] = stage(base + (int64_t)(z0 - 1) * G.nxy, r);
       vc[r] = stage(base + (int64_t)z0 * G.nxy, r);
     }
+    if (hthread && hin && act[r]) hv[r] = stage(hbase + (int64_t)z0 * G.nxy, r);
   }
   T cD = T(0);
   if (in && z0 > 0) cD = a.cz[base + (int64_t)(z0 - 1) * G.nxy];
 
   for (int z = z0; z < z1; ++z) {
+    const int buf = (z - z0) & 1;
     const int64_t c = base + (int64_t)z * G.nxy;
     const bool has_up = z + 1 < G.nz;
+    // plane z into LDS (own values and the halo prefetched one plane ago)
 #pragma unroll
-    for (int r = 0; r < RG; ++r) {
-      vp[r] = (in && act[r] && has_up) ? stage(c + G.nxy, r) : T(0);
-      sm[r][ty + 1][tx + 1] = vc[r];
+    for (int r = 0; r < RG; ++r) sm[buf][r][ty + 1][tx + 1] = vc[r];
+    if (hthread) {
+#pragma unroll
+      for (int r = 0; r < RG; ++r) sm[buf][r][hsy][hsx] = hv[r];
     }
-    if (threadIdx.x < NHALO) {
-      const int64_t hc = hbase + (int64_t)z * G.nxy;
+    // global loads issued before the barrier: own plane z+1, halo of plane
+    // z+1, coefficients and per-cell operands of plane z
 #pragma unroll
-      for (int r = 0; r < RG; ++r) sm[r][hsy][hsx] = (hin && act[r]) ? stage(hc, r) : T(0);
+    for (int r = 0; r < RG; ++r) vp[r] = (in && act[r] && has_up) ? stage(c + G.nxy, r) : T(0);
+    if (hthread && z + 1 < z1) {
+      const int64_t hc = hbase + (int64_t)(z + 1) * G.nxy;
+#pragma unroll
+      for (int r = 0; r < RG; ++r) hv[r] = (hin && act[r]) ? stage(hc, r) : T(0);
+    }
+    T cE = T(0), cW = T(0), cN = T(0), cS = T(0), cU = T(0), dd = T(1);
+    double sdc = 1.0;
+    T o0[RG], o1[RG];
+    double bo[RG];
+    if (in) {
+      cE = a.cx[c];
+      cW = x > 0 ? a.cx[c - 1] : T(0);
+      cN = a.cy[c];
+      cS = y > 0 ? a.cy[c - G.nx] : T(0);
+      cU = a.cz[c];
+      if constexpr (MODE == M_APPLY || MODE == M_TRUE) dd = (T)a.diag[c];
+      if constexpr (MODE == M_PCG2 || MODE == M_RESID) sdc = a.sd[c];
+#pragma unroll
+      for (int r = 0; r < RG; ++r) {
+        const int64_t o = c + G.N * (int64_t)col[r];
+        if constexpr (MODE == M_PCG2) {
+          o0[r] = act[r] ? a.out0[o] : T(0);
+          o1[r] = act[r] ? a.out1[o] : T(0);
+        }
+        if constexpr (MODE == M_RESID || MODE == M_TRUE) bo[r] = act[r] ? a.b[o] : 0.0;
+      }
     }
     __syncthreads();
     if (in) {
-      const T cE = a.cx[c];
-      const T cW = x > 0 ? a.cx[c - 1] : T(0);
-      const T cN = a.cy[c];
-      const T cS = y > 0 ? a.cy[c - G.nx] : T(0);
-      const T cU = a.cz[c];
-      T dd = T(1);
-      if constexpr (MODE == M_APPLY || MODE == M_TRUE) dd = (T)a.diag[c];
 #pragma unroll
       for (int r = 0; r < RG; ++r) {
         if (!act[r]) continue;
-        const T vW = sm[r][ty + 1][tx], vE = sm[r][ty + 1][tx + 2];
-        const T vS = sm[r][ty][tx + 1], vN = sm[r][ty + 2][tx + 1];
+        const T vW = sm[buf][r][ty + 1][tx], vE = sm[buf][r][ty + 1][tx + 2];
+        const T vS = sm[buf][r][ty][tx + 1], vN = sm[buf][r][ty + 2][tx + 1];
         const T Av = dd * vc[r] - cW * vW - cE * vE - cS * vS - cN * vN - cD * vm[r] - cU * vp[r];
         const int64_t o = c + G.N * (int64_t)col[r];
         if constexpr (MODE == M_APPLY) {
           a.out0[o] = Av;
         } else if constexpr (MODE == M_TRUE) {
-          const double rr = a.b[o] - (double)Av;
+          const double rr = bo[r] - (double)Av;
           acc[r][0] += rr * rr;
         } else if constexpr (MODE == M_PCG1) {
           a.out0[o] = vc[r];
           acc[r][0] += (double)vc[r] * (double)Av;
         } else if constexpr (MODE == M_PCG2) {
           const T al = (T)cf[r];
-          const T xn = a.out0[o] + al * vc[r];
-          const T rn = a.out1[o] - al * Av;
+          const T xn = o0[r] + al * vc[r];
+          const T rn = o1[r] - al * Av;
           a.out0[o] = xn;
           a.out1[o] = rn;
           const double rd = (double)rn;
           acc[r][0] += rd * rd;
-          if (a.sd) {
-            const double t = a.sd[c] * rd;
-            acc[r][1] += t * t;
-          }
+          const double t = sdc * rd;
+          acc[r][1] += t * t;
         } else if constexpr (MODE == M_RESID) {
-          const double s = a.sd[c];
-          const double rr = a.b[o] / s - (double)Av;
+          const double rr = bo[r] / sdc - (double)Av;
           a.out0[o] = (T)rr;
           acc[r][0] += rr * rr;
-          const double t = s * rr;
+          const double t = sdc * rr;
           acc[r][1] += t * t;
         }
       }
-      cD = cU;
     }
-    __syncthreads();
+    cD = cU;
 #pragma unroll
     for (int r = 0; r < RG; ++r) {
       vm[r] = vc[r];
@@ -280,7 +316,7 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs<T> a) {
 struct EltArgs {
   Geom G;
   const double* sd;
-  const int* active;    // columns to process
+  const int* mask;      // columns to process (NULL = all)
   const double* scale;  // per column scale
   const double* b;      // INIT: rhs
   double* xh;           // x^ (binary64)
@@ -311,7 +347,7 @@ __global__ __launch_bounds__(NT) void elt_kernel(EltArgs a) {
   for (int r = 0; r < RG; ++r) {
     const int j = grp * RG + r;
     col[r] = j;
-    act[r] = j < G.k && (a.active == nullptr || a.active[j] != 0);
+    act[r] = j < G.k && (a.mask == nullptr || a.mask[j] != 0);
     sc[r] = (act[r] && a.scale) ? a.scale[j] : 0.0;
     any |= act[r];
   }
@@ -332,177 +368,156 @@ __global__ __launch_bounds__(NT) void elt_kernel(EltArgs a) {
           const double rv = bv / a.sd[c];
           a.xh[o] = 0.0;
           a.r64[o] = rv;
+          if (a.d32) a.d32[o] = 0.0f;
           acc[r][0] += rv * rv;
           acc[r][1] += bv * bv;
-        } else if constexpr (MODE == E_INNER_INIT) {
+        } else if constexpr (MODE == E_REPLACE) {
           const float rv = (float)(a.r64[o] / sc[r]);
           a.r32[o] = rv;
-          a.d32[o] = 0.0f;
-          acc[r][0] += (double)rv * (double)rv;
+          const double rd = (double)rv;
+          acc[r][0] += rd * rd;
+          const double t = a.sd[c] * rd;
+          acc[r][1] += t * t;
         } else if constexpr (MODE == E_FOLD) {
           a.xh[o] += sc[r] * (double)a.d32[o];
+          a.d32[o] = 0.0f;
         } else if constexpr (MODE == E_UNSCALE) {
           a.xh[o] = a.xh[o] / a.sd[c];
         }
       }
     }
   }
-  if constexpr (MODE == E_INIT || MODE == E_INNER_INIT) block_partials(acc, G, grp, slot, a.partial);
+  if constexpr (MODE == E_INIT || MODE == E_REPLACE) block_partials(acc, G, grp, slot, a.partial);
 }
 
-// One block: sum per-block partials in fixed order and update per-column state.
+// One block per column: sum that column's per-block partials in fixed order
+// and update its state.  Columns outside `live` are left untouched.
 struct FinArgs {
   int mode;
   int k, nblk;
   const double* partial;
+  const int* live;
   ColState st;
-  double rtol, inner_rtol;
+  double rtol, delta;
 };
 
 __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
-  __shared__ double red[256];
-  __shared__ double tot[2];
+  __shared__ double red[2][256];
+  const int j = blockIdx.x;
+  if (j >= a.k) return;
+  if (a.live && a.live[j] == 0) return;  // uniform over the block
   const ColState& st = a.st;
-  for (int j = 0; j < a.k; ++j) {
-    bool live;
-    if (a.mode == F_INIT || a.mode == F_INIT_IR || a.mode == F_TRUE || a.mode == F_RHO_INNER)
-      live = true;
-    else if (a.mode == F_ALPHA)
-      live = (st.inner_active ? st.inner_active[j] : st.active[j]) != 0;
-    else if (a.mode == F_BETA_INNER)
-      live = st.inner_active[j] != 0;
-    else
-      live = st.active[j] != 0;
-    if (a.mode == F_RHO_INNER && st.active[j] == 0) {
-      // not refined in this outer step: keep it out of the inner solve
-      if (threadIdx.x == 0) st.inner_active[j] = 0;
-      live = false;
-    }
-    if (!live) continue;  // uniform: j and state are the same for every thread
-    for (int acc = 0; acc < 2; ++acc) {
-      const double* p = a.partial + ((int64_t)acc * a.k + j) * a.nblk;
-      double s = 0.0;
-      for (int i = threadIdx.x; i < a.nblk; i += 256) s += p[i];
-      red[threadIdx.x] = s;
-      __syncthreads();
-      for (int w = 128; w >= 1; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-      }
-      if (threadIdx.x == 0) tot[acc] = red[0];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      const double s0 = tot[0], s1 = tot[1];
-      switch (a.mode) {
-        case F_INIT: {
-          const double bn = sqrt(s1);
-          st.bnorm[j] = bn;
-          st.rho[j] = s0;
-          st.iters[j] = 0;
-          st.beta[j] = 0.0;
-          st.flags[j] = 0;
-          if (!isfinite(s0) || !isfinite(s1)) {
-            st.flags[j] |= FLAG_NONFINITE;
-            st.active[j] = 0;
-            st.relres[j] = NAN;
-          } else {
-            st.active[j] = bn > 0.0 ? 1 : 0;
-            st.relres[j] = bn > 0.0 ? 1.0 : 0.0;
-          }
-          break;
-        }
-        case F_INIT_IR: {
-          const double bn = sqrt(s1);
-          st.bnorm[j] = bn;
-          st.scale[j] = sqrt(s0);
-          st.iters[j] = 0;
-          st.flags[j] = 0;
-          if (st.inner_active) st.inner_active[j] = 0;
-          if (!isfinite(s0) || !isfinite(s1)) {
-            st.flags[j] |= FLAG_NONFINITE;
-            st.active[j] = 0;
-            st.relres[j] = NAN;
-          } else {
-            st.active[j] = bn > 0.0 ? 1 : 0;
-            st.relres[j] = bn > 0.0 ? 1.0 : 0.0;
-          }
-          break;
-        }
-        case F_ALPHA: {
-          if (!(s0 > 0.0) || !isfinite(s0)) {
-            st.flags[j] |= isfinite(s0) ? FLAG_BREAKDOWN : FLAG_NONFINITE;
-            st.alpha[j] = 0.0;
-            if (st.inner_active) st.inner_active[j] = 0;
-            st.active[j] = 0;
-          } else {
-            st.alpha[j] = st.rho[j] / s0;
-          }
-          break;
-        }
-        case F_BETA: {
-          st.iters[j] += 1;
-          const double rel = sqrt(s1) / st.bnorm[j];
-          st.relres[j] = rel;
-          if (!isfinite(s0) || !isfinite(s1)) {
-            st.flags[j] |= FLAG_NONFINITE;
-            st.active[j] = 0;
-          } else if (rel <= a.rtol) {
-            st.active[j] = 0;
-          } else {
-            st.beta[j] = s0 / st.rho[j];
-            st.rho[j] = s0;
-          }
-          break;
-        }
-        case F_RHO_INNER: {
-          st.rho[j] = s0;
-          st.beta[j] = 0.0;
-          st.inner_active[j] = (s0 > 0.0 && isfinite(s0)) ? 1 : 0;
-          break;
-        }
-        case F_BETA_INNER: {
-          st.iters[j] += 1;
-          if (!isfinite(s0)) {
-            st.flags[j] |= FLAG_NONFINITE;
-            st.inner_active[j] = 0;
-            st.active[j] = 0;
-          } else if (sqrt(s0) <= a.inner_rtol) {
-            st.inner_active[j] = 0;
-          } else {
-            st.beta[j] = s0 / st.rho[j];
-            st.rho[j] = s0;
-          }
-          break;
-        }
-        case F_OUTER: {
-          const double rel = sqrt(s1) / st.bnorm[j];
-          st.relres[j] = rel;
-          st.scale[j] = sqrt(s0);
-          if (!isfinite(s0) || !isfinite(s1)) {
-            st.flags[j] |= FLAG_NONFINITE;
-            st.active[j] = 0;
-          } else if (rel <= a.rtol || !(s0 > 0.0)) {
-            st.active[j] = 0;
-          }
-          break;
-        }
-        case F_TRUE: {
-          const double bn = st.bnorm[j];
-          st.relres[j] = bn > 0.0 ? sqrt(s0) / bn : sqrt(s0);
-          break;
-        }
-      }
+  for (int q = 0; q < 2; ++q) {
+    const double* p = a.partial + ((int64_t)q * a.k + j) * a.nblk;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < a.nblk; i += 256) s += p[i];
+    red[q][threadIdx.x] = s;
+  }
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + w];
+      red[1][threadIdx.x] += red[1][threadIdx.x + w];
     }
     __syncthreads();
   }
-  // number of still-active columns (inner activity for the inner finalizers)
-  if (threadIdx.x == 0) {
-    int n = 0;
-    const bool inner = (a.mode == F_BETA_INNER || a.mode == F_RHO_INNER ||
-                        (a.mode == F_ALPHA && st.inner_active));
-    for (int j = 0; j < a.k; ++j) n += inner ? (st.inner_active[j] != 0) : (st.active[j] != 0);
-    st.counters[0] = n;
+  if (threadIdx.x != 0) return;
+  const double s0 = red[0][0], s1 = red[1][0];
+  const bool fin = isfinite(s0) && isfinite(s1);
+  switch (a.mode) {
+    case F_INIT: {
+      const double bn = sqrt(s1);
+      st.bnorm[j] = bn;
+      st.rho[j] = s0;
+      st.rho_prev[j] = 0.0;
+      st.scale[j] = sqrt(s0);
+      st.rmax[j] = 0.0;
+      st.beta[j] = 0.0;
+      st.iters[j] = 0;
+      st.flags[j] = 0;
+      st.upd[j] = 0;
+      if (!fin) {
+        st.flags[j] |= FLAG_NONFINITE;
+        st.active[j] = 0;
+        st.relres[j] = NAN;
+      } else {
+        st.active[j] = bn > 0.0 ? 1 : 0;
+        st.relres[j] = bn > 0.0 ? 1.0 : 0.0;
+      }
+      break;
+    }
+    case F_ALPHA: {
+      if (!fin || !(s0 > 0.0)) {
+        st.flags[j] |= fin ? FLAG_BREAKDOWN : FLAG_NONFINITE;
+        st.alpha[j] = 0.0;
+        st.active[j] = 0;
+      } else {
+        st.alpha[j] = st.rho[j] / s0;
+      }
+      break;
+    }
+    case F_BETA: {  // binary64 PCG: stopping test on the recursive residual
+      st.iters[j] += 1;
+      const double rel = sqrt(s1) / st.bnorm[j];
+      st.relres[j] = rel;
+      if (!fin) {
+        st.flags[j] |= FLAG_NONFINITE;
+        st.active[j] = 0;
+      } else if (rel <= a.rtol) {
+        st.active[j] = 0;
+      } else {
+        st.beta[j] = s0 / st.rho[j];
+        st.rho[j] = s0;
+      }
+      break;
+    }
+    case F_BETA_RU: {  // binary32 CG: schedule a reliable update when due
+      st.iters[j] += 1;
+      if (!fin) {
+        st.flags[j] |= FLAG_NONFINITE;
+        st.active[j] = 0;
+        break;
+      }
+      const double rn = sqrt(s0);
+      const double est = st.scale[j] * sqrt(s1) / st.bnorm[j];
+      st.relres[j] = est;
+      st.rho_prev[j] = st.rho[j];
+      st.beta[j] = s0 / st.rho[j];
+      st.rho[j] = s0;
+      st.rmax[j] = fmax(st.rmax[j], rn);
+      if (rn < a.delta * st.rmax[j] || est <= a.rtol) st.upd[j] = 1;
+      break;
+    }
+    case F_RESID: {  // true binary64 residual after folding the correction
+      const double rel = sqrt(s1) / st.bnorm[j];
+      st.relres[j] = rel;
+      if (!fin) {
+        st.flags[j] |= FLAG_NONFINITE;
+        st.active[j] = 0;
+        st.upd[j] = 0;
+      } else if (rel <= a.rtol) {
+        st.active[j] = 0;
+        st.upd[j] = 0;
+      }
+      break;
+    }
+    case F_REPLACE: {  // residual replaced by the true one; keep the direction
+      if (!fin) {
+        st.flags[j] |= FLAG_NONFINITE;
+        st.active[j] = 0;
+      } else {
+        st.beta[j] = st.rho_prev[j] > 0.0 ? s0 / st.rho_prev[j] : 0.0;
+        st.rho[j] = s0;
+        st.rmax[j] = sqrt(s0);
+      }
+      st.upd[j] = 0;
+      break;
+    }
+    case F_TRUE: {
+      const double bn = st.bnorm[j];
+      st.relres[j] = bn > 0.0 ? sqrt(s0) / bn : sqrt(s0);
+      break;
+    }
   }
 }
 
@@ -568,26 +583,89 @@ static size_t layout_workspace(const Geom& G, int precision, char* base, Workspa
   ws.partial = (double*)take((size_t)2 * G.k * G.nblk_col * 8);
   const size_t k = (size_t)G.k;
   ws.st.rho = (double*)take(k * 8);
+  ws.st.rho_prev = (double*)take(k * 8);
   ws.st.alpha = (double*)take(k * 8);
   ws.st.beta = (double*)take(k * 8);
   ws.st.bnorm = (double*)take(k * 8);
   ws.st.relres = (double*)take(k * 8);
   ws.st.scale = (double*)take(k * 8);
+  ws.st.rmax = (double*)take(k * 8);
   ws.st.active = (int*)take(k * 4);
-  ws.st.inner_active = (int*)take(k * 4);
+  ws.st.upd = (int*)take(k * 4);
   ws.st.iters = (int*)take(k * 4);
   ws.st.flags = (int*)take(k * 4);
-  ws.st.counters = (int*)take(64);
   ws.bytes = off;
   if (w) *w = ws;
   return off;
 }
 
+// ------------------------------------------------------------ profiling
+struct ProfState {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  struct Pending {
+    int kind;
+    hipEvent_t e0, e1;
+  };
+  std::vector<Pending> pending;
+  double ms[DOT_PROF_KINDS] = {};
+  int64_t launches[DOT_PROF_KINDS] = {};
+  unsigned long long* cols_dev = nullptr;
+};
+
+static ProfState* prof_of(dot_op* op) { return reinterpret_cast<ProfState*>(op->prof); }
+
+static int prof_drain(dot_op* op) {
+  ProfState* p = prof_of(op);
+  if (!p) return DOT_OK;
+  for (auto& q : p->pending) {
+    float ms = 0.0f;
+    DOT_HIP(hipEventSynchronize(q.e1));
+    DOT_HIP(hipEventElapsedTime(&ms, q.e0, q.e1));
+    p->ms[q.kind] += ms;
+    p->launches[q.kind] += 1;
+    p->pool.push_back(q.e0);
+    p->pool.push_back(q.e1);
+  }
+  p->pending.clear();
+  return DOT_OK;
+}
+
+static int prof_begin(dot_op* op, int kind, hipStream_t s, hipEvent_t* e0, hipEvent_t* e1,
+                      unsigned long long** cols) {
+  *e0 = *e1 = nullptr;
+  *cols = nullptr;
+  ProfState* p = prof_of(op);
+  if (!p || !p->on || kind < 0) return DOT_OK;
+  if (p->pending.size() >= 2048) DOT_TRY(prof_drain(op));
+  for (hipEvent_t* e : {e0, e1}) {
+    if (p->pool.empty()) {
+      hipEvent_t ev;
+      DOT_HIP(hipEventCreate(&ev));
+      p->pool.push_back(ev);
+    }
+    *e = p->pool.back();
+    p->pool.pop_back();
+  }
+  *cols = p->cols_dev + kind;
+  DOT_HIP(hipEventRecord(*e0, s));
+  return DOT_OK;
+}
+
+static int prof_end(dot_op* op, int kind, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  if (!e0) return DOT_OK;
+  DOT_HIP(hipEventRecord(e1, s));
+  prof_of(op)->pending.push_back({kind, e0, e1});
+  return DOT_OK;
+}
+
 template <int MODE, typename T>
-static int launch_sweep(const SweepArgs<T>& a, hipStream_t s) {
+static int launch_sweep(dot_op* op, SweepArgs<T> a, hipStream_t s, int kind = -1) {
+  hipEvent_t e0, e1;
+  DOT_TRY(prof_begin(op, kind, s, &e0, &e1, &a.prof_cols));
   hipLaunchKernelGGL((sweep_kernel<MODE, T>), dim3(a.G.nblocks), dim3(NT), 0, s, a);
   DOT_LAUNCH_CHECK();
-  return DOT_OK;
+  return prof_end(op, kind, s, e0, e1);
 }
 
 template <int MODE>
@@ -597,33 +675,39 @@ static int launch_elt(const EltArgs& a, hipStream_t s) {
   return DOT_OK;
 }
 
-static int launch_fin(int mode, const Geom& G, const Workspace& ws, double rtol, double inner_rtol,
-                      hipStream_t s) {
+static int launch_fin(int mode, const Geom& G, const Workspace& ws, const int* live, double rtol,
+                      double delta, hipStream_t s) {
   FinArgs f;
   f.mode = mode;
   f.k = G.k;
   f.nblk = G.nblk_col;
   f.partial = ws.partial;
+  f.live = live;
   f.st = ws.st;
   f.rtol = rtol;
-  f.inner_rtol = inner_rtol;
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, f);
+  f.delta = delta;
+  hipLaunchKernelGGL(finalize_kernel, dim3(G.k), dim3(256), 0, s, f);
   DOT_LAUNCH_CHECK();
   return DOT_OK;
 }
 
-static int poll_active(dot_op* op, const Workspace& ws, hipStream_t s, int* n) {
-  DOT_HIP(hipMemcpyAsync(op->pinned, ws.st.counters, sizeof(int), hipMemcpyDeviceToHost, s));
+// Copy the activity (and update) flags to pinned host memory and count them.
+static int poll(dot_op* op, const Workspace& ws, int k, hipStream_t s, int* n_active,
+                int* n_upd) {
+  DOT_HIP(hipMemcpyAsync(op->pinned, ws.st.active, k * sizeof(int), hipMemcpyDeviceToHost, s));
+  if (n_upd)
+    DOT_HIP(hipMemcpyAsync(op->pinned + k, ws.st.upd, k * sizeof(int), hipMemcpyDeviceToHost, s));
   DOT_HIP(hipStreamSynchronize(s));
-  *n = op->pinned[0];
+  DOT_TRY(prof_drain(op));
+  int na = 0, nu = 0;
+  for (int j = 0; j < k; ++j) {
+    na += op->pinned[j] != 0;
+    if (n_upd) nu += op->pinned[k + j] != 0;
+  }
+  *n_active = na;
+  if (n_upd) *n_upd = nu;
   return DOT_OK;
 }
-
-#define DOT_TRY(...)                 \
-  do {                               \
-    int rc_ = (__VA_ARGS__);         \
-    if (rc_ != DOT_OK) return rc_;   \
-  } while (0)
 
 static SweepArgs<double> base_args64(dot_op* op, const Geom& G) {
   SweepArgs<double> a{};
@@ -641,7 +725,7 @@ static SweepArgs<float> base_args32(dot_op* op, const Geom& G) {
   a.cx = op->sx32;
   a.cy = op->sy32;
   a.cz = op->sz32;
-  a.sd = nullptr;
+  a.sd = op->sd;
   return a;
 }
 
@@ -661,8 +745,8 @@ static int finish_true(dot_op* op, const Geom& G, const Workspace& ws, const dou
   t.in0 = x;
   t.b = rhs;
   t.partial = ws.partial;
-  DOT_TRY(launch_sweep<M_TRUE, double>(t, s));
-  DOT_TRY(launch_fin(F_TRUE, G, ws, 0.0, 0.0, s));
+  DOT_TRY(launch_sweep<M_TRUE, double>(op, t, s));
+  DOT_TRY(launch_fin(F_TRUE, G, ws, nullptr, 0.0, 0.0, s));
   return DOT_OK;
 }
 
@@ -676,9 +760,9 @@ static int solve_fp64(dot_op* op, const Geom& G, const Workspace& ws, const doub
   e.r64 = ws.r64;
   e.partial = ws.partial;
   DOT_TRY(launch_elt<E_INIT>(e, s));
-  DOT_TRY(launch_fin(F_INIT, G, ws, o.rtol, 0.0, s));
+  DOT_TRY(launch_fin(F_INIT, G, ws, nullptr, o.rtol, 0.0, s));
   int n_active = 0;
-  DOT_TRY(poll_active(op, ws, s, &n_active));
+  DOT_TRY(poll(op, ws, G.k, s, &n_active, nullptr));
   int it = 0;
   int cur = 0;
   while (n_active > 0 && it < o.max_iter) {
@@ -690,8 +774,8 @@ static int solve_fp64(dot_op* op, const Geom& G, const Workspace& ws, const doub
     p1.in1 = ws.p64[cur];
     p1.out0 = ws.p64[cur ^ 1];
     p1.partial = ws.partial;
-    DOT_TRY(launch_sweep<M_PCG1, double>(p1, s));
-    DOT_TRY(launch_fin(F_ALPHA, G, ws, o.rtol, 0.0, s));
+    DOT_TRY(launch_sweep<M_PCG1, double>(op, p1, s, DOT_PROF_PCG1_FP64));
+    DOT_TRY(launch_fin(F_ALPHA, G, ws, ws.st.active, o.rtol, 0.0, s));
     cur ^= 1;
     SweepArgs<double> p2 = base_args64(op, G);
     p2.active = ws.st.active;
@@ -700,18 +784,26 @@ static int solve_fp64(dot_op* op, const Geom& G, const Workspace& ws, const doub
     p2.out0 = x;
     p2.out1 = ws.r64;
     p2.partial = ws.partial;
-    DOT_TRY(launch_sweep<M_PCG2, double>(p2, s));
-    DOT_TRY(launch_fin(F_BETA, G, ws, o.rtol, 0.0, s));
+    DOT_TRY(launch_sweep<M_PCG2, double>(op, p2, s, DOT_PROF_PCG2_FP64));
+    DOT_TRY(launch_fin(F_BETA, G, ws, ws.st.active, o.rtol, 0.0, s));
     ++it;
-    if (it % o.check_every == 0 || it == o.max_iter) DOT_TRY(poll_active(op, ws, s, &n_active));
+    if (it % o.check_every == 0 || it == o.max_iter) DOT_TRY(poll(op, ws, G.k, s, &n_active, nullptr));
   }
   *iters_done = it;
   return finish_true(op, G, ws, rhs, x, s);
 }
 
+// Binary32 CG with binary64 reliable updates: the correction d is accumulated
+// in binary32; when the binary32 residual of a column has dropped by `delta`
+// since its last update, or claims convergence, the correction is folded
+// into x^ in binary64 (x^ += s d), the true residual b^ - A^ x^ is recomputed
+// in binary64 and replaces the binary32 residual.  The search direction is
+// kept, so the Krylov information is not discarded as in a restart.  Every
+// convergence decision is made on the binary64 residual.
 static int solve_mixed(dot_op* op, const Geom& G, const Workspace& ws, const double* rhs,
                        double* x, const dot_solve_opts& o, hipStream_t s, int* iters_done,
                        int* outer_done) {
+  const double delta = o.inner_rtol;
   EltArgs e{};
   e.G = G;
   e.sd = op->sd;
@@ -720,65 +812,67 @@ static int solve_mixed(dot_op* op, const Geom& G, const Workspace& ws, const dou
   e.r64 = ws.r64;
   e.r32 = ws.r32;
   e.d32 = ws.d32;
+  e.scale = ws.st.scale;
   e.partial = ws.partial;
   DOT_TRY(launch_elt<E_INIT>(e, s));
-  DOT_TRY(launch_fin(F_INIT_IR, G, ws, o.rtol, o.inner_rtol, s));
-  int n_active = 0;
-  DOT_TRY(poll_active(op, ws, s, &n_active));
-  int total_inner = 0, outer = 0;
-  while (n_active > 0 && outer < o.max_outer && total_inner < o.max_iter) {
-    // inner right-hand side r32 = r64 / |r64|, correction d32 = 0
-    EltArgs ei = e;
-    ei.active = ws.st.active;
-    ei.scale = ws.st.scale;
-    DOT_TRY(launch_elt<E_INNER_INIT>(ei, s));
-    DOT_TRY(launch_fin(F_RHO_INNER, G, ws, o.rtol, o.inner_rtol, s));
-    int n_inner = n_active;
-    int it = 0, cur = 0;
-    while (n_inner > 0 && total_inner + it < o.max_iter) {
-      SweepArgs<float> p1 = base_args32(op, G);
-      p1.active = ws.st.inner_active;
-      p1.coef = ws.st.beta;
-      p1.first = it == 0;
-      p1.in0 = ws.r32;
-      p1.in1 = ws.p32[cur];
-      p1.out0 = ws.p32[cur ^ 1];
-      p1.partial = ws.partial;
-      DOT_TRY(launch_sweep<M_PCG1, float>(p1, s));
-      DOT_TRY(launch_fin(F_ALPHA, G, ws, o.rtol, o.inner_rtol, s));
-      cur ^= 1;
-      SweepArgs<float> p2 = base_args32(op, G);
-      p2.active = ws.st.inner_active;
-      p2.coef = ws.st.alpha;
-      p2.in0 = ws.p32[cur];
-      p2.out0 = ws.d32;
-      p2.out1 = ws.r32;
-      p2.partial = ws.partial;
-      DOT_TRY(launch_sweep<M_PCG2, float>(p2, s));
-      DOT_TRY(launch_fin(F_BETA_INNER, G, ws, o.rtol, o.inner_rtol, s));
-      ++it;
-      if (it % o.check_every == 0) DOT_TRY(poll_active(op, ws, s, &n_inner));
-    }
-    total_inner += it;
-    ++outer;
-    // x^ += |r| d for the columns that were refined
+  DOT_TRY(launch_fin(F_INIT, G, ws, nullptr, o.rtol, delta, s));
+  EltArgs er = e;
+  er.mask = ws.st.active;
+  DOT_TRY(launch_elt<E_REPLACE>(er, s));
+  DOT_TRY(launch_fin(F_REPLACE, G, ws, ws.st.active, o.rtol, delta, s));
+  int n_active = 0, n_upd = 0;
+  DOT_TRY(poll(op, ws, G.k, s, &n_active, nullptr));
+  int it = 0, updates = 0, cur = 0;
+  while (n_active > 0 && it < o.max_iter) {
+    SweepArgs<float> p1 = base_args32(op, G);
+    p1.active = ws.st.active;
+    p1.coef = ws.st.beta;
+    p1.first = it == 0;
+    p1.in0 = ws.r32;
+    p1.in1 = ws.p32[cur];
+    p1.out0 = ws.p32[cur ^ 1];
+    p1.partial = ws.partial;
+    DOT_TRY(launch_sweep<M_PCG1, float>(op, p1, s, DOT_PROF_PCG1_FP32));
+    DOT_TRY(launch_fin(F_ALPHA, G, ws, ws.st.active, o.rtol, delta, s));
+    cur ^= 1;
+    SweepArgs<float> p2 = base_args32(op, G);
+    p2.active = ws.st.active;
+    p2.coef = ws.st.alpha;
+    p2.in0 = ws.p32[cur];
+    p2.out0 = ws.d32;
+    p2.out1 = ws.r32;
+    p2.partial = ws.partial;
+    DOT_TRY(launch_sweep<M_PCG2, float>(op, p2, s, DOT_PROF_PCG2_FP32));
+    DOT_TRY(launch_fin(F_BETA_RU, G, ws, ws.st.active, o.rtol, delta, s));
+    ++it;
+    if (it % o.check_every != 0 && it != o.max_iter) continue;
+    DOT_TRY(poll(op, ws, G.k, s, &n_active, &n_upd));
+    if (n_upd == 0) continue;
+    // reliable update of the flagged columns
     EltArgs ef = e;
-    ef.active = ws.st.active;
-    ef.scale = ws.st.scale;
+    ef.mask = ws.st.upd;
     DOT_TRY(launch_elt<E_FOLD>(ef, s));
-    // binary64 residual r64 = b^ - A^ x^ and the stopping test
     SweepArgs<double> rs = base_args64(op, G);
-    rs.active = ws.st.active;
+    rs.active = ws.st.upd;
     rs.in0 = x;
     rs.b = rhs;
     rs.out0 = ws.r64;
     rs.partial = ws.partial;
-    DOT_TRY(launch_sweep<M_RESID, double>(rs, s));
-    DOT_TRY(launch_fin(F_OUTER, G, ws, o.rtol, o.inner_rtol, s));
-    DOT_TRY(poll_active(op, ws, s, &n_active));
+    DOT_TRY(launch_sweep<M_RESID, double>(op, rs, s, DOT_PROF_RESID));
+    DOT_TRY(launch_fin(F_RESID, G, ws, ws.st.upd, o.rtol, delta, s));
+    DOT_TRY(launch_elt<E_REPLACE>(ef, s));
+    DOT_TRY(launch_fin(F_REPLACE, G, ws, ws.st.upd, o.rtol, delta, s));
+    ++updates;
+    DOT_TRY(poll(op, ws, G.k, s, &n_active, nullptr));
   }
-  *iters_done = total_inner;
-  *outer_done = outer;
+  // columns stopped by the iteration cap: fold their pending correction
+  if (n_active > 0) {
+    EltArgs ef = e;
+    ef.mask = ws.st.active;
+    DOT_TRY(launch_elt<E_FOLD>(ef, s));
+  }
+  *iters_done = it;
+  *outer_done = updates;
   return finish_true(op, G, ws, rhs, x, s);
 }
 
@@ -789,7 +883,8 @@ using namespace dot;
 extern "C" {
 
 size_t dot_solve_workspace_bytes(const dot_op* op, int k, int precision) {
-  if (!op || k < 1 || (precision != DOT_FP64 && precision != DOT_MIXED)) return 0;
+  if (!op || k < 1 || k > DOT_MAX_COLUMNS || (precision != DOT_FP64 && precision != DOT_MIXED))
+    return 0;
   Geom G = make_geom(op->g, k);
   return layout_workspace(G, precision, nullptr, nullptr);
 }
@@ -812,7 +907,7 @@ int dot_apply(dot_op* op, int k, const double* X_dev, double* Y_dev, void* strea
   a.diag = op->diag;
   a.in0 = X_dev;
   a.out0 = Y_dev;
-  return launch_sweep<M_APPLY, double>(a, as_stream(stream));
+  return launch_sweep<M_APPLY, double>(op, a, as_stream(stream));
 }
 
 int dot_solve_multi_rhs(dot_op* op, int trans, int k, const double* rhs_dev, double* x_dev,
@@ -821,7 +916,7 @@ int dot_solve_multi_rhs(dot_op* op, int trans, int k, const double* rhs_dev, dou
   clear_error();
   if (!op) DOT_FAIL(DOT_EINVAL, "op is NULL");
   if (trans != 0 && trans != 1) DOT_FAIL(DOT_EINVAL, "trans must be 0 or 1");
-  if (k < 1) DOT_FAIL(DOT_EINVAL, "k must be >= 1");
+  if (k < 1 || k > DOT_MAX_COLUMNS) DOT_FAIL(DOT_EINVAL, "k must be in [1, %d]", DOT_MAX_COLUMNS);
   if (!rhs_dev || !x_dev) DOT_FAIL(DOT_EINVAL, "rhs_dev/x_dev is NULL");
   if (!opts) DOT_FAIL(DOT_EINVAL, "opts is NULL");
   if (opts->precision != DOT_FP64 && opts->precision != DOT_MIXED)
@@ -829,11 +924,8 @@ int dot_solve_multi_rhs(dot_op* op, int trans, int k, const double* rhs_dev, dou
   if (!(opts->rtol > 0.0) || !(opts->rtol < 1.0)) DOT_FAIL(DOT_EINVAL, "opts.rtol must be in (0, 1)");
   if (opts->max_iter < 1) DOT_FAIL(DOT_EINVAL, "opts.max_iter must be >= 1");
   if (opts->check_every < 1) DOT_FAIL(DOT_EINVAL, "opts.check_every must be >= 1");
-  if (opts->precision == DOT_MIXED) {
-    if (!(opts->inner_rtol > 0.0) || !(opts->inner_rtol < 1.0))
-      DOT_FAIL(DOT_EINVAL, "opts.inner_rtol must be in (0, 1)");
-    if (opts->max_outer < 1) DOT_FAIL(DOT_EINVAL, "opts.max_outer must be >= 1");
-  }
+  if (opts->precision == DOT_MIXED && (!(opts->inner_rtol > 0.0) || !(opts->inner_rtol < 1.0)))
+    DOT_FAIL(DOT_EINVAL, "opts.inner_rtol must be in (0, 1)");
   const size_t bytes = (size_t)op->g.N * k * sizeof(double);
   const char* ra = (const char*)rhs_dev;
   const char* xa = (const char*)x_dev;
@@ -848,19 +940,19 @@ int dot_solve_multi_rhs(dot_op* op, int trans, int k, const double* rhs_dev, dou
     DOT_FAIL(DOT_EINVAL, "workspace overlaps rhs_dev or x_dev");
   Workspace ws;
   layout_workspace(G, opts->precision, (char*)work_dev, &ws);
-  if (opts->precision == DOT_FP64) ws.st.inner_active = nullptr;
   hipStream_t s = as_stream(stream);
   int iters = 0, outer = 0;
   int rc = opts->precision == DOT_FP64 ? solve_fp64(op, G, ws, rhs_dev, x_dev, *opts, s, &iters)
                                        : solve_mixed(op, G, ws, rhs_dev, x_dev, *opts, s, &iters, &outer);
   if (rc != DOT_OK) return rc;
   // per-column results
-  std::vector<int> it_col(k), flags(k), act(k);
+  std::vector<int> it_col(k), flags(k);
   std::vector<double> rel(k);
   DOT_HIP(hipMemcpyAsync(it_col.data(), ws.st.iters, k * sizeof(int), hipMemcpyDeviceToHost, s));
   DOT_HIP(hipMemcpyAsync(flags.data(), ws.st.flags, k * sizeof(int), hipMemcpyDeviceToHost, s));
   DOT_HIP(hipMemcpyAsync(rel.data(), ws.st.relres, k * sizeof(double), hipMemcpyDeviceToHost, s));
   DOT_HIP(hipStreamSynchronize(s));
+  DOT_TRY(prof_drain(op));
   int imax = 0, fl = 0;
   bool conv = true;
   for (int j = 0; j < k; ++j) {
@@ -885,4 +977,65 @@ int dot_solve_multi_rhs(dot_op* op, int trans, int k, const double* rhs_dev, dou
   return DOT_OK;
 }
 
+int dot_profile_enable(dot_op* op, int enable) {
+  clear_error();
+  if (!op) DOT_FAIL(DOT_EINVAL, "op is NULL");
+  ProfState* p = prof_of(op);
+  if (!p) {
+    p = new ProfState();
+    op->prof = p;
+    hipError_t e = hipMalloc(&p->cols_dev, DOT_PROF_KINDS * sizeof(unsigned long long));
+    if (e != hipSuccess) DOT_FAIL(DOT_EHIP, "hipMalloc: %s", hipGetErrorString(e));
+  }
+  DOT_TRY(prof_drain(op));
+  p->on = enable != 0;
+  for (int i = 0; i < DOT_PROF_KINDS; ++i) {
+    p->ms[i] = 0.0;
+    p->launches[i] = 0;
+  }
+  DOT_HIP(hipMemset(p->cols_dev, 0, DOT_PROF_KINDS * sizeof(unsigned long long)));
+  return DOT_OK;
+}
+
+int dot_profile_read(dot_op* op, int kind, double* ms_total, int64_t* launches,
+                     int64_t* column_sweeps) {
+  clear_error();
+  if (!op) DOT_FAIL(DOT_EINVAL, "op is NULL");
+  if (kind < 0 || kind >= DOT_PROF_KINDS) DOT_FAIL(DOT_EINVAL, "unknown profile kind %d", kind);
+  ProfState* p = prof_of(op);
+  if (!p) DOT_FAIL(DOT_EINVAL, "profiling was never enabled on this handle");
+  DOT_HIP(hipDeviceSynchronize());
+  DOT_TRY(prof_drain(op));
+  unsigned long long cols = 0;
+  DOT_HIP(hipMemcpy(&cols, p->cols_dev + kind, sizeof(cols), hipMemcpyDeviceToHost));
+  if (ms_total) *ms_total = p->ms[kind];
+  if (launches) *launches = p->launches[kind];
+  if (column_sweeps) *column_sweeps = (int64_t)cols;
+  return DOT_OK;
+}
+
 }  // extern "C"
+
+namespace dot {
+void destroy_profile(dot_op* op) {
+  ProfState* p = prof_of(op);
+  if (!p) return;
+  for (auto& q : p->pending) {
+    (void)hipEventDestroy(q.e0);
+    (void)hipEventDestroy(q.e1);
+  }
+  for (hipEvent_t e : p->pool) (void)hipEventDestroy(e);
+  if (p->cols_dev) (void)hipFree(p->cols_dev);
+  delete p;
+  op->prof = nullptr;
+}
+
+// Used by the contraction to time itself when profiling is on.
+int profile_begin(dot_op* op, int kind, hipStream_t s, hipEvent_t* e0, hipEvent_t* e1,
+                  unsigned long long** cols) {
+  return prof_begin(op, kind, s, e0, e1, cols);
+}
+int profile_end(dot_op* op, int kind, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  return prof_end(op, kind, s, e0, e1);
+}
+}  // namespace dot

@@ -68,7 +68,7 @@ def test_invalid_arguments_rejected_before_hip(L):
     # NULL handle everywhere
     assert L.lib.dot_set_mua(None, C.c_void_p(1), None) == L.DOT_EINVAL
     assert L.lib.dot_apply(None, 1, C.c_void_p(1), C.c_void_p(2), None) == L.DOT_EINVAL
-    opts = L.DotSolveOpts(1e-8, 100, 0, 1e-4, 10, 8)
+    opts = L.DotSolveOpts(1e-8, 100, 0, 0.1, 8)
     assert L.lib.dot_solve_multi_rhs(None, 0, 1, C.c_void_p(1), C.c_void_p(2), C.byref(opts),
                                      None, 0, None, None) == L.DOT_EINVAL
     assert L.lib.dot_jacobian(None, 1, None, 1, None, 0, None, None, 0, None) == L.DOT_EINVAL

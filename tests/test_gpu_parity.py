@@ -143,9 +143,9 @@ def test_solve_mixed_reaches_fp64_accuracy(dotlib, dev, name):
         op.pals_mua(pals, th)
         rhs = np.hstack([ref["BW"], ref["CV"]])
         res = op.solve(torch.tensor(rhs, device=dev), rtol=1e-10, precision=dotlib.DOT_MIXED,
-                       inner_rtol=1e-4)
+                       inner_rtol=0.1)
         X = res.x.cpu().numpy()
-    assert res.converged and res.outer >= 2
+    assert res.converged and res.outer >= 1
     true_rel = osol.relative_residuals(ref["A"], X, rhs)
     assert np.all(true_rel <= 1e-10), true_rel.max()
     Xd = np.hstack([ref["U"], ref["Z"]])
