@@ -87,7 +87,8 @@ def main():
     # synthetic data: all sources at theta_true, 0.1% relative noise
     op.pals_mua(pals, th_true)
     B = op.form_rhs(wl.src_cells, torch.eye(cfg.n_s, dtype=torch.float64, device=dev))
-    full = op.solve(B, rtol=1e-10, precision=L.DOT_MIXED)
+    # binary64 solves here, so the binary32 pass kernels run only in the timed workload
+    full = op.solve(B, rtol=1e-10, precision=L.DOT_FP64)
     M_true = full.x.cpu().numpy()[wl.det_cells, :]
     data = torch.tensor(M_true * (1.0 + cfg.noise * wl.xi), device=dev)
     DW = dl.gemm(data, W)

@@ -33,11 +33,35 @@
 
 namespace dot {
 
-constexpr int TX = 64;
-constexpr int TY = 8;
+// Launch geometry (compile-time; the defaults are the tuned values)
+#ifndef DOT_TY
+#define DOT_TY 4
+#endif
+#ifndef DOT_RG64
+#define DOT_RG64 4
+#endif
+#ifndef DOT_RG32
+#define DOT_RG32 4
+#endif
+#ifndef DOT_ZWANT
+#define DOT_ZWANT 2048
+#endif
+#ifndef DOT_ZMIN
+#define DOT_ZMIN 8
+#endif
+constexpr int TX = 64;              // one wave per x row
+constexpr int TY = DOT_TY;          // rows per tile
 constexpr int NT = TX * TY;
-constexpr int RG = 4;
 constexpr int NHALO = 2 * TX + 2 * TY;
+constexpr int RG = DOT_RG64;        // columns per block, binary64 sweeps and elementwise passes
+template <typename T>
+struct ColsPerBlock {
+  static constexpr int value = DOT_RG64;
+};
+template <>
+struct ColsPerBlock<float> {
+  static constexpr int value = DOT_RG32;
+};
 
 enum SweepMode { M_APPLY = 0, M_TRUE = 1, M_PCG1 = 2, M_PCG2 = 3, M_RESID = 4 };
 enum EltMode { E_INIT = 0, E_REPLACE = 1, E_FOLD = 2, E_UNSCALE = 3 };
@@ -62,10 +86,11 @@ enum { FLAG_BREAKDOWN = 1, FLAG_NONFINITE = 2 };
 struct Geom {
   int nx, ny, nz;
   int64_t nxy, N;
-  int tiles_x, ntiles, zc, nzc, ngrp, k;
-  int nblk_col;  // ntiles * nzc
-  int nblocks;   // ntiles * nzc * ngrp
+  int tiles_x, ntiles, zc, nzc, k;
+  int nblk_col;  // ntiles * nzc: partial slots per column
 };
+
+__host__ __device__ inline int n_groups(const Geom& G, int rg) { return (G.k + rg - 1) / rg; }
 
 struct ColState {
   double* rho;       // r.z of the current iteration
@@ -92,9 +117,8 @@ struct SweepArgs {
   const double* sd;    // sqrt(diag)
   const int* active;   // per column, NULL = all
   const double* coef;  // beta (PCG1), alpha (PCG2)
-  int first;           // PCG1: first iteration, p_old ignored
   const T* in0;        // APPLY/TRUE: x; PCG1: r; PCG2: p; RESID: x^
-  const T* in1;        // PCG1: p_old
+  const T* in1;        // PCG1: p_old (zero before the first iteration)
   const double* b;     // TRUE/RESID: right-hand side
   T* out0;             // APPLY: y; PCG1: p_new; PCG2: x (in place); RESID: r64
   T* out1;             // PCG2: r (in place)
@@ -108,6 +132,31 @@ __device__ __forceinline__ int remap_block(int L, int total) {
   return xcd * per + min(xcd, rem) + idx;
 }
 
+// Logical block -> (tile, z chunk, column group).  The column group varies
+// fastest: the blocks of all groups of one tile and z chunk are neighbours in
+// the logical order, so they run together on one XCD and share that tile's
+// coefficient and halo cache lines in its L2.
+#ifndef DOT_HALO_UNCOND
+#define DOT_HALO_UNCOND 1
+#endif
+#ifndef DOT_GROUP_FASTEST
+#define DOT_GROUP_FASTEST 1
+#endif
+__device__ __forceinline__ void block_coords(int logical, const Geom& G, int ngroups, int* tile,
+                                             int* zci, int* grp) {
+#if DOT_GROUP_FASTEST
+  *grp = logical % ngroups;
+  const int rest = logical / ngroups;
+  *tile = rest % G.ntiles;
+  *zci = rest / G.ntiles;
+#else
+  *tile = logical % G.ntiles;
+  const int rest = logical / G.ntiles;
+  *zci = rest % G.nzc;
+  *grp = rest / G.nzc;
+#endif
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -116,6 +165,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Block reduction of acc[RG][2] over NT threads into the per-block partial
 // slots.  Deterministic: fixed shuffle tree, then waves summed in order.
+template <int RG>
 __device__ __forceinline__ void block_partials(double (&acc)[RG][2], const Geom& G, int grp,
                                                int slot, double* partial) {
   __shared__ double red[TY][RG][2];
@@ -140,35 +190,60 @@ __device__ __forceinline__ void block_partials(double (&acc)[RG][2], const Geom&
   }
 }
 
+// Load of element c (32-bit byte offset) from a block-uniform column base.
+template <typename T>
+__device__ __forceinline__ T ld(const T* base, uint32_t c) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + c * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void st(T* base, uint32_t c, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + c * (uint32_t)sizeof(T)) = v;
+}
+
 template <int MODE, typename T>
 __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs<T> a) {
+  constexpr int RG = ColsPerBlock<T>::value;
+  // pass 1 stages p = r + beta p_old: two raw loads per staged value, combined
+  // only where the value is consumed so that no load is waited for early
+  constexpr bool TWO = MODE == M_PCG1;
+  const int ngroups = (a.G.k + RG - 1) / RG;
   // two LDS planes: plane z is written to sm[(z - z0) & 1] while the other
   // buffer may still be read by slower waves of plane z - 1, so one barrier
   // per plane suffices
   __shared__ T sm[2][RG][TY + 2][TX + 2];
   const Geom& G = a.G;
-  const int logical = remap_block((int)blockIdx.x, G.nblocks);
-  const int tile = logical % G.ntiles;
-  const int rest = logical / G.ntiles;
-  const int zci = rest % G.nzc;
-  const int grp = rest / G.nzc;
+  const int logical = remap_block((int)blockIdx.x, (int)gridDim.x);
+  int tile, zci, grp;
+  block_coords(logical, G, ngroups, &tile, &zci, &grp);
   const int slot = tile + G.ntiles * zci;
   const int x0 = (tile % G.tiles_x) * TX, y0 = (tile / G.tiles_x) * TY;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int x = x0 + tx, y = y0 + ty;
   const bool in = x < G.nx && y < G.ny;
   const int z0 = zci * G.zc, z1 = min(G.nz, z0 + G.zc);
+  const uint32_t nxy = (uint32_t)G.nxy;
 
+  // per-column state; the column base pointers are block-uniform, so cell
+  // offsets stay 32-bit
   bool act[RG];
-  int col[RG];
-  double cf[RG];
+  T cf[RG];
+  const T* in0[RG];
+  const T* in1[RG];
+  T* out0[RG];
+  T* out1[RG];
+  const double* bcol[RG];
   bool any = false;
 #pragma unroll
   for (int r = 0; r < RG; ++r) {
     const int j = grp * RG + r;
-    col[r] = j;
     act[r] = j < G.k && (a.active == nullptr || a.active[j] != 0);
-    cf[r] = (act[r] && a.coef) ? a.coef[j] : 0.0;
+    cf[r] = (act[r] && a.coef) ? (T)a.coef[j] : T(0);
+    const int64_t off = G.N * (int64_t)(j < G.k ? j : 0);
+    in0[r] = a.in0 + off;
+    in1[r] = TWO ? a.in1 + off : nullptr;
+    out0[r] = a.out0 ? a.out0 + off : nullptr;
+    out1[r] = a.out1 ? a.out1 + off : nullptr;
+    bcol[r] = a.b ? a.b + off : nullptr;
     any |= act[r];
   }
   if (!any) return;  // uniform over the block
@@ -178,17 +253,6 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs<T> a) {
     for (int r = 0; r < RG; ++r) n += act[r] ? 1 : 0;
     atomicAdd(a.prof_cols, (unsigned long long)n);
   }
-
-  auto stage = [&](int64_t c, int r) -> T {
-    const int64_t o = c + G.N * (int64_t)col[r];
-    if constexpr (MODE == M_PCG1) {
-      T v = a.in0[o];
-      if (!a.first) v += (T)cf[r] * a.in1[o];
-      return v;
-    } else {
-      return a.in0[o];
-    }
-  };
 
   // halo slot owned by this thread (if any)
   int hx = -1, hy = -1, hsy = 0, hsx = 0;
@@ -206,96 +270,144 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs<T> a) {
     }
   }
   const bool hin = hx >= 0 && hx < G.nx && hy >= 0 && hy < G.ny;
-  const int64_t hbase = hin ? (hx + (int64_t)G.nx * hy) : 0;
-  const int64_t base = in ? (x + (int64_t)G.nx * y) : 0;
+  // clamped cell indices: loads are unconditional and always in bounds,
+  // results of out-of-domain cells are discarded
+  const uint32_t hbase = hin ? (uint32_t)(hx + G.nx * hy) : 0u;
+  const uint32_t base = in ? (uint32_t)(x + G.nx * y) : 0u;
+  const uint32_t nx = (uint32_t)G.nx;
 
-  T vm[RG], vc[RG], vp[RG], hv[RG];
+  T vm[RG], vc[RG];        // staged values of planes z-1 and z
+  T pr0[RG], pr1[RG];      // raw loads of the own cell, plane z+1
+  T hr0[RG], hr1[RG];      // raw loads of the halo cell, next plane
   double acc[RG][2];
 #pragma unroll
   for (int r = 0; r < RG; ++r) {
     acc[r][0] = acc[r][1] = 0.0;
-    vm[r] = vc[r] = vp[r] = hv[r] = T(0);
-    if (in && act[r]) {
-      if (z0 > 0) vm[r] = stage(base + (int64_t)(z0 - 1) * G.nxy, r);
-      vc[r] = stage(base + (int64_t)z0 * G.nxy, r);
+    const uint32_t cm = base + (uint32_t)(z0 > 0 ? z0 - 1 : z0) * nxy;
+    const uint32_t c0 = base + (uint32_t)z0 * nxy;
+    const uint32_t h0 = hbase + (uint32_t)z0 * nxy;
+    T m0 = ld(in0[r], cm), q0 = ld(in0[r], c0), g0 = ld(in0[r], h0);
+    if constexpr (TWO) {
+      m0 += cf[r] * ld(in1[r], cm);
+      q0 += cf[r] * ld(in1[r], c0);
+      hr1[r] = ld(in1[r], h0);
+    } else {
+      hr1[r] = T(0);
     }
-    if (hthread && hin && act[r]) hv[r] = stage(hbase + (int64_t)z0 * G.nxy, r);
+    hr0[r] = g0;
+    vm[r] = (z0 > 0 && in) ? m0 : T(0);
+    vc[r] = in ? q0 : T(0);
   }
-  T cD = T(0);
-  if (in && z0 > 0) cD = a.cz[base + (int64_t)(z0 - 1) * G.nxy];
+  T cD = (z0 > 0) ? ld(a.cz, base + (uint32_t)(z0 - 1) * nxy) : T(0);
 
   for (int z = z0; z < z1; ++z) {
     const int buf = (z - z0) & 1;
-    const int64_t c = base + (int64_t)z * G.nxy;
+    const uint32_t c = base + (uint32_t)z * nxy;
     const bool has_up = z + 1 < G.nz;
-    // plane z into LDS (own values and the halo prefetched one plane ago)
+    const uint32_t cu = has_up ? c + nxy : c;
+    // plane z into LDS: own values and the halo loaded one plane ago
 #pragma unroll
     for (int r = 0; r < RG; ++r) sm[buf][r][ty + 1][tx + 1] = vc[r];
     if (hthread) {
 #pragma unroll
-      for (int r = 0; r < RG; ++r) sm[buf][r][hsy][hsx] = hv[r];
-    }
-    // global loads issued before the barrier: own plane z+1, halo of plane
-    // z+1, coefficients and per-cell operands of plane z
-#pragma unroll
-    for (int r = 0; r < RG; ++r) vp[r] = (in && act[r] && has_up) ? stage(c + G.nxy, r) : T(0);
-    if (hthread && z + 1 < z1) {
-      const int64_t hc = hbase + (int64_t)(z + 1) * G.nxy;
-#pragma unroll
-      for (int r = 0; r < RG; ++r) hv[r] = (hin && act[r]) ? stage(hc, r) : T(0);
-    }
-    T cE = T(0), cW = T(0), cN = T(0), cS = T(0), cU = T(0), dd = T(1);
-    double sdc = 1.0;
-    T o0[RG], o1[RG];
-    double bo[RG];
-    if (in) {
-      cE = a.cx[c];
-      cW = x > 0 ? a.cx[c - 1] : T(0);
-      cN = a.cy[c];
-      cS = y > 0 ? a.cy[c - G.nx] : T(0);
-      cU = a.cz[c];
-      if constexpr (MODE == M_APPLY || MODE == M_TRUE) dd = (T)a.diag[c];
-      if constexpr (MODE == M_PCG2 || MODE == M_RESID) sdc = a.sd[c];
-#pragma unroll
       for (int r = 0; r < RG; ++r) {
-        const int64_t o = c + G.N * (int64_t)col[r];
-        if constexpr (MODE == M_PCG2) {
-          o0[r] = act[r] ? a.out0[o] : T(0);
-          o1[r] = act[r] ? a.out1[o] : T(0);
-        }
-        if constexpr (MODE == M_RESID || MODE == M_TRUE) bo[r] = act[r] ? a.b[o] : 0.0;
+        T h = hr0[r];
+        if constexpr (TWO) h += cf[r] * hr1[r];
+        sm[buf][r][hsy][hsx] = hin ? h : T(0);
       }
     }
-    __syncthreads();
-    if (in) {
+    // loads issued before the barrier, in the order they are needed: own
+    // plane z+1, coefficients and per-cell operands of plane z (used after
+    // the barrier), then the halo of plane z+1 last, which stays in flight
+    // until the next plane's LDS write (vmcnt retires in order)
+#pragma unroll
+    for (int r = 0; r < RG; ++r) {
+      pr0[r] = ld(in0[r], cu);
+      if constexpr (TWO) pr1[r] = ld(in1[r], cu);
+    }
+    // every load is unconditional (clamped index, result selected) so the
+    // compiler's in-order vmcnt bookkeeping stays exact across the loop body
+    const bool has_w = in && x > 0, has_s = in && y > 0;
+    const T cE = ld(a.cx, c);
+    const T cWl = ld(a.cx, has_w ? c - 1 : c);
+    const T cN = ld(a.cy, c);
+    const T cSl = ld(a.cy, has_s ? c - nx : c);
+    const T cU = ld(a.cz, c);
+    const T cW = has_w ? cWl : T(0);
+    const T cS = has_s ? cSl : T(0);
+    T dd = T(1);
+    double sdc = 1.0;
+    if constexpr (MODE == M_APPLY || MODE == M_TRUE) dd = (T)ld(a.diag, c);
+    if constexpr (MODE == M_PCG2 || MODE == M_RESID) sdc = ld(a.sd, c);
+    T o0[RG], o1[RG];
+    double bo[RG];
+#pragma unroll
+    for (int r = 0; r < RG; ++r) {
+      if constexpr (MODE == M_PCG2) {
+        o0[r] = ld((const T*)out0[r], c);
+        o1[r] = ld((const T*)out1[r], c);
+      }
+      if constexpr (MODE == M_RESID || MODE == M_TRUE) bo[r] = ld(bcol[r], c);
+    }
+#if DOT_HALO_UNCOND
+    {
+      const uint32_t hc = hbase + (uint32_t)min(z + 1, G.nz - 1) * nxy;
 #pragma unroll
       for (int r = 0; r < RG; ++r) {
-        if (!act[r]) continue;
-        const T vW = sm[buf][r][ty + 1][tx], vE = sm[buf][r][ty + 1][tx + 2];
-        const T vS = sm[buf][r][ty][tx + 1], vN = sm[buf][r][ty + 2][tx + 1];
-        const T Av = dd * vc[r] - cW * vW - cE * vE - cS * vS - cN * vN - cD * vm[r] - cU * vp[r];
-        const int64_t o = c + G.N * (int64_t)col[r];
-        if constexpr (MODE == M_APPLY) {
-          a.out0[o] = Av;
-        } else if constexpr (MODE == M_TRUE) {
-          const double rr = bo[r] - (double)Av;
-          acc[r][0] += rr * rr;
-        } else if constexpr (MODE == M_PCG1) {
-          a.out0[o] = vc[r];
+        hr0[r] = ld(in0[r], hc);
+        if constexpr (TWO) hr1[r] = ld(in1[r], hc);
+      }
+    }
+#else
+    if (z + 1 < z1) {
+      const uint32_t hc = hbase + (uint32_t)(z + 1) * nxy;
+#pragma unroll
+      for (int r = 0; r < RG; ++r) {
+        hr0[r] = ld(in0[r], hc);
+        if constexpr (TWO) hr1[r] = ld(in1[r], hc);
+      }
+    }
+#endif
+    __syncthreads();
+    T vp[RG];
+#pragma unroll
+    for (int r = 0; r < RG; ++r) {
+      T v = pr0[r];
+      if constexpr (TWO) v += cf[r] * pr1[r];
+      vp[r] = (has_up && in) ? v : T(0);
+    }
+#pragma unroll
+    for (int r = 0; r < RG; ++r) {
+      if (!act[r]) continue;  // block-uniform
+      const T vW = sm[buf][r][ty + 1][tx], vE = sm[buf][r][ty + 1][tx + 2];
+      const T vS = sm[buf][r][ty][tx + 1], vN = sm[buf][r][ty + 2][tx + 1];
+      const T Av = dd * vc[r] - cW * vW - cE * vE - cS * vS - cN * vN - cD * vm[r] - cU * vp[r];
+      if constexpr (MODE == M_APPLY) {
+        if (in) st(out0[r], c, Av);
+      } else if constexpr (MODE == M_TRUE) {
+        const double rr = bo[r] - (double)Av;
+        if (in) acc[r][0] += rr * rr;
+      } else if constexpr (MODE == M_PCG1) {
+        if (in) {
+          st(out0[r], c, vc[r]);
           acc[r][0] += (double)vc[r] * (double)Av;
-        } else if constexpr (MODE == M_PCG2) {
-          const T al = (T)cf[r];
-          const T xn = o0[r] + al * vc[r];
-          const T rn = o1[r] - al * Av;
-          a.out0[o] = xn;
-          a.out1[o] = rn;
+        }
+      } else if constexpr (MODE == M_PCG2) {
+        const T al = cf[r];
+        const T xn = o0[r] + al * vc[r];
+        const T rn = o1[r] - al * Av;
+        if (in) {
+          st(out0[r], c, xn);
+          st(out1[r], c, rn);
           const double rd = (double)rn;
           acc[r][0] += rd * rd;
           const double t = sdc * rd;
           acc[r][1] += t * t;
-        } else if constexpr (MODE == M_RESID) {
-          const double rr = bo[r] / sdc - (double)Av;
-          a.out0[o] = (T)rr;
+        }
+      } else if constexpr (MODE == M_RESID) {
+        const double rr = bo[r] / sdc - (double)Av;
+        if (in) {
+          st(out0[r], c, (T)rr);
           acc[r][0] += rr * rr;
           const double t = sdc * rr;
           acc[r][1] += t * t;
@@ -309,7 +421,7 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs<T> a) {
       vc[r] = vp[r];
     }
   }
-  if constexpr (MODE != M_APPLY) block_partials(acc, G, grp, slot, a.partial);
+  if constexpr (MODE != M_APPLY) block_partials<RG>(acc, G, grp, slot, a.partial);
 }
 
 // Elementwise passes on the same block decomposition (same partial slots).
@@ -323,17 +435,18 @@ struct EltArgs {
   double* r64;          // binary64 residual
   float* r32;           // inner residual
   float* d32;           // inner correction
+  double* p64z;         // INIT: binary64 direction buffer to clear (or NULL)
+  float* p32z;          // INIT: binary32 direction buffer to clear (or NULL)
   double* partial;
 };
 
 template <int MODE>
 __global__ __launch_bounds__(NT) void elt_kernel(EltArgs a) {
   const Geom& G = a.G;
-  const int logical = remap_block((int)blockIdx.x, G.nblocks);
-  const int tile = logical % G.ntiles;
-  const int rest = logical / G.ntiles;
-  const int zci = rest % G.nzc;
-  const int grp = rest / G.nzc;
+  const int ngroups = (G.k + RG - 1) / RG;
+  const int logical = remap_block((int)blockIdx.x, (int)gridDim.x);
+  int tile, zci, grp;
+  block_coords(logical, G, ngroups, &tile, &zci, &grp);
   const int slot = tile + G.ntiles * zci;
   const int x = (tile % G.tiles_x) * TX + (threadIdx.x & 63);
   const int y = (tile / G.tiles_x) * TY + (threadIdx.x >> 6);
@@ -369,6 +482,8 @@ __global__ __launch_bounds__(NT) void elt_kernel(EltArgs a) {
           a.xh[o] = 0.0;
           a.r64[o] = rv;
           if (a.d32) a.d32[o] = 0.0f;
+          if (a.p64z) a.p64z[o] = 0.0;
+          if (a.p32z) a.p32z[o] = 0.0f;
           acc[r][0] += rv * rv;
           acc[r][1] += bv * bv;
         } else if constexpr (MODE == E_REPLACE) {
@@ -387,7 +502,7 @@ __global__ __launch_bounds__(NT) void elt_kernel(EltArgs a) {
       }
     }
   }
-  if constexpr (MODE == E_INIT || MODE == E_REPLACE) block_partials(acc, G, grp, slot, a.partial);
+  if constexpr (MODE == E_INIT || MODE == E_REPLACE) block_partials<RG>(acc, G, grp, slot, a.partial);
 }
 
 // One block per column: sum that column's per-block partials in fixed order
@@ -535,17 +650,17 @@ static Geom make_geom(const GridDims& g, int k) {
   G.tiles_x = (g.nx + TX - 1) / TX;
   const int tiles_y = (g.ny + TY - 1) / TY;
   G.ntiles = G.tiles_x * tiles_y;
-  G.ngrp = (k + RG - 1) / RG;
-  // z chunk: aim for >= 2048 blocks, chunks of at least 8 planes
-  const int64_t want = 2048;
-  const int64_t per_z = (int64_t)G.ntiles * G.ngrp;
+  // z chunk: aim for DOT_ZWANT blocks of DOT_RG64 columns, chunks of at least
+  // DOT_ZMIN planes.  The chunking does not depend on the column group size,
+  // so every kernel of a solve shares the partial slots.
+  const int64_t want = DOT_ZWANT;
+  const int64_t per_z = (int64_t)G.ntiles * n_groups(G, DOT_RG64);
   int nzc = (int)std::min<int64_t>(g.nz, std::max<int64_t>(1, (want + per_z - 1) / per_z));
   int zc = (g.nz + nzc - 1) / nzc;
-  zc = std::max(zc, std::min(8, g.nz));
+  zc = std::max(zc, std::min(DOT_ZMIN, g.nz));
   G.zc = zc;
   G.nzc = (g.nz + zc - 1) / zc;
   G.nblk_col = G.ntiles * G.nzc;
-  G.nblocks = G.nblk_col * G.ngrp;
   return G;
 }
 
@@ -663,14 +778,15 @@ template <int MODE, typename T>
 static int launch_sweep(dot_op* op, SweepArgs<T> a, hipStream_t s, int kind = -1) {
   hipEvent_t e0, e1;
   DOT_TRY(prof_begin(op, kind, s, &e0, &e1, &a.prof_cols));
-  hipLaunchKernelGGL((sweep_kernel<MODE, T>), dim3(a.G.nblocks), dim3(NT), 0, s, a);
+  const int blocks = a.G.nblk_col * n_groups(a.G, ColsPerBlock<T>::value);
+  hipLaunchKernelGGL((sweep_kernel<MODE, T>), dim3(blocks), dim3(NT), 0, s, a);
   DOT_LAUNCH_CHECK();
   return prof_end(op, kind, s, e0, e1);
 }
 
 template <int MODE>
 static int launch_elt(const EltArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((elt_kernel<MODE>), dim3(a.G.nblocks), dim3(NT), 0, s, a);
+  hipLaunchKernelGGL((elt_kernel<MODE>), dim3(a.G.nblk_col * n_groups(a.G, RG)), dim3(NT), 0, s, a);
   DOT_LAUNCH_CHECK();
   return DOT_OK;
 }
@@ -758,6 +874,7 @@ static int solve_fp64(dot_op* op, const Geom& G, const Workspace& ws, const doub
   e.b = rhs;
   e.xh = x;
   e.r64 = ws.r64;
+  e.p64z = ws.p64[0];
   e.partial = ws.partial;
   DOT_TRY(launch_elt<E_INIT>(e, s));
   DOT_TRY(launch_fin(F_INIT, G, ws, nullptr, o.rtol, 0.0, s));
@@ -769,7 +886,6 @@ static int solve_fp64(dot_op* op, const Geom& G, const Workspace& ws, const doub
     SweepArgs<double> p1 = base_args64(op, G);
     p1.active = ws.st.active;
     p1.coef = ws.st.beta;
-    p1.first = it == 0;
     p1.in0 = ws.r64;
     p1.in1 = ws.p64[cur];
     p1.out0 = ws.p64[cur ^ 1];
@@ -814,7 +930,9 @@ static int solve_mixed(dot_op* op, const Geom& G, const Workspace& ws, const dou
   e.d32 = ws.d32;
   e.scale = ws.st.scale;
   e.partial = ws.partial;
-  DOT_TRY(launch_elt<E_INIT>(e, s));
+  EltArgs e0 = e;
+  e0.p32z = ws.p32[0];
+  DOT_TRY(launch_elt<E_INIT>(e0, s));
   DOT_TRY(launch_fin(F_INIT, G, ws, nullptr, o.rtol, delta, s));
   EltArgs er = e;
   er.mask = ws.st.active;
@@ -827,7 +945,6 @@ static int solve_mixed(dot_op* op, const Geom& G, const Workspace& ws, const dou
     SweepArgs<float> p1 = base_args32(op, G);
     p1.active = ws.st.active;
     p1.coef = ws.st.beta;
-    p1.first = it == 0;
     p1.in0 = ws.r32;
     p1.in1 = ws.p32[cur];
     p1.out0 = ws.p32[cur ^ 1];
