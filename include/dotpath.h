@@ -68,6 +68,7 @@ extern "C" {
 /* Jacobian precision */
 #define DOT_JAC_FP64 0        /* binary64 products and sums */
 #define DOT_JAC_SPLIT_BF16 1  /* hi/lo bfloat16 operands, 3 MFMA products, fp32 accumulate */
+#define DOT_JAC_SPLIT_BF16X3 2  /* hi/mid/lo bfloat16 operands, 6 MFMA products */
 
 /* PaLS parameter activity bits */
 #define DOT_ACT_ALPHA 1u
@@ -209,8 +210,11 @@ size_t dot_jacobian_workspace_bytes(const dot_op* op, int l_s, int l_d);
  * h^d d mu_c / d p_k, for the parameters of the last dot_pals_mua call
  * (n_p = m0 x number of active bits; parameter k = rbf * n_act + local
  * index in the order alpha, beta, chi_1..chi_d).  Only cells where
- * d mu / d p_k is nonzero are visited.  precision: DOT_JAC_FP64 or
- * DOT_JAC_SPLIT_BF16.  U_dev: N x l_s, Z_dev: N x l_d.
+ * d mu / d p_k is nonzero are visited.  precision: DOT_JAC_FP64 (binary64
+ * throughout), DOT_JAC_SPLIT_BF16 or DOT_JAC_SPLIT_BF16X3 (operands rounded to
+ * binary32 and split into 2 or 3 bfloat16 parts, products on the matrix
+ * cores with binary32 accumulation over 256-cell runs, binary64 sums across
+ * runs and chunks).  U_dev: N x l_s, Z_dev: N x l_d, l_s <= 1024.
  */
 int dot_jacobian(dot_op* op, int l_s, const double* U_dev, int l_d, const double* Z_dev,
                  int precision, double* Js_dev, void* work_dev, size_t work_bytes, void* stream);

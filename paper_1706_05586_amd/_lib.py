@@ -26,6 +26,7 @@ DOT_FP64 = 0
 DOT_MIXED = 1
 DOT_JAC_FP64 = 0
 DOT_JAC_SPLIT_BF16 = 1
+DOT_JAC_SPLIT_BF16X3 = 2
 DOT_ACT_ALPHA = 1
 DOT_ACT_BETA = 2
 DOT_ACT_CHI = 4

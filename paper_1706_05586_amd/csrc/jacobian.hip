@@ -138,6 +138,165 @@ __global__ __launch_bounds__(JT) void jac_chunk_fp64_kernel(
   }
 }
 
+// ----------------------------------------------------------------------
+// Split-bfloat16 MFMA contraction of one chunk.
+//
+// Per chunk the contraction is a dense GEMM:  P[i, n] = sum_c U[c,i] B[c,n],
+// B[c, j + l_d a] = Z[c,j] G[c,a],  i < l_s, n < l_d na, c over the chunk.
+// Operands are rounded to binary32 and split into TERMS bfloat16 parts
+// (x = hi + lo, or hi + mid + lo); the part products of total order at most
+// TERMS - 1 are issued as v_mfma_f32_16x16x32_bf16 (3 products for two parts,
+// 6 for three; the dropped ones are below the representation error), accumulated in binary32 inside the MFMA and flushed
+// into binary64 registers every JFLUSH K-steps of 32 cells.  Block = 8
+// waves; output tiles of 16 x 16 are dealt round-robin to the waves.
+// Operand layout of the instruction (lane l): A row l%16 with 8 consecutive
+// k, B column l%16 with the same 8 k, result rows 4(l/16)..+3, column l%16.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int MK = 32;          // cells per MFMA K-step
+constexpr int MKP = MK + 8;     // padded LDS row (bf16 elements), 80 bytes
+constexpr int MT_THREADS = 512;
+constexpr int JFLUSH = 8;       // K-steps between binary64 flushes (256 cells)
+
+template <int TERMS>
+__device__ __forceinline__ void split_bf16(float x, __bf16* parts) {
+  const __bf16 hi = (__bf16)x;
+  float rem = x - (float)hi;
+  parts[0] = hi;
+  if constexpr (TERMS == 2) {
+    parts[1] = (__bf16)rem;
+  } else {
+    const __bf16 mid = (__bf16)rem;
+    parts[1] = mid;
+    parts[2] = (__bf16)(rem - (float)mid);
+  }
+}
+
+template <int TERMS, int QMAX>
+__global__ __launch_bounds__(MT_THREADS) void jac_chunk_mfma_kernel(
+    GridDims g, JacParams P, const double* __restrict__ theta, const double* __restrict__ phi,
+    const int32_t* __restrict__ pair_cell, const int64_t* __restrict__ chunk_begin,
+    const int32_t* __restrict__ chunk_rbf, int l_s, const double* __restrict__ U, int l_d,
+    const double* __restrict__ Z, double* __restrict__ partial, int ncp) {
+  // ncp: B columns held in LDS (a multiple of 16, >= the padded tile span);
+  // tiles t = wave + 8 q (q < QMAX) cover rows mt = t % MT and columns
+  // 16 (t / MT) .. +15, zero-padded beyond l_s rows / l_d na columns
+  extern __shared__ __attribute__((aligned(16))) unsigned char jsm[];
+  const int ch = blockIdx.x;
+  const int64_t b0 = chunk_begin[ch], b1 = chunk_begin[ch + 1];
+  const double* th = theta + (int64_t)chunk_rbf[ch] * P.stride;
+  const int na = P.n_act;
+  const int lsld = l_s * l_d;
+  const int ncol = l_d * na;
+  const int MT = (l_s + 15) / 16;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __bf16* sA = reinterpret_cast<__bf16*>(jsm);            // [TERMS][MT*16][MKP]
+  __bf16* sB = sA + TERMS * MT * 16 * MKP;                // [TERMS][ncp][MKP]
+  double* sZ = reinterpret_cast<double*>(sB + TERMS * ncp * MKP);  // [MK][l_d]
+  double* sG = sZ + MK * l_d;                             // [MK][na]
+  double* out = partial + (int64_t)ch * lsld * na;
+
+  // per tile: LDS fragment offsets and the output offset of element e = 0
+  int aoff[QMAX], boff[QMAX], ooff[QMAX], orow[QMAX], ocol[QMAX];
+  const int kofs = 8 * (lane >> 4);
+#pragma unroll
+  for (int q = 0; q < QMAX; ++q) {
+    const int t = wave + 8 * q;
+    const int mt = t % MT, nt = t / MT;
+    aoff[q] = (mt * 16 + (lane & 15)) * MKP + kofs;
+    boff[q] = (nt * 16 + (lane & 15)) * MKP + kofs;
+    const int i0 = mt * 16 + 4 * (lane >> 4);
+    const int n = nt * 16 + (lane & 15);
+    orow[q] = i0;
+    ocol[q] = n;
+    ooff[q] = n < ncol ? (n % l_d) + l_d * i0 + lsld * (n / l_d) : 0;
+  }
+  f32x4 acc[QMAX];
+#pragma unroll
+  for (int q = 0; q < QMAX; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+  bool first = true;
+  auto flush = [&]() {
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (orow[q] + e < l_s && ocol[q] < ncol) {
+          double* o = out + ooff[q] + l_d * e;
+          *o = first ? (double)acc[q][e] : *o + (double)acc[q][e];
+        }
+      }
+      acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    first = false;
+  };
+
+  int kstep = 0;
+  for (int64_t cb = b0; cb < b1; cb += MK, ++kstep) {
+    const int nb = (int)min<int64_t>(MK, b1 - cb);
+    __syncthreads();  // previous K-step's MFMA reads are done
+    // U -> A parts (rows beyond l_s and cells beyond nb are zero)
+    for (int t = threadIdx.x; t < MT * 16 * MK; t += MT_THREADS) {
+      const int cc = t % MK, i = t / MK;
+      float v = 0.f;
+      if (cc < nb && i < l_s) v = (float)U[pair_cell[cb + cc] + P.N * (int64_t)i];
+      __bf16 parts[TERMS];
+      split_bf16<TERMS>(v, parts);
+#pragma unroll
+      for (int q = 0; q < TERMS; ++q) sA[(q * MT * 16 + i) * MKP + cc] = parts[q];
+    }
+    // Z staging (binary64) and G of each cell
+    for (int t = threadIdx.x; t < MK * l_d; t += MT_THREADS) {
+      const int cc = t % MK, j = t / MK;
+      sZ[cc * l_d + j] = cc < nb ? Z[pair_cell[cb + cc] + P.N * (int64_t)j] : 0.0;
+    }
+    if (threadIdx.x < MK) {
+      double d[5] = {0, 0, 0, 0, 0};
+      double w = 0.0;
+      if ((int)threadIdx.x < nb) {
+        const int64_t c = pair_cell[cb + threadIdx.x];
+        double x0, x1, x2;
+        cell_xyz(g, c, &x0, &x1, &x2);
+        rbf_dphi(P, th, x0, x1, x2, d);
+        w = band_weight(P, phi[c]);
+      }
+      for (int a = 0; a < na; ++a) sG[threadIdx.x * na + a] = P.hd * (w * d[a]);
+    }
+    __syncthreads();
+    // B parts: B[c, n] = Z[c, j] G[c, a] for n < ncol, zero up to ncp
+    for (int t = threadIdx.x; t < ncp * MK; t += MT_THREADS) {
+      const int cc = t % MK, n = t / MK;
+      float v = 0.f;
+      if (n < ncol) {
+        const int j = n % l_d, a = n / l_d;
+        v = (float)(sZ[cc * l_d + j] * sG[cc * na + a]);
+      }
+      __bf16 parts[TERMS];
+      split_bf16<TERMS>(v, parts);
+#pragma unroll
+      for (int q = 0; q < TERMS; ++q) sB[(q * ncp + n) * MKP + cc] = parts[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) {
+      bf16x8 fa[TERMS], fb[TERMS];
+#pragma unroll
+      for (int p = 0; p < TERMS; ++p) {
+        fa[p] = *reinterpret_cast<const bf16x8*>(&sA[p * MT * 16 * MKP + aoff[q]]);
+        fb[p] = *reinterpret_cast<const bf16x8*>(&sB[p * ncp * MKP + boff[q]]);
+      }
+#pragma unroll
+      for (int pa = 0; pa < TERMS; ++pa)
+#pragma unroll
+        for (int pb = 0; pb < TERMS; ++pb)
+          if (pa + pb <= TERMS - 1)
+            acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[pa], fb[pb], acc[q], 0, 0, 0);
+    }
+    if ((kstep + 1) % JFLUSH == 0) flush();
+  }
+  if (first || kstep % JFLUSH != 0) flush();
+}
+
 // Js[(j + l_d i) + l_s l_d (m na + a)] = - sum over chunks of RBF m.
 __global__ void jac_reduce_kernel(int m0, const int32_t* __restrict__ rbf_chunk0, int lsld, int na,
                                   const double* __restrict__ partial, double* __restrict__ Js) {
@@ -220,6 +379,12 @@ __global__ void grad_reduce_kernel(int m0, const int32_t* __restrict__ rbf_chunk
   gout[k] = -s;
 }
 
+#define DOT_TRY_J(...)             \
+  do {                             \
+    int rc_ = (__VA_ARGS__);       \
+    if (rc_ != DOT_OK) return rc_; \
+  } while (0)
+
 static int n_active_bits(unsigned act, int dim) {
   return ((act & DOT_ACT_ALPHA) ? 1 : 0) + ((act & DOT_ACT_BETA) ? 1 : 0) +
          ((act & DOT_ACT_CHI) ? dim : 0);
@@ -267,33 +432,73 @@ int dot_jacobian(dot_op* op, int l_s, const double* U_dev, int l_d, const double
   if (!op->have_pals) DOT_FAIL(DOT_EINVAL, "dot_pals_mua has not been called on this handle");
   if (l_s < 1 || l_d < 1) DOT_FAIL(DOT_EINVAL, "l_s and l_d must be >= 1");
   if (!U_dev || !Z_dev || !Js_dev) DOT_FAIL(DOT_EINVAL, "NULL argument");
-  if (precision != DOT_JAC_FP64 && precision != DOT_JAC_SPLIT_BF16)
-    DOT_FAIL(DOT_EINVAL, "precision must be DOT_JAC_FP64 or DOT_JAC_SPLIT_BF16");
+  if (precision != DOT_JAC_FP64 && precision != DOT_JAC_SPLIT_BF16 &&
+      precision != DOT_JAC_SPLIT_BF16X3)
+    DOT_FAIL(DOT_EINVAL, "precision must be DOT_JAC_FP64, DOT_JAC_SPLIT_BF16 or _BF16X3");
+  if (l_s > 1024) DOT_FAIL(DOT_EINVAL, "l_s must be <= 1024");
   const size_t need = jac_bytes(op, l_s, l_d);
   if (!work_dev || work_bytes < need)
     DOT_FAIL(DOT_ENOMEM, "workspace too small: need %zu bytes, got %zu", need, work_bytes);
   if ((size_t)JB * (l_s + l_d + 5) * sizeof(double) > 64 * 1024)
     DOT_FAIL(DOT_EINVAL, "l_s + l_d too large for the contraction kernel");
-  if (precision == DOT_JAC_SPLIT_BF16)
-    DOT_FAIL(DOT_EINVAL, "split-bf16 contraction not available in this build");
   hipStream_t s = as_stream(stream);
   const JacParams P = make_params(op);
   const int na = P.n_act;
   const int m0 = op->pals.m0;
   const int lsld = l_s * l_d;
   double* partial = (double*)work_dev;
-  if (op->n_chunks > 0) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  unsigned long long* cols = nullptr;
+  DOT_TRY_J(profile_begin(op, DOT_PROF_JACOBIAN, s, &e0, &e1, &cols));
+  if (op->n_chunks > 0 && precision == DOT_JAC_FP64) {
     const size_t shm = (size_t)JB * (l_s + l_d + na) * sizeof(double);
     hipLaunchKernelGGL(jac_chunk_fp64_kernel, dim3((unsigned)op->n_chunks), dim3(JT), shm, s, op->g,
                        P, op->theta, op->phi, op->pair_cell, op->chunk_begin, op->chunk_rbf, l_s,
                        U_dev, l_d, Z_dev, partial);
     DOT_LAUNCH_CHECK();
+  } else if (op->n_chunks > 0) {
+    const int terms = precision == DOT_JAC_SPLIT_BF16 ? 2 : 3;
+    const int MT = (l_s + 15) / 16, NT = (l_d * na + 15) / 16;
+    const int tiles = MT * NT;
+    if (tiles > 64) DOT_FAIL(DOT_EINVAL, "l_s * l_d * n_act too large for the split-bf16 kernel");
+    const int qmax = (tiles + 7) / 8;
+    // columns reached by the padded tiles t < 8 qmax
+    const int ncp = ((8 * qmax - 1) / MT + 1) * 16;
+    const size_t shm = (size_t)terms * (MT * 16 + ncp) * MKP * 2 +
+                       (size_t)MK * l_d * sizeof(double) + (size_t)MK * na * sizeof(double);
+    auto launch = [&](auto kern) -> int {
+      DOT_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)shm));
+      hipLaunchKernelGGL(kern, dim3((unsigned)op->n_chunks), dim3(MT_THREADS), shm, s, op->g, P,
+                         op->theta, op->phi, op->pair_cell, op->chunk_begin, op->chunk_rbf, l_s,
+                         U_dev, l_d, Z_dev, partial, ncp);
+      DOT_LAUNCH_CHECK();
+      return DOT_OK;
+    };
+    int rc = DOT_EINVAL;
+#define DOT_JAC_CASE(T, Q) \
+  case Q:                  \
+    rc = launch(jac_chunk_mfma_kernel<T, Q>); \
+    break;
+    if (terms == 2) {
+      switch (qmax) {
+        DOT_JAC_CASE(2, 1) DOT_JAC_CASE(2, 2) DOT_JAC_CASE(2, 3) DOT_JAC_CASE(2, 4)
+        DOT_JAC_CASE(2, 5) DOT_JAC_CASE(2, 6) DOT_JAC_CASE(2, 7) DOT_JAC_CASE(2, 8)
+      }
+    } else {
+      switch (qmax) {
+        DOT_JAC_CASE(3, 1) DOT_JAC_CASE(3, 2) DOT_JAC_CASE(3, 3) DOT_JAC_CASE(3, 4)
+        DOT_JAC_CASE(3, 5) DOT_JAC_CASE(3, 6) DOT_JAC_CASE(3, 7) DOT_JAC_CASE(3, 8)
+      }
+    }
+#undef DOT_JAC_CASE
+    if (rc) return rc;
   }
   dim3 grid((lsld * na + 255) / 256, m0);
   hipLaunchKernelGGL(jac_reduce_kernel, grid, dim3(256), 0, s, m0, op->rbf_chunk0, lsld, na,
                      partial, Js_dev);
   DOT_LAUNCH_CHECK();
-  return DOT_OK;
+  return profile_end(op, DOT_PROF_JACOBIAN, s, e0, e1);
 }
 
 int dot_grad_misfit(dot_op* op, int l_s, const double* U_dev, int l_d, const double* Z_dev,

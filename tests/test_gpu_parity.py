@@ -273,3 +273,24 @@ def test_gemm_matches_numpy(dotlib, dev):
                 Bb = B.T.copy() if tb else B
                 C = dotlib.gemm(torch.tensor(Aa, device=dev), torch.tensor(Bb, device=dev), ta, tb)
                 assert np.allclose(C.cpu().numpy(), A @ B, rtol=1e-13, atol=1e-13)
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_jacobian_split_bf16_error(dotlib, dev, name):
+    """Split-bfloat16 contraction against the oracle's binary64 loop nest on
+    identical fields: relative Frobenius error within the split's bound
+    (2 parts: 2^-16 per product, observed ~1e-6; 3 parts: binary32 level)."""
+    wl, prob, W, V, data, ref = case(name)
+    op, grid, pals, th = gpu_operator(dotlib, dev, wl)
+    with op:
+        op.pals_mua(pals, th)
+        U = torch.tensor(ref["U"], device=dev)
+        Z = torch.tensor(ref["Z"], device=dev)
+        J2 = op.jacobian(U, Z, dotlib.DOT_JAC_SPLIT_BF16).cpu().numpy()
+        J3 = op.jacobian(U, Z, dotlib.DOT_JAC_SPLIT_BF16X3).cpu().numpy()
+    Jr = ref["Js"]
+    e2 = np.linalg.norm(J2 - Jr) / np.linalg.norm(Jr)
+    e3 = np.linalg.norm(J3 - Jr) / np.linalg.norm(Jr)
+    print(f"{name}: split-bf16 rel err {e2:.3e}, 3-part {e3:.3e}")
+    assert e2 <= 2e-5
+    assert e3 <= 1e-6
