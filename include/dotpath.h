@@ -259,6 +259,69 @@ int dot_gemm(int transa, int transb, int m, int n, int kdim, double alpha, const
              int lda, const double* B_dev, int ldb, double beta, double* C_dev, int ldc,
              void* stream);
 
+/*
+ * Gram matrix of a tensor unfolding, without forming the unfolding.  T_dev
+ * is a dA x dB x dC tensor (first index fastest).  mode 0: G (dA x dA) =
+ * sum_{b,c} T[a,b,c] T[a',b,c]; mode 1: G (dB x dB) = sum_{a,c} T[a,b,c]
+ * T[a,b',c].  These are the J~ J~^T, K~ K~^T and L~ L~^T of Section 3.2
+ * (eqs. Jtilde, Ktilde, Ltilde): a column permutation of an unfolding does
+ * not change its Gram matrix or left singular vectors.
+ */
+size_t dot_mode_gram_workspace_bytes(int dA, int dB, int dC, int mode);
+int dot_mode_gram(int dA, int dB, int dC, const double* T_dev, int mode, double* G_dev,
+                  void* work_dev, size_t work_bytes, void* stream);
+
+/*
+ * Symmetric eigensolver (cyclic Jacobi): A_dev (n x n, lda) is not modified;
+ * w_dev receives the eigenvalues in descending order and V_dev (n x n, ldv)
+ * the orthonormal eigenvectors in the same order.  *sweeps_host (if not
+ * NULL) receives the number of Jacobi sweeps (-1 for the one-block n <= 64
+ * path).  n <= 8192.  Synchronizes the stream when n > 64.
+ */
+size_t dot_symeig_workspace_bytes(int n);
+int dot_symeig(int n, const double* A_dev, int lda, double* w_dev, double* V_dev, int ldv,
+               void* work_dev, size_t work_bytes, int* sweeps_host, void* stream);
+
+/*
+ * Householder QR of X_dev (n x q, ldx; not modified) with the complete
+ * orthogonal factor Q_dev (n x n, ldq): Q(:, 1:q) spans range(X) and
+ * Q(:, q+1:n) its orthogonal complement.  Reflectors follow LAPACK's
+ * convention, so Q equals LAPACK's (numpy's) complete Q up to rounding.
+ * Used for the optimized directions W_hat = orth(W W~) and their complement
+ * W_c (Section 3.2, eqs. newW, newV).
+ */
+size_t dot_qr_workspace_bytes(int n, int q);
+int dot_qr_complete(int n, int q, const double* X_dev, int ldx, double* Q_dev, int ldq,
+                    void* work_dev, size_t work_bytes, void* stream);
+
+/*
+ * Alg. 1 (optimized simultaneous sources and detectors; HOOI / Tucker2):
+ * J_dev is the (n_d n_s) x n_p Jacobian with the detector index fastest
+ * (eq. Jacobiancomp; the sampled J_s with n_d = l_d, n_s = l_s works the same
+ * way).  Step (1) takes the leading q_d left singular vectors of J~, then
+ * steps (2)-(3) alternate W~ (leading q_s left singular vectors of K~) and V~
+ * (of L~) until the projectors W~ W~^T and V~ V~^T change by less than tol in
+ * Frobenius norm, or maxit iterations.  Outputs W_dev (n_s x q_s), V_dev
+ * (n_d x q_d), the iteration count and the objective ||(W~^T kron V~^T) J||_F^2.
+ * Singular vectors are computed as eigenvectors of the unfoldings' Gram
+ * matrices.  Synchronizes the stream.
+ */
+size_t dot_hooi_workspace_bytes(int n_d, int n_s, int n_p, int q_d, int q_s);
+int dot_hooi(int n_d, int n_s, int n_p, const double* J_dev, int q_d, int q_s, double tol,
+             int maxit, double* W_dev, double* V_dev, int* iters_host, double* objective_host,
+             void* work_dev, size_t work_bytes, void* stream);
+
+/*
+ * Thin SVD A = U diag(s) Y^T of A_dev (m x n, lda = m), m <= n (the sampled
+ * Jacobian behind the Gauss-Newton model, eq. GN): U and s from the
+ * eigendecomposition of A A^T, Y = A^T U diag(1/s) for s > rcut s_max (zero
+ * columns otherwise).  U_dev m x m, s_dev m, Y_dev n x m.  Synchronizes.
+ */
+size_t dot_svd_workspace_bytes(int m, int n);
+int dot_svd_thin(int m, int n, const double* A_dev, int lda, double* s_dev, double* U_dev,
+                 int ldu, double* Y_dev, int ldy, double rcut, void* work_dev, size_t work_bytes,
+                 void* stream);
+
 #ifdef __cplusplus
 }
 #endif

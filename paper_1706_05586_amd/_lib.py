@@ -88,6 +88,17 @@ SIGNATURES = {
     "dot_jacobian": (_i, [_vp, _i, _vp, _i, _vp, _i, _vp, _vp, _sz, _vp]),
     "dot_grad_misfit": (_i, [_vp, _i, _vp, _i, _vp, _vp, _vp, _vp, _sz, _vp]),
     "dot_gemm": (_i, [_i, _i, _i, _i, _i, _d, _vp, _i, _vp, _i, _d, _vp, _i, _vp]),
+    "dot_mode_gram_workspace_bytes": (_sz, [_i, _i, _i, _i]),
+    "dot_mode_gram": (_i, [_i, _i, _i, _vp, _i, _vp, _vp, _sz, _vp]),
+    "dot_symeig_workspace_bytes": (_sz, [_i]),
+    "dot_symeig": (_i, [_i, _vp, _i, _vp, _vp, _i, _vp, _sz, C.POINTER(C.c_int), _vp]),
+    "dot_qr_workspace_bytes": (_sz, [_i, _i]),
+    "dot_qr_complete": (_i, [_i, _i, _vp, _i, _vp, _i, _vp, _sz, _vp]),
+    "dot_hooi_workspace_bytes": (_sz, [_i, _i, _i, _i, _i]),
+    "dot_hooi": (_i, [_i, _i, _i, _vp, _i, _i, _d, _i, _vp, _vp, C.POINTER(C.c_int),
+                      C.POINTER(C.c_double), _vp, _sz, _vp]),
+    "dot_svd_workspace_bytes": (_sz, [_i, _i]),
+    "dot_svd_thin": (_i, [_i, _i, _vp, _i, _vp, _vp, _i, _vp, _i, _d, _vp, _sz, _vp]),
     "dot_profile_enable": (_i, [_vp, _i]),
     "dot_profile_read": (_i, [_vp, _i, C.POINTER(C.c_double), C.POINTER(_i64),
                               C.POINTER(_i64)]),

@@ -21,7 +21,8 @@ from . import _lib as L
 from ._lib import check, lib
 
 __all__ = ["Grid", "Pals", "Operator", "SolveResult", "pals_field", "gemm", "colmajor",
-           "empty_colmajor"]
+           "empty_colmajor", "mode_gram", "symeig", "qr_complete", "hooi", "svd_thin",
+           "optimized_design"]
 
 
 def _stream() -> C.c_void_p:
@@ -123,9 +124,17 @@ def pals_field(grid: Grid, pals: Pals, theta: torch.Tensor, mus_prime: float | N
     return (mua, diff) if diff is not None else mua
 
 
+def _check_colmajor_out(out: torch.Tensor, rows: int, cols: int):
+    if out.shape != (rows, cols) or out.dtype != torch.float64 or not out.is_cuda:
+        raise ValueError(f"out must be a float64 CUDA ({rows}, {cols}) matrix")
+    if cols > 1 and out.stride() != (1, rows) and not (out.stride(0) == 1 and out.stride(1) >= rows):
+        raise ValueError("out must be column-major")
+
+
 def gemm(A: torch.Tensor, B: torch.Tensor, transa: bool = False, transb: bool = False,
-         alpha: float = 1.0) -> torch.Tensor:
-    """alpha op(A) op(B) for logical matrices, computed by the library's FP64 kernel."""
+         alpha: float = 1.0, out: torch.Tensor | None = None) -> torch.Tensor:
+    """alpha op(A) op(B) for logical matrices, computed by the library's FP64 kernel.
+    ``out`` may be a column block of a column-major matrix."""
     Am, Bm = colmajor(A, "A"), colmajor(B, "B")
     ar, ac = A.shape
     br, bc = B.shape
@@ -133,10 +142,115 @@ def gemm(A: torch.Tensor, B: torch.Tensor, transa: bool = False, transb: bool = 
     kb, n = (bc, br) if transb else (br, bc)
     if kd != kb:
         raise ValueError("inner dimensions differ")
-    out = empty_colmajor(m, n, A.device)
+    if out is None:
+        out = empty_colmajor(m, n, A.device)
+        ldc = max(m, 1)
+    else:
+        _check_colmajor_out(out, m, n)
+        ldc = out.stride(1) if n > 1 else max(m, 1)
     check(lib.dot_gemm(int(transa), int(transb), m, n, kd, float(alpha), _ptr(Am), max(ar, 1),
-                       _ptr(Bm), max(br, 1), 0.0, _ptr(out), max(m, 1), _stream()), "dot_gemm")
+                       _ptr(Bm), max(br, 1), 0.0, _ptr(out), ldc, _stream()), "dot_gemm")
     return out
+
+
+def mode_gram(T: torch.Tensor, dims, mode: int) -> torch.Tensor:
+    """Gram matrix of the mode-0 or mode-1 unfolding of a column-major 3-tensor
+    (flat float64 CUDA tensor of dims[0] * dims[1] * dims[2] values)."""
+    dA, dB, dC = (int(v) for v in dims)
+    _need_cuda_f64(T, "T")
+    if T.numel() != dA * dB * dC or not T.is_contiguous():
+        raise ValueError("T must hold dA*dB*dC contiguous values")
+    R = dA if mode == 0 else dB
+    G = empty_colmajor(R, R, T.device)
+    nb = int(lib.dot_mode_gram_workspace_bytes(dA, dB, dC, mode))
+    w = _workspace(nb, T.device)
+    check(lib.dot_mode_gram(dA, dB, dC, _ptr(T), mode, _ptr(G), _ptr(w), w.numel(), _stream()),
+          "dot_mode_gram")
+    return G
+
+
+def symeig(A: torch.Tensor):
+    """Eigenvalues (descending) and eigenvectors of a symmetric matrix (cyclic Jacobi)."""
+    n = A.shape[0]
+    Am = colmajor(A, "A")
+    w = torch.empty(n, dtype=torch.float64, device=A.device)
+    V = empty_colmajor(n, n, A.device)
+    nb = int(lib.dot_symeig_workspace_bytes(n))
+    work = _workspace(nb, A.device)
+    sweeps = C.c_int(0)
+    check(lib.dot_symeig(n, _ptr(Am), n, _ptr(w), _ptr(V), n, _ptr(work), work.numel(),
+                         C.byref(sweeps), _stream()), "dot_symeig")
+    return w, V
+
+
+def qr_complete(X: torch.Tensor) -> torch.Tensor:
+    """Complete orthogonal factor Q (n x n) of X (n x q): Q[:, :q] spans range(X)."""
+    n, q = X.shape
+    Xm = colmajor(X, "X")
+    Q = empty_colmajor(n, n, X.device)
+    w = _workspace(int(lib.dot_qr_workspace_bytes(n, q)), X.device)
+    check(lib.dot_qr_complete(n, q, _ptr(Xm), n, _ptr(Q), n, _ptr(w), w.numel(), _stream()),
+          "dot_qr_complete")
+    return Q
+
+
+def hooi(J: torch.Tensor, n_d: int, n_s: int, q_d: int, q_s: int, tol: float = 1e-10,
+         maxit: int = 50):
+    """Alg. 1 on the (n_d n_s) x n_p Jacobian (detector index fastest).
+    Returns (W~ (n_s x q_s), V~ (n_d x q_d), iterations, objective)."""
+    Jm = colmajor(J, "J")
+    n_p = J.shape[1]
+    if J.shape[0] != n_d * n_s:
+        raise ValueError("J must have n_d * n_s rows")
+    W = empty_colmajor(n_s, q_s, J.device)
+    V = empty_colmajor(n_d, q_d, J.device)
+    nb = int(lib.dot_hooi_workspace_bytes(n_d, n_s, n_p, q_d, q_s))
+    work = _workspace(nb, J.device)
+    it, obj = C.c_int(0), C.c_double(0.0)
+    check(lib.dot_hooi(n_d, n_s, n_p, _ptr(Jm), q_d, q_s, float(tol), int(maxit), _ptr(W),
+                       _ptr(V), C.byref(it), C.byref(obj), _ptr(work), work.numel(), _stream()),
+          "dot_hooi")
+    return W, V, it.value, obj.value
+
+
+def svd_thin(A: torch.Tensor, rcut: float = 1e-12):
+    """Thin SVD of an m x n matrix (m <= n): (s, U, Y) with A = U diag(s) Y^T."""
+    m, n = A.shape
+    Am = colmajor(A, "A")
+    s = torch.empty(m, dtype=torch.float64, device=A.device)
+    U = empty_colmajor(m, m, A.device)
+    Y = empty_colmajor(n, m, A.device)
+    work = _workspace(int(lib.dot_svd_workspace_bytes(m, n)), A.device)
+    check(lib.dot_svd_thin(m, n, _ptr(Am), m, _ptr(s), _ptr(U), m, _ptr(Y), n, float(rcut),
+                           _ptr(work), work.numel(), _stream()), "dot_svd_thin")
+    return s, U, Y
+
+
+def optimized_design(Js: torch.Tensor, W: torch.Tensor, V: torch.Tensor, q_s: int, q_d: int,
+                     y_signs: torch.Tensor, z_signs: torch.Tensor, tol: float = 1e-10,
+                     maxit: int = 50):
+    """Optimized and complementary simultaneous sources/detectors (Section 3.2).
+
+    Alg. 1 on the sampled Jacobian J_s gives W~ (l_s x q_s) and V~ (l_d x q_d);
+    the optimized directions are lifted to the full spaces as W_hat =
+    orth(W W~), V_hat = orth(V V~) by Householder QR, whose complete Q also
+    gives the complements W_c, V_c; the new samples are W = [W_hat, W_c Y]
+    and V = [V_hat, V_c Z] with Y = (l_s - q_s)^{-1/2} y_signs (eqs. newW, newV).
+    Returns (W_new, V_new, info)."""
+    n_s, l_s = W.shape
+    n_d, l_d = V.shape
+    Wt, Vt, it, obj = hooi(Js, l_d, l_s, q_d, q_s, tol, maxit)
+    out = []
+    for S, T, q, l, signs in ((W, Wt, q_s, l_s, y_signs), (V, Vt, q_d, l_d, z_signs)):
+        n = S.shape[0]
+        X = gemm(S, T)                          # n x q
+        Q = qr_complete(X)                      # [S_hat, S_c]
+        new = empty_colmajor(n, l, S.device)
+        new[:, :q].copy_(Q[:, :q])
+        if l > q:
+            gemm(Q[:, q:], signs, alpha=1.0 / np.sqrt(l - q), out=new[:, q:])
+        out.append(new)
+    return out[0], out[1], {"hooi_iters": it, "objective": obj, "W_tilde": Wt, "V_tilde": Vt}
 
 
 @dataclass

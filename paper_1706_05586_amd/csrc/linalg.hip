@@ -1,0 +1,919 @@
+// Dense binary64 linear algebra for the optimized simultaneous sources and
+// detectors (Section 3.2, Alg. 1) and the singular value decomposition of the
+// sampled Jacobian behind the Gauss-Newton model (eq. GN, Section 2).
+//
+//   * Gram matrices of tensor unfoldings, formed without materializing the
+//     unfoldings: for a 3-tensor T (dims A, B, C, first index fastest) the
+//     mode-a Gram  G[a,a'] = sum_{b,c} T[a,b,c] T[a',b,c]  and the mode-b Gram
+//     G[b,b'] = sum_{a,c} T[a,b,c] T[a,b',c]; split over the contraction with
+//     per-chunk partials summed in fixed order.
+//   * Symmetric eigensolver: cyclic two-sided Jacobi with round-robin
+//     (tournament) ordering; each round rotates n/2 disjoint pairs, applied as
+//     A <- A J (columns) then A <- J^T A (rows).  n <= 64 runs in one block
+//     with A and the eigenvectors in LDS; larger n runs rounds from global
+//     memory.  Eigenpairs are returned in descending order.
+//   * Householder QR with LAPACK's reflector convention (beta = -sign(alpha)
+//     ||x||, v(1) = 1, tau = (beta - alpha) / beta) and the complete Q, whose
+//     first q columns span range(X) and the remaining n - q its orthogonal
+//     complement.
+//   * HOOI (Alg. 1) driven from the host on these kernels.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "dot_internal.h"
+
+namespace dot {
+
+#define DOT_TRY_L(...)             \
+  do {                             \
+    int rc_ = (__VA_ARGS__);       \
+    if (rc_ != DOT_OK) return rc_; \
+  } while (0)
+
+// ------------------------------------------------------------ strided Gram
+// Rows i < R at offset i*si; contraction index u = u1 + U1 u2 at u1*s1 + u2*s2.
+struct GramDesc {
+  int R, U1, U2;
+  int64_t si, s1, s2;
+};
+
+constexpr int GT = 32;        // output tile edge
+constexpr int GK = 64;        // contraction slab per LDS stage
+
+__global__ __launch_bounds__(256) void gram_partial_kernel(GramDesc d, const double* __restrict__ X,
+                                                           int64_t chunk, double* __restrict__ part) {
+  __shared__ double sa[GK][GT + 1];
+  __shared__ double sb[GK][GT + 1];
+  const int tiles = (d.R + GT - 1) / GT;
+  const int ti = blockIdx.x % tiles, tj = blockIdx.x / tiles;
+  const int64_t U = (int64_t)d.U1 * d.U2;
+  const int64_t u0 = (int64_t)blockIdx.y * chunk, u1 = min(U, u0 + chunk);
+  // thread owns a 2x2 block of outputs: rows ti*GT + 2*(t%16) .., cols tj*GT + 2*(t/16) ..
+  const int tr = threadIdx.x % 16, tc = threadIdx.x / 16;
+  double acc[2][2] = {{0, 0}, {0, 0}};
+  for (int64_t ub = u0; ub < u1; ub += GK) {
+    for (int e = threadIdx.x; e < GK * GT; e += 256) {
+      const int kk = e / GT, r = e % GT;
+      const int64_t u = ub + kk;
+      double va = 0.0, vb = 0.0;
+      if (u < u1) {
+        const int64_t uo = (u % d.U1) * d.s1 + (u / d.U1) * d.s2;
+        const int ia = ti * GT + r, ib = tj * GT + r;
+        if (ia < d.R) va = X[ia * d.si + uo];
+        if (ib < d.R) vb = X[ib * d.si + uo];
+      }
+      sa[kk][r] = va;
+      sb[kk][r] = vb;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < GK; ++kk) {
+      const double a0 = sa[kk][2 * tr], a1 = sa[kk][2 * tr + 1];
+      const double b0 = sb[kk][2 * tc], b1 = sb[kk][2 * tc + 1];
+      acc[0][0] += a0 * b0;
+      acc[0][1] += a0 * b1;
+      acc[1][0] += a1 * b0;
+      acc[1][1] += a1 * b1;
+    }
+    __syncthreads();
+  }
+  double* out = part + (int64_t)blockIdx.y * d.R * d.R;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      const int i = ti * GT + 2 * tr + a, j = tj * GT + 2 * tc + b;
+      if (i < d.R && j < d.R) out[i + (int64_t)d.R * j] = acc[a][b];
+    }
+}
+
+__global__ void sum_chunks_kernel(int64_t n, int nchunks, const double* __restrict__ part,
+                                  double* __restrict__ out) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunks; ++c) s += part[(int64_t)c * n + e];
+  out[e] = s;
+}
+
+static size_t gram_work_bytes(const GramDesc& d, int* nchunks, int64_t* chunk) {
+  const int64_t U = (int64_t)d.U1 * d.U2;
+  const int tiles = (d.R + GT - 1) / GT;
+  // enough blocks to fill the device, chunks of at least 4 slabs
+  int64_t want = std::max<int64_t>(1, 2048 / ((int64_t)tiles * tiles));
+  int64_t ch = std::max<int64_t>((U + want - 1) / want, 4 * GK);
+  ch = ((ch + GK - 1) / GK) * GK;
+  const int nc = (int)std::max<int64_t>(1, (U + ch - 1) / ch);
+  *nchunks = nc;
+  *chunk = ch;
+  return (size_t)nc * d.R * d.R * sizeof(double);
+}
+
+static int gram(const GramDesc& d, const double* X, double* G, double* work, hipStream_t s) {
+  int nc;
+  int64_t ch;
+  gram_work_bytes(d, &nc, &ch);
+  const int tiles = (d.R + GT - 1) / GT;
+  hipLaunchKernelGGL(gram_partial_kernel, dim3(tiles * tiles, nc), dim3(256), 0, s, d, X, ch, work);
+  DOT_LAUNCH_CHECK();
+  const int64_t n = (int64_t)d.R * d.R;
+  hipLaunchKernelGGL(sum_chunks_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, nc,
+                     work, G);
+  DOT_LAUNCH_CHECK();
+  return DOT_OK;
+}
+
+// out[a, l, c] = sum_b T[a, b, c] M[b, l]   (T: A x B x C, M: B x Lm col-major)
+__global__ void mode_b_product_kernel(int A, int B, int C, int Lm, const double* __restrict__ T,
+                                      const double* __restrict__ M, double* __restrict__ out) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)A * Lm * C;
+  if (e >= total) return;
+  const int a = (int)(e % A);
+  const int l = (int)((e / A) % Lm);
+  const int64_t c = e / ((int64_t)A * Lm);
+  const double* tp = T + a + (int64_t)A * B * c;
+  double s = 0.0;
+  for (int b = 0; b < B; ++b) s += tp[(int64_t)A * b] * M[b + (int64_t)B * l];
+  out[e] = s;
+}
+
+// ------------------------------------------------------------ Jacobi eigensolver
+__device__ __forceinline__ void tournament(int np, int round, int i, int* p, int* q) {
+  auto pos = [&](int k) { return k == 0 ? 0 : ((k - 1 + round) % (np - 1)) + 1; };
+  const int a = pos(i), b = pos(np - 1 - i);
+  *p = min(a, b);
+  *q = max(a, b);
+}
+
+__device__ __forceinline__ void jacobi_angle(double app, double aqq, double apq, double* c,
+                                             double* s) {
+  if (apq == 0.0) {
+    *c = 1.0;
+    *s = 0.0;
+    return;
+  }
+  const double tau = (aqq - app) / (2.0 * apq);
+  const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+  *c = 1.0 / sqrt(1.0 + t * t);
+  *s = t * *c;
+}
+
+constexpr int EIG_SMALL = 64;
+
+// One block: A (n x n, lda) -> eigenvalues w (descending) and eigenvectors V.
+__global__ __launch_bounds__(256) void symeig_small_kernel(int n, const double* __restrict__ Ain,
+                                                           int lda, double* __restrict__ w,
+                                                           double* __restrict__ Vout, int ldv,
+                                                           int max_sweeps, int* sweeps_out) {
+  __shared__ double a[EIG_SMALL][EIG_SMALL + 1];
+  __shared__ double v[EIG_SMALL][EIG_SMALL + 1];
+  __shared__ double cs[EIG_SMALL / 2][2];
+  __shared__ int pq[EIG_SMALL / 2][2];
+  __shared__ double red[256];
+  __shared__ int order[EIG_SMALL];
+  const int np = n + (n & 1);
+  for (int e = threadIdx.x; e < np * np; e += 256) {
+    const int i = e % np, j = e / np;
+    a[i][j] = (i < n && j < n) ? Ain[i + (int64_t)lda * j] : 0.0;
+    v[i][j] = i == j ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  int sweep = 0;
+  for (; sweep < max_sweeps; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int e = threadIdx.x; e < n * n; e += 256) {
+      const int i = e % n, j = e / n;
+      const double x = a[i][j] * a[i][j];
+      tot += x;
+      if (i != j) off += x;
+    }
+    red[threadIdx.x] = off;
+    __syncthreads();
+    for (int s = 128; s >= 1; s >>= 1) {
+      if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    const double offs = red[0];
+    __syncthreads();
+    red[threadIdx.x] = tot;
+    __syncthreads();
+    for (int s = 128; s >= 1; s >>= 1) {
+      if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    const double tots = red[0];
+    __syncthreads();
+    if (!(offs > 1e-30 * tots) || offs == 0.0) break;
+    for (int round = 0; round < np - 1; ++round) {
+      if ((int)threadIdx.x < np / 2) {
+        int p, q;
+        tournament(np, round, threadIdx.x, &p, &q);
+        double c = 1.0, s = 0.0;
+        if (q < n) jacobi_angle(a[p][p], a[q][q], a[p][q], &c, &s);
+        pq[threadIdx.x][0] = p;
+        pq[threadIdx.x][1] = q;
+        cs[threadIdx.x][0] = c;
+        cs[threadIdx.x][1] = s;
+      }
+      __syncthreads();
+      // columns: A <- A J, V <- V J
+      for (int e = threadIdx.x; e < (np / 2) * np; e += 256) {
+        const int k = e / np, r = e % np;
+        const int p = pq[k][0], q = pq[k][1];
+        const double c = cs[k][0], s = cs[k][1];
+        const double arp = a[r][p], arq = a[r][q];
+        a[r][p] = c * arp - s * arq;
+        a[r][q] = s * arp + c * arq;
+        const double vrp = v[r][p], vrq = v[r][q];
+        v[r][p] = c * vrp - s * vrq;
+        v[r][q] = s * vrp + c * vrq;
+      }
+      __syncthreads();
+      // rows: A <- J^T A
+      for (int e = threadIdx.x; e < (np / 2) * np; e += 256) {
+        const int k = e / np, r = e % np;
+        const int p = pq[k][0], q = pq[k][1];
+        const double c = cs[k][0], s = cs[k][1];
+        const double apr = a[p][r], aqr = a[q][r];
+        a[p][r] = c * apr - s * aqr;
+        a[q][r] = s * apr + c * aqr;
+      }
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < n; ++i) order[i] = i;
+    for (int i = 0; i < n; ++i) {  // selection sort, descending, stable on ties
+      int best = i;
+      for (int j = i + 1; j < n; ++j)
+        if (a[order[j]][order[j]] > a[order[best]][order[best]]) best = j;
+      const int t = order[i];
+      order[i] = order[best];
+      order[best] = t;
+    }
+    if (sweeps_out) *sweeps_out = sweep;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n * n; e += 256) {
+    const int r = e % n, j = e / n;
+    Vout[r + (int64_t)ldv * j] = v[r][order[j]];
+  }
+  for (int j = threadIdx.x; j < n; j += 256) w[j] = a[order[j]][order[j]];
+}
+
+// Medium n (<= EIG_BLOCK): all sweeps in one workgroup, A and V in global
+// memory (L2-resident), pairs and angles in LDS, convergence tested in-kernel.
+constexpr int EIG_BLOCK = 512;
+
+__global__ __launch_bounds__(1024) void symeig_block_kernel(int n, double* __restrict__ A,
+                                                            double* __restrict__ V, int max_sweeps,
+                                                            int* sweeps_out) {
+  __shared__ double cs[EIG_BLOCK / 2][2];
+  __shared__ int pq[EIG_BLOCK / 2][2];
+  __shared__ double red[2][1024];
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int np = n + (n & 1);
+  const int npairs = np / 2;
+  for (int64_t e = t; e < (int64_t)n * n; e += nt) V[e] = (e % n == e / n) ? 1.0 : 0.0;
+  __syncthreads();
+  int sweep = 0;
+  for (; sweep < max_sweeps; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int64_t e = t; e < (int64_t)n * n; e += nt) {
+      const double x = A[e] * A[e];
+      tot += x;
+      if (e % n != e / n) off += x;
+    }
+    red[0][t] = off;
+    red[1][t] = tot;
+    __syncthreads();
+    for (int s = nt / 2; s >= 1; s >>= 1) {
+      if (t < s) {
+        red[0][t] += red[0][t + s];
+        red[1][t] += red[1][t + s];
+      }
+      __syncthreads();
+    }
+    const double offs = red[0][0], tots = red[1][0];
+    __syncthreads();
+    if (!(offs > 1e-30 * tots) || offs == 0.0) break;
+    for (int round = 0; round < np - 1; ++round) {
+      for (int k = t; k < npairs; k += nt) {
+        int p, q;
+        tournament(np, round, k, &p, &q);
+        double c = 1.0, s = 0.0;
+        if (q < n) jacobi_angle(A[p + (int64_t)n * p], A[q + (int64_t)n * q], A[p + (int64_t)n * q], &c, &s);
+        pq[k][0] = p;
+        pq[k][1] = q;
+        cs[k][0] = c;
+        cs[k][1] = s;
+      }
+      __syncthreads();
+      for (int64_t e = t; e < (int64_t)npairs * n; e += nt) {
+        const int k = (int)(e / n), r = (int)(e % n);
+        const int p = pq[k][0], q = pq[k][1];
+        if (q >= n) continue;
+        const double c = cs[k][0], s = cs[k][1];
+        double* ap = A + (int64_t)n * p;
+        double* aq = A + (int64_t)n * q;
+        const double arp = ap[r], arq = aq[r];
+        ap[r] = c * arp - s * arq;
+        aq[r] = s * arp + c * arq;
+        double* vp = V + (int64_t)n * p;
+        double* vq = V + (int64_t)n * q;
+        const double vrp = vp[r], vrq = vq[r];
+        vp[r] = c * vrp - s * vrq;
+        vq[r] = s * vrp + c * vrq;
+      }
+      __syncthreads();
+      for (int64_t e = t; e < (int64_t)npairs * n; e += nt) {
+        const int k = (int)(e % npairs), r = (int)(e / npairs);
+        const int p = pq[k][0], q = pq[k][1];
+        if (q >= n) continue;
+        const double c = cs[k][0], s = cs[k][1];
+        double* col = A + (int64_t)n * r;
+        const double apr = col[p], aqr = col[q];
+        col[p] = c * apr - s * aqr;
+        col[q] = s * apr + c * aqr;
+      }
+      __syncthreads();
+    }
+  }
+  if (t == 0 && sweeps_out) *sweeps_out = sweep;
+}
+
+// Large n: one round of rotations from global memory (A and V are n x n, ld n).
+__global__ void jacobi_angles_kernel(int n, int np, int round, const double* __restrict__ A,
+                                     int* __restrict__ pq, double* __restrict__ cs) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= np / 2) return;
+  int p, q;
+  tournament(np, round, k, &p, &q);
+  double c = 1.0, s = 0.0;
+  if (q < n) jacobi_angle(A[p + (int64_t)n * p], A[q + (int64_t)n * q], A[p + (int64_t)n * q], &c, &s);
+  pq[2 * k] = p;
+  pq[2 * k + 1] = q;
+  cs[2 * k] = c;
+  cs[2 * k + 1] = s;
+}
+
+__global__ void jacobi_cols_kernel(int n, int npairs, const int* __restrict__ pq,
+                                   const double* __restrict__ cs, double* __restrict__ A,
+                                   double* __restrict__ V) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)npairs * n) return;
+  const int k = (int)(e / n), r = (int)(e % n);
+  const int p = pq[2 * k], q = pq[2 * k + 1];
+  if (q >= n) return;
+  const double c = cs[2 * k], s = cs[2 * k + 1];
+  double* ap = A + (int64_t)n * p;
+  double* aq = A + (int64_t)n * q;
+  const double arp = ap[r], arq = aq[r];
+  ap[r] = c * arp - s * arq;
+  aq[r] = s * arp + c * arq;
+  double* vp = V + (int64_t)n * p;
+  double* vq = V + (int64_t)n * q;
+  const double vrp = vp[r], vrq = vq[r];
+  vp[r] = c * vrp - s * vrq;
+  vq[r] = s * vrp + c * vrq;
+}
+
+__global__ void jacobi_rows_kernel(int n, int npairs, const int* __restrict__ pq,
+                                   const double* __restrict__ cs, double* __restrict__ A) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)npairs * n) return;
+  const int k = (int)(e % npairs), r = (int)(e / npairs);
+  const int p = pq[2 * k], q = pq[2 * k + 1];
+  if (q >= n) return;
+  const double c = cs[2 * k], s = cs[2 * k + 1];
+  double* col = A + (int64_t)n * r;
+  const double apr = col[p], aqr = col[q];
+  col[p] = c * apr - s * aqr;
+  col[q] = s * apr + c * aqr;
+}
+
+// off-diagonal and total squared norms, per-block partials then fixed-order sum
+__global__ void offnorm_kernel(int n, const double* __restrict__ A, double* __restrict__ part) {
+  __shared__ double r0[256], r1[256];
+  double off = 0.0, tot = 0.0;
+  const int64_t nn = (int64_t)n * n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nn;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double x = A[e] * A[e];
+    tot += x;
+    if (e % n != e / n) off += x;
+  }
+  r0[threadIdx.x] = off;
+  r1[threadIdx.x] = tot;
+  __syncthreads();
+  for (int s = 128; s >= 1; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      r0[threadIdx.x] += r0[threadIdx.x + s];
+      r1[threadIdx.x] += r1[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = r0[0];
+    part[2 * blockIdx.x + 1] = r1[0];
+  }
+}
+
+__global__ void eye_kernel(int n, double* __restrict__ V) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * n) return;
+  V[e] = (e % n == e / n) ? 1.0 : 0.0;
+}
+
+__global__ void copy_matrix_kernel(int m, int n, const double* __restrict__ X, int ldx,
+                                   double* __restrict__ Y, int ldy) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)m * n) return;
+  const int i = (int)(e % m), j = (int)(e / m);
+  Y[i + (int64_t)ldy * j] = X[i + (int64_t)ldx * j];
+}
+
+// order eigenpairs descending (one thread; n <= 4096 selection on the host copy
+// would need a sync, so the permutation is built on the device)
+__global__ void eig_order_kernel(int n, const double* __restrict__ A, int* __restrict__ order,
+                                 double* __restrict__ w) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int i = 0; i < n; ++i) order[i] = i;
+  // insertion sort on the diagonal (n is moderate; O(n^2) once per solve)
+  for (int i = 1; i < n; ++i) {
+    const int t = order[i];
+    const double key = A[t + (int64_t)n * t];
+    int j = i - 1;
+    while (j >= 0 && A[order[j] + (int64_t)n * order[j]] < key) {
+      order[j + 1] = order[j];
+      --j;
+    }
+    order[j + 1] = t;
+  }
+  for (int i = 0; i < n; ++i) w[i] = A[order[i] + (int64_t)n * order[i]];
+}
+
+__global__ void permute_cols_kernel(int n, const double* __restrict__ V, const int* __restrict__ order,
+                                    double* __restrict__ Vout, int ldv) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * n) return;
+  const int r = (int)(e % n), j = (int)(e / n);
+  Vout[r + (int64_t)ldv * j] = V[r + (int64_t)n * order[j]];
+}
+
+static size_t symeig_work_bytes(int n) {
+  if (n <= EIG_SMALL) return 256;
+  const int np = n + (n & 1);
+  const size_t nn = (size_t)n * n * sizeof(double);
+  return 2 * nn + (size_t)np * (sizeof(int) + sizeof(double)) * 2 + 512 * 2 * sizeof(double) +
+         (size_t)n * sizeof(int) + 8 * 256;
+}
+
+static size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+static int symeig(int n, const double* A, int lda, double* w, double* V, int ldv, char* work,
+                  hipStream_t s, int max_sweeps, int* sweeps) {
+  if (n <= EIG_SMALL) {
+    hipLaunchKernelGGL(symeig_small_kernel, dim3(1), dim3(256), 0, s, n, A, lda, w, V, ldv,
+                       max_sweeps, (int*)nullptr);
+    DOT_LAUNCH_CHECK();
+    if (sweeps) *sweeps = -1;
+    return DOT_OK;
+  }
+  const int np = n + (n & 1);
+  const size_t nn = (size_t)n * n;
+  size_t off = 0;
+  double* Aw = (double*)(work + off);
+  off += al256(nn * 8);
+  double* Vw = (double*)(work + off);
+  off += al256(nn * 8);
+  int* pq = (int*)(work + off);
+  off += al256((size_t)np * sizeof(int));
+  double* cs = (double*)(work + off);
+  off += al256((size_t)np * sizeof(double));
+  double* part = (double*)(work + off);
+  off += al256(512 * 2 * sizeof(double));
+  int* order = (int*)(work + off);
+  const unsigned b = (unsigned)((nn + 255) / 256);
+  hipLaunchKernelGGL(copy_matrix_kernel, dim3(b), dim3(256), 0, s, n, n, A, lda, Aw, n);
+  DOT_LAUNCH_CHECK();
+  int sweep = 0;
+  if (n <= EIG_BLOCK) {
+    hipLaunchKernelGGL(symeig_block_kernel, dim3(1), dim3(1024), 0, s, n, Aw, Vw, max_sweeps, order);
+    DOT_LAUNCH_CHECK();
+    if (sweeps) {
+      DOT_HIP(hipMemcpyAsync(&sweep, order, sizeof(int), hipMemcpyDeviceToHost, s));
+      DOT_HIP(hipStreamSynchronize(s));
+    }
+  } else {
+    hipLaunchKernelGGL(eye_kernel, dim3(b), dim3(256), 0, s, n, Vw);
+    DOT_LAUNCH_CHECK();
+    std::vector<double> hp(1024);
+    const int nblk_off = (int)std::min<int64_t>(512, ((int64_t)nn + 255) / 256);
+    const int npairs = np / 2;
+    for (; sweep < max_sweeps; ++sweep) {
+      hipLaunchKernelGGL(offnorm_kernel, dim3(nblk_off), dim3(256), 0, s, n, Aw, part);
+      DOT_LAUNCH_CHECK();
+      DOT_HIP(hipMemcpyAsync(hp.data(), part, 2 * nblk_off * sizeof(double), hipMemcpyDeviceToHost, s));
+      DOT_HIP(hipStreamSynchronize(s));
+      double offs = 0.0, tots = 0.0;
+      for (int i = 0; i < nblk_off; ++i) {
+        offs += hp[2 * i];
+        tots += hp[2 * i + 1];
+      }
+      if (!(offs > 1e-30 * tots) || offs == 0.0) break;
+      const unsigned bp = (unsigned)(((int64_t)npairs * n + 255) / 256);
+      for (int round = 0; round < np - 1; ++round) {
+        hipLaunchKernelGGL(jacobi_angles_kernel, dim3((npairs + 255) / 256), dim3(256), 0, s, n, np,
+                           round, Aw, pq, cs);
+        DOT_LAUNCH_CHECK();
+        hipLaunchKernelGGL(jacobi_cols_kernel, dim3(bp), dim3(256), 0, s, n, npairs, pq, cs, Aw, Vw);
+        DOT_LAUNCH_CHECK();
+        hipLaunchKernelGGL(jacobi_rows_kernel, dim3(bp), dim3(256), 0, s, n, npairs, pq, cs, Aw);
+        DOT_LAUNCH_CHECK();
+      }
+    }
+  }
+  if (sweeps) *sweeps = sweep;
+  hipLaunchKernelGGL(eig_order_kernel, dim3(1), dim3(1), 0, s, n, Aw, order, w);
+  DOT_LAUNCH_CHECK();
+  hipLaunchKernelGGL(permute_cols_kernel, dim3(b), dim3(256), 0, s, n, Vw, order, V, ldv);
+  DOT_LAUNCH_CHECK();
+  return DOT_OK;
+}
+
+// ------------------------------------------------------------ Householder QR
+// One block.  X (n x q) is overwritten by the reflectors; Q (n x n) receives
+// the complete orthogonal factor.
+__global__ __launch_bounds__(1024) void householder_qr_kernel(int n, int q, double* __restrict__ X,
+                                                              int ldx, double* __restrict__ tau,
+                                                              double* __restrict__ Q, int ldq,
+                                                              double* __restrict__ wbuf) {
+  __shared__ double red[1024];
+  __shared__ double sh_beta, sh_tau, sh_scale;
+  const int t = threadIdx.x, nt = blockDim.x;
+  auto block_sum = [&](double v) -> double {
+    red[t] = v;
+    __syncthreads();
+    for (int s = nt / 2; s >= 1; s >>= 1) {
+      if (t < s) red[t] += red[t + s];
+      __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+  };
+  for (int j = 0; j < q; ++j) {
+    double* xj = X + (int64_t)ldx * j;
+    double part = 0.0;
+    for (int i = j + 1 + t; i < n; i += nt) part += xj[i] * xj[i];
+    const double xnorm2 = block_sum(part);
+    if (t == 0) {
+      const double alpha = xj[j];
+      if (xnorm2 == 0.0) {
+        sh_tau = 0.0;
+        sh_beta = alpha;
+        sh_scale = 0.0;
+      } else {
+        const double nrm = sqrt(alpha * alpha + xnorm2);
+        const double beta = alpha >= 0.0 ? -nrm : nrm;
+        sh_tau = (beta - alpha) / beta;
+        sh_scale = 1.0 / (alpha - beta);
+        sh_beta = beta;
+      }
+      tau[j] = sh_tau;
+    }
+    __syncthreads();
+    const double tj = sh_tau, sc = sh_scale;
+    for (int i = j + 1 + t; i < n; i += nt) xj[i] *= sc;
+    __syncthreads();
+    if (t == 0) xj[j] = sh_beta;
+    __syncthreads();
+    // apply H = I - tau v v^T (v = [1; x(j+1:)]) to the trailing columns
+    for (int c = j + 1; c < q; ++c) {
+      double* xc = X + (int64_t)ldx * c;
+      double pp = 0.0;
+      for (int i = j + 1 + t; i < n; i += nt) pp += xj[i] * xc[i];
+      const double dot = block_sum(pp) + xc[j];
+      const double f = tj * dot;
+      if (t == 0) xc[j] -= f;
+      for (int i = j + 1 + t; i < n; i += nt) xc[i] -= f * xj[i];
+      __syncthreads();
+    }
+  }
+  // Q = H_1 ... H_q I, accumulated backwards
+  for (int64_t e = t; e < (int64_t)n * n; e += nt) {
+    const int i = (int)(e % n), c = (int)(e / n);
+    Q[i + (int64_t)ldq * c] = i == c ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int j = q - 1; j >= 0; --j) {
+    const double* v = X + (int64_t)ldx * j;
+    const double tj = tau[j];
+    if (tj == 0.0) continue;  // uniform
+    // w[c] = v^T Q[j:, c]
+    for (int c = t; c < n; c += nt) {
+      const double* qc = Q + (int64_t)ldq * c;
+      double s = qc[j];
+      for (int i = j + 1; i < n; ++i) s += v[i] * qc[i];
+      wbuf[c] = s;
+    }
+    __syncthreads();
+    for (int64_t e = t; e < (int64_t)n * (n - j); e += nt) {
+      const int ii = (int)(e % (n - j)) + j, c = (int)(e / (n - j));
+      const double vi = ii == j ? 1.0 : v[ii];
+      Q[ii + (int64_t)ldq * c] -= tj * vi * wbuf[c];
+    }
+    __syncthreads();
+  }
+}
+
+static size_t qr_work_bytes(int n, int q) {
+  return al256((size_t)n * q * 8) + al256((size_t)q * 8) + al256((size_t)n * 8);
+}
+
+static int qr_complete(int n, int q, const double* X, int ldx, double* Q, int ldq, char* work,
+                       hipStream_t s) {
+  double* Xw = (double*)work;
+  double* tau = (double*)(work + al256((size_t)n * q * 8));
+  double* wb = (double*)(work + al256((size_t)n * q * 8) + al256((size_t)q * 8));
+  if (q > 0) {
+    const unsigned b = (unsigned)(((int64_t)n * q + 255) / 256);
+    hipLaunchKernelGGL(copy_matrix_kernel, dim3(b), dim3(256), 0, s, n, q, X, ldx, Xw, n);
+    DOT_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(householder_qr_kernel, dim3(1), dim3(1024), 0, s, n, q, Xw, n, tau, Q, ldq, wb);
+  DOT_LAUNCH_CHECK();
+  return DOT_OK;
+}
+
+// ------------------------------------------------------------ small helpers
+// r[0] = ||P - P0||_F^2 = 2 q - 2 ||X0^T X||_F^2 for orthonormal X, X0 (n x q)
+__global__ void projector_change_kernel(int n, int q, const double* __restrict__ X,
+                                        const double* __restrict__ X0, double* __restrict__ r) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < q * q; e += 256) {
+    const int a = e % q, b = e / q;
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += X0[i + (int64_t)n * a] * X[i + (int64_t)n * b];
+    acc += s * s;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s >= 1; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) r[0] = fmax(0.0, 2.0 * q - 2.0 * red[0]);
+}
+
+__global__ void sum_first_kernel(int q, const double* __restrict__ w, double* __restrict__ r) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < q; ++i) s += w[i];
+    r[0] = s;
+  }
+}
+
+// B[:, j] = A[:, j] * f(d[j]): f = 1/sqrt (scale by the inverse singular value)
+__global__ void scale_cols_inv_sqrt_kernel(int m, int n, const double* __restrict__ A, int lda,
+                                           const double* __restrict__ lam, double cutoff,
+                                           double* __restrict__ B, int ldb) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)m * n) return;
+  const int i = (int)(e % m), j = (int)(e / m);
+  const double l = lam[j];
+  B[i + (int64_t)ldb * j] = l > cutoff ? A[i + (int64_t)lda * j] / sqrt(l) : 0.0;
+}
+
+__global__ void sqrt_clamp_kernel(int n, const double* __restrict__ lam, double* __restrict__ s) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) s[i] = sqrt(fmax(lam[i], 0.0));
+}
+
+int gemm_launch(int transa, int transb, int m, int n, int kdim, double alpha, const double* A,
+                int lda, const double* B, int ldb, double beta, double* C, int ldc, hipStream_t s);
+
+}  // namespace dot
+
+using namespace dot;
+
+extern "C" {
+
+size_t dot_mode_gram_workspace_bytes(int dA, int dB, int dC, int mode) {
+  if (dA < 1 || dB < 1 || dC < 1 || (mode != 0 && mode != 1)) return 0;
+  GramDesc d;
+  if (mode == 0) d = GramDesc{dA, dB, dC, 1, dA, (int64_t)dA * dB};
+  else d = GramDesc{dB, dA, dC, dA, 1, (int64_t)dA * dB};
+  int nc;
+  int64_t ch;
+  return al256(gram_work_bytes(d, &nc, &ch));
+}
+
+int dot_mode_gram(int dA, int dB, int dC, const double* T_dev, int mode, double* G_dev,
+                  void* work_dev, size_t work_bytes, void* stream) {
+  clear_error();
+  if (dA < 1 || dB < 1 || dC < 1) DOT_FAIL(DOT_EINVAL, "tensor dimensions must be >= 1");
+  if (mode != 0 && mode != 1) DOT_FAIL(DOT_EINVAL, "mode must be 0 (first index) or 1 (second)");
+  if (!T_dev || !G_dev || !work_dev) DOT_FAIL(DOT_EINVAL, "NULL argument");
+  const size_t need = dot_mode_gram_workspace_bytes(dA, dB, dC, mode);
+  if (work_bytes < need) DOT_FAIL(DOT_ENOMEM, "workspace too small: need %zu", need);
+  GramDesc d = mode == 0 ? GramDesc{dA, dB, dC, 1, dA, (int64_t)dA * dB}
+                         : GramDesc{dB, dA, dC, dA, 1, (int64_t)dA * dB};
+  return gram(d, T_dev, G_dev, (double*)work_dev, as_stream(stream));
+}
+
+size_t dot_symeig_workspace_bytes(int n) { return n < 1 ? 0 : al256(symeig_work_bytes(n)); }
+
+int dot_symeig(int n, const double* A_dev, int lda, double* w_dev, double* V_dev, int ldv,
+               void* work_dev, size_t work_bytes, int* sweeps_host, void* stream) {
+  clear_error();
+  if (n < 1 || n > 8192) DOT_FAIL(DOT_EINVAL, "n must be in [1, 8192]");
+  if (lda < n || ldv < n) DOT_FAIL(DOT_EINVAL, "leading dimension too small");
+  if (!A_dev || !w_dev || !V_dev) DOT_FAIL(DOT_EINVAL, "NULL argument");
+  const size_t need = dot_symeig_workspace_bytes(n);
+  if (n > EIG_SMALL && (!work_dev || work_bytes < need))
+    DOT_FAIL(DOT_ENOMEM, "workspace too small: need %zu", need);
+  return symeig(n, A_dev, lda, w_dev, V_dev, ldv, (char*)work_dev, as_stream(stream), 60,
+                sweeps_host);
+}
+
+size_t dot_qr_workspace_bytes(int n, int q) {
+  return (n < 1 || q < 0 || q > n) ? 0 : qr_work_bytes(n, q);
+}
+
+int dot_qr_complete(int n, int q, const double* X_dev, int ldx, double* Q_dev, int ldq,
+                    void* work_dev, size_t work_bytes, void* stream) {
+  clear_error();
+  if (n < 1 || q < 0 || q > n || n > 16384) DOT_FAIL(DOT_EINVAL, "need 0 <= q <= n <= 16384");
+  if (ldx < n || ldq < n) DOT_FAIL(DOT_EINVAL, "leading dimension too small");
+  if ((q > 0 && !X_dev) || !Q_dev || !work_dev) DOT_FAIL(DOT_EINVAL, "NULL argument");
+  if (work_bytes < qr_work_bytes(n, q)) DOT_FAIL(DOT_ENOMEM, "workspace too small");
+  return qr_complete(n, q, X_dev, ldx, Q_dev, ldq, (char*)work_dev, as_stream(stream));
+}
+
+// ------------------------------------------------------------ HOOI (Alg. 1)
+static size_t hooi_layout(int n_d, int n_s, int n_p, int q_d, int q_s, size_t* parts) {
+  const int nmax = std::max(n_d, n_s);
+  size_t sz[8];
+  sz[0] = al256((size_t)nmax * nmax * 8);                       // Gram
+  sz[1] = al256((size_t)nmax * 8);                              // eigenvalues
+  sz[2] = al256((size_t)nmax * nmax * 8);                       // eigenvectors
+  sz[3] = al256((size_t)std::max(q_d * n_s, n_d * q_s) * n_p * 8);  // M or L tensor
+  sz[4] = al256((size_t)(n_d * q_d + n_s * q_s) * 8 * 2);       // V, W and previous
+  sz[5] = al256(64 * 8);                                        // scalars
+  const size_t g1 = dot_mode_gram_workspace_bytes(n_d, n_s, n_p, 0);
+  const size_t g2 = dot_mode_gram_workspace_bytes(q_d, n_s, n_p, 1);
+  const size_t g3 = dot_mode_gram_workspace_bytes(n_d, q_s, n_p, 0);
+  sz[6] = al256(std::max(std::max(g1, g2), std::max(g3, dot_symeig_workspace_bytes(nmax))));
+  sz[7] = 0;
+  size_t off = 0;
+  for (int i = 0; i < 8; ++i) {
+    if (parts) parts[i] = off;
+    off += sz[i];
+  }
+  return off;
+}
+
+size_t dot_hooi_workspace_bytes(int n_d, int n_s, int n_p, int q_d, int q_s) {
+  if (n_d < 1 || n_s < 1 || n_p < 1 || q_d < 1 || q_s < 1 || q_d > n_d || q_s > n_s) return 0;
+  return hooi_layout(n_d, n_s, n_p, q_d, q_s, nullptr);
+}
+
+int dot_hooi(int n_d, int n_s, int n_p, const double* J_dev, int q_d, int q_s, double tol,
+             int maxit, double* W_dev, double* V_dev, int* iters_host, double* objective_host,
+             void* work_dev, size_t work_bytes, void* stream) {
+  clear_error();
+  if (n_d < 1 || n_s < 1 || n_p < 1) DOT_FAIL(DOT_EINVAL, "dimensions must be >= 1");
+  if (q_d < 1 || q_s < 1 || q_d > n_d || q_s > n_s) DOT_FAIL(DOT_EINVAL, "need 1 <= q <= n");
+  if (n_d > 4096 || n_s > 4096) DOT_FAIL(DOT_EINVAL, "n_d, n_s must be <= 4096");
+  if (!J_dev || !W_dev || !V_dev || !work_dev) DOT_FAIL(DOT_EINVAL, "NULL argument");
+  if (!(tol >= 0.0) || maxit < 1) DOT_FAIL(DOT_EINVAL, "tol must be >= 0 and maxit >= 1");
+  size_t off[8];
+  const size_t need = hooi_layout(n_d, n_s, n_p, q_d, q_s, off);
+  if (work_bytes < need) DOT_FAIL(DOT_ENOMEM, "workspace too small: need %zu", need);
+  hipStream_t s = as_stream(stream);
+  char* wb = (char*)work_dev;
+  double* G = (double*)(wb + off[0]);
+  double* lam = (double*)(wb + off[1]);
+  double* E = (double*)(wb + off[2]);
+  double* T = (double*)(wb + off[3]);
+  double* Vc = (double*)(wb + off[4]);
+  double* Wc = Vc + (size_t)n_d * q_d;
+  double* Vp = Wc + (size_t)n_s * q_s;
+  double* Wp = Vp + (size_t)n_d * q_d;
+  double* sc = (double*)(wb + off[5]);
+  double* gw = (double*)(wb + off[6]);
+  const size_t gwb = need - off[6];
+  auto leading = [&](int n, int q, double* out) -> int {
+    DOT_TRY_L(symeig(n, G, n, lam, E, n, (char*)gw, s, 60, nullptr));
+    const unsigned b = (unsigned)(((int64_t)n * q + 255) / 256);
+    hipLaunchKernelGGL(copy_matrix_kernel, dim3(b), dim3(256), 0, s, n, q, E, n, out, n);
+    DOT_LAUNCH_CHECK();
+    return DOT_OK;
+  };
+  // (1) V <- leading q_d left singular vectors of J~ (mode-a Gram of J)
+  {
+    GramDesc d{n_d, n_s, n_p, 1, n_d, (int64_t)n_d * n_s};
+    DOT_TRY_L(gram(d, J_dev, G, gw, s));
+    DOT_TRY_L(leading(n_d, q_d, Vc));
+  }
+  (void)gwb;
+  int it = 0;
+  double obj = 0.0;
+  std::vector<double> hs(4);
+  for (it = 1; it <= maxit; ++it) {
+    // (2) M = V^T J~ as a (q_d, n_s, n_p) tensor; W <- leading vectors of its mode-b Gram
+    DOT_TRY_L(gemm_launch(1, 0, q_d, n_s * n_p, n_d, 1.0, Vc, n_d, J_dev, n_d, 0.0, T, q_d, s));
+    {
+      GramDesc d{n_s, q_d, n_p, q_d, 1, (int64_t)q_d * n_s};
+      DOT_TRY_L(gram(d, T, G, gw, s));
+      if (it > 1)
+        DOT_HIP(hipMemcpyAsync(Wp, Wc, (size_t)n_s * q_s * 8, hipMemcpyDeviceToDevice, s));
+      DOT_TRY_L(leading(n_s, q_s, Wc));
+    }
+    // (3) L = J x_b W as a (n_d, q_s, n_p) tensor; V <- leading vectors of its mode-a Gram
+    {
+      const int64_t tot = (int64_t)n_d * q_s * n_p;
+      hipLaunchKernelGGL(mode_b_product_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                         n_d, n_s, n_p, q_s, J_dev, Wc, T);
+      DOT_LAUNCH_CHECK();
+      GramDesc d{n_d, q_s, n_p, 1, n_d, (int64_t)n_d * q_s};
+      DOT_TRY_L(gram(d, T, G, gw, s));
+      DOT_HIP(hipMemcpyAsync(Vp, Vc, (size_t)n_d * q_d * 8, hipMemcpyDeviceToDevice, s));
+      DOT_TRY_L(leading(n_d, q_d, Vc));
+      // objective ||(W^T kron V^T) J||_F^2 = sum of the q_d leading eigenvalues
+      hipLaunchKernelGGL(sum_first_kernel, dim3(1), dim3(1), 0, s, q_d, lam, sc);
+      DOT_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(projector_change_kernel, dim3(1), dim3(256), 0, s, n_d, q_d, Vc, Vp, sc + 1);
+    DOT_LAUNCH_CHECK();
+    if (it > 1) {
+      hipLaunchKernelGGL(projector_change_kernel, dim3(1), dim3(256), 0, s, n_s, q_s, Wc, Wp, sc + 2);
+      DOT_LAUNCH_CHECK();
+    }
+    DOT_HIP(hipMemcpyAsync(hs.data(), sc, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    DOT_HIP(hipStreamSynchronize(s));
+    obj = hs[0];
+    const double dV = sqrt(hs[1]), dW = it > 1 ? sqrt(hs[2]) : INFINITY;
+    if (dV < tol && dW < tol) break;
+  }
+  if (it > maxit) it = maxit;
+  DOT_HIP(hipMemcpyAsync(W_dev, Wc, (size_t)n_s * q_s * 8, hipMemcpyDeviceToDevice, s));
+  DOT_HIP(hipMemcpyAsync(V_dev, Vc, (size_t)n_d * q_d * 8, hipMemcpyDeviceToDevice, s));
+  DOT_HIP(hipStreamSynchronize(s));
+  if (iters_host) *iters_host = it;
+  if (objective_host) *objective_host = obj;
+  return DOT_OK;
+}
+
+// ------------------------------------------------------------ thin SVD
+size_t dot_svd_workspace_bytes(int m, int n) {
+  if (m < 1 || n < 1) return 0;
+  GramDesc d{m, n, 1, 1, m, (int64_t)m * n};
+  int nc;
+  int64_t ch;
+  const size_t g = al256(gram_work_bytes(d, &nc, &ch));
+  return al256((size_t)m * m * 8) * 2 + al256((size_t)m * 8) + std::max(g, dot_symeig_workspace_bytes(m));
+}
+
+// A (m x n, lda) = U diag(s) Y^T, economy size with r = m singular triplets
+// (m <= n expected): U (m x m), s (m), Y (n x m).  Singular values below
+// rcut * s_max get a zero right vector.
+int dot_svd_thin(int m, int n, const double* A_dev, int lda, double* s_dev, double* U_dev,
+                 int ldu, double* Y_dev, int ldy, double rcut, void* work_dev, size_t work_bytes,
+                 void* stream) {
+  clear_error();
+  if (m < 1 || n < 1 || m > 8192) DOT_FAIL(DOT_EINVAL, "need 1 <= m <= 8192, n >= 1");
+  if (lda < m || ldu < m || ldy < n) DOT_FAIL(DOT_EINVAL, "leading dimension too small");
+  if (!A_dev || !s_dev || !U_dev || !Y_dev || !work_dev) DOT_FAIL(DOT_EINVAL, "NULL argument");
+  if (!(rcut >= 0.0)) DOT_FAIL(DOT_EINVAL, "rcut must be >= 0");
+  const size_t need = dot_svd_workspace_bytes(m, n);
+  if (work_bytes < need) DOT_FAIL(DOT_ENOMEM, "workspace too small: need %zu", need);
+  hipStream_t s = as_stream(stream);
+  char* wb = (char*)work_dev;
+  double* G = (double*)wb;
+  double* Us = (double*)(wb + al256((size_t)m * m * 8));
+  double* lam = (double*)(wb + 2 * al256((size_t)m * m * 8));
+  char* rest = wb + 2 * al256((size_t)m * m * 8) + al256((size_t)m * 8);
+  if (lda != m) DOT_FAIL(DOT_EINVAL, "lda must equal m");
+  GramDesc d{m, n, 1, 1, m, (int64_t)m * n};
+  DOT_TRY_L(gram(d, A_dev, G, (double*)rest, s));
+  DOT_TRY_L(symeig(m, G, m, lam, U_dev, ldu, rest, s, 60, nullptr));
+  hipLaunchKernelGGL(sqrt_clamp_kernel, dim3((m + 255) / 256), dim3(256), 0, s, m, lam, s_dev);
+  DOT_LAUNCH_CHECK();
+  // Y = A^T U diag(1/s) for s > rcut s_max
+  std::vector<double> l0(1);
+  DOT_HIP(hipMemcpyAsync(l0.data(), lam, sizeof(double), hipMemcpyDeviceToHost, s));
+  DOT_HIP(hipStreamSynchronize(s));
+  const double cut = (rcut * rcut) * std::max(l0[0], 0.0);
+  const unsigned b = (unsigned)(((int64_t)m * m + 255) / 256);
+  hipLaunchKernelGGL(scale_cols_inv_sqrt_kernel, dim3(b), dim3(256), 0, s, m, m, U_dev, ldu, lam,
+                     std::max(cut, 1e-300), Us, m);
+  DOT_LAUNCH_CHECK();
+  DOT_TRY_L(gemm_launch(1, 0, n, m, m, 1.0, A_dev, lda, Us, m, 0.0, Y_dev, ldy, s));
+  return DOT_OK;
+}
+
+}  // extern "C"

@@ -91,6 +91,16 @@ __global__ __launch_bounds__(256) void gemm_kernel(int ta, int tb, int m, int n,
   }
 }
 
+int gemm_launch(int transa, int transb, int m, int n, int kdim, double alpha, const double* A,
+                int lda, const double* B, int ldb, double beta, double* C, int ldc, hipStream_t s) {
+  if (m == 0 || n == 0) return DOT_OK;
+  dim3 grid((n + 15) / 16, (m + 15) / 16);
+  hipLaunchKernelGGL(gemm_kernel, grid, dim3(256), 0, s, transa, transb, m, n, kdim, alpha, A, lda, B,
+                     ldb, beta, C, ldc);
+  DOT_LAUNCH_CHECK();
+  return DOT_OK;
+}
+
 }  // namespace dot
 
 using namespace dot;
@@ -157,11 +167,10 @@ int dot_gemm(int transa, int transb, int m, int n, int kdim, double alpha, const
   const int arows = transa ? kdim : m, brows = transb ? n : kdim;
   if (lda < std::max(1, arows) || ldb < std::max(1, brows) || ldc < std::max(1, m))
     DOT_FAIL(DOT_EINVAL, "leading dimension too small");
-  dim3 grid((n + 15) / 16, (m + 15) / 16);
-  hipLaunchKernelGGL(gemm_kernel, grid, dim3(256), 0, as_stream(stream), transa, transb, m, n, kdim,
-                     alpha, A_dev, lda, B_dev, ldb, beta, C_dev, ldc);
-  DOT_LAUNCH_CHECK();
-  return DOT_OK;
+  if ((int64_t)(n + 15) / 16 > 2147483647 || (m + 15) / 16 > 65535)
+    DOT_FAIL(DOT_EINVAL, "matrix too large for dot_gemm");
+  return gemm_launch(transa, transb, m, n, kdim, alpha, A_dev, lda, B_dev, ldb, beta, C_dev, ldc,
+                     as_stream(stream));
 }
 
 }  // extern "C"

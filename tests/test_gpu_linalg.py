@@ -1,0 +1,146 @@
+"""GPU dense linear algebra behind Alg. 1 and the Gauss-Newton SVD, against
+LAPACK (numpy) and the oracle's Alg. 1.  Where several results are correct
+(eigenvector signs, bases of invariant subspaces) projectors are compared."""
+
+import numpy as np
+import pytest
+import torch
+
+import synthetic
+from oracle import design as odesign
+from oracle import estimators as oest
+from oracle import problem as oprob
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dl():
+    import paper_1706_05586_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return torch.device("cuda:0")
+
+
+def T(x, dev):
+    return torch.tensor(np.asarray(x, dtype=np.float64), device=dev)
+
+
+@pytest.mark.parametrize("n", [1, 5, 40, 64, 65, 130, 513, 600])
+def test_symeig_matches_lapack(dl, dev, n):
+    rng = np.random.default_rng(n)
+    X = rng.standard_normal((n, n))
+    A = X @ X.T + np.diag(np.arange(n, dtype=float))
+    w, V = dl.symeig(T(A, dev))
+    w, V = w.cpu().numpy(), V.cpu().numpy()
+    wr = np.linalg.eigvalsh(A)[::-1]
+    assert np.max(np.abs(w - wr)) <= 1e-12 * np.abs(wr).max()
+    assert np.allclose(V.T @ V, np.eye(n), atol=1e-12)
+    assert np.linalg.norm(A @ V - V * w) <= 1e-11 * np.linalg.norm(A)
+
+
+@pytest.mark.parametrize("n,q", [(12, 3), (256, 10), (40, 40), (7, 0)])
+def test_qr_complete_matches_lapack(dl, dev, n, q):
+    rng = np.random.default_rng(n + q)
+    X = rng.standard_normal((n, q))
+    Q = dl.qr_complete(T(X, dev)).cpu().numpy()
+    assert np.allclose(Q.T @ Q, np.eye(n), atol=1e-13)
+    if q > 0:
+        Qr, _ = np.linalg.qr(X, mode="complete")
+        assert np.allclose(Q, Qr, atol=1e-12)          # same reflector convention
+        P = X @ np.linalg.pinv(X)
+        assert np.allclose(Q[:, :q] @ Q[:, :q].T, P, atol=1e-12)
+
+
+def test_mode_grams_match_tensordot(dl, dev):
+    rng = np.random.default_rng(3)
+    dA, dB, dC = 7, 5, 900
+    Tn = rng.standard_normal((dA, dB, dC))
+    flat = T(Tn.reshape(-1, order="F"), dev)
+    G0 = dl.mode_gram(flat, (dA, dB, dC), 0).cpu().numpy()
+    G1 = dl.mode_gram(flat, (dA, dB, dC), 1).cpu().numpy()
+    assert np.allclose(G0, np.einsum("abc,dbc->ad", Tn, Tn), rtol=1e-13, atol=1e-10)
+    assert np.allclose(G1, np.einsum("abc,adc->bd", Tn, Tn), rtol=1e-13, atol=1e-10)
+
+
+def _jac_case(name):
+    wl = synthetic.make_workload(synthetic.get_config(name))
+    prob = oprob.build(wl)
+    W, V = oest.sample_matrix(wl.w_signs), oest.sample_matrix(wl.v_signs)
+    data = oprob.synthetic_data(prob, wl)
+    ref = oprob.evaluate(prob, wl, wl.theta_ref, W, V, data)
+    return wl, W, V, ref
+
+
+@pytest.mark.parametrize("qd,qs", [(1, 1), (2, 3), (3, 2)])
+def test_hooi_matches_oracle_on_random_tensor(dl, dev, qd, qs):
+    rng = np.random.default_rng(10 * qd + qs)
+    n_d, n_s, n_p = 9, 8, 30
+    J = rng.standard_normal((n_d * n_s, n_p))
+    Wg, Vg, it, obj = dl.hooi(T(J, dev), n_d, n_s, qd, qs, tol=1e-12, maxit=200)
+    Wr, Vr, hist, itr = odesign.hooi(J, n_d, n_s, qd, qs, tol=1e-12, maxit=200)
+    Wg, Vg = Wg.cpu().numpy(), Vg.cpu().numpy()
+    assert obj == pytest.approx(hist[-1], rel=1e-10)
+    assert obj == pytest.approx(odesign.objective(J, Wg, Vg), rel=1e-10)
+    # HOOI converges linearly: two runs stopped by the same projector-change
+    # test can sit ~1e-7 apart when singular values are poorly separated
+    assert np.linalg.norm(Wg @ Wg.T - Wr @ Wr.T) < 1e-6
+    assert np.linalg.norm(Vg @ Vg.T - Vr @ Vr.T) < 1e-6
+
+
+def test_hooi_theorem_3_2_one_iteration(dl, dev):
+    rng = np.random.default_rng(5)
+    n_s, n_d, n_p, qs, qd = 12, 10, 7, 3, 2
+    W0, _ = np.linalg.qr(rng.standard_normal((n_s, qs)))
+    V0, _ = np.linalg.qr(rng.standard_normal((n_d, qd)))
+    J = np.kron(W0, V0) @ rng.standard_normal((qs * qd, n_p))
+    Wg, Vg, it, obj = dl.hooi(T(J, dev), n_d, n_s, qd, qs, tol=0.0, maxit=1)
+    assert obj == pytest.approx(np.sum(J ** 2), rel=1e-12)
+    Wg = Wg.cpu().numpy()
+    assert np.linalg.norm(Wg @ Wg.T - W0 @ W0.T) < 1e-10
+
+
+@pytest.mark.parametrize("name", ["t3d_b", "t3d_c"])
+def test_optimized_design_matches_oracle(dl, dev, name):
+    wl, W, V, ref = _jac_case(name)
+    Js = ref["Js"]
+    ls, ld = W.shape[1], V.shape[1]
+    qs = qd = 2
+    ys = wl.y_signs if wl.y_signs.shape == (W.shape[0] - qs, ls - qs) else \
+        np.sign(np.random.default_rng(1).standard_normal((W.shape[0] - qs, ls - qs)))
+    zs = wl.z_signs if wl.z_signs.shape == (V.shape[0] - qd, ld - qd) else \
+        np.sign(np.random.default_rng(2).standard_normal((V.shape[0] - qd, ld - qd)))
+    Wn, Vn, info = dl.optimized_design(T(Js, dev), T(W, dev), T(V, dev), qs, qd, T(ys, dev),
+                                       T(zs, dev))
+    Wn, Vn = Wn.cpu().numpy(), Vn.cpu().numpy()
+    # oracle: Alg. 1 on the sampled tensor, lift, complement
+    Wt, Vt, hist, _ = odesign.hooi(Js, ld, ls, qd, qs)
+    What, Vhat = odesign.lift(W, Wt), odesign.lift(V, Vt)
+    assert info["objective"] == pytest.approx(hist[-1], rel=1e-9)
+    for new, hat, signs, q, l in ((Wn, What, ys, qs, ls), (Vn, Vhat, zs, qd, ld)):
+        assert new.shape == (hat.shape[0], l)
+        P = new[:, :q] @ new[:, :q].T
+        assert np.linalg.norm(P - hat @ hat.T) < 1e-8
+        assert np.allclose(new[:, :q].T @ new[:, :q], np.eye(q), atol=1e-12)
+        comp = new[:, q:]
+        assert np.allclose(new[:, :q].T @ comp, 0.0, atol=1e-12)
+        Y = signs / np.sqrt(l - q)
+        assert np.allclose(comp.T @ comp, Y.T @ Y, atol=1e-12)   # W_c orthonormal
+        # same Householder convention as LAPACK: identical complement
+        Wc = odesign.orthonormal_complement(odesign.lift(
+            W if hat is What else V, Wt if hat is What else Vt))
+        assert np.allclose(comp, Wc @ Y, atol=1e-8)
+
+
+@pytest.mark.parametrize("m,n", [(20, 60), (64, 64), (150, 400)])
+def test_svd_thin_matches_lapack(dl, dev, m, n):
+    rng = np.random.default_rng(m)
+    A = rng.standard_normal((m, n)) @ np.diag(np.logspace(0, -3, n))
+    s, U, Y = dl.svd_thin(T(A, dev), rcut=1e-10)
+    s, U, Y = s.cpu().numpy(), U.cpu().numpy(), Y.cpu().numpy()
+    sr = np.linalg.svd(A, compute_uv=False)
+    assert np.max(np.abs(s - sr)) <= 1e-10 * sr[0]
+    assert np.linalg.norm((U * s) @ Y.T - A) <= 1e-10 * np.linalg.norm(A)
