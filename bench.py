@@ -1,18 +1,22 @@
-"""Benchmark of one step of the randomized DOT hot path on one MI355X.
+"""Benchmark of the randomized DOT hot path on one MI355X.
 
-Workload (the 128^3 configuration): 3D diffusion on 128^3 cells (2,097,152
+Workload (128^3 configuration): 3D diffusion on 128^3 cells (2,097,152
 unknowns), Robin top/bottom and Dirichlet lateral faces, 256 sources on the
 top face and 256 detectors on the bottom face, l_s = l_d = 20 simultaneous
-sources/detectors, PaLS absorption with 64 RBFs (320 parameters).  A step is
-one pass of the whole hot path over that batch:
-  PaLS absorption and A(theta) -> right-hand sides B W and C V -> the 40
-  forward + adjoint solves to a per-column relative residual of 1e-8
-  (binary32 CG inside binary64 refinement) -> sampled misfit -> sampled
-  Jacobian (400 x 320) -> adjoint gradient.
-The metric is right-hand sides solved per second over whole steps.  A second
-leg times the same 40 solves in plain binary64 CG at the same 1e-8.
+sources and detectors made of 10 optimized directions (Alg. 1 on a sampled
+Jacobian) plus 10 random directions in their orthogonal complement, PaLS
+absorption with 64 RBFs (320 parameters).  One step is one pass of the whole
+hot path:
+  PaLS absorption and A(theta) -> B W and C V -> the 40 forward + adjoint
+  solves to per-column relative residual 1e-8 (binary32 CG in binary64
+  refinement) -> sampled misfit -> split-bfloat16 sampled Jacobian (400 x 320)
+  -> adjoint gradient -> Alg. 1 + lift + complement (next optimized design)
+  -> thin SVD of the sampled Jacobian (Gauss-Newton model).
+The metric is right-hand sides solved per second over whole steps.  Legs
+beside it: the same 40 solves in plain binary64 CG at equal 1e-8, and the
+1600 x 5000 Jacobian of the 128^3, 1000-RBF configuration (TFLOP/s).
 
-Printed: one JSON line (see keys below); progress goes to stderr.
+Prints one JSON line; progress goes to stderr.
 """
 
 from __future__ import annotations
@@ -29,7 +33,9 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per cell per column for each CG pass (vector streams only)
+BF16_PEAK_TFLOPS = 2500.0
+FP64_PEAK_TFLOPS = 78.6
+# algorithmic bytes per cell per column of each CG pass (vector streams only)
 PASS_BYTES = {
     "pcg1_fp32": 12,   # read r, p_old; write p      (binary32)
     "pcg2_fp32": 20,   # read p, d, r; write d, r    (binary32)
@@ -50,8 +56,18 @@ def parse():
     ap.add_argument("--config", default="C3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-leg", action="store_true")
+    ap.add_argument("--no-jacobian-leg", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=120)
     return ap.parse_args()
+
+
+def setup_fields(dl, L, torch, dev, cfg, wl, op, pals, W, V, precision, rtol=1e-8):
+    ls, ld = W.shape[1], V.shape[1]
+    rhs = dl.empty_colmajor(op.N, ls + ld, dev)
+    op.form_rhs(wl.src_cells, W, out=rhs[:, :ls])
+    op.form_rhs(wl.det_cells, V, out=rhs[:, ls:])
+    res = op.solve(rhs, rtol=rtol, precision=precision)
+    return res.x[:, :ls], res.x[:, ls:]
 
 
 def main():
@@ -82,18 +98,31 @@ def main():
     th_true = torch.tensor(wl.theta_true, device=dev)
     _, D = dl.pals_field(grid, pals, th_ref, cfg.mus_prime)
     op = dl.Operator(grid, D)
-    W = torch.tensor(wl.w_signs / np.sqrt(ls), device=dev)
-    V = torch.tensor(wl.v_signs / np.sqrt(ld), device=dev)
-    # synthetic data: all sources at theta_true, 0.1% relative noise
+    # synthetic data: all sources at theta_true, 0.1% relative noise (binary64
+    # solves, so the binary32 pass kernels run only in the timed workload)
     op.pals_mua(pals, th_true)
     B = op.form_rhs(wl.src_cells, torch.eye(cfg.n_s, dtype=torch.float64, device=dev))
-    # binary64 solves here, so the binary32 pass kernels run only in the timed workload
     full = op.solve(B, rtol=1e-10, precision=L.DOT_FP64)
     M_true = full.x.cpu().numpy()[wl.det_cells, :]
     data = torch.tensor(M_true * (1.0 + cfg.noise * wl.xi), device=dev)
-    DW = dl.gemm(data, W)
     del B, full
-    log("[bench] setup done (data synthesized with 256 solves)")
+    # optimized design: Alg. 1 on the sampled Jacobian of random samples, then
+    # q optimized + (l - q) complementary random directions
+    W0 = torch.tensor(wl.w_signs / np.sqrt(ls), device=dev)
+    V0 = torch.tensor(wl.v_signs / np.sqrt(ld), device=dev)
+    op.pals_mua(pals, th_ref)
+    U0, Z0 = setup_fields(dl, L, torch, dev, cfg, wl, op, pals, W0, V0, L.DOT_FP64, 1e-10)
+    Js0 = op.jacobian(U0, Z0, L.DOT_JAC_FP64)
+    ys = torch.tensor(wl.y_signs, dtype=torch.float64, device=dev)
+    zs = torch.tensor(wl.z_signs, dtype=torch.float64, device=dev)
+    if cfg.q_s > 0:
+        W, V, _ = dl.optimized_design(Js0, W0, V0, cfg.q_s, cfg.q_d, ys, zs)
+    else:
+        W, V = W0, V0
+    DW = dl.gemm(data, W)
+    del U0, Z0, Js0
+    log(f"[bench] setup done: data from {cfg.n_s} solves, W/V = {cfg.q_s} optimized + "
+        f"{ls - cfg.q_s} complementary random")
 
     rhs = dl.empty_colmajor(N, k, dev)
     x = dl.empty_colmajor(N, k, dev)
@@ -114,9 +143,15 @@ def main():
         if full_path:
             U, Z = x[:, :ls], x[:, ls:]
             Rs, f = op.sampled_misfit(wl.det_cells, U, V, DW)
-            Js = op.jacobian(U, Z, L.DOT_JAC_FP64)
+            Js = op.jacobian(U, Z, L.DOT_JAC_SPLIT_BF16)
             g = op.grad_misfit(U, Z, Rs)
-            state.update(f=f, Js=Js, g=g)
+            if cfg.q_s > 0:
+                Wn, Vn, info = dl.optimized_design(Js, W, V, cfg.q_s, cfg.q_d, ys, zs)
+            # Gauss-Newton model: thin SVD of J_s or J_s^T, whichever is wide
+            sv, _, _ = dl.svd_thin(Js.t() if Js.shape[1] <= Js.shape[0] else Js, rcut=1e-10)
+            state.update(f=f, Js=Js, g=g, sv=sv)
+            if cfg.q_s > 0:
+                state.update(W_next=Wn, V_next=Vn, hooi_iters=info["hooi_iters"])
 
     for _ in range(args.warmup):
         step(th_ref)
@@ -129,17 +164,27 @@ def main():
     elapsed = time.perf_counter() - t0
     ms2, n2, cols2 = op.profile_read(L.DOT_PROF_PCG2_FP32)
     ms1, n1, cols1 = op.profile_read(L.DOT_PROF_PCG1_FP32)
+    msj, nj, _ = op.profile_read(L.DOT_PROF_JACOBIAN)
     op.profile_enable(False)
     res = state["res"]
     value = k * args.steps / elapsed
-    log(f"[bench] mixed: {elapsed / args.steps * 1e3:.1f} ms/step, {value:.2f} RHS/s, "
+    solve_ms = None
+    log(f"[bench] step: {elapsed / args.steps * 1e3:.1f} ms, {value:.2f} RHS/s, "
         f"iters={res.iters_max}, updates={res.outer}, relres_max={res.relres.max():.2e}")
 
-    # dominant kernel: CG pass 2 in binary32
     bytes2 = cols2 * N * PASS_BYTES["pcg2_fp32"]
     achieved2 = bytes2 / (ms2 * 1e-3) / 1e9 if ms2 > 0 else 0.0
     bytes1 = cols1 * N * PASS_BYTES["pcg1_fp32"]
     achieved1 = bytes1 / (ms1 * 1e-3) / 1e9 if ms1 > 0 else 0.0
+
+    # solve-only timing of the mixed form (same 40 RHS) for the comparison
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    nrep = max(1, args.steps // 2)
+    for _ in range(nrep):
+        step(th_ref, precision=L.DOT_MIXED, full_path=False)
+    torch.cuda.synchronize()
+    solve_ms = (time.perf_counter() - t1) / nrep * 1e3
 
     # ---------------------------------------------------------- FP64 leg
     fp64 = None
@@ -148,12 +193,10 @@ def main():
                            device=dev)
         work_saved = work
         work = wk64[(-wk64.data_ptr()) % 256:]
-        op.pals_mua(pals, th_ref)
         step(th_ref, precision=L.DOT_FP64, full_path=False)
         torch.cuda.synchronize()
         op.profile_enable(True)
         t1 = time.perf_counter()
-        nrep = max(1, args.steps // 2)
         for _ in range(nrep):
             step(th_ref, precision=L.DOT_FP64, full_path=False)
         torch.cuda.synchronize()
@@ -161,13 +204,19 @@ def main():
         m64, n64, c64 = op.profile_read(L.DOT_PROF_PCG2_FP64)
         op.profile_enable(False)
         r64 = state["res"]
-        fp64 = {"rhs_per_s": k / e64, "ms_per_solve": e64 * 1e3, "iters": int(r64.iters_max),
-                "relres_max": float(r64.relres.max()),
-                "pcg2_achieved_gbs": (c64 * N * PASS_BYTES["pcg2_fp64"] / (m64 * 1e-3) / 1e9)
+        fp64 = {"rhs_per_s": round(k / e64, 3), "ms_per_solve": round(e64 * 1e3, 2),
+                "iters": int(r64.iters_max), "relres_max": float(r64.relres.max()),
+                "pcg2_fp64_achieved_gbs": round(c64 * N * PASS_BYTES["pcg2_fp64"] / (m64 * 1e-3) / 1e9, 1)
                 if m64 > 0 else None}
         work = work_saved
         log(f"[bench] fp64 solve: {e64 * 1e3:.1f} ms, {k / e64:.2f} RHS/s, iters={r64.iters_max}")
         del wk64
+
+    # ---------------------------------------------------------- Jacobian leg
+    jac = None
+    if not args.no_jacobian_leg:
+        jac = jacobian_leg(dl, L, torch, dev)
+        log(f"[bench] jacobian leg: {jac}")
 
     # ---------------------------------------------------------- CPU baseline
     cpu = None
@@ -189,10 +238,12 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {
-            "workload": f"{cfg.name}: 3D DOT {cfg.n[0]}x{cfg.n[1]}x{cfg.n[2]} "
-                        f"({N} cells), {cfg.n_s} sources / {cfg.n_d} detectors, "
-                        f"{ls}+{ld} simultaneous RHS, {cfg.m0} RBFs ({cfg.n_p} params), "
-                        "binary32 CG in binary64 refinement to relres 1e-8",
+            "workload": f"{cfg.name}: 3D DOT {cfg.n[0]}x{cfg.n[1]}x{cfg.n[2]} ({N} cells), "
+                        f"{cfg.n_s} sources / {cfg.n_d} detectors, {ls}+{ld} simultaneous RHS "
+                        f"({cfg.q_s} optimized + {ls - cfg.q_s} complementary random each), "
+                        f"{cfg.m0} RBFs ({cfg.n_p} params), binary32 CG in binary64 refinement "
+                        "to relres 1e-8; step = PaLS, RHS, solves, misfit, split-bf16 Jacobian, "
+                        "gradient, Alg. 1 design, thin SVD",
             "grid": list(cfg.n), "rhs_per_step": k, "rtol": 1e-8, "n_params": cfg.n_p,
         },
         "roofline": {
@@ -207,23 +258,117 @@ def main():
             "avg_launch_us": round(ms2 / max(n2, 1) * 1e3, 2),
             "launches": n2,
             "pass1_achieved_gbs": round(achieved1, 1),
+            "pass1_avg_launch_us": round(ms1 / max(n1, 1) * 1e3, 2),
         },
         "mixed": {"iters": int(res.iters_max), "updates": int(res.outer),
-                  "relres_max": float(res.relres.max())},
+                  "relres_max": float(res.relres.max()), "ms_per_solve": round(solve_ms, 2),
+                  "rhs_per_s_solve_only": round(k / (solve_ms * 1e-3), 3)},
         "fp64": fp64,
-        "speedup_mixed_vs_fp64": (round(value / fp64["rhs_per_s"], 3) if fp64 else None),
+        "speedup_mixed_vs_fp64_solve": (round(fp64["ms_per_solve"] / solve_ms, 3)
+                                        if fp64 else None),
+        "step_jacobian_ms": round(msj / max(nj, 1), 3),
+        "jacobian": jac,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     op.close()
 
 
+def jacobian_leg(dl, L, torch, dev):
+    """1600 x 5000 sampled Jacobian on 128^3 with 1000 RBFs: split-bf16 vs binary64,
+    algorithmic TFLOP/s = 2 l_s l_d n_act (band pairs) / time; error vs binary64
+    and, on a sample of columns, vs the oracle's loop nest."""
+    import synthetic
+
+    cfg = synthetic.get_config("C5")
+    wl = synthetic.make_workload(cfg)
+    grid, pals = dl.Grid.from_config(cfg), dl.Pals.from_config(cfg)
+    th = torch.tensor(wl.theta_ref, device=dev)
+    _, D = dl.pals_field(grid, pals, th, cfg.mus_prime)
+    op = dl.Operator(grid, D)
+    op.pals_mua(pals, th)
+    W = torch.tensor(wl.w_signs / np.sqrt(cfg.l_s), device=dev)
+    V = torch.tensor(wl.v_signs / np.sqrt(cfg.l_d), device=dev)
+    U, Z = setup_fields(dl, L, torch, dev, cfg, wl, op, pals, W, V, L.DOT_MIXED, 1e-8)
+    pairs = op.n_pairs
+    na = pals.n_act(grid.dim)
+    flops = 2.0 * cfg.l_s * cfg.l_d * na * pairs
+    out = {"workload": f"C5: 128^3, {cfg.m0} RBFs, {cfg.l_s}x{cfg.l_d} sampled rows, "
+                       f"{cfg.n_p} params", "band_pairs": pairs, "algorithmic_gflop": flops / 1e9}
+    Js = {}
+    for prec, name in ((L.DOT_JAC_SPLIT_BF16, "split_bf16"), (L.DOT_JAC_SPLIT_BF16X3, "split_bf16x3"),
+                       (L.DOT_JAC_FP64, "fp64")):
+        Js[name] = op.jacobian(U, Z, prec)
+        torch.cuda.synchronize()
+        op.profile_enable(True)
+        for _ in range(5):
+            Js[name] = op.jacobian(U, Z, prec)
+        ms, n, _ = op.profile_read(L.DOT_PROF_JACOBIAN)
+        op.profile_enable(False)
+        t = ms / n * 1e-3
+        out[name] = {"ms": round(ms / n, 3), "tflops_algorithmic": round(flops / t / 1e12, 3)}
+    ref = Js["fp64"]
+    for name in ("split_bf16", "split_bf16x3"):
+        out[name]["rel_err_vs_fp64"] = float(torch.linalg.norm(Js[name] - ref) / torch.linalg.norm(ref))
+    out["split_bf16"]["frac_of_bf16_peak_algorithmic"] = round(
+        out["split_bf16"]["tflops_algorithmic"] / BF16_PEAK_TFLOPS, 5)
+    out["fp64"]["frac_of_fp64_peak"] = round(out["fp64"]["tflops_algorithmic"] / FP64_PEAK_TFLOPS, 4)
+    # sampled oracle check on the columns of three RBFs
+    out["sampled_oracle_rel_err"] = sampled_oracle_columns(wl, U, Z, Js["split_bf16"], [0, 417, 999])
+    # thin SVD of the 1600 x 5000 sampled Jacobian (Gauss-Newton model)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s, _, _ = dl.svd_thin(Js["split_bf16"], rcut=1e-10)
+    torch.cuda.synchronize()
+    out["svd_1600x5000_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
+    op.close()
+    return out
+
+
+def sampled_oracle_columns(wl, U, Z, Js, rbfs):
+    """Oracle loop nest for the Jacobian columns of a few RBFs at full size: the
+    columns of h^3 d mu / d p for RBF m on its support box, then the oracle's
+    sparse loop nest on the fields gathered there."""
+    from oracle import discretization as odisc
+    from oracle import estimators as oest
+    from oracle import pals as opals
+
+    cfg = wl.cfg
+    th = wl.theta_ref
+    cols = opals.active_columns(cfg.active, cfg.dim)
+    na = len(cols)
+    n = tuple(cfg.n)
+    h = odisc.spacing(n)
+    errs = []
+    for m in rbfs:
+        R = 1.0 / th[m, 1]
+        lo = np.maximum(0, np.floor((th[m, 2:] - R) / h - 0.5).astype(int))
+        hi = np.minimum(np.array(n) - 1, np.ceil((th[m, 2:] + R) / h - 0.5).astype(int))
+        axes = [np.arange(lo[a], hi[a] + 1) for a in range(3)]
+        gz, gy, gx = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+        cells = (gx + n[0] * (gy + n[1] * gz)).ravel()
+        x = np.stack([(gx.ravel() + 0.5) * h, (gy.ravel() + 0.5) * h, (gz.ravel() + 0.5) * h], 1)
+        band = (cfg.mu_in - cfg.mu_out) * opals.delta_eps(
+            opals.phi(x, th, cfg.gamma) - cfg.cutoff, cfg.eps)
+        G = h ** 3 * band[:, None] * opals.dphi_dtheta_j(x, th[m], cfg.gamma)[:, cols]
+        keep = np.any(G != 0, axis=1)
+        idx = torch_index(cells[keep], U.device)
+        Jref = oest.jacobian_sparse_loops(U[idx, :].cpu().numpy(), Z[idx, :].cpu().numpy(),
+                                          G[keep])
+        Jgpu = Js[:, m * na:(m + 1) * na].cpu().numpy()
+        errs.append(np.linalg.norm(Jgpu - Jref) / np.linalg.norm(Jref))
+    return float(max(errs))
+
+
+def torch_index(a, device):
+    import torch
+    return torch.tensor(np.asarray(a, dtype=np.int64), device=device)
+
+
 def cpu_baseline(wl, iters, gpu_res):
     """The oracle's Jacobi-PCG (scipy CSR) on one right-hand side of the same
     workload, run for a bounded number of iterations and scaled to the
     iteration count a full solve to 1e-8 needs."""
-    import scipy.sparse.linalg  # noqa: F401
-
     from oracle import estimators as oest
     from oracle import problem as oprob
     from oracle import solvers as osol
@@ -237,12 +382,13 @@ def cpu_baseline(wl, iters, gpu_res):
     t1 = time.perf_counter()
     _, it, rel = osol.pcg_jacobi(A, b, rtol=1e-30, maxiter=iters)
     t_it = (time.perf_counter() - t1) / it
-    need = int(gpu_res.iters_max)   # the GPU binary32 run's count (matches binary64 CG within a few %)
+    need = int(gpu_res.iters_max)
     per_rhs = t_it * need
     return {"value": round(1.0 / per_rhs, 5), "unit": "RHS/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle Jacobi-PCG (scipy CSR, one thread) on 1 RHS of the 128^3 workload: "
-                      f"{it} iterations timed ({t_it * 1e3:.1f} ms each), scaled to {need} "
-                      f"iterations; operator assembly {t_setup:.1f} s not included"}
+            "sample": f"oracle Jacobi-PCG (scipy CSR SpMV, one thread) on 1 RHS of the 128^3 "
+                      f"workload: {it} iterations timed ({t_it * 1e3:.1f} ms each), scaled to the "
+                      f"{need} iterations a 1e-8 solve takes; oracle assembly ({t_setup:.1f} s) "
+                      "not included"}
 
 
 if __name__ == "__main__":

@@ -157,6 +157,11 @@ int dot_set_mua(dot_op* op, const double* mua_dev, void* stream);
 int dot_pals_mua(dot_op* op, const dot_pals* pals, const double* theta_dev, double* mua_dev,
                  void* stream);
 
+/* Number of (RBF, cell) pairs in the band lists of the last dot_pals_mua call:
+ * the nonzeros of G = h^d d mu / d p per active parameter kind, i.e. the cells
+ * the contraction visits summed over RBFs (-1 if no PaLS state). */
+int64_t dot_pals_pairs(const dot_op* op);
+
 /* Y = A X for k columns (X_dev and Y_dev are N x k and must not overlap). */
 int dot_apply(dot_op* op, int k, const double* X_dev, double* Y_dev, void* stream);
 

@@ -75,6 +75,7 @@ SIGNATURES = {
     "dot_build_operator": (_i, [C.POINTER(DotGrid), _vp, _vp, C.POINTER(_vp)]),
     "dot_destroy_operator": (_i, [_vp]),
     "dot_operator_cells": (_i64, [_vp]),
+    "dot_pals_pairs": (_i64, [_vp]),
     "dot_set_mua": (_i, [_vp, _vp, _vp]),
     "dot_pals_mua": (_i, [_vp, C.POINTER(DotPals), _vp, _vp, _vp]),
     "dot_apply": (_i, [_vp, _i, _vp, _vp, _vp]),

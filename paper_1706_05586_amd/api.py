@@ -315,6 +315,11 @@ class Operator:
         self.pals = pals
         return mua
 
+    @property
+    def n_pairs(self) -> int:
+        """(RBF, cell) pairs of the band lists of the last pals_mua call."""
+        return int(lib.dot_pals_pairs(self._handle))
+
     def apply(self, X: torch.Tensor) -> torch.Tensor:
         X2 = X.reshape(-1, 1) if X.dim() == 1 else X
         Xm = colmajor(X2, "X")

@@ -499,6 +499,8 @@ int dot_destroy_operator(dot_op* op) {
 
 int64_t dot_operator_cells(const dot_op* op) { return op ? op->g.N : -1; }
 
+int64_t dot_pals_pairs(const dot_op* op) { return (op && op->have_pals) ? op->n_pairs : -1; }
+
 int dot_set_mua(dot_op* op, const double* mua_dev, void* stream) {
   clear_error();
   if (!op) DOT_FAIL(DOT_EINVAL, "op is NULL");
