@@ -277,11 +277,12 @@ int dot_mode_gram(int dA, int dB, int dC, const double* T_dev, int mode, double*
                   void* work_dev, size_t work_bytes, void* stream);
 
 /*
- * Symmetric eigensolver (cyclic Jacobi): A_dev (n x n, lda) is not modified;
- * w_dev receives the eigenvalues in descending order and V_dev (n x n, ldv)
- * the orthonormal eigenvectors in the same order.  *sweeps_host (if not
- * NULL) receives the number of Jacobi sweeps (-1 for the one-block n <= 64
- * path).  n <= 8192.  Synchronizes the stream when n > 64.
+ * Symmetric eigensolver (cyclic Jacobi; block Jacobi on 16-index blocks
+ * for n > 64): A_dev (n x n, lda) is not modified; w_dev receives the
+ * eigenvalues in descending order and V_dev (n x n, ldv) the orthonormal
+ * eigenvectors in the same order.  *sweeps_host (if not NULL) receives the
+ * number of block sweeps (-1 for the one-block n <= 64 path).  n <= 8192.
+ * Synchronizes the stream once per sweep when n > 64.
  */
 size_t dot_symeig_workspace_bytes(int n);
 int dot_symeig(int n, const double* A_dev, int lda, double* w_dev, double* V_dev, int ldv,

@@ -29,17 +29,53 @@ def T(x, dev):
     return torch.tensor(np.asarray(x, dtype=np.float64), device=dev)
 
 
-@pytest.mark.parametrize("n", [1, 5, 40, 64, 65, 130, 513, 600])
+EPS = np.finfo(np.float64).eps
+
+
+def check_eig(A, w, V, thresh=30.0):
+    """LAPACK's eigensolver test ratios (residual, orthogonality and eigenvalue
+    error, each over n eps ||A||) below thresh: a sequence of orthogonal
+    similarity transforms has a backward error that grows like n eps."""
+    n = A.shape[0]
+    wr = np.linalg.eigvalsh(A)[::-1]
+    nA = max(np.linalg.norm(A, 2), 1e-300)
+    assert np.max(np.abs(w - wr)) <= thresh * n * EPS * nA
+    assert np.linalg.norm(V.T @ V - np.eye(n), 1) <= thresh * n * EPS
+    assert np.linalg.norm(A @ V - V * w, 1) <= thresh * n * EPS * np.linalg.norm(A, 1)
+
+
+@pytest.mark.parametrize("n", [1, 5, 40, 64, 65, 130, 513, 600, 1600])
 def test_symeig_matches_lapack(dl, dev, n):
     rng = np.random.default_rng(n)
     X = rng.standard_normal((n, n))
     A = X @ X.T + np.diag(np.arange(n, dtype=float))
     w, V = dl.symeig(T(A, dev))
+    check_eig(A, w.cpu().numpy(), V.cpu().numpy())
+
+
+@pytest.mark.parametrize("n,r", [(100, 30), (333, 7), (70, 0)])
+def test_symeig_rank_deficient_gram(dl, dev, n, r):
+    """A Gram matrix of rank r: n - r zero eigenvalues in one cluster, a graded
+    nonzero spectrum (the shape of J_s J_s^T), and an all-zero matrix."""
+    rng = np.random.default_rng(n + r)
+    X = rng.standard_normal((n, r)) @ np.diag(np.logspace(0, -4, r)) if r else np.zeros((n, 1))
+    A = X @ X.T
+    w, V = dl.symeig(T(A, dev))
     w, V = w.cpu().numpy(), V.cpu().numpy()
-    wr = np.linalg.eigvalsh(A)[::-1]
-    assert np.max(np.abs(w - wr)) <= 1e-12 * np.abs(wr).max()
-    assert np.allclose(V.T @ V, np.eye(n), atol=1e-12)
-    assert np.linalg.norm(A @ V - V * w) <= 1e-11 * np.linalg.norm(A)
+    check_eig(A, w, V)
+    assert np.all(np.diff(w) <= 0.0)
+
+
+def test_symeig_indefinite_with_ties(dl, dev):
+    """Indefinite matrix with repeated eigenvalues: Q diag(d) Q^T."""
+    rng = np.random.default_rng(5)
+    n = 150
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    d = np.repeat([3.0, -2.0, 0.5, -7.0, 1e-3], n // 5)
+    A = (Q * d) @ Q.T
+    A = 0.5 * (A + A.T)
+    w, V = dl.symeig(T(A, dev))
+    check_eig(A, w.cpu().numpy(), V.cpu().numpy())
 
 
 @pytest.mark.parametrize("n,q", [(12, 3), (256, 10), (40, 40), (7, 0)])
@@ -135,7 +171,7 @@ def test_optimized_design_matches_oracle(dl, dev, name):
         assert np.allclose(comp, Wc @ Y, atol=1e-8)
 
 
-@pytest.mark.parametrize("m,n", [(20, 60), (64, 64), (150, 400)])
+@pytest.mark.parametrize("m,n", [(20, 60), (64, 64), (150, 400), (320, 400), (1600, 5000)])
 def test_svd_thin_matches_lapack(dl, dev, m, n):
     rng = np.random.default_rng(m)
     A = rng.standard_normal((m, n)) @ np.diag(np.logspace(0, -3, n))
