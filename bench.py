@@ -58,7 +58,22 @@ def parse():
     ap.add_argument("--no-fp64-leg", action="store_true")
     ap.add_argument("--no-jacobian-leg", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=120)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB between two device buffers 5 times (reference "
+                         "kernel for scaling the FETCH_SIZE / WRITE_SIZE counters) and exit")
     return ap.parse_args()
+
+
+def calibrate_copy(mib):
+    import torch
+    n = mib * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes_read": n * 4, "calibrate_copy_bytes_written": n * 4,
+                      "launches": 5}), flush=True)
 
 
 def setup_fields(dl, L, torch, dev, cfg, wl, op, pals, W, V, precision, rtol=1e-8):
@@ -77,6 +92,10 @@ def main():
               "MI355X (the multi-GPU sharding is described in DESIGN.md, not run); "
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
 
     import torch
 
@@ -289,7 +308,9 @@ def jacobian_leg(dl, L, torch, dev):
     op.pals_mua(pals, th)
     W = torch.tensor(wl.w_signs / np.sqrt(cfg.l_s), device=dev)
     V = torch.tensor(wl.v_signs / np.sqrt(cfg.l_d), device=dev)
-    U, Z = setup_fields(dl, L, torch, dev, cfg, wl, op, pals, W, V, L.DOT_MIXED, 1e-8)
+    # binary64 solves, so every binary32 CG pass of the run belongs to the
+    # timed 128^3, 64-RBF workload
+    U, Z = setup_fields(dl, L, torch, dev, cfg, wl, op, pals, W, V, L.DOT_FP64, 1e-8)
     pairs = op.n_pairs
     na = pals.n_act(grid.dim)
     flops = 2.0 * cfg.l_s * cfg.l_d * na * pairs
