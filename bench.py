@@ -44,6 +44,31 @@ PASS_BYTES = {
 }
 
 
+# HBM bytes per launch of the binary32 CG passes on this workload, from the
+# FETCH_SIZE (x 1.99983, calibrated on a 320 MiB copy) and WRITE_SIZE counter
+# runs summarized in profiles/sweep_pcg_fp32_128cube_40rhs_hbm_traffic.md; valid
+# while the sweep kernel sources hash to the value recorded with them.
+TRAFFIC = {
+    "sources": ("paper_1706_05586_amd/csrc/solve.hip", "paper_1706_05586_amd/csrc/dot_internal.h"),
+    "sha256": "76a2dc993992d247f495c695784ea9e4d5364e9ac8be6462faeb446e15687ab0",
+    "config": "C3",
+    "pcg2_fp32_bytes_per_launch": 1.7731e9,
+    "pcg1_fp32_bytes_per_launch": 1.3255e9,
+}
+
+
+def measured_traffic(config_name):
+    """Counter-measured bytes per launch, or None once the kernel has changed."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC["sources"]:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != TRAFFIC["sha256"] or config_name != TRAFFIC["config"]:
+        return None
+    return TRAFFIC
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -243,6 +268,7 @@ def main():
         cpu = cpu_baseline(wl, args.cpu_iters, res)
         log(f"[bench] cpu baseline: {cpu}")
 
+    traffic = measured_traffic(cfg.name)
     out = {
         "metric": "RHS solves/sec at rel-res 1e-8 (128^3) + Jacobian TFLOP/s, mixed vs FP64",
         "value": round(value, 3),
@@ -272,8 +298,10 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved2 / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": (traffic["pcg2_fp32_bytes_per_launch"] if traffic else None),
+            "traffic_unit": "B per launch (FETCH_SIZE x 1.99983 + WRITE_SIZE)",
             "bytes_per_cell_column": PASS_BYTES["pcg2_fp32"],
+            "algorithmic_bytes_per_launch": round(bytes2 / max(n2, 1)),
             "avg_launch_us": round(ms2 / max(n2, 1) * 1e3, 2),
             "launches": n2,
             "pass1_achieved_gbs": round(achieved1, 1),

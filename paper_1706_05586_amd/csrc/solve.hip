@@ -14,18 +14,22 @@
 // alpha, beta, norms and the convergence mask live on the device; the host
 // polls the number of active columns every few iterations.
 //
-// Mixed precision: binary32 PCG on A^ d = r / |r| inside binary64 iterative
-// refinement (binary64 residual b^ - A^ x^, update x^ += |r| d, stopping
-// test on the binary64 residual).
+// Mixed precision: binary32 CG on the scaled system with binary64 reliable
+// updates (solve_mixed below): the binary32 correction is folded into the
+// binary64 x^ and the binary32 residual is replaced by the binary64 b^ - A^ x^
+// whenever it has dropped by inner_rtol; the search direction is kept, and
+// every stopping decision is taken on the binary64 residual.
 //
-// Kernel layout for gfx950: a block is a 64 x 8 tile in (x, y) (one wave per
+// Kernel layout for gfx950: a block is a 64 x TY tile in (x, y) (one wave per
 // x row) marching through a chunk of z planes; z neighbours stay in
-// registers, x/y neighbours come from an LDS plane with a one-cell halo.  A
-// block processes a group of RG columns so each coefficient is loaded once
-// per cell per group.  Blocks are renumbered so that each of the 8 XCDs
-// gets a contiguous run of tiles (halo reuse in its L2).  Reductions are
-// deterministic: wave shuffles, then LDS in fixed order, then per-block
-// partials summed in fixed order by a one-block finalize kernel.
+// registers, x/y neighbours come from a double-buffered LDS plane with a
+// one-cell halo that is prefetched one plane ahead.  A block processes a
+// group of RG columns so each coefficient is loaded once per cell per group;
+// the column group varies fastest in the block order, so the groups of one
+// tile run together and share its coefficients in L2, and the tiles are
+// spread over the 8 XCDs in contiguous runs.  Reductions are deterministic:
+// wave shuffles, then LDS in fixed order, then per-block partials summed in
+// fixed order by a finalize kernel (one block per column).
 #include <algorithm>
 #include <vector>
 
@@ -48,6 +52,9 @@ namespace dot {
 #endif
 #ifndef DOT_ZMIN
 #define DOT_ZMIN 8
+#endif
+#ifndef DOT_PADW
+#define DOT_PADW 1088
 #endif
 constexpr int TX = 64;              // one wave per x row
 constexpr int TY = DOT_TY;          // rows per tile
@@ -86,6 +93,7 @@ enum { FLAG_BREAKDOWN = 1, FLAG_NONFINITE = 2 };
 struct Geom {
   int nx, ny, nz;
   int64_t nxy, N;
+  int64_t ldw;   // column stride of the library's own work vectors (>= N)
   int tiles_x, ntiles, zc, nzc, k;
   int nblk_col;  // ntiles * nzc: partial slots per column
 };
@@ -117,6 +125,9 @@ struct SweepArgs {
   const double* sd;    // sqrt(diag)
   const int* active;   // per column, NULL = all
   const double* coef;  // beta (PCG1), alpha (PCG2)
+  // column strides of in0, in1, out0, out1 (0 = N, the caller's layout)
+  int64_t ld_in0, ld_in1, ld_out0, ld_out1;
+  bool norm_s;         // PCG2: also accumulate |S r|^2 (reads sqrt(diag))
   const T* in0;        // APPLY/TRUE: x; PCG1: r; PCG2: p; RESID: x^
   const T* in1;        // PCG1: p_old (zero before the first iteration)
   const double* b;     // TRUE/RESID: right-hand side
@@ -238,12 +249,12 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs<T> a) {
     const int j = grp * RG + r;
     act[r] = j < G.k && (a.active == nullptr || a.active[j] != 0);
     cf[r] = (act[r] && a.coef) ? (T)a.coef[j] : T(0);
-    const int64_t off = G.N * (int64_t)(j < G.k ? j : 0);
-    in0[r] = a.in0 + off;
-    in1[r] = TWO ? a.in1 + off : nullptr;
-    out0[r] = a.out0 ? a.out0 + off : nullptr;
-    out1[r] = a.out1 ? a.out1 + off : nullptr;
-    bcol[r] = a.b ? a.b + off : nullptr;
+    const int64_t jj = j < G.k ? j : 0;
+    in0[r] = a.in0 + (a.ld_in0 ? a.ld_in0 : G.N) * jj;
+    in1[r] = TWO ? a.in1 + (a.ld_in1 ? a.ld_in1 : G.N) * jj : nullptr;
+    out0[r] = a.out0 ? a.out0 + (a.ld_out0 ? a.ld_out0 : G.N) * jj : nullptr;
+    out1[r] = a.out1 ? a.out1 + (a.ld_out1 ? a.ld_out1 : G.N) * jj : nullptr;
+    bcol[r] = a.b ? a.b + G.N * jj : nullptr;
     any |= act[r];
   }
   if (!any) return;  // uniform over the block
@@ -338,7 +349,10 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs<T> a) {
     T dd = T(1);
     double sdc = 1.0;
     if constexpr (MODE == M_APPLY || MODE == M_TRUE) dd = (T)ld(a.diag, c);
-    if constexpr (MODE == M_PCG2 || MODE == M_RESID) sdc = ld(a.sd, c);
+    if constexpr (MODE == M_RESID) sdc = ld(a.sd, c);
+    // block-uniform: the sqrt(diag) stream is read only when the caller
+    // wants the unscaled norm of this iteration
+    if constexpr (MODE == M_PCG2) sdc = a.norm_s ? ld(a.sd, c) : 1.0;
     T o0[RG], o1[RG];
     double bo[RG];
 #pragma unroll
@@ -401,8 +415,10 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs<T> a) {
           st(out1[r], c, rn);
           const double rd = (double)rn;
           acc[r][0] += rd * rd;
-          const double t = sdc * rd;
-          acc[r][1] += t * t;
+          if (a.norm_s) {
+            const double t = sdc * rd;
+            acc[r][1] += t * t;
+          }
         }
       } else if constexpr (MODE == M_RESID) {
         const double rr = bo[r] / sdc - (double)Av;
@@ -475,27 +491,28 @@ __global__ __launch_bounds__(NT) void elt_kernel(EltArgs a) {
 #pragma unroll
       for (int r = 0; r < RG; ++r) {
         if (!act[r]) continue;
-        const int64_t o = c + G.N * (int64_t)col[r];
+        const int64_t o = c + G.N * (int64_t)col[r];     // caller's arrays
+        const int64_t w = c + G.ldw * (int64_t)col[r];   // work vectors
         if constexpr (MODE == E_INIT) {
           const double bv = a.b[o];
           const double rv = bv / a.sd[c];
           a.xh[o] = 0.0;
-          a.r64[o] = rv;
-          if (a.d32) a.d32[o] = 0.0f;
-          if (a.p64z) a.p64z[o] = 0.0;
-          if (a.p32z) a.p32z[o] = 0.0f;
+          a.r64[w] = rv;
+          if (a.d32) a.d32[w] = 0.0f;
+          if (a.p64z) a.p64z[w] = 0.0;
+          if (a.p32z) a.p32z[w] = 0.0f;
           acc[r][0] += rv * rv;
           acc[r][1] += bv * bv;
         } else if constexpr (MODE == E_REPLACE) {
-          const float rv = (float)(a.r64[o] / sc[r]);
-          a.r32[o] = rv;
+          const float rv = (float)(a.r64[w] / sc[r]);
+          a.r32[w] = rv;
           const double rd = (double)rv;
           acc[r][0] += rd * rd;
           const double t = a.sd[c] * rd;
           acc[r][1] += t * t;
         } else if constexpr (MODE == E_FOLD) {
-          a.xh[o] += sc[r] * (double)a.d32[o];
-          a.d32[o] = 0.0f;
+          a.xh[o] += sc[r] * (double)a.d32[w];
+          a.d32[w] = 0.0f;
         } else if constexpr (MODE == E_UNSCALE) {
           a.xh[o] = a.xh[o] / a.sd[c];
         }
@@ -514,6 +531,7 @@ struct FinArgs {
   const int* live;
   ColState st;
   double rtol, delta;
+  int have_s;   // F_BETA_RU: the sweep accumulated the unscaled norm |S r|^2
 };
 
 __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
@@ -594,13 +612,19 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
         break;
       }
       const double rn = sqrt(s0);
-      const double est = st.scale[j] * sqrt(s1) / st.bnorm[j];
-      st.relres[j] = est;
+      // the unscaled estimate exists on the iterations the host polls,
+      // which are the only ones whose update flags it acts on
+      bool claims = false;
+      if (a.have_s) {
+        const double est = st.scale[j] * sqrt(s1) / st.bnorm[j];
+        st.relres[j] = est;
+        claims = est <= a.rtol;
+      }
       st.rho_prev[j] = st.rho[j];
       st.beta[j] = s0 / st.rho[j];
       st.rho[j] = s0;
       st.rmax[j] = fmax(st.rmax[j], rn);
-      if (rn < a.delta * st.rmax[j] || est <= a.rtol) st.upd[j] = 1;
+      if (rn < a.delta * st.rmax[j] || claims) st.upd[j] = 1;
       break;
     }
     case F_RESID: {  // true binary64 residual after folding the correction
@@ -646,6 +670,9 @@ static Geom make_geom(const GridDims& g, int k) {
   G.nz = g.nz;
   G.nxy = g.nxy;
   G.N = g.N;
+  // work-vector columns DOT_PADW elements apart beyond N, so that the columns
+  // of a group and the vectors of one sweep do not sit a power of two apart
+  G.ldw = g.N + DOT_PADW;
   G.k = k;
   G.tiles_x = (g.nx + TX - 1) / TX;
   const int tiles_y = (g.ny + TY - 1) / TY;
@@ -676,7 +703,7 @@ struct Workspace {
 };
 
 static size_t layout_workspace(const Geom& G, int precision, char* base, Workspace* w) {
-  const size_t Nk = (size_t)G.N * G.k;
+  const size_t Nk = (size_t)G.ldw * G.k;
   size_t off = 0;
   auto take = [&](size_t bytes) -> char* {
     char* p = base ? base + off : nullptr;
@@ -792,8 +819,9 @@ static int launch_elt(const EltArgs& a, hipStream_t s) {
 }
 
 static int launch_fin(int mode, const Geom& G, const Workspace& ws, const int* live, double rtol,
-                      double delta, hipStream_t s) {
+                      double delta, hipStream_t s, int have_s = 1) {
   FinArgs f;
+  f.have_s = have_s;
   f.mode = mode;
   f.k = G.k;
   f.nblk = G.nblk_col;
@@ -889,6 +917,7 @@ static int solve_fp64(dot_op* op, const Geom& G, const Workspace& ws, const doub
     p1.in0 = ws.r64;
     p1.in1 = ws.p64[cur];
     p1.out0 = ws.p64[cur ^ 1];
+    p1.ld_in0 = p1.ld_in1 = p1.ld_out0 = G.ldw;
     p1.partial = ws.partial;
     DOT_TRY(launch_sweep<M_PCG1, double>(op, p1, s, DOT_PROF_PCG1_FP64));
     DOT_TRY(launch_fin(F_ALPHA, G, ws, ws.st.active, o.rtol, 0.0, s));
@@ -899,6 +928,8 @@ static int solve_fp64(dot_op* op, const Geom& G, const Workspace& ws, const doub
     p2.in0 = ws.p64[cur];
     p2.out0 = x;
     p2.out1 = ws.r64;
+    p2.ld_in0 = p2.ld_out1 = G.ldw;
+    p2.norm_s = true;
     p2.partial = ws.partial;
     DOT_TRY(launch_sweep<M_PCG2, double>(op, p2, s, DOT_PROF_PCG2_FP64));
     DOT_TRY(launch_fin(F_BETA, G, ws, ws.st.active, o.rtol, 0.0, s));
@@ -948,6 +979,7 @@ static int solve_mixed(dot_op* op, const Geom& G, const Workspace& ws, const dou
     p1.in0 = ws.r32;
     p1.in1 = ws.p32[cur];
     p1.out0 = ws.p32[cur ^ 1];
+    p1.ld_in0 = p1.ld_in1 = p1.ld_out0 = G.ldw;
     p1.partial = ws.partial;
     DOT_TRY(launch_sweep<M_PCG1, float>(op, p1, s, DOT_PROF_PCG1_FP32));
     DOT_TRY(launch_fin(F_ALPHA, G, ws, ws.st.active, o.rtol, delta, s));
@@ -958,9 +990,12 @@ static int solve_mixed(dot_op* op, const Geom& G, const Workspace& ws, const dou
     p2.in0 = ws.p32[cur];
     p2.out0 = ws.d32;
     p2.out1 = ws.r32;
+    p2.ld_in0 = p2.ld_out0 = p2.ld_out1 = G.ldw;
     p2.partial = ws.partial;
+    const bool polled = (it + 1) % o.check_every == 0 || it + 1 == o.max_iter;
+    p2.norm_s = polled;
     DOT_TRY(launch_sweep<M_PCG2, float>(op, p2, s, DOT_PROF_PCG2_FP32));
-    DOT_TRY(launch_fin(F_BETA_RU, G, ws, ws.st.active, o.rtol, delta, s));
+    DOT_TRY(launch_fin(F_BETA_RU, G, ws, ws.st.active, o.rtol, delta, s, polled ? 1 : 0));
     ++it;
     if (it % o.check_every != 0 && it != o.max_iter) continue;
     DOT_TRY(poll(op, ws, G.k, s, &n_active, &n_upd));
@@ -974,6 +1009,7 @@ static int solve_mixed(dot_op* op, const Geom& G, const Workspace& ws, const dou
     rs.in0 = x;
     rs.b = rhs;
     rs.out0 = ws.r64;
+    rs.ld_out0 = G.ldw;
     rs.partial = ws.partial;
     DOT_TRY(launch_sweep<M_RESID, double>(op, rs, s, DOT_PROF_RESID));
     DOT_TRY(launch_fin(F_RESID, G, ws, ws.st.upd, o.rtol, delta, s));
