@@ -50,10 +50,10 @@ PASS_BYTES = {
 # while the sweep kernel sources hash to the value recorded with them.
 TRAFFIC = {
     "sources": ("paper_1706_05586_amd/csrc/solve.hip", "paper_1706_05586_amd/csrc/dot_internal.h"),
-    "sha256": "76a2dc993992d247f495c695784ea9e4d5364e9ac8be6462faeb446e15687ab0",
+    "sha256": "de90bd4ca6d9e22b95efaf8f3beb7dfce8ec6d10371197f64f9396d033ae91e5",
     "config": "C3",
-    "pcg2_fp32_bytes_per_launch": 1.7731e9,
-    "pcg1_fp32_bytes_per_launch": 1.3255e9,
+    "pcg2_fp32_bytes_per_launch": 1.6774e9,
+    "pcg1_fp32_bytes_per_launch": 1.2882e9,
 }
 
 
@@ -210,6 +210,9 @@ def main():
     ms1, n1, cols1 = op.profile_read(L.DOT_PROF_PCG1_FP32)
     msj, nj, _ = op.profile_read(L.DOT_PROF_JACOBIAN)
     op.profile_enable(False)
+    # error of the step's split-bf16 J_s against binary64 on the same fields
+    J64 = op.jacobian(x[:, :ls], x[:, ls:], L.DOT_JAC_FP64)
+    jac_err = float(torch.linalg.norm(state["Js"] - J64) / torch.linalg.norm(J64))
     res = state["res"]
     value = k * args.steps / elapsed
     solve_ms = None
@@ -314,6 +317,7 @@ def main():
         "speedup_mixed_vs_fp64_solve": (round(fp64["ms_per_solve"] / solve_ms, 3)
                                         if fp64 else None),
         "step_jacobian_ms": round(msj / max(nj, 1), 3),
+        "step_jacobian_rel_err_vs_fp64": jac_err,
         "jacobian": jac,
         "cpu_baseline": cpu,
     }

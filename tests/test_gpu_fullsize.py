@@ -1,0 +1,170 @@
+"""Parity at the full 128^3 sizes, in the launch configuration the benchmark
+times, on outputs the oracle can compute piece by piece:
+
+  * 40-RHS binary32-in-binary64 solve to 1e-8: every column's true relative
+    residual recomputed with the oracle's CSR operator;
+  * sampled misfit from the GPU fields against the oracle's definition;
+  * binary64 and split-bfloat16 J_s on the columns of sampled RBFs against
+    the oracle's sparse loop nest over that RBF's support box;
+  * gradient entries of sampled RBFs against the oracle's adjoint form;
+  * 1000-RBF workload: the same Jacobian check at 1600 x 5000, and the thin
+    SVD of that J_s by reconstruction and orthogonality (properties that hold
+    at any size).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import synthetic
+from oracle import discretization as odisc
+from oracle import estimators as oest
+from oracle import pals as opals
+from oracle import problem as oprob
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dl():
+    import paper_1706_05586_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return torch.device("cuda:0")
+
+
+def support_columns(wl, m):
+    """Cells of RBF m's support box and the oracle's h^3 dmu/dp columns of
+    its active parameters there (rows that are zero are dropped)."""
+    cfg = wl.cfg
+    th = wl.theta_ref
+    cols = opals.active_columns(cfg.active, cfg.dim)
+    n = tuple(cfg.n)
+    h = odisc.spacing(n)
+    R = 1.0 / th[m, 1]
+    lo = np.maximum(0, np.floor((th[m, 2:] - R) / h - 0.5).astype(int))
+    hi = np.minimum(np.array(n) - 1, np.ceil((th[m, 2:] + R) / h - 0.5).astype(int))
+    axes = [np.arange(lo[a], hi[a] + 1) for a in range(3)]
+    gz, gy, gx = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+    cells = (gx + n[0] * (gy + n[1] * gz)).ravel()
+    x = np.stack([(gx.ravel() + 0.5) * h, (gy.ravel() + 0.5) * h, (gz.ravel() + 0.5) * h], 1)
+    band = (cfg.mu_in - cfg.mu_out) * opals.delta_eps(
+        opals.phi(x, th, cfg.gamma) - cfg.cutoff, cfg.eps)
+    G = h ** 3 * band[:, None] * opals.dphi_dtheta_j(x, th[m], cfg.gamma)[:, cols]
+    keep = np.any(G != 0, axis=1)
+    return cells[keep], G[keep], len(cols)
+
+
+def gpu_setup(dl, dev, name, precision, rtol):
+    from paper_1706_05586_amd import _lib as L
+    cfg = synthetic.get_config(name)
+    wl = synthetic.make_workload(cfg)
+    grid, pals = dl.Grid.from_config(cfg), dl.Pals.from_config(cfg)
+    th = torch.tensor(wl.theta_ref, device=dev)
+    _, D = dl.pals_field(grid, pals, th, cfg.mus_prime)
+    op = dl.Operator(grid, D)
+    op.pals_mua(pals, th)
+    W = torch.tensor(wl.w_signs / np.sqrt(cfg.l_s), device=dev)
+    V = torch.tensor(wl.v_signs / np.sqrt(cfg.l_d), device=dev)
+    k = cfg.l_s + cfg.l_d
+    rhs = dl.empty_colmajor(grid.N, k, dev)
+    op.form_rhs(wl.src_cells, W, out=rhs[:, :cfg.l_s])
+    op.form_rhs(wl.det_cells, V, out=rhs[:, cfg.l_s:])
+    print(f"[fullsize] {name}: solving {k} columns, precision {precision}", flush=True)
+    res = op.solve(rhs, rtol=rtol, precision=precision, inner_rtol=0.1, check_every=8)
+    assert res.converged
+    return wl, op, W, V, rhs, res, L
+
+
+def test_128cubed_40rhs_mixed_solve_misfit_jacobian_gradient(dl, dev):
+    wl, op, W, V, rhs, res, L = gpu_setup(dl, dev, "C3", 1, 1e-8)
+    cfg = wl.cfg
+    ls, ld = cfg.l_s, cfg.l_d
+    with op:
+        X = res.x.cpu().numpy()
+        B = rhs.cpu().numpy()
+        prob = oprob.build(wl)
+        A = prob.operator(wl.theta_ref)
+        true_rel = np.linalg.norm(B - A @ X, axis=0) / np.linalg.norm(B, axis=0)
+        print(f"[fullsize] C3 true relres max {true_rel.max():.3e}", flush=True)
+        assert np.all(true_rel <= 1e-8), true_rel.max()
+        assert np.allclose(true_rel, res.relres, rtol=1e-3, atol=1e-13)
+        # misfit with a synthetic data block (the definition is linear in it)
+        rng = np.random.default_rng(7)
+        data = rng.standard_normal((cfg.n_d, cfg.n_s))
+        Wn, Vn = W.cpu().numpy(), V.cpu().numpy()
+        DW = torch.tensor(data @ Wn, device=dev)
+        U, Z = res.x[:, :ls], res.x[:, ls:]
+        Rs, f = op.sampled_misfit(wl.det_cells, U, V, DW)
+        Rs_ref = oest.sampled_residual(X[:, :ls], wl.det_cells, Vn, data @ Wn)
+        assert np.linalg.norm(Rs.cpu().numpy() - Rs_ref) <= 1e-12 * np.linalg.norm(Rs_ref)
+        assert f == pytest.approx(oest.misfit(Rs_ref), rel=1e-12)
+        J64 = op.jacobian(U, Z, L.DOT_JAC_FP64).cpu().numpy()
+        J2 = op.jacobian(U, Z, L.DOT_JAC_SPLIT_BF16).cpu().numpy()
+        g = op.grad_misfit(U, Z, Rs).cpu().numpy()
+        Rn = Rs.cpu().numpy()
+        for m in (0, 21, 42, 63):
+            cells, G, na = support_columns(wl, m)
+            Uc, Zc = X[cells, :ls], X[cells, ls:]
+            Jr = oest.jacobian_sparse_loops(Uc, Zc, G)
+            sl = slice(m * na, (m + 1) * na)
+            e64 = np.linalg.norm(J64[:, sl] - Jr) / np.linalg.norm(Jr)
+            e2 = np.linalg.norm(J2[:, sl] - Jr) / np.linalg.norm(Jr)
+            gr = oest.gradient_adjoint(Uc, Zc, Rn, G)
+            eg = np.linalg.norm(g[sl] - gr) / np.linalg.norm(gr)
+            print(f"[fullsize] C3 RBF {m}: J64 {e64:.2e} split {e2:.2e} grad {eg:.2e}", flush=True)
+            assert e64 <= 1e-11
+            assert e2 <= 1e-6
+            assert eg <= 1e-11
+
+
+def test_1000rbf_jacobian_and_thin_svd(dl, dev):
+    wl, op, W, V, rhs, res, L = gpu_setup(dl, dev, "C5", 0, 1e-8)
+    cfg = wl.cfg
+    ls = cfg.l_s
+    with op:
+        U, Z = res.x[:, :ls], res.x[:, ls:]
+        J64 = op.jacobian(U, Z, L.DOT_JAC_FP64)
+        J2 = op.jacobian(U, Z, L.DOT_JAC_SPLIT_BF16)
+        J3 = op.jacobian(U, Z, L.DOT_JAC_SPLIT_BF16X3)
+        e2 = float(torch.linalg.norm(J2 - J64) / torch.linalg.norm(J64))
+        e3 = float(torch.linalg.norm(J3 - J64) / torch.linalg.norm(J64))
+        print(f"[fullsize] C5 split-bf16 {e2:.2e}, 3-part {e3:.2e} vs binary64", flush=True)
+        assert e2 <= 1e-6 and e3 <= 1e-6
+        X = res.x
+        J64n = J64.cpu().numpy()
+        for m in (0, 417, 999):
+            cells, G, na = support_columns(wl, m)
+            idx = torch.tensor(cells.astype(np.int64), device=dev)
+            Xc = X[idx, :].cpu().numpy()
+            Jr = oest.jacobian_sparse_loops(Xc[:, :ls], Xc[:, ls:], G)
+            sl = slice(m * na, (m + 1) * na)
+            e = np.linalg.norm(J64n[:, sl] - Jr) / np.linalg.norm(Jr)
+            print(f"[fullsize] C5 RBF {m}: J64 {e:.2e}", flush=True)
+            assert e <= 1e-11
+        s, Us, Ys = dl.svd_thin(J2, rcut=1e-10)
+        s, Us, Ys = s.cpu().numpy(), Us.cpu().numpy(), Ys.cpu().numpy()
+        Jn = J2.cpu().numpy()
+        m_, n_ = Jn.shape
+        assert np.all(np.diff(s) <= 0.0) and s[-1] >= 0.0
+        eps = np.finfo(np.float64).eps
+        assert np.linalg.norm(Us.T @ Us - np.eye(m_), 1) <= 30 * m_ * eps
+        # right vectors Y = J^T U / s: the Gram route leaves U^T G U off the
+        # diagonal by O(m eps s_max^2), so (Y^T Y - I)_ij is bounded by that
+        # over s_i s_j (large for the smallest singular values, by design)
+        keep = s > 1e-10 * s[0]
+        Yk, sk = Ys[:, keep], s[keep]
+        E = np.abs(Yk.T @ Yk - np.eye(int(keep.sum())))
+        assert np.all(E <= 30 * m_ * eps * s[0] ** 2 / np.outer(sk, sk) + 1e-13)
+        rec = np.linalg.norm((Us * s) @ Ys.T - Jn) / np.linalg.norm(Jn)
+        print(f"[fullsize] C5 SVD: reconstruction {rec:.2e}, kept {int(keep.sum())}", flush=True)
+        assert rec <= 1e-10
+        # the Gram route resolves eigenvalues of J J^T to d = O(m eps s_max^2):
+        # |s - s_ref| <= min(sqrt(d), d / (2 s_ref))
+        sr = np.linalg.svd(Jn, compute_uv=False)
+        d = 30 * m_ * eps * sr[0] ** 2
+        bound = np.minimum(np.sqrt(d), d / (2.0 * np.maximum(sr, 1e-300)))
+        assert np.all(np.abs(s - sr) <= bound + 1e-14 * sr[0])
