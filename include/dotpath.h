@@ -27,7 +27,7 @@
  *     IEEE binary64 unless stated.
  *   - The caller owns every data buffer.  The library allocates device memory
  *     only inside dot_build_operator (coefficients, level set, small state)
- *     and dot_pals_mua (per-RBF cell lists); dot_solve_multi_rhs,
+ *     and dot_pals_mua (per-RBF cell lists and per-pair data); dot_solve_multi_rhs,
  *     dot_jacobian and dot_grad_misfit use the caller's workspace.
  *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Work is
  *     enqueued on it; calls that return host values synchronize it.
@@ -150,9 +150,11 @@ int dot_set_mua(dot_op* op, const double* mua_dev, void* stream);
  * Set A(theta): evaluate the PaLS absorption at every cell, update the
  * diagonal, and keep on the handle what dot_jacobian and dot_grad_misfit
  * need at this theta (a copy of theta and the descriptor, the level set phi,
- * and per-RBF lists of cells where d mu / d p is nonzero).  Allocates device
- * memory for those lists when they grow.  If mua_dev is not NULL it receives
- * mu.  Synchronizes the stream.
+ * per-RBF lists of cells where d mu / d p is nonzero, h^d d mu / d p of each
+ * (RBF, cell) pair, and the numbering of all listed cells in cell order,
+ * which the contraction uses to read the fields as packed rows).  Allocates
+ * device memory for these when they grow.  If mua_dev is not NULL it
+ * receives mu.  Synchronizes the stream.
  */
 int dot_pals_mua(dot_op* op, const dot_pals* pals, const double* theta_dev, double* mua_dev,
                  void* stream);
@@ -216,10 +218,16 @@ size_t dot_jacobian_workspace_bytes(const dot_op* op, int l_s, int l_d);
  * (n_p = m0 x number of active bits; parameter k = rbf * n_act + local
  * index in the order alpha, beta, chi_1..chi_d).  Only cells where
  * d mu / d p_k is nonzero are visited.  precision: DOT_JAC_FP64 (binary64
- * throughout), DOT_JAC_SPLIT_BF16 or DOT_JAC_SPLIT_BF16X3 (operands rounded to
- * binary32 and split into 2 or 3 bfloat16 parts, products on the matrix
- * cores with binary32 accumulation over 256-cell runs, binary64 sums across
- * runs and chunks).  U_dev: N x l_s, Z_dev: N x l_d, l_s <= 1024.
+ * throughout, on the binary64 matrix cores), DOT_JAC_SPLIT_BF16 or
+ * DOT_JAC_SPLIT_BF16X3 (operands rounded to binary32 and split into 2 or 3
+ * bfloat16 parts, products on the matrix cores with binary32 accumulation
+ * over 256-cell runs, binary64 sums across runs and chunks).  U_dev: N x l_s,
+ * Z_dev: N x l_d, l_s <= 1024.  The matrix-core kernels need
+ * ceil(l_s / 16) ceil(l_d n_act / 16) <= 64 (split forms: l_s <= 64 and
+ * ceil(l_s / 16) ceil(l_d n_act / 128) <= 8) and l_s + l_d <= 128; beyond
+ * that DOT_JAC_FP64 runs a plain binary64 kernel and the split forms return
+ * DOT_EINVAL.  The workspace holds per-chunk partial blocks and the packed
+ * rows of U and Z at the listed cells.
  */
 int dot_jacobian(dot_op* op, int l_s, const double* U_dev, int l_d, const double* Z_dev,
                  int precision, double* Js_dev, void* work_dev, size_t work_bytes, void* stream);

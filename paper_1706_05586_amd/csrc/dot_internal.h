@@ -89,6 +89,19 @@ struct dot_op {
   int64_t chunk_cap = 0;
   int64_t n_chunks = 0;
   int64_t rbf_cap = 0;
+  // per pair: h^d d mu / d p of its RBF's active parameters (pair-major), and
+  // its row in the band-cell list (every cell of any list, in cell order),
+  // through which the contraction reads U and Z rows packed cell-major
+  double* pair_g = nullptr;
+  int64_t pair_g_cap = 0;        // doubles
+  int32_t* pair_band = nullptr;
+  int64_t pair_band_cap = 0;
+  int32_t* band_idx = nullptr;   // N: band row of a cell, -1 elsewhere
+  int32_t* band_cells = nullptr; // cell of each band row
+  int64_t band_cap = 0;
+  int64_t n_band = 0;
+  int64_t* band_part = nullptr;  // per 2048-cell block: band cells before it
+  int64_t band_part_cap = 0;
   // small device/pinned staging
   int32_t* cells_dev = nullptr;   // optode cells staging
   int64_t cells_cap = 0;
@@ -107,6 +120,8 @@ int profile_begin(dot_op* op, int kind, hipStream_t s, hipEvent_t* e0, hipEvent_
 int profile_end(dot_op* op, int kind, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 constexpr int kPinnedInts = 2 * DOT_MAX_COLUMNS + 64;
 int ensure_cells_dev(dot_op* op, int n, const int32_t* cells_host, hipStream_t s);
+// after the pair lists of dot_pals_mua: per-pair d mu / d p and band rows
+int jac_prepare(dot_op* op, hipStream_t s);
 
 constexpr int kWave = 64;
 

@@ -14,6 +14,7 @@
 // Gradient (eq. UnbiasedGrad, sampled): g = Js^T vec(Rs) evaluated as
 // g_k = - sum_c G[c,k] s_c with s_c = sum_i U[c,i] (Z Rs)[c,i].
 #include <algorithm>
+#include <type_traits>
 
 #include "dot_internal.h"
 
@@ -139,25 +140,191 @@ __global__ __launch_bounds__(JT) void jac_chunk_fp64_kernel(
 }
 
 // ----------------------------------------------------------------------
-// Split-bfloat16 MFMA contraction of one chunk.
-//
-// Per chunk the contraction is a dense GEMM:  P[i, n] = sum_c U[c,i] B[c,n],
-// B[c, j + l_d a] = Z[c,j] G[c,a],  i < l_s, n < l_d na, c over the chunk.
-// Operands are rounded to binary32 and split into TERMS bfloat16 parts
-// (x = hi + lo, or hi + mid + lo); the part products of total order at most
-// TERMS - 1 are issued as v_mfma_f32_16x16x32_bf16 (3 products for two parts,
-// 6 for three; the dropped ones are below the representation error), accumulated in binary32 inside the MFMA and flushed
-// into binary64 registers every JFLUSH K-steps of 32 cells.  Block = 8
-// waves; output tiles of 16 x 16 are dealt round-robin to the waves.
-// Operand layout of the instruction (lane l): A row l%16 with 8 consecutive
-// k, B column l%16 with the same 8 k, result rows 4(l/16)..+3, column l%16.
+// Preparation, run by dot_pals_mua once the pair lists exist:
+//   pair_g[p * na + a] = h^d d mu / d p_a at the pair's cell, for its RBF;
+//   band rows: every cell of any pair list, numbered in cell order, so the
+//   contraction can read the U and Z values of a pair as one packed row.
+__global__ __launch_bounds__(256) void pair_g_kernel(GridDims g, JacParams P,
+                                                     const double* __restrict__ theta,
+                                                     const double* __restrict__ phi,
+                                                     const int64_t* __restrict__ rbf_start,
+                                                     const int32_t* __restrict__ pair_cell,
+                                                     double* __restrict__ pair_g) {
+  const int m = blockIdx.x;
+  const double* th = theta + (int64_t)m * P.stride;
+  const int na = P.n_act;
+  for (int64_t p = rbf_start[m] + threadIdx.x; p < rbf_start[m + 1]; p += 256) {
+    const int64_t c = pair_cell[p];
+    double x0, x1, x2, d[5];
+    cell_xyz(g, c, &x0, &x1, &x2);
+    rbf_dphi(P, th, x0, x1, x2, d);
+    const double w = band_weight(P, phi[c]);
+    for (int a = 0; a < na; ++a) pair_g[p * na + a] = P.hd * (w * d[a]);
+  }
+}
+
+__global__ void fill_int_kernel(int32_t* __restrict__ a, int64_t n, int32_t v) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+__global__ void band_mark_kernel(int64_t n_pairs, const int32_t* __restrict__ pair_cell,
+                                 int32_t* __restrict__ flag) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p < n_pairs) flag[pair_cell[p]] = 1;
+}
+
+constexpr int BAND_BLK = 2048;   // cells per block: 256 threads x 8 consecutive cells
+
+// Exclusive scan of one int per thread over the block (nwaves waves).
+template <typename T>
+__device__ __forceinline__ T block_excl_scan(T v, T* s_wave, int nwaves, T* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  T x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const T y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) s_wave[wave] = x;
+  __syncthreads();
+  T woff = 0, tot = 0;
+  for (int w = 0; w < nwaves; ++w) {
+    if (w < wave) woff += s_wave[w];
+    tot += s_wave[w];
+  }
+  *total = tot;
+  return woff + x - v;
+}
+
+__global__ __launch_bounds__(256) void band_count_kernel(int64_t N, const int32_t* __restrict__ flag,
+                                                         int64_t* __restrict__ cnt) {
+  __shared__ int s_wave[4];
+  const int64_t c0 = (int64_t)blockIdx.x * BAND_BLK + threadIdx.x * 8;
+  int n = 0;
+  for (int q = 0; q < 8; ++q)
+    if (c0 + q < N) n += flag[c0 + q] != 0 ? 1 : 0;
+  int tot;
+  block_excl_scan<int>(n, s_wave, 4, &tot);
+  if (threadIdx.x == 0) cnt[blockIdx.x] = tot;
+}
+
+// One block: part[b] = band cells in blocks before b, part[nb] = all of them.
+__global__ __launch_bounds__(1024) void band_scan_kernel(int nb, const int64_t* __restrict__ cnt,
+                                                         int64_t* __restrict__ part) {
+  __shared__ long long s_wave[16];
+  const int t = threadIdx.x;
+  const int per = (nb + 1023) / 1024;
+  const int b0 = min(nb, t * per), b1 = min(nb, b0 + per);
+  long long loc = 0;
+  for (int b = b0; b < b1; ++b) loc += cnt[b];
+  long long tot;
+  long long run = block_excl_scan<long long>(loc, s_wave, 16, &tot);
+  for (int b = b0; b < b1; ++b) {
+    part[b] = run;
+    run += cnt[b];
+  }
+  if (t == 0) part[nb] = tot;
+}
+
+// flags -> band rows (-1 off the band) and the cell of each band row
+__global__ __launch_bounds__(256) void band_fill_kernel(int64_t N, const int64_t* __restrict__ part,
+                                                        int32_t* __restrict__ idx,
+                                                        int32_t* __restrict__ cells) {
+  __shared__ int s_wave[4];
+  const int64_t c0 = (int64_t)blockIdx.x * BAND_BLK + threadIdx.x * 8;
+  int f[8], n = 0;
+  for (int q = 0; q < 8; ++q) {
+    f[q] = (c0 + q < N && idx[c0 + q] != 0) ? 1 : 0;
+    n += f[q];
+  }
+  int tot;
+  const int off = block_excl_scan<int>(n, s_wave, 4, &tot);
+  int64_t r = part[blockIdx.x] + off;
+  for (int q = 0; q < 8; ++q) {
+    if (c0 + q >= N) break;
+    if (f[q]) {
+      idx[c0 + q] = (int32_t)r;
+      cells[r] = (int32_t)(c0 + q);
+      ++r;
+    } else {
+      idx[c0 + q] = -1;
+    }
+  }
+}
+
+__global__ void pair_band_kernel(int64_t n_pairs, const int32_t* __restrict__ pair_cell,
+                                 const int32_t* __restrict__ idx, int32_t* __restrict__ pair_band) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p < n_pairs) pair_band[p] = idx[pair_cell[p]];
+}
+
+// Packed rows: packed[b * L + i] = U[c_b, i] (i < l_s) or Z[c_b, i - l_s],
+// L = l_s + l_d, through a 64-row x 64-column LDS tile so that both the
+// column reads and the row writes are contiguous.
+template <typename T>
+__global__ __launch_bounds__(256) void pack_rows_kernel(int64_t N, int64_t n_band,
+                                                        const int32_t* __restrict__ band_cells,
+                                                        int l_s, const double* __restrict__ U,
+                                                        int l_d, const double* __restrict__ Z,
+                                                        T* __restrict__ packed) {
+  __shared__ T tile[64][65];
+  const int L = l_s + l_d;
+  const int64_t b0 = (int64_t)blockIdx.x * 64;
+  const int i0 = blockIdx.y * 64;
+  const int t = threadIdx.x, bl = t & 63;
+  const int64_t b = b0 + bl;
+  const int64_t c = b < n_band ? band_cells[b] : 0;
+#pragma unroll 4
+  for (int r = 0; r < 16; ++r) {
+    const int il = (t >> 6) + 4 * r;
+    const int i = i0 + il;
+    T v = T(0);
+    if (b < n_band && i < L) v = (T)(i < l_s ? U[c + N * (int64_t)i] : Z[c + N * (int64_t)(i - l_s)]);
+    tile[bl][il] = v;
+  }
+  __syncthreads();
+#pragma unroll 4
+  for (int r = 0; r < 16; ++r) {
+    const int e = t + 256 * r;
+    const int bb = e >> 6, ii = e & 63;
+    const int64_t ob = b0 + bb;
+    const int oi = i0 + ii;
+    if (ob < n_band && oi < L) packed[ob * L + oi] = tile[bb][ii];
+  }
+}
+
+// ----------------------------------------------------------------------
+// Matrix-core contraction of one chunk (the pairs of one RBF, or a piece of
+// them).  Per chunk it is a dense product
+//     P[i, n] = sum_p U[c_p, i] B[p, n],  B[p, j + l_d a] = Z[c_p, j] G[p, a],
+// i < l_s, n < l_d na, over the chunk's pairs in K-steps of 32.  A thread
+// stages the values i = t % 16 + 16 r of pair t / 16 of a step from its packed
+// row (one contiguous row per pair) into LDS: U as the A operand, Z times the
+// pair's G as the B operand.  The next step's rows are loaded while the
+// matrix cores work on the current one (band rows two steps ahead).
+// MODE 0: binary64 operands, v_mfma_f64_16x16x4f64, binary64 accumulation.
+// MODE 2 / 3: operands rounded to binary32 and split into 2 / 3 bfloat16
+// parts (x = hi + lo, or hi + mid + lo); the part products of total order at
+// most MODE - 1 are issued as v_mfma_f32_16x16x32_bf16 (3 products for two
+// parts, 6 for three), accumulated in binary32 and flushed into the binary64
+// partial block every JFLUSH K-steps (256 pairs).
+// Output tiles of 16 x 16 are dealt to the 8 waves round-robin: tile
+// t = wave + 8 q covers rows 16 (t % MT) .. +15 and columns 16 (t / MT) .. +15,
+// zero-padded beyond l_s rows and l_d na columns.  Lane layout of both
+// instructions: A row l % 16, B column l % 16, k in groups by l / 16; result
+// column l % 16, rows 4 (l / 16) + e for the bfloat16 form and l / 16 + 4 e
+// for the binary64 form (e < 4).
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-constexpr int MK = 32;          // cells per MFMA K-step
-constexpr int MKP = MK + 8;     // padded LDS row (bf16 elements), 80 bytes
-constexpr int MT_THREADS = 512;
-constexpr int JFLUSH = 8;       // K-steps between binary64 flushes (256 cells)
+constexpr int JK = 32;            // pairs per K-step
+constexpr int JKP32 = JK + 4;     // padded binary32 LDS row (144 bytes)
+constexpr int JKP64 = JK + 1;     // padded binary64 LDS row
+constexpr int JTHREADS = 512;     // 8 waves; 16 threads per pair of a step
+constexpr int JRMAX = 8;          // values per thread and step: l_s + l_d <= 128
+constexpr int JFLUSH = 8;         // K-steps between binary64 flushes
 
 template <int TERMS>
 __device__ __forceinline__ void split_bf16(float x, __bf16* parts) {
@@ -173,48 +340,85 @@ __device__ __forceinline__ void split_bf16(float x, __bf16* parts) {
   }
 }
 
-template <int TERMS, int QMAX>
-__global__ __launch_bounds__(MT_THREADS) void jac_chunk_mfma_kernel(
-    GridDims g, JacParams P, const double* __restrict__ theta, const double* __restrict__ phi,
-    const int32_t* __restrict__ pair_cell, const int64_t* __restrict__ chunk_begin,
-    const int32_t* __restrict__ chunk_rbf, int l_s, const double* __restrict__ U, int l_d,
-    const double* __restrict__ Z, double* __restrict__ partial, int ncp) {
-  // ncp: B columns held in LDS (a multiple of 16, >= the padded tile span);
-  // tiles t = wave + 8 q (q < QMAX) cover rows mt = t % MT and columns
-  // 16 (t / MT) .. +15, zero-padded beyond l_s rows / l_d na columns
+template <int MODE>
+struct JacPack {
+  using type = float;
+};
+template <>
+struct JacPack<0> {
+  using type = double;
+};
+
+__host__ __device__ inline size_t jac_lds_bytes(int mode, int rows, int ncp) {
+  return mode == 0 ? (size_t)(rows + ncp) * JKP64 * sizeof(double)
+                   : (size_t)(rows + ncp) * JKP32 * sizeof(float);
+}
+
+// MTC: the row-tile count ceil(l_s / 16) as a constant (split forms), or 0
+// (binary64, which takes it at run time)
+template <int MODE, int QMAX, int MTC>
+__global__ __launch_bounds__(JTHREADS) void jac_mfma_kernel(
+    const int32_t* __restrict__ pair_band, const double* __restrict__ pair_g,
+    const int64_t* __restrict__ chunk_begin, int l_s, int l_d, int na,
+    const typename JacPack<MODE>::type* __restrict__ packed, double* __restrict__ partial,
+    int ncp) {
+  using PT = typename JacPack<MODE>::type;
+  constexpr int TERMS = MODE == 0 ? 1 : MODE;
   extern __shared__ __attribute__((aligned(16))) unsigned char jsm[];
   const int ch = blockIdx.x;
   const int64_t b0 = chunk_begin[ch], b1 = chunk_begin[ch + 1];
-  const double* th = theta + (int64_t)chunk_rbf[ch] * P.stride;
-  const int na = P.n_act;
+  const int L = l_s + l_d;
   const int lsld = l_s * l_d;
   const int ncol = l_d * na;
-  const int MT = (l_s + 15) / 16;
+  const int MT = MTC > 0 ? MTC : (l_s + 15) / 16;
+  const int rows = MT * 16;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  __bf16* sA = reinterpret_cast<__bf16*>(jsm);            // [TERMS][MT*16][MKP]
-  __bf16* sB = sA + TERMS * MT * 16 * MKP;                // [TERMS][ncp][MKP]
-  double* sZ = reinterpret_cast<double*>(sB + TERMS * ncp * MKP);  // [MK][l_d]
-  double* sG = sZ + MK * l_d;                             // [MK][na]
   double* out = partial + (int64_t)ch * lsld * na;
+  float* fA = reinterpret_cast<float*>(jsm);     // [rows][JKP32]
+  float* fB = fA + rows * JKP32;                 // [ncp][JKP32]
+  double* dA = reinterpret_cast<double*>(jsm);   // [rows][JKP64]
+  double* dB = dA + rows * JKP64;                // [ncp][JKP64]
+  {  // rows >= l_s and columns >= ncol are never written: clear once
+    const int words = (int)(jac_lds_bytes(MODE, rows, ncp) / 4);
+    for (int e = threadIdx.x; e < words; e += JTHREADS) reinterpret_cast<int*>(jsm)[e] = 0;
+  }
 
-  // per tile: LDS fragment offsets and the output offset of element e = 0
-  int aoff[QMAX], boff[QMAX], ooff[QMAX], orow[QMAX], ocol[QMAX];
-  const int kofs = 8 * (lane >> 4);
+  // per tile: operand rows/columns of this lane and the output offset.
+  // Binary64: tiles t = wave + 8 q round-robin.  Split bfloat16: wave w owns
+  // the column tiles nt = w + 8 c (c < QN) with every row tile mt, tile
+  // q = c MT + mt, so a wave splits each A fragment once per K-step and each
+  // B fragment once (the splitting, not the matrix cores, bounds that form).
+  const int QN = MODE == 0 ? 0 : QMAX / MT;
+  int arow[QMAX], bcol[QMAX], ooff[QMAX], orow[QMAX], ocol[QMAX];
 #pragma unroll
   for (int q = 0; q < QMAX; ++q) {
-    const int t = wave + 8 * q;
-    const int mt = t % MT, nt = t / MT;
-    aoff[q] = (mt * 16 + (lane & 15)) * MKP + kofs;
-    boff[q] = (nt * 16 + (lane & 15)) * MKP + kofs;
-    const int i0 = mt * 16 + 4 * (lane >> 4);
-    const int n = nt * 16 + (lane & 15);
+    int mt, nt;
+    if constexpr (MODE == 0) {
+      const int t = wave + 8 * q;
+      mt = t % MT;
+      nt = t / MT;
+    } else {
+      mt = q % MT;
+      nt = wave + 8 * (q / MT);
+    }
+    arow[q] = mt * 16 + (lane & 15);
+    bcol[q] = nt * 16 + (lane & 15);
+    // result element e of this lane: row i0 + rstep e (binary32 form: rows
+    // 4 (l / 16) + e; binary64 form: rows l / 16 + 4 e), column bcol
+    const int i0 = MODE == 0 ? mt * 16 + (lane >> 4) : mt * 16 + 4 * (lane >> 4);
+    const int n = bcol[q];
     orow[q] = i0;
     ocol[q] = n;
     ooff[q] = n < ncol ? (n % l_d) + l_d * i0 + lsld * (n / l_d) : 0;
   }
+  constexpr int rstep = MODE == 0 ? 4 : 1;
   f32x4 acc[QMAX];
+  f64x4 acc64[QMAX];
 #pragma unroll
-  for (int q = 0; q < QMAX; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int q = 0; q < QMAX; ++q) {
+    acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    acc64[q] = f64x4{0.0, 0.0, 0.0, 0.0};
+  }
   bool first = true;
   auto flush = [&]() {
 #pragma unroll
@@ -231,70 +435,144 @@ __global__ __launch_bounds__(MT_THREADS) void jac_chunk_mfma_kernel(
     first = false;
   };
 
+  // staging: thread t holds values i = qv + 16 r of pair pb of a step, in two
+  // register slots: the rows of step s + 2 are loaded while step s is staged
+  // and multiplied, so a load has two steps to arrive
+  const int pb = threadIdx.x >> 4, qv = threadIdx.x & 15;
+  const int nr = (L + 15) / 16;
+  // G in binary32 for the split forms: it only scales the binary32 B operand
+  using GT = typename std::conditional<MODE == 0, double, float>::type;
+  PT val[2][JRMAX];
+  GT gv[2][5];
+  auto band_row = [&](int64_t base) -> int {
+    return base + pb < b1 ? pair_band[base + pb] : -1;
+  };
+  auto load_step = [&](auto slot_c, int64_t base, int bi) {
+    constexpr int S = decltype(slot_c)::value;
+    const bool valid = bi >= 0;
+    const PT* row = packed + (int64_t)(valid ? bi : 0) * L;
+#pragma unroll
+    for (int r = 0; r < JRMAX; ++r) {
+      const int i = qv + 16 * r;
+      val[S][r] = (r < nr && i < L && valid) ? row[i] : PT(0);
+    }
+    const int64_t p = valid ? base + pb : b0;
+#pragma unroll
+    for (int a = 0; a < 5; ++a) gv[S][a] = (a < na && valid) ? (GT)pair_g[p * na + a] : GT(0);
+  };
+  auto store_step = [&](auto slot_c) {
+    constexpr int S = decltype(slot_c)::value;
+#pragma unroll
+    for (int r = 0; r < JRMAX; ++r) {
+      const int i = qv + 16 * r;
+      if (r >= nr || i >= L) continue;
+      if (i < l_s) {
+        if constexpr (MODE == 0) {
+          dA[i * JKP64 + pb] = val[S][r];
+        } else {
+          fA[i * JKP32 + pb] = val[S][r];
+        }
+      } else {
+        const int j = i - l_s;
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+          if (a >= na) break;
+          const int n = j + l_d * a;
+          if constexpr (MODE == 0) {
+            dB[n * JKP64 + pb] = val[S][r] * gv[S][a];
+          } else {
+            fB[n * JKP32 + pb] = val[S][r] * gv[S][a];
+          }
+        }
+      }
+    }
+  };
+  auto multiply = [&]() {
+    if constexpr (MODE == 0) {
+      const int kl = lane >> 4;
+#pragma unroll
+      for (int q = 0; q < QMAX; ++q) {
+#pragma unroll
+        for (int ks = 0; ks < JK / 4; ++ks) {
+          const double a = dA[arow[q] * JKP64 + 4 * ks + kl];
+          const double b = dB[bcol[q] * JKP64 + 4 * ks + kl];
+          acc64[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc64[q], 0, 0, 0);
+        }
+      }
+    } else {
+      // binary32 operands staged in LDS, split into bfloat16 parts while the
+      // fragments are built (8 consecutive k per lane): the MT row fragments
+      // once, then per owned column tile its fragment and MT products
+      const int kofs = 8 * (lane >> 4);
+      auto build = [&](const float* src, bf16x8* f) {
+        const float4* p4 = reinterpret_cast<const float4*>(src);
+        const float4 x0 = p4[0], x1 = p4[1];
+        const float xv[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          __bf16 xp[TERMS];
+          split_bf16<TERMS>(xv[e], xp);
+#pragma unroll
+          for (int p = 0; p < TERMS; ++p) f[p][e] = xp[p];
+        }
+      };
+      constexpr int MTS = MTC > 0 ? MTC : 1;
+      bf16x8 fa[MTS][TERMS];
+#pragma unroll
+      for (int mt = 0; mt < MTS; ++mt) build(&fA[(mt * 16 + (lane & 15)) * JKP32 + kofs], fa[mt]);
+      bf16x8 fbc[TERMS];
+#pragma unroll
+      for (int q = 0; q < QMAX; ++q) {
+        const int mt = q % MTS;
+        if (mt == 0) build(&fB[(wave + 8 * (q / MTS)) * 16 * JKP32 + (lane & 15) * JKP32 + kofs], fbc);
+#pragma unroll
+        for (int pa = 0; pa < TERMS; ++pa)
+#pragma unroll
+          for (int pq = 0; pq < TERMS; ++pq)
+            if (pa + pq <= TERMS - 1)
+              acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[mt][pa], fbc[pq], acc[q], 0, 0, 0);
+      }
+    }
+  };
+
+  // prologue: rows of steps 0 and 1 in flight, band rows of steps 2 and 3
+  using S0 = std::integral_constant<int, 0>;
+  using S1 = std::integral_constant<int, 1>;
+  load_step(S0{}, b0, band_row(b0));
+  load_step(S1{}, b0 + JK, band_row(b0 + JK));
+  int biA = band_row(b0 + 2 * JK), biB = band_row(b0 + 3 * JK);
+  __syncthreads();  // LDS cleared before the first store
   int kstep = 0;
-  for (int64_t cb = b0; cb < b1; cb += MK, ++kstep) {
-    const int nb = (int)min<int64_t>(MK, b1 - cb);
-    __syncthreads();  // previous K-step's MFMA reads are done
-    // U -> A parts (rows beyond l_s and cells beyond nb are zero)
-    for (int t = threadIdx.x; t < MT * 16 * MK; t += MT_THREADS) {
-      const int cc = t % MK, i = t / MK;
-      float v = 0.f;
-      if (cc < nb && i < l_s) v = (float)U[pair_cell[cb + cc] + P.N * (int64_t)i];
-      __bf16 parts[TERMS];
-      split_bf16<TERMS>(v, parts);
-#pragma unroll
-      for (int q = 0; q < TERMS; ++q) sA[(q * MT * 16 + i) * MKP + cc] = parts[q];
-    }
-    // Z staging (binary64) and G of each cell
-    for (int t = threadIdx.x; t < MK * l_d; t += MT_THREADS) {
-      const int cc = t % MK, j = t / MK;
-      sZ[cc * l_d + j] = cc < nb ? Z[pair_cell[cb + cc] + P.N * (int64_t)j] : 0.0;
-    }
-    if (threadIdx.x < MK) {
-      double d[5] = {0, 0, 0, 0, 0};
-      double w = 0.0;
-      if ((int)threadIdx.x < nb) {
-        const int64_t c = pair_cell[cb + threadIdx.x];
-        double x0, x1, x2;
-        cell_xyz(g, c, &x0, &x1, &x2);
-        rbf_dphi(P, th, x0, x1, x2, d);
-        w = band_weight(P, phi[c]);
-      }
-      for (int a = 0; a < na; ++a) sG[threadIdx.x * na + a] = P.hd * (w * d[a]);
-    }
+  // one K-step from register slot S: stage, multiply, refill the slot with
+  // the rows of the step two ahead
+  auto step = [&](auto slot_c, int64_t base) {
+    const int bnext = band_row(base + 4 * JK);   // used four steps on
+    store_step(slot_c);
     __syncthreads();
-    // B parts: B[c, n] = Z[c, j] G[c, a] for n < ncol, zero up to ncp
-    for (int t = threadIdx.x; t < ncp * MK; t += MT_THREADS) {
-      const int cc = t % MK, n = t / MK;
-      float v = 0.f;
-      if (n < ncol) {
-        const int j = n % l_d, a = n / l_d;
-        v = (float)(sZ[cc * l_d + j] * sG[cc * na + a]);
-      }
-      __bf16 parts[TERMS];
-      split_bf16<TERMS>(v, parts);
-#pragma unroll
-      for (int q = 0; q < TERMS; ++q) sB[(q * ncp + n) * MKP + cc] = parts[q];
+    if (base + 2 * JK < b1) load_step(slot_c, base + 2 * JK, biA);
+    multiply();
+    if constexpr (MODE != 0) {
+      if ((kstep + 1) % JFLUSH == 0) flush();
     }
-    __syncthreads();
+    __syncthreads();  // operand reads done before the next store
+    biA = biB;
+    biB = bnext;
+    ++kstep;
+  };
+  for (int64_t base = b0; base < b1; base += 2 * JK) {
+    step(S0{}, base);
+    if (base + JK < b1) step(S1{}, base + JK);
+  }
+  if constexpr (MODE == 0) {
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
-      bf16x8 fa[TERMS], fb[TERMS];
 #pragma unroll
-      for (int p = 0; p < TERMS; ++p) {
-        fa[p] = *reinterpret_cast<const bf16x8*>(&sA[p * MT * 16 * MKP + aoff[q]]);
-        fb[p] = *reinterpret_cast<const bf16x8*>(&sB[p * ncp * MKP + boff[q]]);
-      }
-#pragma unroll
-      for (int pa = 0; pa < TERMS; ++pa)
-#pragma unroll
-        for (int pb = 0; pb < TERMS; ++pb)
-          if (pa + pb <= TERMS - 1)
-            acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[pa], fb[pb], acc[q], 0, 0, 0);
+      for (int e = 0; e < 4; ++e)
+        if (orow[q] + rstep * e < l_s && ocol[q] < ncol) out[ooff[q] + l_d * rstep * e] = acc64[q][e];
     }
-    if ((kstep + 1) % JFLUSH == 0) flush();
+  } else {
+    if (first || kstep % JFLUSH != 0) flush();
   }
-  if (first || kstep % JFLUSH != 0) flush();
 }
 
 // Js[(j + l_d i) + l_s l_d (m na + a)] = - sum over chunks of RBF m.
@@ -336,28 +614,18 @@ __global__ __launch_bounds__(256) void grad_cell_kernel(GridDims g, JacParams P,
   sc[c] = s;
 }
 
-__global__ __launch_bounds__(256) void grad_chunk_kernel(GridDims g, JacParams P,
-                                                         const double* __restrict__ theta,
-                                                         const double* __restrict__ phi,
-                                                         const int32_t* __restrict__ pair_cell,
+__global__ __launch_bounds__(256) void grad_chunk_kernel(int na, const int32_t* __restrict__ pair_cell,
+                                                         const double* __restrict__ pair_g,
                                                          const int64_t* __restrict__ chunk_begin,
-                                                         const int32_t* __restrict__ chunk_rbf,
                                                          const double* __restrict__ sc,
                                                          double* __restrict__ partial) {
   __shared__ double red[5][256];
   const int ch = blockIdx.x;
   const int64_t b0 = chunk_begin[ch], b1 = chunk_begin[ch + 1];
-  const double* th = theta + (int64_t)chunk_rbf[ch] * P.stride;
-  const int na = P.n_act;
   double acc[5] = {0, 0, 0, 0, 0};
   for (int64_t p = b0 + threadIdx.x; p < b1; p += 256) {
-    const int64_t c = pair_cell[p];
-    double x0, x1, x2, d[5];
-    cell_xyz(g, c, &x0, &x1, &x2);
-    rbf_dphi(P, th, x0, x1, x2, d);
-    const double w = band_weight(P, phi[c]);
-    const double s = sc[c];
-    for (int a = 0; a < na; ++a) acc[a] += (P.hd * (w * d[a])) * s;
+    const double s = sc[pair_cell[p]];
+    for (int a = 0; a < na; ++a) acc[a] += pair_g[p * na + a] * s;
   }
   for (int a = 0; a < na; ++a) red[a][threadIdx.x] = acc[a];
   __syncthreads();
@@ -406,12 +674,82 @@ static JacParams make_params(const dot_op* op) {
   return P;
 }
 
+static size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Workspace of dot_jacobian / dot_grad_misfit: per-chunk partial blocks, then
+// the packed band rows (binary64, which also holds the binary32 packing).
+static size_t jac_partial_bytes(const dot_op* op, int l_s, int l_d) {
+  const int na = n_active_bits(op->pals.active, op->g.dim);
+  return al256((size_t)std::max<int64_t>(op->n_chunks, 1) * l_s * l_d * na * sizeof(double));
+}
+
 static size_t jac_bytes(const dot_op* op, int l_s, int l_d) {
   const int na = n_active_bits(op->pals.active, op->g.dim);
-  const size_t jac = (size_t)std::max<int64_t>(op->n_chunks, 1) * l_s * l_d * na * sizeof(double);
+  const size_t jac = jac_partial_bytes(op, l_s, l_d) +
+                     al256((size_t)std::max<int64_t>(op->n_band, 1) * (l_s + l_d) * sizeof(double));
   const size_t grad = (size_t)op->g.N * sizeof(double) +
                       (size_t)std::max<int64_t>(op->n_chunks, 1) * na * sizeof(double) + 256;
-  return ((std::max(jac, grad) + 255) / 256) * 256;
+  return al256(std::max(jac, grad));
+}
+
+template <typename T>
+static int grow(T** p, int64_t* cap, int64_t need) {
+  if (need <= *cap) return DOT_OK;
+  if (*p) DOT_HIP(hipFree(*p));
+  *p = nullptr;
+  *cap = 0;
+  const int64_t n = std::max<int64_t>(need + need / 8, 1024);
+  DOT_HIP(hipMalloc(p, (size_t)n * sizeof(T)));
+  *cap = n;
+  return DOT_OK;
+}
+
+int jac_prepare(dot_op* op, hipStream_t s) {
+  const JacParams P = make_params(op);
+  const int na = P.n_act;
+  const int64_t N = op->g.N, np = op->n_pairs;
+  const int m0 = op->pals.m0;
+  int rc = grow(&op->pair_g, &op->pair_g_cap, std::max<int64_t>(np * na, 1));
+  if (rc) return rc;
+  rc = grow(&op->pair_band, &op->pair_band_cap, std::max<int64_t>(np, 1));
+  if (rc) return rc;
+  if (!op->band_idx) DOT_HIP(hipMalloc(&op->band_idx, (size_t)N * sizeof(int32_t)));
+  const int64_t nb = (N + BAND_BLK - 1) / BAND_BLK;
+  rc = grow(&op->band_part, &op->band_part_cap, 2 * (nb + 1));
+  if (rc) return rc;
+  int64_t* cnt = op->band_part + (nb + 1);
+  if (np > 0) {
+    hipLaunchKernelGGL(pair_g_kernel, dim3(m0), dim3(256), 0, s, op->g, P, op->theta, op->phi,
+                       op->rbf_start, op->pair_cell, op->pair_g);
+    DOT_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(fill_int_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s,
+                     op->band_idx, N, 0);
+  DOT_LAUNCH_CHECK();
+  if (np > 0) {
+    hipLaunchKernelGGL(band_mark_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, np,
+                       op->pair_cell, op->band_idx);
+    DOT_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(band_count_kernel, dim3((unsigned)nb), dim3(256), 0, s, N, op->band_idx, cnt);
+  DOT_LAUNCH_CHECK();
+  hipLaunchKernelGGL(band_scan_kernel, dim3(1), dim3(1024), 0, s, (int)nb, cnt, op->band_part);
+  DOT_LAUNCH_CHECK();
+  int64_t n_band = 0;
+  DOT_HIP(hipMemcpyAsync(&n_band, op->band_part + nb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  DOT_HIP(hipStreamSynchronize(s));
+  rc = grow(&op->band_cells, &op->band_cap, std::max<int64_t>(n_band, 1));
+  if (rc) return rc;
+  hipLaunchKernelGGL(band_fill_kernel, dim3((unsigned)nb), dim3(256), 0, s, N, op->band_part,
+                     op->band_idx, op->band_cells);
+  DOT_LAUNCH_CHECK();
+  if (np > 0) {
+    hipLaunchKernelGGL(pair_band_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, np,
+                       op->pair_cell, op->band_idx, op->pair_band);
+    DOT_LAUNCH_CHECK();
+  }
+  op->n_band = n_band;
+  return DOT_OK;
 }
 
 }  // namespace dot
@@ -439,59 +777,92 @@ int dot_jacobian(dot_op* op, int l_s, const double* U_dev, int l_d, const double
   const size_t need = jac_bytes(op, l_s, l_d);
   if (!work_dev || work_bytes < need)
     DOT_FAIL(DOT_ENOMEM, "workspace too small: need %zu bytes, got %zu", need, work_bytes);
-  if ((size_t)JB * (l_s + l_d + 5) * sizeof(double) > 64 * 1024)
-    DOT_FAIL(DOT_EINVAL, "l_s + l_d too large for the contraction kernel");
   hipStream_t s = as_stream(stream);
   const JacParams P = make_params(op);
   const int na = P.n_act;
   const int m0 = op->pals.m0;
   const int lsld = l_s * l_d;
+  const int L = l_s + l_d;
+  const int MT = (l_s + 15) / 16, NT = (l_d * na + 15) / 16;
+  const int tiles = MT * NT;
+  // the matrix-core kernels hold at most 8 tiles per wave and JRMAX staged
+  // values per thread (the split form: every row tile of its column tiles,
+  // MT <= 4); binary64 beyond that runs the plain kernel
+  const int qn_split = (NT + 7) / 8;
+  const bool mfma_fits = precision == DOT_JAC_FP64
+                             ? tiles <= 64 && L <= 16 * JRMAX
+                             : MT <= 4 && MT * qn_split <= 8 && L <= 16 * JRMAX;
+  if (precision != DOT_JAC_FP64 && !mfma_fits)
+    DOT_FAIL(DOT_EINVAL, "l_s, l_d and n_act too large for the split-bf16 kernel");
+  if (precision == DOT_JAC_FP64 && !mfma_fits &&
+      (size_t)JB * (l_s + l_d + 5) * sizeof(double) > 64 * 1024)
+    DOT_FAIL(DOT_EINVAL, "l_s + l_d too large for the contraction kernel");
   double* partial = (double*)work_dev;
+  char* packed = (char*)work_dev + jac_partial_bytes(op, l_s, l_d);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   unsigned long long* cols = nullptr;
   DOT_TRY_J(profile_begin(op, DOT_PROF_JACOBIAN, s, &e0, &e1, &cols));
-  if (op->n_chunks > 0 && precision == DOT_JAC_FP64) {
+  if (op->n_chunks > 0 && !mfma_fits) {
     const size_t shm = (size_t)JB * (l_s + l_d + na) * sizeof(double);
     hipLaunchKernelGGL(jac_chunk_fp64_kernel, dim3((unsigned)op->n_chunks), dim3(JT), shm, s, op->g,
                        P, op->theta, op->phi, op->pair_cell, op->chunk_begin, op->chunk_rbf, l_s,
                        U_dev, l_d, Z_dev, partial);
     DOT_LAUNCH_CHECK();
   } else if (op->n_chunks > 0) {
-    const int terms = precision == DOT_JAC_SPLIT_BF16 ? 2 : 3;
-    const int MT = (l_s + 15) / 16, NT = (l_d * na + 15) / 16;
-    const int tiles = MT * NT;
-    if (tiles > 64) DOT_FAIL(DOT_EINVAL, "l_s * l_d * n_act too large for the split-bf16 kernel");
-    const int qmax = (tiles + 7) / 8;
-    // columns reached by the padded tiles t < 8 qmax
-    const int ncp = ((8 * qmax - 1) / MT + 1) * 16;
-    const size_t shm = (size_t)terms * (MT * 16 + ncp) * MKP * 2 +
-                       (size_t)MK * l_d * sizeof(double) + (size_t)MK * na * sizeof(double);
-    auto launch = [&](auto kern) -> int {
-      DOT_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)shm));
-      hipLaunchKernelGGL(kern, dim3((unsigned)op->n_chunks), dim3(MT_THREADS), shm, s, op->g, P,
-                         op->theta, op->phi, op->pair_cell, op->chunk_begin, op->chunk_rbf, l_s,
-                         U_dev, l_d, Z_dev, partial, ncp);
-      DOT_LAUNCH_CHECK();
-      return DOT_OK;
-    };
-    int rc = DOT_EINVAL;
-#define DOT_JAC_CASE(T, Q) \
-  case Q:                  \
-    rc = launch(jac_chunk_mfma_kernel<T, Q>); \
-    break;
-    if (terms == 2) {
-      switch (qmax) {
-        DOT_JAC_CASE(2, 1) DOT_JAC_CASE(2, 2) DOT_JAC_CASE(2, 3) DOT_JAC_CASE(2, 4)
-        DOT_JAC_CASE(2, 5) DOT_JAC_CASE(2, 6) DOT_JAC_CASE(2, 7) DOT_JAC_CASE(2, 8)
-      }
+    const int mode = precision == DOT_JAC_FP64 ? 0 : precision == DOT_JAC_SPLIT_BF16 ? 2 : 3;
+    const dim3 pgrid((unsigned)((op->n_band + 63) / 64), (unsigned)((L + 63) / 64));
+    if (mode == 0) {
+      hipLaunchKernelGGL(pack_rows_kernel<double>, pgrid, dim3(256), 0, s, op->g.N, op->n_band,
+                         op->band_cells, l_s, U_dev, l_d, Z_dev, (double*)packed);
     } else {
-      switch (qmax) {
-        DOT_JAC_CASE(3, 1) DOT_JAC_CASE(3, 2) DOT_JAC_CASE(3, 3) DOT_JAC_CASE(3, 4)
-        DOT_JAC_CASE(3, 5) DOT_JAC_CASE(3, 6) DOT_JAC_CASE(3, 7) DOT_JAC_CASE(3, 8)
-      }
+      hipLaunchKernelGGL(pack_rows_kernel<float>, pgrid, dim3(256), 0, s, op->g.N, op->n_band,
+                         op->band_cells, l_s, U_dev, l_d, Z_dev, (float*)packed);
     }
-#undef DOT_JAC_CASE
+    DOT_LAUNCH_CHECK();
+    // tiles per wave, and the columns the padded tiles reach
+    const int qmax = mode == 0 ? (tiles + 7) / 8 : MT * qn_split;
+    const int ncp = mode == 0 ? ((8 * qmax - 1) / MT + 1) * 16 : 8 * qn_split * 16;
+    const size_t shm = jac_lds_bytes(mode, MT * 16, ncp);
+    int rc = DOT_EINVAL;
+#define DOT_JAC_LAUNCH(M, Q, MTV)                                                              \
+  {                                                                                            \
+    auto kern = jac_mfma_kernel<M, Q, MTV>;                                                    \
+    DOT_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                                (int)shm));                                                    \
+    hipLaunchKernelGGL(kern, dim3((unsigned)op->n_chunks), dim3(JTHREADS), shm, s,             \
+                       op->pair_band, op->pair_g, op->chunk_begin, l_s, l_d, na,               \
+                       reinterpret_cast<const typename JacPack<M>::type*>(packed), partial,    \
+                       ncp);                                                                   \
+    DOT_LAUNCH_CHECK();                                                                        \
+    rc = DOT_OK;                                                                               \
+  }
+#define DOT_JAC_F64(Q) \
+  case Q:              \
+    DOT_JAC_LAUNCH(0, Q, 0) break;
+// split forms: qmax = MT * QN, dispatched on (MT, QN)
+#define DOT_JAC_SPLIT(M, MTV, QNV)       \
+  if (MT == MTV && qn_split == QNV) {    \
+    DOT_JAC_LAUNCH(M, (MTV) * (QNV), MTV) \
+  }
+#define DOT_JAC_SPLIT_ALL(M)                                                                     \
+  DOT_JAC_SPLIT(M, 1, 1) DOT_JAC_SPLIT(M, 1, 2) DOT_JAC_SPLIT(M, 1, 3) DOT_JAC_SPLIT(M, 1, 4)    \
+  DOT_JAC_SPLIT(M, 1, 5) DOT_JAC_SPLIT(M, 1, 6) DOT_JAC_SPLIT(M, 1, 7) DOT_JAC_SPLIT(M, 1, 8)    \
+  DOT_JAC_SPLIT(M, 2, 1) DOT_JAC_SPLIT(M, 2, 2) DOT_JAC_SPLIT(M, 2, 3) DOT_JAC_SPLIT(M, 2, 4)    \
+  DOT_JAC_SPLIT(M, 3, 1) DOT_JAC_SPLIT(M, 3, 2) DOT_JAC_SPLIT(M, 4, 1) DOT_JAC_SPLIT(M, 4, 2)
+    if (mode == 0) {
+      switch (qmax) {
+        DOT_JAC_F64(1) DOT_JAC_F64(2) DOT_JAC_F64(3) DOT_JAC_F64(4)
+        DOT_JAC_F64(5) DOT_JAC_F64(6) DOT_JAC_F64(7) DOT_JAC_F64(8)
+      }
+    } else if (mode == 2) {
+      DOT_JAC_SPLIT_ALL(2)
+    } else {
+      DOT_JAC_SPLIT_ALL(3)
+    }
+#undef DOT_JAC_SPLIT_ALL
+#undef DOT_JAC_SPLIT
+#undef DOT_JAC_F64
+#undef DOT_JAC_LAUNCH
     if (rc) return rc;
   }
   dim3 grid((lsld * na + 255) / 256, m0);
@@ -525,9 +896,8 @@ int dot_grad_misfit(dot_op* op, int l_s, const double* U_dev, int l_d, const dou
                      Z_dev, Rs_dev, sc);
   DOT_LAUNCH_CHECK();
   if (op->n_chunks > 0) {
-    hipLaunchKernelGGL(grad_chunk_kernel, dim3((unsigned)op->n_chunks), dim3(256), 0, s, op->g, P,
-                       op->theta, op->phi, op->pair_cell, op->chunk_begin, op->chunk_rbf, sc,
-                       partial);
+    hipLaunchKernelGGL(grad_chunk_kernel, dim3((unsigned)op->n_chunks), dim3(256), 0, s, na,
+                       op->pair_cell, op->pair_g, op->chunk_begin, sc, partial);
     DOT_LAUNCH_CHECK();
   }
   hipLaunchKernelGGL(grad_reduce_kernel, dim3((m0 * na + 255) / 256), dim3(256), 0, s, m0,

@@ -488,7 +488,8 @@ int dot_destroy_operator(dot_op* op) {
   void* ptrs[] = {op->cx,        op->cy,         op->cz,          op->b0,        op->diag,
                   op->sd,        op->sx,         op->sy,          op->sz,        op->sx32,
                   op->sy32,      op->sz32,       op->phi,         op->theta,     op->pair_cell,
-                  op->rbf_start, op->chunk_rbf,  op->chunk_begin, op->rbf_chunk0, op->cells_dev,  op->small_dev};
+                  op->rbf_start, op->chunk_rbf,  op->chunk_begin, op->rbf_chunk0, op->cells_dev,  op->small_dev,
+                  op->pair_g,    op->pair_band,  op->band_idx,    op->band_cells, op->band_part};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (op->pinned) (void)hipHostFree(op->pinned);
@@ -611,6 +612,8 @@ int dot_pals_mua(dot_op* op, const dot_pals* pals, const double* theta_dev, doub
   op->n_pairs = total;
   op->n_chunks = nch;
   op->pals = *pals;
+  rc = jac_prepare(op, s);
+  if (rc) return rc;
   op->have_pals = true;
   return DOT_OK;
 }

@@ -240,6 +240,32 @@ def test_jacobian_fp64_matches_oracle(dotlib, dev, name):
     assert np.linalg.norm(Js - Jr) <= 1e-12 * np.linalg.norm(Jr)
 
 
+@pytest.mark.parametrize("ls,ld", [(64, 64), (3, 70)])
+def test_jacobian_large_sample_counts(dotlib, dev, ls, ld):
+    """Sample counts beyond the matrix-core tiling (64 x 64: the plain binary64
+    kernel; split forms refuse) and a ragged l_s + l_d = 73, against the
+    oracle's loop nest on random fields (the contraction is linear in them)."""
+    wl = synthetic.make_workload(synthetic.get_config("t3d"))
+    prob = oprob.build(wl)
+    rng = np.random.default_rng(ls * 100 + ld)
+    U = rng.standard_normal((prob.N, ls))
+    Z = rng.standard_normal((prob.N, ld))
+    Jr = oest.jacobian_sparse_loops(U, Z, prob.G(wl.theta_ref))
+    op, grid, pals, th = gpu_operator(dotlib, dev, wl)
+    with op:
+        op.pals_mua(pals, th)
+        Ut, Zt = torch.tensor(U, device=dev), torch.tensor(Z, device=dev)
+        Js = op.jacobian(Ut, Zt, dotlib.DOT_JAC_FP64).cpu().numpy()
+        assert np.linalg.norm(Js - Jr) <= 1e-12 * np.linalg.norm(Jr)
+        if ls == 64:
+            with pytest.raises(dotlib.DotError) as ei:
+                op.jacobian(Ut, Zt, dotlib.DOT_JAC_SPLIT_BF16)
+            assert ei.value.code == -1
+        else:
+            J2 = op.jacobian(Ut, Zt, dotlib.DOT_JAC_SPLIT_BF16X3).cpu().numpy()
+            assert np.linalg.norm(J2 - Jr) <= 1e-6 * np.linalg.norm(Jr)
+
+
 @pytest.mark.parametrize("name", NAMES)
 def test_gradient_matches_oracle(dotlib, dev, name):
     wl, prob, W, V, data, ref = case(name)
