@@ -221,7 +221,7 @@ size_t dot_jacobian_workspace_bytes(const dot_op* op, int l_s, int l_d);
  * throughout, on the binary64 matrix cores), DOT_JAC_SPLIT_BF16 or
  * DOT_JAC_SPLIT_BF16X3 (operands rounded to binary32 and split into 2 or 3
  * bfloat16 parts, products on the matrix cores with binary32 accumulation
- * over 256-cell runs, binary64 sums across runs and chunks).  U_dev: N x l_s,
+ * over 512-cell runs, binary64 sums across runs and chunks).  U_dev: N x l_s,
  * Z_dev: N x l_d, l_s <= 1024.  The matrix-core kernels need
  * ceil(l_s / 16) ceil(l_d n_act / 16) <= 64 (split forms: l_s <= 64 and
  * ceil(l_s / 16) ceil(l_d n_act / 128) <= 8) and l_s + l_d <= 128; beyond

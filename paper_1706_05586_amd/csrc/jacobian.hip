@@ -163,6 +163,11 @@ __global__ __launch_bounds__(256) void pair_g_kernel(GridDims g, JacParams P,
   }
 }
 
+__global__ void fill_double_kernel(double* __restrict__ a, int n, double v) {
+  const int i = threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
 __global__ void fill_int_kernel(int32_t* __restrict__ a, int64_t n, int32_t v) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) a[i] = v;
@@ -308,7 +313,7 @@ __global__ __launch_bounds__(256) void pack_rows_kernel(int64_t N, int64_t n_ban
 // parts (x = hi + lo, or hi + mid + lo); the part products of total order at
 // most MODE - 1 are issued as v_mfma_f32_16x16x32_bf16 (3 products for two
 // parts, 6 for three), accumulated in binary32 and flushed into the binary64
-// partial block every JFLUSH K-steps (256 pairs).
+// partial block every JFLUSH K-steps (512 pairs).
 // Output tiles of 16 x 16 are dealt to the 8 waves round-robin: tile
 // t = wave + 8 q covers rows 16 (t % MT) .. +15 and columns 16 (t / MT) .. +15,
 // zero-padded beyond l_s rows and l_d na columns.  Lane layout of both
@@ -324,7 +329,7 @@ constexpr int JKP32 = JK + 4;     // padded binary32 LDS row (144 bytes)
 constexpr int JKP64 = JK + 1;     // padded binary64 LDS row
 constexpr int JTHREADS = 512;     // 8 waves; 16 threads per pair of a step
 constexpr int JRMAX = 8;          // values per thread and step: l_s + l_d <= 128
-constexpr int JFLUSH = 8;         // K-steps between binary64 flushes
+constexpr int JFLUSH = 16;        // K-steps between binary64 flushes
 
 template <int TERMS>
 __device__ __forceinline__ void split_bf16(float x, __bf16* parts) {
@@ -349,16 +354,18 @@ struct JacPack<0> {
   using type = double;
 };
 
+// A rows, B columns, and one discard row for the stores of lanes that hold
+// no operand value (their stores are unconditional)
 __host__ __device__ inline size_t jac_lds_bytes(int mode, int rows, int ncp) {
-  return mode == 0 ? (size_t)(rows + ncp) * JKP64 * sizeof(double)
-                   : (size_t)(rows + ncp) * JKP32 * sizeof(float);
+  return mode == 0 ? (size_t)(rows + ncp + 1) * JKP64 * sizeof(double)
+                   : (size_t)(rows + ncp + 1) * JKP32 * sizeof(float);
 }
 
 // MTC: the row-tile count ceil(l_s / 16) as a constant (split forms), or 0
 // (binary64, which takes it at run time)
 template <int MODE, int QMAX, int MTC>
 __global__ __launch_bounds__(JTHREADS) void jac_mfma_kernel(
-    const int32_t* __restrict__ pair_band, const double* __restrict__ pair_g,
+    const int32_t* __restrict__ pair_band, const double* __restrict__ pair_g, int64_t n_pairs,
     const int64_t* __restrict__ chunk_begin, int l_s, int l_d, int na,
     const typename JacPack<MODE>::type* __restrict__ packed, double* __restrict__ partial,
     int ncp) {
@@ -444,45 +451,57 @@ __global__ __launch_bounds__(JTHREADS) void jac_mfma_kernel(
   using GT = typename std::conditional<MODE == 0, double, float>::type;
   PT val[2][JRMAX];
   GT gv[2][5];
+  // Loads are unconditional, from clamped (always valid) addresses, and no
+  // loaded value is selected on afterwards (a select lets the compiler sink
+  // the load into a branch that then waits for it): a pair beyond the chunk
+  // reads band row 0 and the zero G entries past the last pair (n_pairs),
+  // so its B entries vanish and its A entries multiply zeros; a value index
+  // beyond L is clamped and its stores go to the discard row.
   auto band_row = [&](int64_t base) -> int {
-    return base + pb < b1 ? pair_band[base + pb] : -1;
+    return pair_band[base + pb < b1 ? base + pb : b1 - 1];
   };
   auto load_step = [&](auto slot_c, int64_t base, int bi) {
     constexpr int S = decltype(slot_c)::value;
-    const bool valid = bi >= 0;
+    const bool valid = base + pb < b1;
     const PT* row = packed + (int64_t)(valid ? bi : 0) * L;
 #pragma unroll
     for (int r = 0; r < JRMAX; ++r) {
+      if (r >= nr) break;
       const int i = qv + 16 * r;
-      val[S][r] = (r < nr && i < L && valid) ? row[i] : PT(0);
+      val[S][r] = row[i < L ? i : L - 1];
     }
-    const int64_t p = valid ? base + pb : b0;
+    const double* gp = pair_g + (valid ? base + pb : n_pairs) * na;
 #pragma unroll
-    for (int a = 0; a < 5; ++a) gv[S][a] = (a < na && valid) ? (GT)pair_g[p * na + a] : GT(0);
+    for (int a = 0; a < 5; ++a) {
+      if (a >= na) break;
+      gv[S][a] = (GT)gp[a];
+    }
   };
+  // every lane stores every slot; a value that is not an A entry (or not a
+  // B entry) goes to the discard row instead, so the stores need no branches
+  const int discard = rows + ncp;
   auto store_step = [&](auto slot_c) {
     constexpr int S = decltype(slot_c)::value;
 #pragma unroll
     for (int r = 0; r < JRMAX; ++r) {
+      if (r >= nr) break;
       const int i = qv + 16 * r;
-      if (r >= nr || i >= L) continue;
-      if (i < l_s) {
-        if constexpr (MODE == 0) {
-          dA[i * JKP64 + pb] = val[S][r];
-        } else {
-          fA[i * JKP32 + pb] = val[S][r];
-        }
+      const bool isA = i < l_s, isB = i >= l_s && i < L;
+      const int arow_s = isA ? i : discard;
+      const int j = isB ? i - l_s : 0;
+      if constexpr (MODE == 0) {
+        dA[arow_s * JKP64 + pb] = val[S][r];
       } else {
-        const int j = i - l_s;
+        fA[arow_s * JKP32 + pb] = val[S][r];
+      }
 #pragma unroll
-        for (int a = 0; a < 5; ++a) {
-          if (a >= na) break;
-          const int n = j + l_d * a;
-          if constexpr (MODE == 0) {
-            dB[n * JKP64 + pb] = val[S][r] * gv[S][a];
-          } else {
-            fB[n * JKP32 + pb] = val[S][r] * gv[S][a];
-          }
+      for (int a = 0; a < 5; ++a) {
+        if (a >= na) break;
+        const int n = isB ? rows + j + l_d * a : discard;   // row of B within the LDS block
+        if constexpr (MODE == 0) {
+          dA[n * JKP64 + pb] = val[S][r] * gv[S][a];
+        } else {
+          fA[n * JKP32 + pb] = val[S][r] * gv[S][a];
         }
       }
     }
@@ -709,8 +728,11 @@ int jac_prepare(dot_op* op, hipStream_t s) {
   const int na = P.n_act;
   const int64_t N = op->g.N, np = op->n_pairs;
   const int m0 = op->pals.m0;
-  int rc = grow(&op->pair_g, &op->pair_g_cap, std::max<int64_t>(np * na, 1));
+  // one zero G record past the last pair (read by absent pairs of a K-step)
+  int rc = grow(&op->pair_g, &op->pair_g_cap, (np + 1) * na + 8);
   if (rc) return rc;
+  hipLaunchKernelGGL(fill_double_kernel, dim3(1), dim3(64), 0, s, op->pair_g + np * na, 8, 0.0);
+  DOT_LAUNCH_CHECK();
   rc = grow(&op->pair_band, &op->pair_band_cap, std::max<int64_t>(np, 1));
   if (rc) return rc;
   if (!op->band_idx) DOT_HIP(hipMalloc(&op->band_idx, (size_t)N * sizeof(int32_t)));
@@ -830,7 +852,7 @@ int dot_jacobian(dot_op* op, int l_s, const double* U_dev, int l_d, const double
     DOT_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, \
                                 (int)shm));                                                    \
     hipLaunchKernelGGL(kern, dim3((unsigned)op->n_chunks), dim3(JTHREADS), shm, s,             \
-                       op->pair_band, op->pair_g, op->chunk_begin, l_s, l_d, na,               \
+                       op->pair_band, op->pair_g, op->n_pairs, op->chunk_begin, l_s, l_d, na,  \
                        reinterpret_cast<const typename JacPack<M>::type*>(packed), partial,    \
                        ncp);                                                                   \
     DOT_LAUNCH_CHECK();                                                                        \
