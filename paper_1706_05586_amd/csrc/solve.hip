@@ -60,6 +60,7 @@ constexpr int TX = 64;              // one wave per x row
 constexpr int TY = DOT_TY;          // rows per tile
 constexpr int NT = TX * TY;
 constexpr int NHALO = 2 * TX + 2 * TY;
+static_assert(NT >= NHALO, "every halo cell of a tile needs a thread of its block");
 constexpr int RG = DOT_RG64;        // columns per block, binary64 sweeps and elementwise passes
 template <typename T>
 struct ColsPerBlock {
