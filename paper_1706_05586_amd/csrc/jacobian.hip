@@ -392,10 +392,10 @@ __global__ __launch_bounds__(JTHREADS) void jac_mfma_kernel(
 
   // per tile: operand rows/columns of this lane and the output offset.
   // Binary64: tiles t = wave + 8 q round-robin.  Split bfloat16: wave w owns
-  // the column tiles nt = w + 8 c (c < QN) with every row tile mt, tile
-  // q = c MT + mt, so a wave splits each A fragment once per K-step and each
-  // B fragment once (the splitting, not the matrix cores, bounds that form).
-  const int QN = MODE == 0 ? 0 : QMAX / MT;
+  // the column tiles nt = w + 8 c (c < QMAX / MT) with every row tile mt,
+  // tile q = c MT + mt, so a wave splits each A fragment once per K-step and
+  // each B fragment once (the splitting, not the matrix cores, bounds that
+  // form).
   int arow[QMAX], bcol[QMAX], ooff[QMAX], orow[QMAX], ocol[QMAX];
 #pragma unroll
   for (int q = 0; q < QMAX; ++q) {
