@@ -108,3 +108,12 @@ def lift(W: np.ndarray, Wt: np.ndarray) -> np.ndarray:
 def thin_svd(Js: np.ndarray):
     """J_s = U diag(s) Y^T, economy size (the SVD behind the Gauss-Newton model, eq. GN)."""
     return np.linalg.svd(Js, full_matrices=False)
+
+
+def tsvd_step(Js: np.ndarray, r: np.ndarray, t: int) -> np.ndarray:
+    """Truncated-SVD Gauss-Newton step for min ||J_s d + r_s|| (eqs. Eq:NLLS,
+    TREGS J), kept to the t largest singular values (the directions the
+    regularized model favours): d = -sum_{i < t} (u_i^T r / s_i) y_i."""
+    U, s, Yt = np.linalg.svd(np.asarray(Js), full_matrices=False)
+    c = (U[:, :t].T @ np.asarray(r)) / s[:t]
+    return -(Yt[:t].T @ c)

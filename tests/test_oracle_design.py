@@ -112,3 +112,29 @@ def test_lift_and_thin_svd():
     Js = rng.standard_normal((12, 30))
     U, s, Yt = design.thin_svd(Js)
     assert np.allclose((U * s) @ Yt, Js, atol=1e-13)
+
+
+@pytest.mark.parametrize("shape", [(30, 12), (12, 30)])
+def test_tsvd_step_full_rank_is_least_squares(shape):
+    """All singular values kept: the minimum-norm least-squares solution of
+    J d = -r (numpy.linalg.lstsq), tall and wide."""
+    rng = np.random.default_rng(sum(shape))
+    J = rng.standard_normal(shape)
+    r = rng.standard_normal(shape[0])
+    d = design.tsvd_step(J, r, min(shape))
+    ref = -np.linalg.lstsq(J, r, rcond=None)[0]
+    assert np.allclose(d, ref, atol=1e-12)
+
+
+def test_tsvd_step_truncated_residual_orthogonal_to_kept_directions():
+    """With t < rank the step lies in the span of the first t right vectors
+    and the model residual J d + r has no component along the first t left
+    vectors."""
+    rng = np.random.default_rng(3)
+    J = rng.standard_normal((25, 10)) @ np.diag(np.logspace(0, -6, 10))
+    r = rng.standard_normal(25)
+    t = 4
+    d = design.tsvd_step(J, r, t)
+    U, s, Yt = np.linalg.svd(J, full_matrices=False)
+    assert np.linalg.norm(U[:, :t].T @ (J @ d + r)) <= 1e-12 * np.linalg.norm(r)
+    assert np.linalg.norm(Yt[t:] @ d) <= 1e-12 * np.linalg.norm(d)
