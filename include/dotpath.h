@@ -336,6 +336,20 @@ int dot_svd_thin(int m, int n, const double* A_dev, int lda, double* s_dev, doub
                  int ldu, double* Y_dev, int ldy, double rcut, void* work_dev, size_t work_bytes,
                  void* stream);
 
+/*
+ * Truncated-SVD Gauss-Newton step for min ||J d + r|| (Section 2, eq. GN and
+ * Eq:NLLS; its sampled form eq. TREGS J), kept to the t leading singular
+ * triplets of J = L diag(s) R^T:  x = -sum_{i < t} (L(:, i)^T r / s_i) R(:, i).
+ * L_dev rows x k (ldl), s_dev k (descending, s_i > 0 for i < t), R_dev
+ * cols x k (ldr), r_dev rows, x_dev cols (all device).  For the sampled
+ * Jacobian J_s (l_s l_d x n_p) either factor order of dot_svd_thin applies:
+ * the SVD of J_s^T gives L = Y, R = U.  Deterministic; does not synchronize.
+ */
+size_t dot_tsvd_step_workspace_bytes(int t);
+int dot_tsvd_step(int rows, int cols, int k, const double* L_dev, int ldl, const double* s_dev,
+                  const double* R_dev, int ldr, int t, const double* r_dev, double* x_dev,
+                  void* work_dev, size_t work_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

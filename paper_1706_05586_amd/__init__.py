@@ -8,7 +8,8 @@ from ._lib import (DOT_ACT_ALPHA, DOT_ACT_BETA, DOT_ACT_CHI, DOT_BC_DIRICHLET, D
                    DOT_FP64, DOT_JAC_FP64, DOT_JAC_SPLIT_BF16, DOT_JAC_SPLIT_BF16X3, DOT_MIXED, DotError, NotConverged,
                    LIB_PATH)
 from .api import (Grid, Operator, Pals, SolveResult, colmajor, empty_colmajor, gemm, hooi,
-                  mode_gram, optimized_design, pals_field, qr_complete, svd_thin, symeig)
+                  mode_gram, optimized_design, pals_field, qr_complete, svd_thin, symeig,
+                  tsvd_step)
 from .autograd import MisfitFn, MisfitProblem, misfit
 
 __all__ = [
@@ -16,5 +17,5 @@ __all__ = [
     "DOT_FP64", "DOT_MIXED", "DOT_JAC_FP64", "DOT_JAC_SPLIT_BF16", "DOT_JAC_SPLIT_BF16X3", "DotError", "NotConverged",
     "LIB_PATH", "Grid", "Operator", "Pals", "SolveResult", "colmajor", "empty_colmajor",
     "gemm", "pals_field", "MisfitFn", "MisfitProblem", "misfit", "mode_gram", "symeig",
-    "qr_complete", "hooi", "svd_thin", "optimized_design",
+    "qr_complete", "hooi", "svd_thin", "tsvd_step", "optimized_design",
 ]

@@ -100,6 +100,8 @@ SIGNATURES = {
                       C.POINTER(C.c_double), _vp, _sz, _vp]),
     "dot_svd_workspace_bytes": (_sz, [_i, _i]),
     "dot_svd_thin": (_i, [_i, _i, _vp, _i, _vp, _vp, _i, _vp, _i, _d, _vp, _sz, _vp]),
+    "dot_tsvd_step_workspace_bytes": (_sz, [_i]),
+    "dot_tsvd_step": (_i, [_i, _i, _i, _vp, _i, _vp, _vp, _i, _i, _vp, _vp, _vp, _sz, _vp]),
     "dot_profile_enable": (_i, [_vp, _i]),
     "dot_profile_read": (_i, [_vp, _i, C.POINTER(C.c_double), C.POINTER(_i64),
                               C.POINTER(_i64)]),

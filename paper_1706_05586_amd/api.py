@@ -22,7 +22,7 @@ from ._lib import check, lib
 
 __all__ = ["Grid", "Pals", "Operator", "SolveResult", "pals_field", "gemm", "colmajor",
            "empty_colmajor", "mode_gram", "symeig", "qr_complete", "hooi", "svd_thin",
-           "optimized_design"]
+           "tsvd_step", "optimized_design"]
 
 
 def _stream() -> C.c_void_p:
@@ -224,6 +224,24 @@ def svd_thin(A: torch.Tensor, rcut: float = 1e-12):
     check(lib.dot_svd_thin(m, n, _ptr(Am), m, _ptr(s), _ptr(U), m, _ptr(Y), n, float(rcut),
                            _ptr(work), work.numel(), _stream()), "dot_svd_thin")
     return s, U, Y
+
+
+def tsvd_step(L: torch.Tensor, s: torch.Tensor, R: torch.Tensor, r: torch.Tensor, t: int):
+    """Truncated-SVD Gauss-Newton step for min ||J d + r|| with J = L diag(s) R^T:
+    d = -sum_{i < t} (L[:, i]^T r / s_i) R[:, i]."""
+    rows, k = L.shape
+    cols = R.shape[0]
+    if R.shape[1] != k or s.numel() < k or r.numel() != rows:
+        raise ValueError("shape mismatch in tsvd_step")
+    Lm, Rm = colmajor(L, "L"), colmajor(R, "R")
+    _need_cuda_f64(s, "s")
+    _need_cuda_f64(r, "r")
+    x = torch.empty(cols, dtype=torch.float64, device=L.device)
+    work = _workspace(int(lib.dot_tsvd_step_workspace_bytes(int(t))), L.device)
+    check(lib.dot_tsvd_step(rows, cols, k, _ptr(Lm), rows, _ptr(s.contiguous()), _ptr(Rm), cols,
+                            int(t), _ptr(r.contiguous()), _ptr(x), _ptr(work), work.numel(),
+                            _stream()), "dot_tsvd_step")
+    return x
 
 
 def optimized_design(Js: torch.Tensor, W: torch.Tensor, V: torch.Tensor, q_s: int, q_d: int,

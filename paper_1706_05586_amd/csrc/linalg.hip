@@ -866,6 +866,40 @@ int gemm_launch(int transa, int transb, int m, int n, int kdim, double alpha, co
 
 }  // namespace dot
 
+namespace dot {
+
+// c_i = (L(:, i)^T r) / s_i for i < t: one block per i, fixed-order sum
+__global__ __launch_bounds__(256) void tsvd_coef_kernel(int rows, const double* __restrict__ L, int ldl,
+                                                        const double* __restrict__ s,
+                                                        const double* __restrict__ r,
+                                                        double* __restrict__ c) {
+  __shared__ double red[256];
+  const int i = blockIdx.x;
+  const double* col = L + (int64_t)ldl * i;
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < rows; e += 256) acc += col[e] * r[e];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) c[i] = red[0] / s[i];
+}
+
+// x_j = -sum_{i < t} R(j, i) c_i
+__global__ __launch_bounds__(256) void tsvd_combine_kernel(int cols, int t, const double* __restrict__ R,
+                                                           int ldr, const double* __restrict__ c,
+                                                           double* __restrict__ x) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cols) return;
+  double acc = 0.0;
+  for (int i = 0; i < t; ++i) acc += R[j + (int64_t)ldr * i] * c[i];
+  x[j] = -acc;
+}
+
+}  // namespace dot
+
 using namespace dot;
 
 extern "C" {
@@ -1082,6 +1116,30 @@ int dot_svd_thin(int m, int n, const double* A_dev, int lda, double* s_dev, doub
                      std::max(cut, 1e-300), Us, m);
   DOT_LAUNCH_CHECK();
   DOT_TRY_L(gemm_launch(1, 0, n, m, m, 1.0, A_dev, lda, Us, m, 0.0, Y_dev, ldy, s));
+  return DOT_OK;
+}
+
+size_t dot_tsvd_step_workspace_bytes(int t) { return t < 1 ? 256 : al256((size_t)t * sizeof(double)); }
+
+int dot_tsvd_step(int rows, int cols, int k, const double* L_dev, int ldl, const double* s_dev,
+                  const double* R_dev, int ldr, int t, const double* r_dev, double* x_dev,
+                  void* work_dev, size_t work_bytes, void* stream) {
+  clear_error();
+  if (rows < 1 || cols < 1 || k < 1) DOT_FAIL(DOT_EINVAL, "rows, cols and k must be >= 1");
+  if (t < 0 || t > k) DOT_FAIL(DOT_EINVAL, "need 0 <= t <= k");
+  if (ldl < rows || ldr < cols) DOT_FAIL(DOT_EINVAL, "leading dimension too small");
+  if (!L_dev || !s_dev || !R_dev || !r_dev || !x_dev) DOT_FAIL(DOT_EINVAL, "NULL argument");
+  if (!work_dev || work_bytes < dot_tsvd_step_workspace_bytes(t))
+    DOT_FAIL(DOT_ENOMEM, "workspace too small");
+  hipStream_t s = as_stream(stream);
+  double* c = (double*)work_dev;
+  if (t > 0) {
+    hipLaunchKernelGGL(tsvd_coef_kernel, dim3(t), dim3(256), 0, s, rows, L_dev, ldl, s_dev, r_dev, c);
+    DOT_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(tsvd_combine_kernel, dim3((cols + 255) / 256), dim3(256), 0, s, cols, t, R_dev,
+                     ldr, c, x_dev);
+  DOT_LAUNCH_CHECK();
   return DOT_OK;
 }
 

@@ -180,3 +180,23 @@ def test_svd_thin_matches_lapack(dl, dev, m, n):
     sr = np.linalg.svd(A, compute_uv=False)
     assert np.max(np.abs(s - sr)) <= 1e-10 * sr[0]
     assert np.linalg.norm((U * s) @ Y.T - A) <= 1e-10 * np.linalg.norm(A)
+
+
+@pytest.mark.parametrize("m,n,t", [(400, 320, 320), (400, 320, 40), (150, 400, 150), (150, 400, 17)])
+def test_tsvd_step_matches_oracle(dl, dev, m, n, t):
+    """Truncated-SVD Gauss-Newton step from the library's thin SVD (of J^T for
+    a tall J, as for the sampled Jacobian of the 128^3 workload) against the
+    oracle's numpy-SVD step.  The Gram route resolves a singular vector to
+    about eps s_max^2 / (gap of s^2), about 1e-9 for the smallest of these
+    spectra (s from 1 to 1e-3), hence the 1e-7 bound."""
+    rng = np.random.default_rng(m + n + t)
+    J = rng.standard_normal((m, n)) @ np.diag(np.logspace(0, -3, n))
+    r = rng.standard_normal(m)
+    if m >= n:
+        s, U, Y = dl.svd_thin(T(J.T, dev), rcut=1e-12)   # J = Y diag(s) U^T
+        L, R = Y, U
+    else:
+        s, L, R = dl.svd_thin(T(J, dev), rcut=1e-12)     # J = U diag(s) Y^T
+    d = dl.tsvd_step(L, s, R, T(r, dev), t).cpu().numpy()
+    ref = odesign.tsvd_step(J, r, t)
+    assert np.linalg.norm(d - ref) <= 1e-7 * np.linalg.norm(ref)
