@@ -222,12 +222,12 @@ size_t dot_jacobian_workspace_bytes(const dot_op* op, int l_s, int l_d);
  * DOT_JAC_SPLIT_BF16X3 (operands rounded to binary32 and split into 2 or 3
  * bfloat16 parts, products on the matrix cores with binary32 accumulation
  * over 512-cell runs, binary64 sums across runs and chunks).  U_dev: N x l_s,
- * Z_dev: N x l_d, l_s <= 1024.  The matrix-core kernels need
- * ceil(l_s / 16) ceil(l_d n_act / 16) <= 64 (split forms: l_s <= 64 and
- * ceil(l_s / 16) ceil(l_d n_act / 128) <= 8) and l_s + l_d <= 128; beyond
- * that DOT_JAC_FP64 runs a plain binary64 kernel and the split forms return
- * DOT_EINVAL.  The workspace holds per-chunk partial blocks and the packed
- * rows of U and Z at the listed cells.
+ * Z_dev: N x l_d, l_s <= 1024.  The binary64 matrix-core kernel needs
+ * ceil(l_s / 16) ceil(l_d n_act / 16) <= 64 and l_s + l_d <= 128, beyond
+ * that DOT_JAC_FP64 runs a plain binary64 kernel; the split forms need
+ * l_s <= 64 and l_d <= 64 and return DOT_EINVAL beyond.  The workspace holds
+ * per-chunk partial blocks and the packed rows of U and Z at the listed
+ * cells (for the split forms U already split into its bfloat16 parts).
  */
 int dot_jacobian(dot_op* op, int l_s, const double* U_dev, int l_d, const double* Z_dev,
                  int precision, double* Js_dev, void* work_dev, size_t work_bytes, void* stream);

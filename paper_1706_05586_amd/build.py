@@ -22,6 +22,10 @@ LIB = os.path.join(PKG, "libdotpath.so")
 ARCH = "gfx950"
 
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# per-source extras.  jacobian.hip: matrix-core accumulators in ordinary
+# VGPRs, which keeps the split-bfloat16 contraction from holding a second
+# copy of them in AGPRs (one more resident wave per SIMD).
+FILE_FLAGS = {"jacobian.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 COMMON = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Wall",
           "-Wno-unused-function", "-Wno-unknown-pragmas", "-I", os.path.join(ROOT, "include")]
 
@@ -35,7 +39,8 @@ def hipcc() -> str:
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [hipcc(), *COMMON, *DEVICE_FLAGS, "-c", src, "-o", obj]
+    cmd = [hipcc(), *COMMON, *DEVICE_FLAGS, *FILE_FLAGS.get(os.path.basename(src), []),
+           "-c", src, "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{res.stderr}")

@@ -14,6 +14,9 @@
 
 namespace dot {
 
+// pairs per chunk of the contraction (a chunk never spans two RBFs)
+constexpr int64_t DOT_PAIR_CHUNK = 512;
+
 // ---------------------------------------------------------------- errors
 void set_error(const char* fmt, ...);
 void clear_error();
@@ -87,13 +90,15 @@ struct dot_op {
   int64_t* chunk_begin = nullptr;  // device, per chunk: first pair
   int32_t* rbf_chunk0 = nullptr;   // device, m0 + 1: first chunk of each RBF
   int64_t chunk_cap = 0;
-  int64_t n_chunks = 0;
+  int64_t n_chunks = 0;            // chunks hold at most DOT_PAIR_CHUNK pairs
   int64_t rbf_cap = 0;
   // per pair: h^d d mu / d p of its RBF's active parameters (pair-major), and
   // its row in the band-cell list (every cell of any list, in cell order),
   // through which the contraction reads U and Z rows packed cell-major
   double* pair_g = nullptr;
   int64_t pair_g_cap = 0;        // doubles
+  float* pair_g32 = nullptr;     // the same values rounded to binary32
+  int64_t pair_g32_cap = 0;
   int32_t* pair_band = nullptr;
   int64_t pair_band_cap = 0;
   int32_t* band_idx = nullptr;   // N: band row of a cell, -1 elsewhere

@@ -149,7 +149,8 @@ __global__ __launch_bounds__(256) void pair_g_kernel(GridDims g, JacParams P,
                                                      const double* __restrict__ phi,
                                                      const int64_t* __restrict__ rbf_start,
                                                      const int32_t* __restrict__ pair_cell,
-                                                     double* __restrict__ pair_g) {
+                                                     double* __restrict__ pair_g,
+                                                     float* __restrict__ pair_g32) {
   const int m = blockIdx.x;
   const double* th = theta + (int64_t)m * P.stride;
   const int na = P.n_act;
@@ -159,11 +160,20 @@ __global__ __launch_bounds__(256) void pair_g_kernel(GridDims g, JacParams P,
     cell_xyz(g, c, &x0, &x1, &x2);
     rbf_dphi(P, th, x0, x1, x2, d);
     const double w = band_weight(P, phi[c]);
-    for (int a = 0; a < na; ++a) pair_g[p * na + a] = P.hd * (w * d[a]);
+    for (int a = 0; a < na; ++a) {
+      const double v = P.hd * (w * d[a]);
+      pair_g[p * na + a] = v;
+      pair_g32[p * na + a] = (float)v;
+    }
   }
 }
 
 __global__ void fill_double_kernel(double* __restrict__ a, int n, double v) {
+  const int i = threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+__global__ void fill_float_kernel(float* __restrict__ a, int n, float v) {
   const int i = threadIdx.x;
   if (i < n) a[i] = v;
 }
@@ -300,36 +310,30 @@ __global__ __launch_bounds__(256) void pack_rows_kernel(int64_t N, int64_t n_ban
 }
 
 // ----------------------------------------------------------------------
-// Matrix-core contraction of one chunk (the pairs of one RBF, or a piece of
-// them).  Per chunk it is a dense product
+// Binary64 matrix-core contraction of one chunk (the pairs of one RBF, or a
+// piece of them).  Per chunk it is a dense product
 //     P[i, n] = sum_p U[c_p, i] B[p, n],  B[p, j + l_d a] = Z[c_p, j] G[p, a],
 // i < l_s, n < l_d na, over the chunk's pairs in K-steps of 32.  A thread
 // stages the values i = t % 16 + 16 r of pair t / 16 of a step from its packed
 // row (one contiguous row per pair) into LDS: U as the A operand, Z times the
 // pair's G as the B operand.  The next step's rows are loaded while the
-// matrix cores work on the current one (band rows two steps ahead).
-// MODE 0: binary64 operands, v_mfma_f64_16x16x4f64, binary64 accumulation.
-// MODE 2 / 3: operands rounded to binary32 and split into 2 / 3 bfloat16
-// parts (x = hi + lo, or hi + mid + lo); the part products of total order at
-// most MODE - 1 are issued as v_mfma_f32_16x16x32_bf16 (3 products for two
-// parts, 6 for three), accumulated in binary32 and flushed into the binary64
-// partial block every JFLUSH K-steps (512 pairs).
+// matrix cores work on the current one (band rows two steps ahead).  The
+// products run on v_mfma_f64_16x16x4f64 with binary64 accumulation.
 // Output tiles of 16 x 16 are dealt to the 8 waves round-robin: tile
 // t = wave + 8 q covers rows 16 (t % MT) .. +15 and columns 16 (t / MT) .. +15,
-// zero-padded beyond l_s rows and l_d na columns.  Lane layout of both
-// instructions: A row l % 16, B column l % 16, k in groups by l / 16; result
-// column l % 16, rows 4 (l / 16) + e for the bfloat16 form and l / 16 + 4 e
-// for the binary64 form (e < 4).
+// zero-padded beyond l_s rows and l_d na columns.  Lane layout: A row l % 16,
+// B column l % 16, k = l / 16 + 4 s; result column l % 16, rows l / 16 + 4 e.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr int JK = 32;            // pairs per K-step
-constexpr int JKP32 = JK + 4;     // padded binary32 LDS row (144 bytes)
 constexpr int JKP64 = JK + 1;     // padded binary64 LDS row
 constexpr int JTHREADS = 512;     // 8 waves; 16 threads per pair of a step
 constexpr int JRMAX = 8;          // values per thread and step: l_s + l_d <= 128
-constexpr int JFLUSH = 16;        // K-steps between binary64 flushes
+constexpr int JFLUSH = 16;        // K-steps per binary32 run of the split forms
+constexpr int JSLOT = JK * JFLUSH;                                    // pairs per run
+constexpr int JSPC = (int)((DOT_PAIR_CHUNK + JSLOT - 1) / JSLOT);     // runs per chunk
 
 template <int TERMS>
 __device__ __forceinline__ void split_bf16(float x, __bf16* parts) {
@@ -345,112 +349,60 @@ __device__ __forceinline__ void split_bf16(float x, __bf16* parts) {
   }
 }
 
-template <int MODE>
-struct JacPack {
-  using type = float;
-};
-template <>
-struct JacPack<0> {
-  using type = double;
-};
-
 // A rows, B columns, and one discard row for the stores of lanes that hold
 // no operand value (their stores are unconditional)
-__host__ __device__ inline size_t jac_lds_bytes(int mode, int rows, int ncp) {
-  return mode == 0 ? (size_t)(rows + ncp + 1) * JKP64 * sizeof(double)
-                   : (size_t)(rows + ncp + 1) * JKP32 * sizeof(float);
+__host__ __device__ inline size_t jac_lds_bytes(int rows, int ncp) {
+  return (size_t)(rows + ncp + 1) * JKP64 * sizeof(double);
 }
 
-// MTC: the row-tile count ceil(l_s / 16) as a constant (split forms), or 0
-// (binary64, which takes it at run time)
-template <int MODE, int QMAX, int MTC>
+template <int QMAX>
 __global__ __launch_bounds__(JTHREADS) void jac_mfma_kernel(
     const int32_t* __restrict__ pair_band, const double* __restrict__ pair_g, int64_t n_pairs,
     const int64_t* __restrict__ chunk_begin, int l_s, int l_d, int na,
-    const typename JacPack<MODE>::type* __restrict__ packed, double* __restrict__ partial,
-    int ncp) {
-  using PT = typename JacPack<MODE>::type;
-  constexpr int TERMS = MODE == 0 ? 1 : MODE;
+    const double* __restrict__ packed, double* __restrict__ partial, int ncp) {
   extern __shared__ __attribute__((aligned(16))) unsigned char jsm[];
   const int ch = blockIdx.x;
   const int64_t b0 = chunk_begin[ch], b1 = chunk_begin[ch + 1];
   const int L = l_s + l_d;
   const int lsld = l_s * l_d;
   const int ncol = l_d * na;
-  const int MT = MTC > 0 ? MTC : (l_s + 15) / 16;
+  const int MT = (l_s + 15) / 16;
   const int rows = MT * 16;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   double* out = partial + (int64_t)ch * lsld * na;
-  float* fA = reinterpret_cast<float*>(jsm);     // [rows][JKP32]
-  float* fB = fA + rows * JKP32;                 // [ncp][JKP32]
   double* dA = reinterpret_cast<double*>(jsm);   // [rows][JKP64]
   double* dB = dA + rows * JKP64;                // [ncp][JKP64]
   {  // rows >= l_s and columns >= ncol are never written: clear once
-    const int words = (int)(jac_lds_bytes(MODE, rows, ncp) / 4);
+    const int words = (int)(jac_lds_bytes(rows, ncp) / 4);
     for (int e = threadIdx.x; e < words; e += JTHREADS) reinterpret_cast<int*>(jsm)[e] = 0;
   }
 
-  // per tile: operand rows/columns of this lane and the output offset.
-  // Binary64: tiles t = wave + 8 q round-robin.  Split bfloat16: wave w owns
-  // the column tiles nt = w + 8 c (c < QMAX / MT) with every row tile mt,
-  // tile q = c MT + mt, so a wave splits each A fragment once per K-step and
-  // each B fragment once (the splitting, not the matrix cores, bounds that
-  // form).
+  // per tile t = wave + 8 q: operand rows/columns of this lane and the output
+  // offset of its result rows l / 16 + 4 e
   int arow[QMAX], bcol[QMAX], ooff[QMAX], orow[QMAX], ocol[QMAX];
 #pragma unroll
   for (int q = 0; q < QMAX; ++q) {
-    int mt, nt;
-    if constexpr (MODE == 0) {
-      const int t = wave + 8 * q;
-      mt = t % MT;
-      nt = t / MT;
-    } else {
-      mt = q % MT;
-      nt = wave + 8 * (q / MT);
-    }
+    const int t = wave + 8 * q;
+    const int mt = t % MT, nt = t / MT;
     arow[q] = mt * 16 + (lane & 15);
     bcol[q] = nt * 16 + (lane & 15);
-    // result element e of this lane: row i0 + rstep e (binary32 form: rows
-    // 4 (l / 16) + e; binary64 form: rows l / 16 + 4 e), column bcol
-    const int i0 = MODE == 0 ? mt * 16 + (lane >> 4) : mt * 16 + 4 * (lane >> 4);
+    const int i0 = mt * 16 + (lane >> 4);
     const int n = bcol[q];
     orow[q] = i0;
     ocol[q] = n;
     ooff[q] = n < ncol ? (n % l_d) + l_d * i0 + lsld * (n / l_d) : 0;
   }
-  constexpr int rstep = MODE == 0 ? 4 : 1;
-  f32x4 acc[QMAX];
   f64x4 acc64[QMAX];
 #pragma unroll
-  for (int q = 0; q < QMAX; ++q) {
-    acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-    acc64[q] = f64x4{0.0, 0.0, 0.0, 0.0};
-  }
-  bool first = true;
-  auto flush = [&]() {
-#pragma unroll
-    for (int q = 0; q < QMAX; ++q) {
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        if (orow[q] + e < l_s && ocol[q] < ncol) {
-          double* o = out + ooff[q] + l_d * e;
-          *o = first ? (double)acc[q][e] : *o + (double)acc[q][e];
-        }
-      }
-      acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-    }
-    first = false;
-  };
+  for (int q = 0; q < QMAX; ++q) acc64[q] = f64x4{0.0, 0.0, 0.0, 0.0};
 
   // staging: thread t holds values i = qv + 16 r of pair pb of a step, in two
   // register slots: the rows of step s + 2 are loaded while step s is staged
   // and multiplied, so a load has two steps to arrive
   const int pb = threadIdx.x >> 4, qv = threadIdx.x & 15;
   const int nr = (L + 15) / 16;
-  // G in binary32 for the split forms: it only scales the binary32 B operand
-  using GT = typename std::conditional<MODE == 0, double, float>::type;
-  PT val[2][JRMAX];
-  GT gv[2][5];
+  double val[2][JRMAX];
+  double gv[2][5];
   // Loads are unconditional, from clamped (always valid) addresses, and no
   // loaded value is selected on afterwards (a select lets the compiler sink
   // the load into a branch that then waits for it): a pair beyond the chunk
@@ -463,7 +415,7 @@ __global__ __launch_bounds__(JTHREADS) void jac_mfma_kernel(
   auto load_step = [&](auto slot_c, int64_t base, int bi) {
     constexpr int S = decltype(slot_c)::value;
     const bool valid = base + pb < b1;
-    const PT* row = packed + (int64_t)(valid ? bi : 0) * L;
+    const double* row = packed + (int64_t)(valid ? bi : 0) * L;
 #pragma unroll
     for (int r = 0; r < JRMAX; ++r) {
       if (r >= nr) break;
@@ -474,7 +426,7 @@ __global__ __launch_bounds__(JTHREADS) void jac_mfma_kernel(
 #pragma unroll
     for (int a = 0; a < 5; ++a) {
       if (a >= na) break;
-      gv[S][a] = (GT)gp[a];
+      gv[S][a] = gp[a];
     }
   };
   // every lane stores every slot; a value that is not an A entry (or not a
@@ -489,67 +441,24 @@ __global__ __launch_bounds__(JTHREADS) void jac_mfma_kernel(
       const bool isA = i < l_s, isB = i >= l_s && i < L;
       const int arow_s = isA ? i : discard;
       const int j = isB ? i - l_s : 0;
-      if constexpr (MODE == 0) {
-        dA[arow_s * JKP64 + pb] = val[S][r];
-      } else {
-        fA[arow_s * JKP32 + pb] = val[S][r];
-      }
+      dA[arow_s * JKP64 + pb] = val[S][r];
 #pragma unroll
       for (int a = 0; a < 5; ++a) {
         if (a >= na) break;
         const int n = isB ? rows + j + l_d * a : discard;   // row of B within the LDS block
-        if constexpr (MODE == 0) {
-          dA[n * JKP64 + pb] = val[S][r] * gv[S][a];
-        } else {
-          fA[n * JKP32 + pb] = val[S][r] * gv[S][a];
-        }
+        dA[n * JKP64 + pb] = val[S][r] * gv[S][a];
       }
     }
   };
   auto multiply = [&]() {
-    if constexpr (MODE == 0) {
-      const int kl = lane >> 4;
+    const int kl = lane >> 4;
 #pragma unroll
-      for (int q = 0; q < QMAX; ++q) {
+    for (int q = 0; q < QMAX; ++q) {
 #pragma unroll
-        for (int ks = 0; ks < JK / 4; ++ks) {
-          const double a = dA[arow[q] * JKP64 + 4 * ks + kl];
-          const double b = dB[bcol[q] * JKP64 + 4 * ks + kl];
-          acc64[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc64[q], 0, 0, 0);
-        }
-      }
-    } else {
-      // binary32 operands staged in LDS, split into bfloat16 parts while the
-      // fragments are built (8 consecutive k per lane): the MT row fragments
-      // once, then per owned column tile its fragment and MT products
-      const int kofs = 8 * (lane >> 4);
-      auto build = [&](const float* src, bf16x8* f) {
-        const float4* p4 = reinterpret_cast<const float4*>(src);
-        const float4 x0 = p4[0], x1 = p4[1];
-        const float xv[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          __bf16 xp[TERMS];
-          split_bf16<TERMS>(xv[e], xp);
-#pragma unroll
-          for (int p = 0; p < TERMS; ++p) f[p][e] = xp[p];
-        }
-      };
-      constexpr int MTS = MTC > 0 ? MTC : 1;
-      bf16x8 fa[MTS][TERMS];
-#pragma unroll
-      for (int mt = 0; mt < MTS; ++mt) build(&fA[(mt * 16 + (lane & 15)) * JKP32 + kofs], fa[mt]);
-      bf16x8 fbc[TERMS];
-#pragma unroll
-      for (int q = 0; q < QMAX; ++q) {
-        const int mt = q % MTS;
-        if (mt == 0) build(&fB[(wave + 8 * (q / MTS)) * 16 * JKP32 + (lane & 15) * JKP32 + kofs], fbc);
-#pragma unroll
-        for (int pa = 0; pa < TERMS; ++pa)
-#pragma unroll
-          for (int pq = 0; pq < TERMS; ++pq)
-            if (pa + pq <= TERMS - 1)
-              acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[mt][pa], fbc[pq], acc[q], 0, 0, 0);
+      for (int ks = 0; ks < JK / 4; ++ks) {
+        const double a = dA[arow[q] * JKP64 + 4 * ks + kl];
+        const double b = dB[bcol[q] * JKP64 + 4 * ks + kl];
+        acc64[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc64[q], 0, 0, 0);
       }
     }
   };
@@ -561,7 +470,6 @@ __global__ __launch_bounds__(JTHREADS) void jac_mfma_kernel(
   load_step(S1{}, b0 + JK, band_row(b0 + JK));
   int biA = band_row(b0 + 2 * JK), biB = band_row(b0 + 3 * JK);
   __syncthreads();  // LDS cleared before the first store
-  int kstep = 0;
   // one K-step from register slot S: stage, multiply, refill the slot with
   // the rows of the step two ahead
   auto step = [&](auto slot_c, int64_t base) {
@@ -570,28 +478,326 @@ __global__ __launch_bounds__(JTHREADS) void jac_mfma_kernel(
     __syncthreads();
     if (base + 2 * JK < b1) load_step(slot_c, base + 2 * JK, biA);
     multiply();
-    if constexpr (MODE != 0) {
-      if ((kstep + 1) % JFLUSH == 0) flush();
-    }
     __syncthreads();  // operand reads done before the next store
     biA = biB;
     biB = bnext;
-    ++kstep;
   };
   for (int64_t base = b0; base < b1; base += 2 * JK) {
     step(S0{}, base);
     if (base + JK < b1) step(S1{}, base + JK);
   }
-  if constexpr (MODE == 0) {
 #pragma unroll
-    for (int q = 0; q < QMAX; ++q) {
+  for (int q = 0; q < QMAX; ++q) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
-        if (orow[q] + rstep * e < l_s && ocol[q] < ncol) out[ooff[q] + l_d * rstep * e] = acc64[q][e];
-    }
-  } else {
-    if (first || kstep % JFLUSH != 0) flush();
+    for (int e = 0; e < 4; ++e)
+      if (orow[q] + 4 * e < l_s && ocol[q] < ncol) out[ooff[q] + l_d * 4 * e] = acc64[q][e];
   }
+}
+
+// ----------------------------------------------------------------------
+// Split-bfloat16 contraction with operands split once.
+//
+// pack_split_kernel writes, per band row b (cell c_b), the bfloat16 parts of
+// U[c_b, i] rounded to binary32 (i < MT 16, zero for i >= l_s) as one word
+// per value (hi | lo << 16 for two parts; {hi | mid << 16, lo} for three)
+// and Z[c_b, j] in binary32.  jac_split_kernel then runs one block of four
+// waves per chunk, in K-steps of 32 pairs: the 16 threads of a pair couple
+// (k, k + 1) copy the A parts of both pairs into LDS as [part][i][k] and
+// form the B values Z[c_k, j] G[k, a] for their columns j = q + 16 r,
+// splitting each product once and storing its parts as [part][n][k],
+// n = j + l_d a; the next step's rows and G are loaded while the waves
+// multiply.  Wave w owns the column tiles nt = w + 4 q with every row tile;
+// per (row tile, column tile) it issues the part products of total order at
+// most TERMS - 1 on v_mfma_f32_16x16x32_bf16, accumulates in binary32 and
+// flushes into the binary64 partial block every JFLUSH K-steps.
+template <int TERMS>
+struct SplitWord {
+  using type = uint32_t;
+};
+template <>
+struct SplitWord<3> {
+  using type = uint2;
+};
+
+__device__ __forceinline__ unsigned short bf16_bits(__bf16 v) {
+  return __builtin_bit_cast(unsigned short, v);
+}
+
+template <int TERMS>
+__device__ __forceinline__ typename SplitWord<TERMS>::type split_word(float x) {
+  __bf16 p[TERMS];
+  split_bf16<TERMS>(x, p);
+  if constexpr (TERMS == 2) {
+    return (uint32_t)bf16_bits(p[0]) | ((uint32_t)bf16_bits(p[1]) << 16);
+  } else {
+    return uint2{(uint32_t)bf16_bits(p[0]) | ((uint32_t)bf16_bits(p[1]) << 16),
+                 (uint32_t)bf16_bits(p[2])};
+  }
+}
+
+// the parts of x0 and x1 (two pairs of one column) packed two to a word:
+// word p = part p of x0 | part p of x1 << 16, one two-way conversion per part
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+template <int TERMS>
+__device__ __forceinline__ void split_pair(float x0, float x1, uint32_t* w) {
+  f32x2 r = f32x2{x0, x1};
+#pragma unroll
+  for (int p = 0; p < TERMS; ++p) {
+    const uint32_t b = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, bf16x2));
+    w[p] = b;
+    if (p + 1 < TERMS) {
+      r.x -= __builtin_bit_cast(float, b << 16);
+      r.y -= __builtin_bit_cast(float, b & 0xffff0000u);
+    }
+  }
+}
+
+// part p of a split word
+template <int TERMS>
+__device__ __forceinline__ uint32_t word_part(const typename SplitWord<TERMS>::type& w, int p) {
+  if constexpr (TERMS == 2) {
+    return p == 0 ? (w & 0xffffu) : (w >> 16);
+  } else {
+    return p == 0 ? (w.x & 0xffffu) : p == 1 ? (w.x >> 16) : (w.y & 0xffffu);
+  }
+}
+
+template <int TERMS>
+__global__ __launch_bounds__(256) void pack_split_kernel(int64_t N, int64_t n_band,
+                                                         const int32_t* __restrict__ band_cells,
+                                                         int l_s, const double* __restrict__ U,
+                                                         int l_d, const double* __restrict__ Z,
+                                                         int mt16, int ldj,
+                                                         typename SplitWord<TERMS>::type* __restrict__ pu,
+                                                         float* __restrict__ pz) {
+  extern __shared__ float ptile[];  // [64][L + 1]
+  const int L = l_s + l_d, LP = L + 1;
+  const int64_t b0 = (int64_t)blockIdx.x * 64;
+  const int t = threadIdx.x, bl = t & 63;
+  const int64_t b = b0 + bl;
+  const int64_t c = b < n_band ? band_cells[b] : 0;
+  // columns i = t / 64 + 4 k, eight loads in flight per thread (a row of
+  // band cells is a gather: latency, not bandwidth, bounds one load at a
+  // time).  Loads and stores are unconditional (a guarded load is waited
+  // for inside its branch): rows past n_band read cell 0 and are never
+  // written out, columns past L are clamped and land in the pad column L.
+  for (int i0 = t >> 6; i0 < L; i0 += 32) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int i = min(i0 + 4 * k, L - 1);
+      const double* src = i < l_s ? U + N * (int64_t)i : Z + N * (int64_t)(i - l_s);
+      v[k] = src[c];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) ptile[bl * LP + min(i0 + 4 * k, L)] = (float)v[k];
+  }
+  __syncthreads();
+  const int rows = (int)(n_band - b0 < 64 ? n_band - b0 : 64);
+  for (int e = t; e < rows * mt16; e += 256) {
+    const int r = e / mt16, i = e - r * mt16;
+    pu[(b0 + r) * mt16 + i] = split_word<TERMS>(i < l_s ? ptile[r * LP + i] : 0.f);
+  }
+  for (int e = t; e < rows * ldj; e += 256) {
+    const int r = e / ldj, j = e - r * ldj;
+    pz[(b0 + r) * ldj + j] = j < l_d ? ptile[r * LP + l_s + j] : 0.f;
+  }
+}
+
+constexpr int JS_THREADS = 256;   // 4 waves; 16 threads per pair couple of a K-step
+constexpr int JS_KP = 40;         // LDS row of one operand value over a K-step: 32 pairs + 8 pad (80 B)
+
+// A: [TERMS][MT 16][JS_KP]; B: [TERMS][na JR 16][JS_KP] (column n = a JR 16 + j)
+__host__ __device__ inline size_t jac_split_lds_bytes(int terms, int mt, int jr, int na) {
+  return (size_t)terms * (mt + na * jr) * 16 * JS_KP * sizeof(unsigned short);
+}
+
+// MT row tiles (l_s <= 16 MT), JR detector-sample tiles per parameter
+// (l_d <= 16 JR); the B columns of parameter a start at a 16 JR, so every
+// LDS offset of a staging thread is a constant from one base address.
+// Column tiles: na JR, at most 5 JR; wave w owns tiles w + 4 q, q < NTW.
+template <int TERMS, int MT, int JR>
+__global__ __launch_bounds__(JS_THREADS) void jac_split_kernel(
+    const int32_t* __restrict__ pair_band, const float* __restrict__ pair_g, int64_t n_pairs,
+    const int64_t* __restrict__ chunk_begin, int l_s, int l_d, int na,
+    const typename SplitWord<TERMS>::type* __restrict__ pu, const float* __restrict__ pz,
+    float* __restrict__ partial) {
+  using SW = typename SplitWord<TERMS>::type;
+  constexpr int MT16 = MT * 16;
+  constexpr int LDJ = JR * 16;
+  constexpr int NTW = (5 * JR + 3) / 4;
+  extern __shared__ __attribute__((aligned(16))) unsigned char jsm[];
+  unsigned short* sA = reinterpret_cast<unsigned short*>(jsm);  // [TERMS][MT16][JS_KP]
+  unsigned short* sB = sA + TERMS * MT16 * JS_KP;                // [TERMS][na LDJ][JS_KP]
+  const int ch = blockIdx.x;
+  const int64_t b0 = chunk_begin[ch], b1 = chunk_begin[ch + 1];
+  const int lsld = l_s * l_d;
+  const int nt = na * JR;
+  const int brows = na * LDJ;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  float* out = partial + (int64_t)ch * JSPC * lsld * na;
+
+  f32x4 acc[NTW][MT];
+#pragma unroll
+  for (int q = 0; q < NTW; ++q)
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) acc[q][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // the binary32 block of run `slot` (JFLUSH K-steps) is stored, not added:
+  // no load waits in the K loop; the reduce sums the runs in binary64
+  auto flush = [&](int slot) {
+    // an opaque copy of the lane index keeps the output addresses from being
+    // computed once before the K loop and held in registers throughout
+    int lo = lane;
+    asm volatile("" : "+v"(lo));
+    float* o_s = out + (int64_t)slot * lsld * na;
+#pragma unroll
+    for (int q = 0; q < NTW; ++q) {
+      const int n = (wave + 4 * q) * 16 + (lo & 15);
+      const int a = n / LDJ, j = n - a * LDJ;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const int i0 = mt * 16 + 4 * (lo >> 4);
+        if (a < na && j < l_d) {
+          float* o = o_s + j + l_d * i0 + lsld * a;
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (i0 + e < l_s) o[l_d * e] = acc[q][mt][e];
+        }
+        acc[q][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+    }
+  };
+
+  // staging roles: pair couple cp (pairs 2 cp, 2 cp + 1 of a step), value
+  // index qv: A rows i = qv + 16 r (r < MT), B detector samples j = qv + 16 r
+  // (r < JR; the packed Z rows are zero past l_d)
+  const int cp = threadIdx.x >> 4, qv = threadIdx.x & 15;
+  SW ua[MT][2];
+  float zv[JR][2];
+  float gv[5][2];
+  // Loads are unconditional from clamped addresses: a pair beyond the chunk
+  // reads band row 0 and the zero G record past the last pair (n_pairs), so
+  // its B values vanish.
+  auto band_rows = [&](int64_t base, int* r) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t p = base + 2 * cp + h;
+      r[h] = p < b1 ? pair_band[p] : 0;
+    }
+  };
+  auto load_step = [&](int64_t base, const int* brow) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t p = base + 2 * cp + h;
+      const SW* ur = pu + (int64_t)brow[h] * MT16 + qv;
+#pragma unroll
+      for (int r = 0; r < MT; ++r) ua[r][h] = ur[16 * r];
+      const float* zr = pz + (int64_t)brow[h] * LDJ + qv;
+#pragma unroll
+      for (int r = 0; r < JR; ++r) zv[r][h] = zr[16 * r];
+      const float* gp = pair_g + (p < b1 ? p : n_pairs) * na;
+#pragma unroll
+      for (int a = 0; a < 5; ++a) {
+        if (a >= na) break;
+        gv[a][h] = gp[a];
+      }
+    }
+  };
+  // this thread's LDS words: pairs 2 cp, 2 cp + 1 of row qv (+ constants)
+  uint32_t* const wA = reinterpret_cast<uint32_t*>(sA + qv * JS_KP + 2 * cp);
+  uint32_t* const wB = reinterpret_cast<uint32_t*>(sB + qv * JS_KP + 2 * cp);
+  const int partB = brows * JS_KP / 2;  // words between parts of B
+  auto store_step = [&]() {
+#pragma unroll
+    for (int r = 0; r < MT; ++r)
+#pragma unroll
+      for (int p = 0; p < TERMS; ++p)
+        wA[(p * MT16 + 16 * r) * (JS_KP / 2)] =
+            word_part<TERMS>(ua[r][0], p) | (word_part<TERMS>(ua[r][1], p) << 16);
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+      if (a >= na) break;
+#pragma unroll
+      for (int r = 0; r < JR; ++r) {
+        uint32_t w[TERMS];
+        split_pair<TERMS>(zv[r][0] * gv[a][0], zv[r][1] * gv[a][1], w);
+#pragma unroll
+        for (int p = 0; p < TERMS; ++p) wB[p * partB + (a * LDJ + 16 * r) * (JS_KP / 2)] = w[p];
+      }
+    }
+  };
+  auto multiply = [&]() {
+    const int kofs = 8 * (lane >> 4);
+    bf16x8 fa[MT][TERMS];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int p = 0; p < TERMS; ++p)
+        fa[mt][p] = *reinterpret_cast<const bf16x8*>(sA + (p * MT16 + mt * 16 + (lane & 15)) * JS_KP + kofs);
+    // a wave with fewer than NTW column tiles repeats its last valid tile
+    // into the spare accumulators (never flushed): no branch around the
+    // matrix-core instructions
+#pragma unroll
+    for (int q = 0; q < NTW; ++q) {
+      const int ntq = min(wave + 4 * q, nt - 1);
+      bf16x8 fb[TERMS];
+#pragma unroll
+      for (int p = 0; p < TERMS; ++p)
+        fb[p] = *reinterpret_cast<const bf16x8*>(sB + (p * brows + ntq * 16 + (lane & 15)) * JS_KP + kofs);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int pa = 0; pa < TERMS; ++pa)
+#pragma unroll
+          for (int pb = 0; pb < TERMS; ++pb)
+            if (pa + pb <= TERMS - 1)
+              acc[q][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[mt][pa], fb[pb], acc[q][mt], 0, 0, 0);
+    }
+  };
+
+  int brow[2], bnext[2];
+  band_rows(b0, brow);
+  load_step(b0, brow);
+  band_rows(b0 + JK, bnext);
+  int kstep = 0;
+  for (int64_t base = b0; base < b1; base += JK) {
+    store_step();
+    __syncthreads();
+    if (base + JK < b1) {
+      brow[0] = bnext[0];
+      brow[1] = bnext[1];
+      load_step(base + JK, brow);
+      band_rows(base + 2 * JK, bnext);
+    }
+    multiply();
+    if ((kstep + 1) % JFLUSH == 0) flush(kstep / JFLUSH);
+    __syncthreads();  // operand reads done before the next store
+    ++kstep;
+  }
+  if (kstep % JFLUSH != 0) flush(kstep / JFLUSH);
+}
+
+// Js[(j + l_d i) + l_s l_d (m na + a)] = - sum over the chunks of RBF m and
+// their runs of JFLUSH K-steps (binary32 blocks), in order, in binary64.
+__global__ void jac_reduce_runs_kernel(int m0, const int32_t* __restrict__ rbf_chunk0,
+                                       const int64_t* __restrict__ chunk_begin, int lsld, int na,
+                                       const float* __restrict__ partial, double* __restrict__ Js) {
+  const int m = blockIdx.y;
+  const int nout = lsld * na;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= m0 || e >= nout) return;
+  const int c0 = rbf_chunk0[m], c1 = rbf_chunk0[m + 1];
+  double s = 0.0;
+  for (int ch = c0; ch < c1; ++ch) {
+    const int64_t len = chunk_begin[ch + 1] - chunk_begin[ch];
+    const int runs = (int)((len + JSLOT - 1) / JSLOT);
+    const float* p = partial + (int64_t)ch * JSPC * nout + e;
+    for (int r = 0; r < runs; ++r) s += (double)p[(int64_t)r * nout];
+  }
+  const int a = e / lsld, row = e % lsld;
+  Js[row + (int64_t)lsld * (m * na + a)] = -s;
 }
 
 // Js[(j + l_d i) + l_s l_d (m na + a)] = - sum over chunks of RBF m.
@@ -697,15 +903,27 @@ static size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // Workspace of dot_jacobian / dot_grad_misfit: per-chunk partial blocks, then
 // the packed band rows (binary64, which also holds the binary32 packing).
+// binary64 per chunk, or binary32 per run of JSLOT pairs (JSPC per chunk)
 static size_t jac_partial_bytes(const dot_op* op, int l_s, int l_d) {
   const int na = n_active_bits(op->pals.active, op->g.dim);
-  return al256((size_t)std::max<int64_t>(op->n_chunks, 1) * l_s * l_d * na * sizeof(double));
+  return al256((size_t)std::max<int64_t>(op->n_chunks, 1) * l_s * l_d * na *
+               std::max(sizeof(double), JSPC * sizeof(float)));
+}
+
+// packed band rows: binary64 rows of l_s + l_d values, or for the split
+// forms the split words of U (at most 8 bytes, l_s rounded up to 16 per row)
+// followed by binary32 rows of Z (l_d rounded up to 16)
+static size_t packed_split_u_bytes(const dot_op* op, int l_s) {
+  return al256((size_t)std::max<int64_t>(op->n_band, 1) * ((l_s + 15) / 16) * 16 * 8);
 }
 
 static size_t jac_bytes(const dot_op* op, int l_s, int l_d) {
   const int na = n_active_bits(op->pals.active, op->g.dim);
-  const size_t jac = jac_partial_bytes(op, l_s, l_d) +
-                     al256((size_t)std::max<int64_t>(op->n_band, 1) * (l_s + l_d) * sizeof(double));
+  const size_t nb = (size_t)std::max<int64_t>(op->n_band, 1);
+  const size_t packed = std::max(al256(nb * (l_s + l_d) * sizeof(double)),
+                                 packed_split_u_bytes(op, l_s) +
+                                     al256(nb * ((l_d + 15) / 16) * 16 * sizeof(float)));
+  const size_t jac = jac_partial_bytes(op, l_s, l_d) + packed;
   const size_t grad = (size_t)op->g.N * sizeof(double) +
                       (size_t)std::max<int64_t>(op->n_chunks, 1) * na * sizeof(double) + 256;
   return al256(std::max(jac, grad));
@@ -733,6 +951,10 @@ int jac_prepare(dot_op* op, hipStream_t s) {
   if (rc) return rc;
   hipLaunchKernelGGL(fill_double_kernel, dim3(1), dim3(64), 0, s, op->pair_g + np * na, 8, 0.0);
   DOT_LAUNCH_CHECK();
+  rc = grow(&op->pair_g32, &op->pair_g32_cap, (np + 1) * na + 8);
+  if (rc) return rc;
+  hipLaunchKernelGGL(fill_float_kernel, dim3(1), dim3(64), 0, s, op->pair_g32 + np * na, 8, 0.f);
+  DOT_LAUNCH_CHECK();
   rc = grow(&op->pair_band, &op->pair_band_cap, std::max<int64_t>(np, 1));
   if (rc) return rc;
   if (!op->band_idx) DOT_HIP(hipMalloc(&op->band_idx, (size_t)N * sizeof(int32_t)));
@@ -742,7 +964,7 @@ int jac_prepare(dot_op* op, hipStream_t s) {
   int64_t* cnt = op->band_part + (nb + 1);
   if (np > 0) {
     hipLaunchKernelGGL(pair_g_kernel, dim3(m0), dim3(256), 0, s, op->g, P, op->theta, op->phi,
-                       op->rbf_start, op->pair_cell, op->pair_g);
+                       op->rbf_start, op->pair_cell, op->pair_g, op->pair_g32);
     DOT_LAUNCH_CHECK();
   }
   hipLaunchKernelGGL(fill_int_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s,
@@ -807,13 +1029,11 @@ int dot_jacobian(dot_op* op, int l_s, const double* U_dev, int l_d, const double
   const int L = l_s + l_d;
   const int MT = (l_s + 15) / 16, NT = (l_d * na + 15) / 16;
   const int tiles = MT * NT;
-  // the matrix-core kernels hold at most 8 tiles per wave and JRMAX staged
-  // values per thread (the split form: every row tile of its column tiles,
-  // MT <= 4); binary64 beyond that runs the plain kernel
-  const int qn_split = (NT + 7) / 8;
-  const bool mfma_fits = precision == DOT_JAC_FP64
-                             ? tiles <= 64 && L <= 16 * JRMAX
-                             : MT <= 4 && MT * qn_split <= 8 && L <= 16 * JRMAX;
+  // binary64: at most 8 tiles per wave and JRMAX staged values per thread,
+  // beyond that the plain kernel.  Split forms: l_s <= 64 and l_d <= 64.
+  const int JRs = (l_d + 15) / 16;
+  const bool mfma_fits = precision == DOT_JAC_FP64 ? tiles <= 64 && L <= 16 * JRMAX
+                                                   : MT <= 4 && JRs <= 4;
   if (precision != DOT_JAC_FP64 && !mfma_fits)
     DOT_FAIL(DOT_EINVAL, "l_s, l_d and n_act too large for the split-bf16 kernel");
   if (precision == DOT_JAC_FP64 && !mfma_fits &&
@@ -830,66 +1050,82 @@ int dot_jacobian(dot_op* op, int l_s, const double* U_dev, int l_d, const double
                        P, op->theta, op->phi, op->pair_cell, op->chunk_begin, op->chunk_rbf, l_s,
                        U_dev, l_d, Z_dev, partial);
     DOT_LAUNCH_CHECK();
-  } else if (op->n_chunks > 0) {
-    const int mode = precision == DOT_JAC_FP64 ? 0 : precision == DOT_JAC_SPLIT_BF16 ? 2 : 3;
+  } else if (op->n_chunks > 0 && precision == DOT_JAC_FP64) {
     const dim3 pgrid((unsigned)((op->n_band + 63) / 64), (unsigned)((L + 63) / 64));
-    if (mode == 0) {
-      hipLaunchKernelGGL(pack_rows_kernel<double>, pgrid, dim3(256), 0, s, op->g.N, op->n_band,
-                         op->band_cells, l_s, U_dev, l_d, Z_dev, (double*)packed);
-    } else {
-      hipLaunchKernelGGL(pack_rows_kernel<float>, pgrid, dim3(256), 0, s, op->g.N, op->n_band,
-                         op->band_cells, l_s, U_dev, l_d, Z_dev, (float*)packed);
-    }
+    hipLaunchKernelGGL(pack_rows_kernel<double>, pgrid, dim3(256), 0, s, op->g.N, op->n_band,
+                       op->band_cells, l_s, U_dev, l_d, Z_dev, (double*)packed);
     DOT_LAUNCH_CHECK();
     // tiles per wave, and the columns the padded tiles reach
-    const int qmax = mode == 0 ? (tiles + 7) / 8 : MT * qn_split;
-    const int ncp = mode == 0 ? ((8 * qmax - 1) / MT + 1) * 16 : 8 * qn_split * 16;
-    const size_t shm = jac_lds_bytes(mode, MT * 16, ncp);
+    const int qmax = (tiles + 7) / 8;
+    const int ncp = ((8 * qmax - 1) / MT + 1) * 16;
+    const size_t shm = jac_lds_bytes(MT * 16, ncp);
     int rc = DOT_EINVAL;
-#define DOT_JAC_LAUNCH(M, Q, MTV)                                                              \
-  {                                                                                            \
-    auto kern = jac_mfma_kernel<M, Q, MTV>;                                                    \
-    DOT_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, \
-                                (int)shm));                                                    \
-    hipLaunchKernelGGL(kern, dim3((unsigned)op->n_chunks), dim3(JTHREADS), shm, s,             \
-                       op->pair_band, op->pair_g, op->n_pairs, op->chunk_begin, l_s, l_d, na,  \
-                       reinterpret_cast<const typename JacPack<M>::type*>(packed), partial,    \
-                       ncp);                                                                   \
-    DOT_LAUNCH_CHECK();                                                                        \
-    rc = DOT_OK;                                                                               \
-  }
-#define DOT_JAC_F64(Q) \
-  case Q:              \
-    DOT_JAC_LAUNCH(0, Q, 0) break;
-// split forms: qmax = MT * QN, dispatched on (MT, QN)
-#define DOT_JAC_SPLIT(M, MTV, QNV)       \
-  if (MT == MTV && qn_split == QNV) {    \
-    DOT_JAC_LAUNCH(M, (MTV) * (QNV), MTV) \
-  }
-#define DOT_JAC_SPLIT_ALL(M)                                                                     \
-  DOT_JAC_SPLIT(M, 1, 1) DOT_JAC_SPLIT(M, 1, 2) DOT_JAC_SPLIT(M, 1, 3) DOT_JAC_SPLIT(M, 1, 4)    \
-  DOT_JAC_SPLIT(M, 1, 5) DOT_JAC_SPLIT(M, 1, 6) DOT_JAC_SPLIT(M, 1, 7) DOT_JAC_SPLIT(M, 1, 8)    \
-  DOT_JAC_SPLIT(M, 2, 1) DOT_JAC_SPLIT(M, 2, 2) DOT_JAC_SPLIT(M, 2, 3) DOT_JAC_SPLIT(M, 2, 4)    \
-  DOT_JAC_SPLIT(M, 3, 1) DOT_JAC_SPLIT(M, 3, 2) DOT_JAC_SPLIT(M, 4, 1) DOT_JAC_SPLIT(M, 4, 2)
-    if (mode == 0) {
-      switch (qmax) {
-        DOT_JAC_F64(1) DOT_JAC_F64(2) DOT_JAC_F64(3) DOT_JAC_F64(4)
-        DOT_JAC_F64(5) DOT_JAC_F64(6) DOT_JAC_F64(7) DOT_JAC_F64(8)
-      }
-    } else if (mode == 2) {
-      DOT_JAC_SPLIT_ALL(2)
-    } else {
-      DOT_JAC_SPLIT_ALL(3)
+#define DOT_JAC_F64(Q)                                                                           \
+  case Q: {                                                                                      \
+    auto kern = jac_mfma_kernel<Q>;                                                              \
+    DOT_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,   \
+                                (int)shm));                                                      \
+    hipLaunchKernelGGL(kern, dim3((unsigned)op->n_chunks), dim3(JTHREADS), shm, s, op->pair_band, \
+                       op->pair_g, op->n_pairs, op->chunk_begin, l_s, l_d, na,                   \
+                       (const double*)packed, partial, ncp);                                     \
+    DOT_LAUNCH_CHECK();                                                                          \
+    rc = DOT_OK;                                                                                 \
+  } break;
+    switch (qmax) {
+      DOT_JAC_F64(1) DOT_JAC_F64(2) DOT_JAC_F64(3) DOT_JAC_F64(4)
+      DOT_JAC_F64(5) DOT_JAC_F64(6) DOT_JAC_F64(7) DOT_JAC_F64(8)
     }
-#undef DOT_JAC_SPLIT_ALL
-#undef DOT_JAC_SPLIT
 #undef DOT_JAC_F64
-#undef DOT_JAC_LAUNCH
+    if (rc) return rc;
+  } else if (op->n_chunks > 0) {
+    const int terms = precision == DOT_JAC_SPLIT_BF16 ? 2 : 3;
+    char* pu = packed;
+    float* pz = reinterpret_cast<float*>(packed + packed_split_u_bytes(op, l_s));
+    const size_t pshm = (size_t)64 * (L + 1) * sizeof(float);
+    const unsigned pblocks = (unsigned)((op->n_band + 63) / 64);
+    if (terms == 2) {
+      hipLaunchKernelGGL(pack_split_kernel<2>, dim3(pblocks), dim3(256), pshm, s, op->g.N,
+                         op->n_band, op->band_cells, l_s, U_dev, l_d, Z_dev, MT * 16, JRs * 16,
+                         reinterpret_cast<uint32_t*>(pu), pz);
+    } else {
+      hipLaunchKernelGGL(pack_split_kernel<3>, dim3(pblocks), dim3(256), pshm, s, op->g.N,
+                         op->n_band, op->band_cells, l_s, U_dev, l_d, Z_dev, MT * 16, JRs * 16,
+                         reinterpret_cast<uint2*>(pu), pz);
+    }
+    DOT_LAUNCH_CHECK();
+    const size_t shm = jac_split_lds_bytes(terms, MT, JRs, na);
+    int rc = DOT_EINVAL;
+#define DOT_JS_LAUNCH(T, M, J)                                                                   \
+  if (terms == T && MT == M && JRs == J) {                                                       \
+    auto kern = jac_split_kernel<T, M, J>;                                                       \
+    DOT_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,   \
+                                (int)shm));                                                      \
+    hipLaunchKernelGGL(kern, dim3((unsigned)op->n_chunks), dim3(JS_THREADS), shm, s,             \
+                       op->pair_band, op->pair_g32, op->n_pairs, op->chunk_begin, l_s, l_d, na,  \
+                       reinterpret_cast<const typename SplitWord<T>::type*>(pu), pz,             \
+                       reinterpret_cast<float*>(partial));                                       \
+    DOT_LAUNCH_CHECK();                                                                          \
+    rc = DOT_OK;                                                                                 \
+  }
+#define DOT_JS_MT(T)                                                                             \
+  DOT_JS_LAUNCH(T, 1, 1) DOT_JS_LAUNCH(T, 1, 2) DOT_JS_LAUNCH(T, 1, 3) DOT_JS_LAUNCH(T, 1, 4)    \
+  DOT_JS_LAUNCH(T, 2, 1) DOT_JS_LAUNCH(T, 2, 2) DOT_JS_LAUNCH(T, 2, 3) DOT_JS_LAUNCH(T, 2, 4)    \
+  DOT_JS_LAUNCH(T, 3, 1) DOT_JS_LAUNCH(T, 3, 2) DOT_JS_LAUNCH(T, 3, 3) DOT_JS_LAUNCH(T, 3, 4)    \
+  DOT_JS_LAUNCH(T, 4, 1) DOT_JS_LAUNCH(T, 4, 2) DOT_JS_LAUNCH(T, 4, 3) DOT_JS_LAUNCH(T, 4, 4)
+    DOT_JS_MT(2)
+    DOT_JS_MT(3)
+#undef DOT_JS_MT
+#undef DOT_JS_LAUNCH
     if (rc) return rc;
   }
   dim3 grid((lsld * na + 255) / 256, m0);
-  hipLaunchKernelGGL(jac_reduce_kernel, grid, dim3(256), 0, s, m0, op->rbf_chunk0, lsld, na,
-                     partial, Js_dev);
+  if (precision != DOT_JAC_FP64 && op->n_chunks > 0) {
+    hipLaunchKernelGGL(jac_reduce_runs_kernel, grid, dim3(256), 0, s, m0, op->rbf_chunk0,
+                       op->chunk_begin, lsld, na, reinterpret_cast<const float*>(partial), Js_dev);
+  } else {
+    hipLaunchKernelGGL(jac_reduce_kernel, grid, dim3(256), 0, s, m0, op->rbf_chunk0, lsld, na,
+                       partial, Js_dev);
+  }
   DOT_LAUNCH_CHECK();
   return profile_end(op, DOT_PROF_JACOBIAN, s, e0, e1);
 }

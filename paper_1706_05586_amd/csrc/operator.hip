@@ -489,7 +489,8 @@ int dot_destroy_operator(dot_op* op) {
                   op->sd,        op->sx,         op->sy,          op->sz,        op->sx32,
                   op->sy32,      op->sz32,       op->phi,         op->theta,     op->pair_cell,
                   op->rbf_start, op->chunk_rbf,  op->chunk_begin, op->rbf_chunk0, op->cells_dev,  op->small_dev,
-                  op->pair_g,    op->pair_band,  op->band_idx,    op->band_cells, op->band_part};
+                  op->pair_g,    op->pair_g32,   op->pair_band,   op->band_idx,   op->band_cells,
+                  op->band_part};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (op->pinned) (void)hipHostFree(op->pinned);
@@ -560,8 +561,8 @@ int dot_pals_mua(dot_op* op, const dot_pals* pals, const double* theta_dev, doub
   std::vector<int64_t> start(m0 + 1, 0);
   for (int m = 0; m < m0; ++m) start[m + 1] = start[m] + counts[m];
   const int64_t total = start[m0];
-  // chunk table: each RBF's list split into chunks of at most kPairChunk cells
-  const int64_t kPairChunk = 2048;
+  // chunk table: each RBF's list split into chunks of at most DOT_PAIR_CHUNK cells
+  const int64_t kPairChunk = DOT_PAIR_CHUNK;
   std::vector<int32_t> chunk_rbf;
   std::vector<int64_t> chunk_begin;
   std::vector<int32_t> rbf_chunk0(m0 + 1, 0);

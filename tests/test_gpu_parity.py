@@ -240,11 +240,13 @@ def test_jacobian_fp64_matches_oracle(dotlib, dev, name):
     assert np.linalg.norm(Js - Jr) <= 1e-12 * np.linalg.norm(Jr)
 
 
-@pytest.mark.parametrize("ls,ld", [(64, 64), (3, 70)])
+@pytest.mark.parametrize("ls,ld", [(64, 64), (3, 70), (9, 64)])
 def test_jacobian_large_sample_counts(dotlib, dev, ls, ld):
-    """Sample counts beyond the matrix-core tiling (64 x 64: the plain binary64
-    kernel; split forms refuse) and a ragged l_s + l_d = 73, against the
-    oracle's loop nest on random fields (the contraction is linear in them)."""
+    """Sample counts at and beyond the matrix-core tilings, against the
+    oracle's loop nest on random fields (the contraction is linear in them):
+    64 x 64 (the plain binary64 kernel when the tiles exceed 64; the split
+    forms at their largest tiling), l_d = 70 (ragged l_s + l_d = 73; the split
+    forms refuse l_d > 64) and 9 x 64 (one row tile, four detector tiles)."""
     wl = synthetic.make_workload(synthetic.get_config("t3d"))
     prob = oprob.build(wl)
     rng = np.random.default_rng(ls * 100 + ld)
@@ -257,13 +259,19 @@ def test_jacobian_large_sample_counts(dotlib, dev, ls, ld):
         Ut, Zt = torch.tensor(U, device=dev), torch.tensor(Z, device=dev)
         Js = op.jacobian(Ut, Zt, dotlib.DOT_JAC_FP64).cpu().numpy()
         assert np.linalg.norm(Js - Jr) <= 1e-12 * np.linalg.norm(Jr)
-        if ls == 64:
+        if ld > 64:
             with pytest.raises(dotlib.DotError) as ei:
                 op.jacobian(Ut, Zt, dotlib.DOT_JAC_SPLIT_BF16)
             assert ei.value.code == -1
         else:
-            J2 = op.jacobian(Ut, Zt, dotlib.DOT_JAC_SPLIT_BF16X3).cpu().numpy()
-            assert np.linalg.norm(J2 - Jr) <= 1e-6 * np.linalg.norm(Jr)
+            # two parts: each product is exact to about 2^-16 relative
+            # (dropped lo lo term and lo rounding); three parts: 2^-24
+            J2 = op.jacobian(Ut, Zt, dotlib.DOT_JAC_SPLIT_BF16).cpu().numpy()
+            J3 = op.jacobian(Ut, Zt, dotlib.DOT_JAC_SPLIT_BF16X3).cpu().numpy()
+            e2 = np.linalg.norm(J2 - Jr) / np.linalg.norm(Jr)
+            e3 = np.linalg.norm(J3 - Jr) / np.linalg.norm(Jr)
+            print(f"[jac {ls}x{ld}] split-bf16 {e2:.2e}, 3-part {e3:.2e}", flush=True)
+            assert e2 <= 1.5e-5 and e3 <= 1e-6
 
 
 @pytest.mark.parametrize("name", NAMES)
