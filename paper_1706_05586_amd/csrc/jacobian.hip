@@ -790,11 +790,22 @@ __global__ void jac_reduce_runs_kernel(int m0, const int32_t* __restrict__ rbf_c
   if (m >= m0 || e >= nout) return;
   const int c0 = rbf_chunk0[m], c1 = rbf_chunk0[m + 1];
   double s = 0.0;
-  for (int ch = c0; ch < c1; ++ch) {
-    const int64_t len = chunk_begin[ch + 1] - chunk_begin[ch];
-    const int runs = (int)((len + JSLOT - 1) / JSLOT);
-    const float* p = partial + (int64_t)ch * JSPC * nout + e;
-    for (int r = 0; r < runs; ++r) s += (double)p[(int64_t)r * nout];
+  if (JSPC == 1) {
+    // one run per chunk: four loads in flight as in jac_reduce_kernel
+    for (int ch = c0; ch < c1; ch += 4) {
+      float v[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[k] = partial[(int64_t)min(ch + k, c1 - 1) * nout + e];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s += (double)v[k] * (double)(ch + k < c1);
+    }
+  } else {
+    for (int ch = c0; ch < c1; ++ch) {
+      const int64_t len = chunk_begin[ch + 1] - chunk_begin[ch];
+      const int runs = (int)((len + JSLOT - 1) / JSLOT);
+      const float* p = partial + (int64_t)ch * JSPC * nout + e;
+      for (int r = 0; r < runs; ++r) s += (double)p[(int64_t)r * nout];
+    }
   }
   const int a = e / lsld, row = e % lsld;
   Js[row + (int64_t)lsld * (m * na + a)] = -s;
@@ -809,7 +820,15 @@ __global__ void jac_reduce_kernel(int m0, const int32_t* __restrict__ rbf_chunk0
   if (m >= m0 || e >= nout) return;
   const int c0 = rbf_chunk0[m], c1 = rbf_chunk0[m + 1];
   double s = 0.0;
-  for (int ch = c0; ch < c1; ++ch) s += partial[(int64_t)ch * nout + e];
+  // four loads in flight, from clamped chunks whose surplus terms are
+  // multiplied by zero (the summation order is the chunk order)
+  for (int ch = c0; ch < c1; ch += 4) {
+    double v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = partial[(int64_t)min(ch + k, c1 - 1) * nout + e];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s += v[k] * (double)(ch + k < c1);
+  }
   const int a = e / lsld, row = e % lsld;
   Js[row + (int64_t)lsld * (m * na + a)] = -s;
 }
