@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define DOT_ABI_VERSION 1
+#define DOT_ABI_VERSION 2
 
 /* return codes */
 #define DOT_OK 0
@@ -54,7 +54,7 @@ extern "C" {
 #define DOT_EINVAL (-1)       /* invalid argument */
 #define DOT_ENOMEM (-2)       /* workspace too small or device allocation failed */
 #define DOT_EHIP (-3)         /* HIP runtime error */
-#define DOT_EBREAKDOWN (-4)   /* CG breakdown: p^T A p <= 0 (operator not SPD) */
+#define DOT_EBREAKDOWN (-4)   /* CG breakdown: p^T A p <= 0 or r^T M^-1 r <= 0 (not SPD) */
 #define DOT_ENONFINITE (-5)   /* NaN or Inf in the data */
 
 /* boundary codes per face */
@@ -62,8 +62,13 @@ extern "C" {
 #define DOT_BC_ROBIN 1
 
 /* solve precision */
-#define DOT_FP64 0    /* Jacobi-PCG in binary64 */
-#define DOT_MIXED 1   /* binary32 Jacobi-PCG inside binary64 iterative refinement */
+#define DOT_FP64 0    /* PCG in binary64 */
+#define DOT_MIXED 1   /* binary32 PCG inside binary64 iterative refinement */
+
+/* solve preconditioner */
+#define DOT_PRECOND_AUTO 0    /* multigrid where the grid has a hierarchy, else Jacobi */
+#define DOT_PRECOND_JACOBI 1  /* Jacobi (the symmetric diagonal scaling alone) */
+#define DOT_PRECOND_MG 2      /* geometric multigrid V-cycle (DOT_EINVAL without a hierarchy) */
 
 /* Jacobian precision */
 #define DOT_JAC_FP64 0        /* binary64 products and sums */
@@ -98,6 +103,7 @@ typedef struct dot_solve_opts {
                          drop before its correction is folded into x in binary64 and its
                          residual is replaced by the binary64 b - A x (e.g. 0.1) */
   int check_every;    /* iterations between host polls of the column flags (>= 1) */
+  int precond;        /* DOT_PRECOND_AUTO, DOT_PRECOND_JACOBI or DOT_PRECOND_MG */
 } dot_solve_opts;
 
 typedef struct dot_solve_info {
@@ -183,13 +189,20 @@ size_t dot_solve_workspace_bytes(const dot_op* op, int k, int precision);
  * Multi-right-hand-side solve A X = RHS (trans = 0) or A^T X = RHS (trans =
  * 1; identical here since A is symmetric), Section 3.3: the forward fields
  * z_i of A z_i = B w_i and the adjoint fields y_j of A^T y_j = C v_j.
- * Jacobi-preconditioned CG from x0 = 0 per column until
- * ||b - A x||_2 <= rtol ||b||_2.  DOT_MIXED runs the CG recurrences (stencil,
+ * Preconditioned CG from x0 = 0 per column until ||b - A x||_2 <= rtol
+ * ||b||_2, on the symmetrically Jacobi-scaled system.  Preconditioner
+ * (opts.precond): a geometric multigrid V-cycle on 3D grids whose sides
+ * halve down to at least 4 cells (2 x 2 x 2 aggregation, the same
+ * finite-volume operator on every level with D and mu averaged, one damped
+ * Jacobi pre- and post-smoothing step, piecewise-constant transfers, damped
+ * Jacobi steps on the coarsest level), or the Jacobi scaling alone.  The
+ * hierarchy is rebuilt by dot_build_operator, dot_set_mua and dot_pals_mua.
+ * DOT_MIXED runs the CG recurrences (stencil,
  * vectors) in binary32 inside binary64 iterative refinement: the binary32
  * correction is folded into x in binary64, and the residual b - A x is
  * recomputed in binary64 and replaces the binary32 one whenever the latter
  * has dropped by inner_rtol (the search direction is kept); convergence is
- * decided on the binary64 residual.
+ * decided on the binary64 residual; the V-cycle then runs in binary32.
  * rhs_dev, x_dev: N x k, must not overlap.  work_dev: >= the size from
  * dot_solve_workspace_bytes, 256-byte aligned.  Synchronizes the stream.
  * Returns DOT_OK, DOT_NOT_CONVERGED (outputs valid), or an error.
@@ -197,6 +210,23 @@ size_t dot_solve_workspace_bytes(const dot_op* op, int k, int precision);
 int dot_solve_multi_rhs(dot_op* op, int trans, int k, const double* rhs_dev, double* x_dev,
                         const dot_solve_opts* opts, void* work_dev, size_t work_bytes,
                         dot_solve_info* info, void* stream);
+
+/* Levels of the multigrid hierarchy the solver uses for this operator, or 0
+ * when it preconditions with Jacobi (2D grids, sides that do not halve to at
+ * least 4 cells, or a level whose diagonal is not positive). */
+int dot_multigrid_levels(const dot_op* op);
+
+/* Workspace bytes for dot_multigrid_apply with k columns (0 without a hierarchy). */
+size_t dot_multigrid_workspace_bytes(const dot_op* op, int k);
+
+/*
+ * One binary64 V-cycle of the solver's preconditioner as an approximate
+ * inverse of A: Z_dev = S^-1 V(S^-1 R_dev), S = diag(A)^(1/2), V the V-cycle on
+ * the scaled system (symmetric positive definite).  R_dev, Z_dev: N x k.
+ * DOT_EINVAL without a hierarchy.
+ */
+int dot_multigrid_apply(dot_op* op, int k, const double* R_dev, double* Z_dev, void* work_dev,
+                        size_t work_bytes, void* stream);
 
 /*
  * Sampled residual and misfit (Section 3.3, eq. EsTResidual; Thm 3.1):
@@ -256,6 +286,8 @@ int dot_grad_misfit(dot_op* op, int l_s, const double* U_dev, int l_d, const dou
 #define DOT_PROF_PCG2_FP32 3
 #define DOT_PROF_RESID 4       /* binary64 residual of the refinement */
 #define DOT_PROF_JACOBIAN 5    /* Jacobian contraction */
+#define DOT_PROF_VCYCLE_FP64 6 /* multigrid V-cycle (all levels), binary64 */
+#define DOT_PROF_VCYCLE_FP32 7 /* multigrid V-cycle (all levels), binary32 */
 #define DOT_PROF_KINDS 8
 int dot_profile_enable(dot_op* op, int enable);
 int dot_profile_read(dot_op* op, int kind, double* ms_total, int64_t* launches,

@@ -24,6 +24,9 @@ DOT_BC_DIRICHLET = 0
 DOT_BC_ROBIN = 1
 DOT_FP64 = 0
 DOT_MIXED = 1
+DOT_PRECOND_AUTO = 0
+DOT_PRECOND_JACOBI = 1
+DOT_PRECOND_MG = 2
 DOT_JAC_FP64 = 0
 DOT_JAC_SPLIT_BF16 = 1
 DOT_JAC_SPLIT_BF16X3 = 2
@@ -37,6 +40,8 @@ DOT_PROF_PCG1_FP32 = 2
 DOT_PROF_PCG2_FP32 = 3
 DOT_PROF_RESID = 4
 DOT_PROF_JACOBIAN = 5
+DOT_PROF_VCYCLE_FP64 = 6
+DOT_PROF_VCYCLE_FP32 = 7
 
 
 class DotGrid(C.Structure):
@@ -51,7 +56,7 @@ class DotPals(C.Structure):
 
 class DotSolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int), ("precision", C.c_int),
-                ("inner_rtol", C.c_double), ("check_every", C.c_int)]
+                ("inner_rtol", C.c_double), ("check_every", C.c_int), ("precond", C.c_int)]
 
 
 class DotSolveInfo(C.Structure):
@@ -79,6 +84,9 @@ SIGNATURES = {
     "dot_set_mua": (_i, [_vp, _vp, _vp]),
     "dot_pals_mua": (_i, [_vp, C.POINTER(DotPals), _vp, _vp, _vp]),
     "dot_apply": (_i, [_vp, _i, _vp, _vp, _vp]),
+    "dot_multigrid_levels": (_i, [_vp]),
+    "dot_multigrid_workspace_bytes": (_sz, [_vp, _i]),
+    "dot_multigrid_apply": (_i, [_vp, _i, _vp, _vp, _vp, _sz, _vp]),
     "dot_form_rhs": (_i, [_vp, _i, _pi32, _i, _vp, _vp, _vp]),
     "dot_solve_workspace_bytes": (_sz, [_vp, _i, _i]),
     "dot_solve_multi_rhs": (_i, [_vp, _i, _i, _vp, _vp, C.POINTER(DotSolveOpts), _vp, _sz,

@@ -338,6 +338,22 @@ class Operator:
         """(RBF, cell) pairs of the band lists of the last pals_mua call."""
         return int(lib.dot_pals_pairs(self._handle))
 
+    @property
+    def multigrid_levels(self) -> int:
+        """Levels of the V-cycle hierarchy the solver uses (0: Jacobi)."""
+        return int(lib.dot_multigrid_levels(self._handle))
+
+    def multigrid_apply(self, R: torch.Tensor) -> torch.Tensor:
+        """One binary64 V-cycle as an approximate inverse of A (N x k in and out)."""
+        Rm = colmajor(R, "R")
+        k = R.shape[1]
+        Z = empty_colmajor(self.N, k, self.device)
+        nbytes = int(lib.dot_multigrid_workspace_bytes(self._handle, k))
+        work = _workspace(max(nbytes, 256), self.device)
+        check(lib.dot_multigrid_apply(self._handle, k, _ptr(Rm), _ptr(Z), _ptr(work), work.numel(),
+                                      _stream()), "dot_multigrid_apply")
+        return Z
+
     def apply(self, X: torch.Tensor) -> torch.Tensor:
         X2 = X.reshape(-1, 1) if X.dim() == 1 else X
         Xm = colmajor(X2, "X")
@@ -370,14 +386,15 @@ class Operator:
     def solve(self, rhs: torch.Tensor, rtol: float = 1e-10, precision: int = L.DOT_FP64,
               max_iter: int = 20000, inner_rtol: float = 0.1,
               check_every: int = 8, trans: int = 0, out: torch.Tensor | None = None,
-              work: torch.Tensor | None = None, warn: bool = True) -> SolveResult:
+              work: torch.Tensor | None = None, warn: bool = True,
+              precond: int = L.DOT_PRECOND_AUTO) -> SolveResult:
         Bm = colmajor(rhs, "rhs")
         k = rhs.shape[1]
         x = out if out is not None else empty_colmajor(self.N, k, self.device)
         nbytes = self.solve_workspace_bytes(k, precision)
         if work is None or work.numel() < nbytes or work.data_ptr() % 256:
             work = _workspace(nbytes, self.device)
-        opts = L.DotSolveOpts(rtol, max_iter, precision, inner_rtol, check_every)
+        opts = L.DotSolveOpts(rtol, max_iter, precision, inner_rtol, check_every, precond)
         iters = np.zeros(k, dtype=np.int32)
         rel = np.zeros(k, dtype=np.float64)
         info = L.DotSolveInfo(0, 0, iters.ctypes.data_as(C.POINTER(C.c_int32)),

@@ -52,6 +52,36 @@ struct GridDims {
 
 struct dot_state_arrays;
 
+// ---------------------------------------------------------------- multigrid
+// Geometric hierarchy for the V-cycle preconditioner (3D grids whose sides
+// halve): level l + 1 aggregates 2 x 2 x 2 cells of level l and is the same
+// finite-volume discretization on the coarse cells, with D and mu averaged
+// over the children.  Every level is kept in the symmetrically scaled form
+// (unit diagonal): couplings to +x, +y, +z in binary64 and binary32.
+constexpr int DOT_MG_MAXLEV = 12;
+
+struct MgLevel {
+  GridDims g;
+  // level 0 points at the operator's arrays; coarse levels own theirs
+  double* D = nullptr;     // diffusion
+  double* mu = nullptr;    // absorption (mass h^d mu)
+  double* cx = nullptr;
+  double* cy = nullptr;
+  double* cz = nullptr;
+  double* b0 = nullptr;
+  double* diag = nullptr;
+  double* sd = nullptr;    // sqrt(diag)
+  double* sx = nullptr;
+  double* sy = nullptr;
+  double* sz = nullptr;
+  float* sx32 = nullptr;
+  float* sy32 = nullptr;
+  float* sz32 = nullptr;
+  // all but the coarsest: sd(cell) / sd_{l+1}(parent), the prolongation weight
+  double* q = nullptr;
+  float* q32 = nullptr;
+};
+
 }  // namespace dot
 
 struct dot_op {
@@ -114,6 +144,13 @@ struct dot_op {
   void* prof = nullptr;           // kernel timing state (solve.hip)
   int32_t* pinned = nullptr;      // pinned host mailbox (counters/flags)
   double* pinned_d = nullptr;     // pinned host doubles (misfit, small results)
+  // multigrid hierarchy (levels 0 .. mg_nlev - 1; mg_nlev < 2: not available)
+  double* D0 = nullptr;           // copy of the frozen diffusion field
+  double* mu0 = nullptr;          // absorption of the current diagonal
+  int mg_nlev = 0;
+  bool mg_ok = false;             // every level's diagonal positive and finite
+  int* mg_flag = nullptr;         // device flag of that check
+  dot::MgLevel mg[dot::DOT_MG_MAXLEV];
 };
 
 namespace dot {
@@ -127,6 +164,35 @@ constexpr int kPinnedInts = 2 * DOT_MAX_COLUMNS + 64;
 int ensure_cells_dev(dot_op* op, int n, const int32_t* cells_host, hipStream_t s);
 // after the pair lists of dot_pals_mua: per-pair d mu / d p and band rows
 int jac_prepare(dot_op* op, hipStream_t s);
+// multigrid: levels of the grid (0 or 1: none), hierarchy (re)build after
+// the diagonal changed, and one V-cycle z = M^-1 r on the scaled system
+int mg_levels_for(const GridDims& g, GridDims* levels);
+int mg_refresh(dot_op* op, hipStream_t s);
+void mg_free(dot_op* op);
+
+// Work vectors of one V-cycle: per level l >= 1 a right-hand side, an
+// iterate and a result (N_l columns apart); level 0 an iterate x0 in the
+// solver's layout.
+template <typename T>
+struct MgWork {
+  int nlev = 0;
+  T* b[DOT_MG_MAXLEV] = {};
+  T* x[DOT_MG_MAXLEV] = {};
+  T* z[DOT_MG_MAXLEV] = {};
+  int64_t ld[DOT_MG_MAXLEV] = {};
+};
+// bytes of MgWork<T> for k columns on op's hierarchy (0 without one);
+// carve the vectors from base (256-aligned), level-0 iterate with stride ld0
+size_t mg_work_bytes(const dot_op* op, int k, int64_t ld0, size_t elem);
+template <typename T>
+void mg_work_layout(const dot_op* op, int k, int64_t ld0, char* base, MgWork<T>* w);
+// partial slots per column of the level-0 smoothing kernel (the dot (r, z))
+int mg_partial_slots(const dot_op* op, int k);
+// z0 = V-cycle applied to r0 (both k columns ld0 apart; columns outside
+// `active` are skipped); partial[0][j][slot] receives r0_j . z0_j
+template <typename T>
+int mg_vcycle(dot_op* op, const MgWork<T>& w, int k, const T* r0, int64_t ld0, T* z0,
+              const int* active, double* partial, hipStream_t s);
 
 constexpr int kWave = 64;
 

@@ -1,0 +1,443 @@
+// Geometric multigrid V-cycle: the preconditioner of the multi-right-hand-side
+// CG on 3D grids that halve (the forward and adjoint solves of Section 3.3).
+//
+// The CG runs on the symmetrically scaled system A^ = S^-1 A S^-1 (S =
+// sqrt(diag A)); its preconditioner is z = S V(S r), V one V-cycle for A.
+// Every level is kept in scaled form (unit diagonal), so with P the 2 x 2 x 2
+// piecewise-constant prolongation the transfers between level l (scaling S_l)
+// and level l + 1 (S_{l+1}) are
+//     prolongation  x^_l += S_l P S_{l+1}^-1 x^_{l+1}   (weight q = sd / sd_parent)
+//     restriction   b^_{l+1} = S_{l+1}^-1 P^T S_l r^_l   (its transpose)
+// and the coarse operator is the same finite-volume discretization on the
+// coarse cells (D and mu averaged over the children).  One V-cycle:
+//     down, level l:  x = w b;  b_{l+1} = R (b - A^ x)          (one kernel)
+//     coarsest:       NU_C damped Jacobi steps from zero
+//     up, level l:    y = x + P z_{l+1};  z = y + w (b - A^ y)   (one kernel)
+// with w = MG_OMEGA.  Pre- and post-smoothing are the same symmetric Jacobi
+// step and R = P^T, so the preconditioner is symmetric; it is positive
+// definite because w < 2 / lambda_max(A^) for these diagonally dominant
+// operators (lambda_max <= 2) and every coarse correction is positive
+// semidefinite.  The up kernel of level 0 also forms r . z per column.
+//
+// Kernel layout: a block is a 32 x 8 (x, y) tile (each wave two rows of 32,
+// so the 2 x 2 aggregates of a plane are pairs of lanes l, l ^ 1 and l, l ^ 32)
+// marching through an even chunk of z planes with the z neighbours in
+// registers and the x/y neighbours from a double-buffered LDS plane; a block
+// handles MRG columns so coefficients are read once per group.  Results are
+// deterministic: the coarse sums are formed in a fixed order and the dot
+// products reduce through wave shuffles and per-block partial slots.
+#include <algorithm>
+
+#include "dot_internal.h"
+
+namespace dot {
+
+constexpr int MTX = 32;                 // tile width: half a wave
+constexpr int MTY = 8;                  // tile rows: two per wave
+constexpr int MNT = MTX * MTY;          // 256 threads
+constexpr int MNH = 2 * MTX + 2 * MTY;  // halo cells of a tile
+static_assert(MNT >= MNH, "every halo cell needs a thread");
+constexpr int MRG = 4;                  // columns per block
+constexpr int MG_NU_C = 8;              // Jacobi steps on the coarsest level
+#define MG_OMEGA 0.9
+
+enum MgMode { MG_DOWN = 0, MG_UP = 1 };
+
+struct MgGeom {
+  int nx, ny, nz;
+  int64_t nxy;
+  int tiles_x, ntiles, zc, nzc;  // zc even
+  int cnx, cny;                  // coarse level (down: written, up: read)
+  int64_t cnxy;
+};
+
+template <typename T>
+struct MgArgs {
+  MgGeom G;
+  int k;
+  const T* sx;
+  const T* sy;
+  const T* sz;
+  const double* sd;    // down: sqrt(diag) of this level
+  const double* sdc;   // down: sqrt(diag) of the coarse level
+  const T* q;          // up: sd / sd_coarse(parent)
+  const int* active;   // columns to process (NULL = all)
+  const T* b;          // right-hand side of this level (ld)
+  const T* xin;        // up: iterate after the down step (ld)
+  const T* xc;         // up: coarse correction (cld)
+  T* out;              // down: iterate x (ld); up: result z (ld)
+  T* bc;               // down: coarse right-hand side (cld)
+  int64_t ld, cld;
+  double* partial;     // up on level 0: [2][k][nblk] slots of b . z (else NULL)
+  int nblk;
+};
+
+static MgGeom mg_geom(const GridDims& g, const GridDims* gc, int k) {
+  MgGeom G{};
+  G.nx = g.nx;
+  G.ny = g.ny;
+  G.nz = g.nz;
+  G.nxy = g.nxy;
+  G.tiles_x = (g.nx + MTX - 1) / MTX;
+  G.ntiles = G.tiles_x * ((g.ny + MTY - 1) / MTY);
+  // z chunks: aim for about 2048 blocks, chunks of an even number of planes
+  const int groups = (k + MRG - 1) / MRG;
+  const int64_t per_z = (int64_t)G.ntiles * groups;
+  int nzc = (int)std::min<int64_t>(std::max(1, g.nz / 2), std::max<int64_t>(1, (2048 + per_z - 1) / per_z));
+  int zc = (g.nz + nzc - 1) / nzc;
+  zc += zc & 1;
+  G.zc = zc;
+  G.nzc = (g.nz + zc - 1) / zc;
+  if (gc) {
+    G.cnx = gc->nx;
+    G.cny = gc->ny;
+    G.cnxy = gc->nxy;
+  }
+  return G;
+}
+
+template <typename T>
+__device__ __forceinline__ T mg_ld(const T* p, int64_t i) {
+  return p[i];
+}
+
+template <int MODE, typename T>
+__global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T> a) {
+  const MgGeom& G = a.G;
+  const int groups = (a.k + MRG - 1) / MRG;
+  const int grp = blockIdx.x % groups;
+  const int rest = blockIdx.x / groups;
+  const int tile = rest % G.ntiles, zci = rest / G.ntiles;
+  const int slot = tile + G.ntiles * zci;
+  const int x0 = (tile % G.tiles_x) * MTX, y0 = (tile / G.tiles_x) * MTY;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tx = lane & 31, ty = 2 * wave + (lane >> 5);
+  const int x = x0 + tx, y = y0 + ty;
+  const bool in = x < G.nx && y < G.ny;
+  const int z0 = zci * G.zc, z1 = min(G.nz, z0 + G.zc);
+  const T w = (T)MG_OMEGA;
+  __shared__ T sm[2][MRG][MTY + 2][MTX + 2];
+
+  bool act[MRG];
+  int64_t col[MRG];
+  bool any = false;
+#pragma unroll
+  for (int r = 0; r < MRG; ++r) {
+    const int j = grp * MRG + r;
+    act[r] = j < a.k && (a.active == nullptr || a.active[j] != 0);
+    col[r] = j < a.k ? j : 0;
+    any |= act[r];
+  }
+  if (!any) return;  // uniform over the block
+
+  // halo cell owned by this thread (if any)
+  int hx = -1, hy = -1, hsy = 0, hsx = 0;
+  const bool hthread = threadIdx.x < MNH;
+  if (hthread) {
+    const int s = threadIdx.x;
+    if (s < MTX) {
+      hx = x0 + s; hy = y0 - 1; hsy = 0; hsx = s + 1;
+    } else if (s < 2 * MTX) {
+      hx = x0 + s - MTX; hy = y0 + MTY; hsy = MTY + 1; hsx = s - MTX + 1;
+    } else if (s < 2 * MTX + MTY) {
+      hx = x0 - 1; hy = y0 + s - 2 * MTX; hsy = s - 2 * MTX + 1; hsx = 0;
+    } else {
+      hx = x0 + MTX; hy = y0 + s - 2 * MTX - MTY; hsy = s - 2 * MTX - MTY + 1; hsx = MTX + 1;
+    }
+  }
+  const bool hin = hx >= 0 && hx < G.nx && hy >= 0 && hy < G.ny;
+  // clamped cells: every load is in bounds, values of cells outside the
+  // domain are replaced by zero where they are used
+  const int64_t hbase = hin ? hx + (int64_t)G.nx * hy : 0;
+  const int64_t base = in ? x + (int64_t)G.nx * y : 0;
+  // parents (up): coarse (x/2, y/2) of the own and the halo cell
+  const int64_t pbase = in ? (x >> 1) + (int64_t)G.cnx * (y >> 1) : 0;
+  const int64_t phbase = hin ? (hx >> 1) + (int64_t)G.cnx * (hy >> 1) : 0;
+
+  // staged value of a cell at plane z: down w b, up x + q xc(parent)
+  auto stage = [&](int r, int64_t c, int64_t p) -> T {
+    if constexpr (MODE == MG_DOWN) {
+      return w * mg_ld(a.b, c + a.ld * col[r]);
+    } else {
+      return mg_ld(a.xin, c + a.ld * col[r]) + mg_ld(a.q, c) * mg_ld(a.xc, p + a.cld * col[r]);
+    }
+  };
+
+  T vm[MRG], vc[MRG];
+#pragma unroll
+  for (int r = 0; r < MRG; ++r) {
+    const int zm = z0 > 0 ? z0 - 1 : z0;
+    const T m = stage(r, base + zm * G.nxy, pbase + (zm >> 1) * G.cnxy);
+    const T c0 = stage(r, base + z0 * G.nxy, pbase + (z0 >> 1) * G.cnxy);
+    vm[r] = (z0 > 0 && in) ? m : T(0);
+    vc[r] = in ? c0 : T(0);
+  }
+  T cD = z0 > 0 ? mg_ld(a.sz, base + (z0 - 1) * G.nxy) : T(0);
+  T zacc[MRG];
+  double acc[MRG];
+#pragma unroll
+  for (int r = 0; r < MRG; ++r) {
+    zacc[r] = T(0);
+    acc[r] = 0.0;
+  }
+
+  for (int z = z0; z < z1; ++z) {
+    const int buf = (z - z0) & 1;
+    const int64_t c = base + z * G.nxy;
+    const bool has_up = z + 1 < G.nz;
+    const int zu = has_up ? z + 1 : z;
+#pragma unroll
+    for (int r = 0; r < MRG; ++r) sm[buf][r][ty + 1][tx + 1] = vc[r];
+    if (hthread) {
+#pragma unroll
+      for (int r = 0; r < MRG; ++r) {
+        const T h = stage(r, hbase + z * G.nxy, phbase + (z >> 1) * G.cnxy);
+        sm[buf][r][hsy][hsx] = hin ? h : T(0);
+      }
+    }
+    T vp[MRG], bv[MRG];
+#pragma unroll
+    for (int r = 0; r < MRG; ++r) {
+      const T v = stage(r, base + zu * G.nxy, pbase + (zu >> 1) * G.cnxy);
+      vp[r] = (has_up && in) ? v : T(0);
+      bv[r] = mg_ld(a.b, c + a.ld * col[r]);
+    }
+    const bool has_w = in && x > 0, has_s = in && y > 0;
+    const T cE = mg_ld(a.sx, c);
+    const T cWl = mg_ld(a.sx, has_w ? c - 1 : c);
+    const T cN = mg_ld(a.sy, c);
+    const T cSl = mg_ld(a.sy, has_s ? c - G.nx : c);
+    const T cU = mg_ld(a.sz, c);
+    const T cW = has_w ? cWl : T(0);
+    const T cS = has_s ? cSl : T(0);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < MRG; ++r) {
+      if (!act[r]) continue;  // block-uniform
+      const T vW = sm[buf][r][ty + 1][tx], vE = sm[buf][r][ty + 1][tx + 2];
+      const T vS = sm[buf][r][ty][tx + 1], vN = sm[buf][r][ty + 2][tx + 1];
+      const T Av = vc[r] - cW * vW - cE * vE - cS * vS - cN * vN - cD * vm[r] - cU * vp[r];
+      if constexpr (MODE == MG_DOWN) {
+        if (in) a.out[c + a.ld * col[r]] = vc[r];
+        // restriction: S_l (b - A^ x) summed over the 2 x 2 x 2 aggregate
+        const T e = in ? (T)mg_ld(a.sd, c) * (bv[r] - Av) : T(0);
+        T s2 = e + __shfl_xor(e, 1, 64);
+        s2 += __shfl_xor(s2, 32, 64);
+        if ((z & 1) == 0) {
+          zacc[r] = s2;
+        } else {
+          zacc[r] += s2;
+          if (in && (lane & 33) == 0) {
+            const int64_t C = (x >> 1) + (int64_t)G.cnx * (y >> 1) + G.cnxy * (z >> 1);
+            a.bc[C + a.cld * col[r]] = zacc[r] / (T)mg_ld(a.sdc, C);
+          }
+        }
+      } else {
+        const T zv = vc[r] + w * (bv[r] - Av);
+        if (in) {
+          a.out[c + a.ld * col[r]] = zv;
+          acc[r] += (double)bv[r] * (double)zv;
+        }
+      }
+    }
+    cD = cU;
+#pragma unroll
+    for (int r = 0; r < MRG; ++r) {
+      vm[r] = vc[r];
+      vc[r] = vp[r];
+    }
+  }
+  if constexpr (MODE == MG_UP) {
+    if (a.partial) {
+      __shared__ double red[MNT / 64][MRG];
+#pragma unroll
+      for (int r = 0; r < MRG; ++r) {
+        double v = acc[r];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) red[wave][r] = v;
+      }
+      __syncthreads();
+      if (threadIdx.x < MRG) {
+        const int r = threadIdx.x;
+        const int j = grp * MRG + r;
+        if (j < a.k) {
+          double s = 0.0;
+          for (int q = 0; q < MNT / 64; ++q) s += red[q][r];
+          a.partial[(int64_t)j * a.nblk + slot] = s;
+          a.partial[((int64_t)a.k + j) * a.nblk + slot] = 0.0;
+        }
+      }
+    }
+  }
+}
+
+// One damped Jacobi step on the coarsest level, one thread per cell and
+// column: out = in + w (b - A^ in), or out = w b when in is NULL.
+template <typename T>
+__global__ __launch_bounds__(256) void mg_jacobi_kernel(GridDims g, int k, const T* __restrict__ sx,
+                                                        const T* __restrict__ sy,
+                                                        const T* __restrict__ sz,
+                                                        const int* __restrict__ active,
+                                                        const T* __restrict__ b,
+                                                        const T* __restrict__ xin, T* __restrict__ out,
+                                                        int64_t ld) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= g.N * k) return;
+  const int j = (int)(t / g.N);
+  const int64_t c = t - (int64_t)j * g.N;
+  if (active && active[j] == 0) return;
+  const T w = (T)MG_OMEGA;
+  const T* bj = b + ld * j;
+  T* oj = out + ld * j;
+  if (!xin) {
+    oj[c] = w * bj[c];
+    return;
+  }
+  const T* xj = xin + ld * j;
+  const int x = (int)(c % g.nx);
+  const int y = (int)((c / g.nx) % g.ny);
+  const int z = (int)(c / g.nxy);
+  T Av = xj[c] - sx[c] * (x + 1 < g.nx ? xj[c + 1] : T(0)) - sy[c] * (y + 1 < g.ny ? xj[c + g.nx] : T(0)) -
+         sz[c] * (z + 1 < g.nz ? xj[c + g.nxy] : T(0));
+  if (x > 0) Av -= sx[c - 1] * xj[c - 1];
+  if (y > 0) Av -= sy[c - g.nx] * xj[c - g.nx];
+  if (z > 0) Av -= sz[c - g.nxy] * xj[c - g.nxy];
+  oj[c] = xj[c] + w * (bj[c] - Av);
+}
+
+static size_t mg_al(size_t v) { return (v + 255) & ~(size_t)255; }
+
+size_t mg_work_bytes(const dot_op* op, int k, int64_t ld0, size_t elem) {
+  if (op->mg_nlev < 2) return 0;
+  size_t off = mg_al((size_t)ld0 * k * elem);  // level-0 iterate
+  for (int l = 1; l < op->mg_nlev; ++l) off += 3 * mg_al((size_t)op->mg[l].g.N * k * elem);
+  return off;
+}
+
+template <typename T>
+void mg_work_layout(const dot_op* op, int k, int64_t ld0, char* base, MgWork<T>* w) {
+  *w = MgWork<T>{};
+  if (op->mg_nlev < 2) return;
+  w->nlev = op->mg_nlev;
+  size_t off = 0;
+  w->x[0] = reinterpret_cast<T*>(base + off);
+  w->ld[0] = ld0;
+  off += mg_al((size_t)ld0 * k * sizeof(T));
+  for (int l = 1; l < op->mg_nlev; ++l) {
+    const size_t bytes = mg_al((size_t)op->mg[l].g.N * k * sizeof(T));
+    w->ld[l] = op->mg[l].g.N;
+    w->b[l] = reinterpret_cast<T*>(base + off);
+    off += bytes;
+    w->x[l] = reinterpret_cast<T*>(base + off);
+    off += bytes;
+    w->z[l] = reinterpret_cast<T*>(base + off);
+    off += bytes;
+  }
+}
+template void mg_work_layout<float>(const dot_op*, int, int64_t, char*, MgWork<float>*);
+template void mg_work_layout<double>(const dot_op*, int, int64_t, char*, MgWork<double>*);
+
+int mg_partial_slots(const dot_op* op, int k) {
+  if (op->mg_nlev < 2) return 0;
+  const MgGeom G = mg_geom(op->mg[0].g, &op->mg[1].g, k);
+  return G.ntiles * G.nzc;
+}
+
+template <typename T>
+struct MgCoef;
+template <>
+struct MgCoef<double> {
+  static const double* sx(const MgLevel& L) { return L.sx; }
+  static const double* sy(const MgLevel& L) { return L.sy; }
+  static const double* sz(const MgLevel& L) { return L.sz; }
+  static const double* q(const MgLevel& L) { return L.q; }
+};
+template <>
+struct MgCoef<float> {
+  static const float* sx(const MgLevel& L) { return L.sx32; }
+  static const float* sy(const MgLevel& L) { return L.sy32; }
+  static const float* sz(const MgLevel& L) { return L.sz32; }
+  static const float* q(const MgLevel& L) { return L.q32; }
+};
+
+template <typename T>
+int mg_vcycle(dot_op* op, const MgWork<T>& w, int k, const T* r0, int64_t ld0, T* z0,
+              const int* active, double* partial, hipStream_t s) {
+  const int nl = op->mg_nlev;
+  if (nl < 2 || w.nlev != nl) DOT_FAIL(DOT_EINVAL, "multigrid hierarchy not available");
+  const int groups = (k + MRG - 1) / MRG;
+  // right-hand side, iterate and result of level l
+  auto bl = [&](int l) -> const T* { return l == 0 ? r0 : w.b[l]; };
+  auto zl = [&](int l) -> T* { return l == 0 ? z0 : w.z[l]; };
+  // down the hierarchy
+  for (int l = 0; l + 1 < nl; ++l) {
+    const MgLevel& L = op->mg[l];
+    const MgLevel& Lc = op->mg[l + 1];
+    MgArgs<T> a{};
+    a.G = mg_geom(L.g, &Lc.g, k);
+    a.k = k;
+    a.sx = MgCoef<T>::sx(L);
+    a.sy = MgCoef<T>::sy(L);
+    a.sz = MgCoef<T>::sz(L);
+    a.sd = L.sd;
+    a.sdc = Lc.sd;
+    a.active = active;
+    a.b = bl(l);
+    a.out = w.x[l];
+    a.bc = w.b[l + 1];
+    a.ld = l == 0 ? ld0 : w.ld[l];
+    a.cld = w.ld[l + 1];
+    const int blocks = a.G.ntiles * a.G.nzc * groups;
+    hipLaunchKernelGGL((mg_level_kernel<MG_DOWN, T>), dim3(blocks), dim3(MNT), 0, s, a);
+    DOT_LAUNCH_CHECK();
+  }
+  // coarsest level: MG_NU_C Jacobi steps from zero, ending in z
+  {
+    const int l = nl - 1;
+    const MgLevel& L = op->mg[l];
+    const unsigned blocks = (unsigned)((L.g.N * k + 255) / 256);
+    T* bufs[2] = {w.x[l], w.z[l]};
+    // step i writes bufs[(MG_NU_C - 1 - i) & 1], so the last one lands in z
+    const T* prev = nullptr;
+    for (int i = 0; i < MG_NU_C; ++i) {
+      T* o = bufs[(MG_NU_C - 1 - i) & 1 ? 0 : 1];
+      hipLaunchKernelGGL((mg_jacobi_kernel<T>), dim3(blocks), dim3(256), 0, s, L.g, k,
+                         MgCoef<T>::sx(L), MgCoef<T>::sy(L), MgCoef<T>::sz(L), active, w.b[l], prev,
+                         o, w.ld[l]);
+      DOT_LAUNCH_CHECK();
+      prev = o;
+    }
+  }
+  // up the hierarchy
+  for (int l = nl - 2; l >= 0; --l) {
+    const MgLevel& L = op->mg[l];
+    const MgLevel& Lc = op->mg[l + 1];
+    MgArgs<T> a{};
+    a.G = mg_geom(L.g, &Lc.g, k);
+    a.k = k;
+    a.sx = MgCoef<T>::sx(L);
+    a.sy = MgCoef<T>::sy(L);
+    a.sz = MgCoef<T>::sz(L);
+    a.q = MgCoef<T>::q(L);
+    a.active = active;
+    a.b = bl(l);
+    a.xin = w.x[l];
+    a.xc = w.z[l + 1];
+    a.out = zl(l);
+    a.ld = l == 0 ? ld0 : w.ld[l];
+    a.cld = w.ld[l + 1];
+    a.partial = l == 0 ? partial : nullptr;
+    a.nblk = a.G.ntiles * a.G.nzc;
+    const int blocks = a.G.ntiles * a.G.nzc * groups;
+    hipLaunchKernelGGL((mg_level_kernel<MG_UP, T>), dim3(blocks), dim3(MNT), 0, s, a);
+    DOT_LAUNCH_CHECK();
+  }
+  return DOT_OK;
+}
+template int mg_vcycle<float>(dot_op*, const MgWork<float>&, int, const float*, int64_t, float*,
+                              const int*, double*, hipStream_t);
+template int mg_vcycle<double>(dot_op*, const MgWork<double>&, int, const double*, int64_t,
+                               double*, const int*, double*, hipStream_t);
+
+}  // namespace dot

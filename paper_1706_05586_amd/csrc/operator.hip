@@ -312,6 +312,168 @@ __global__ void scale_kernel(GridDims g, const double* __restrict__ cx, const do
 
 static unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// ------------------------------------------------------------------ multigrid setup
+// coarse D and mu: means over the 2 x 2 x 2 children
+__global__ void mg_coarsen_kernel(GridDims gf, GridDims gc, const double* __restrict__ Df,
+                                  const double* __restrict__ muf, double* __restrict__ Dc,
+                                  double* __restrict__ muc) {
+  const int64_t C = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (C >= gc.N) return;
+  const int X = (int)(C % gc.nx);
+  const int Y = (int)((C / gc.nx) % gc.ny);
+  const int Z = (int)(C / gc.nxy);
+  double sD = 0.0, sm = 0.0;
+  for (int dz = 0; dz < 2; ++dz)
+    for (int dy = 0; dy < 2; ++dy)
+      for (int dx = 0; dx < 2; ++dx) {
+        const int64_t c = (2 * X + dx) + gf.nx * ((int64_t)(2 * Y + dy) + gf.ny * (int64_t)(2 * Z + dz));
+        sD += Df[c];
+        sm += muf[c];
+      }
+  Dc[C] = 0.125 * sD;
+  muc[C] = 0.125 * sm;
+}
+
+// prolongation weight sd(c) / sd_coarse(parent(c))
+__global__ void mg_q_kernel(GridDims gf, GridDims gc, const double* __restrict__ sdf,
+                            const double* __restrict__ sdc, double* __restrict__ q,
+                            float* __restrict__ q32) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= gf.N) return;
+  const int x = (int)(c % gf.nx);
+  const int y = (int)((c / gf.nx) % gf.ny);
+  const int z = (int)(c / gf.nxy);
+  const int64_t P = (x >> 1) + gc.nx * ((int64_t)(y >> 1) + gc.ny * (int64_t)(z >> 1));
+  const double v = sdf[c] / sdc[P];
+  q[c] = v;
+  q32[c] = (float)v;
+}
+
+// flag = 1 if some diagonal entry is not positive (or not finite)
+__global__ void mg_check_kernel(int64_t N, const double* __restrict__ diag, int* __restrict__ flag) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c < N && !(diag[c] > 0.0 && diag[c] < INFINITY)) flag[0] = 1;
+}
+
+__global__ void mg_flag_clear_kernel(int* __restrict__ flag) { flag[0] = 0; }
+
+int mg_levels_for(const GridDims& g, GridDims* lv) {
+  if (g.dim != 3) return 0;
+  int n = 0;
+  GridDims cur = g;
+  lv[n++] = cur;
+  while (n < DOT_MG_MAXLEV && cur.nx % 2 == 0 && cur.ny % 2 == 0 && cur.nz % 2 == 0 &&
+         std::min(cur.nx, std::min(cur.ny, cur.nz)) >= 8) {
+    GridDims c = cur;
+    c.nx /= 2;
+    c.ny /= 2;
+    c.nz /= 2;
+    c.nxy = (int64_t)c.nx * c.ny;
+    c.N = c.nxy * c.nz;
+    c.h = 2.0 * cur.h;
+    c.hd = c.h * c.h * c.h;
+    lv[n++] = c;
+    cur = c;
+  }
+  return n;
+}
+
+void mg_free(dot_op* op) {
+  for (int l = 0; l < op->mg_nlev; ++l) {
+    MgLevel& L = op->mg[l];
+    if (l > 0) {
+      void* ptrs[] = {L.D, L.mu, L.cx, L.cy, L.cz, L.b0, L.diag, L.sd, L.sx, L.sy, L.sz,
+                      L.sx32, L.sy32, L.sz32};
+      for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    }
+    if (L.q) (void)hipFree(L.q);
+    if (L.q32) (void)hipFree(L.q32);
+    L = MgLevel{};
+  }
+  if (op->mg_flag) (void)hipFree(op->mg_flag);
+  op->mg_flag = nullptr;
+  op->mg_nlev = 0;
+  op->mg_ok = false;
+}
+
+// (Re)build the hierarchy from the operator's current diagonal.
+int mg_refresh(dot_op* op, hipStream_t s) {
+  GridDims lv[DOT_MG_MAXLEV];
+  const int n = op->D0 ? mg_levels_for(op->g, lv) : 0;
+  if (n < 2) return DOT_OK;
+  if (op->mg_nlev != n) {
+    mg_free(op);
+    MgLevel& L0 = op->mg[0];
+    L0.g = lv[0];
+    L0.D = op->D0;
+    L0.mu = op->mu0;
+    L0.cx = op->cx;
+    L0.cy = op->cy;
+    L0.cz = op->cz;
+    L0.b0 = op->b0;
+    L0.diag = op->diag;
+    L0.sd = op->sd;
+    L0.sx = op->sx;
+    L0.sy = op->sy;
+    L0.sz = op->sz;
+    L0.sx32 = op->sx32;
+    L0.sy32 = op->sy32;
+    L0.sz32 = op->sz32;
+    op->mg_nlev = n;  // from here mg_free releases whatever was allocated
+    for (int l = 1; l < n; ++l) {
+      MgLevel& L = op->mg[l];
+      L.g = lv[l];
+      const size_t n8 = (size_t)lv[l].N * sizeof(double), n4 = (size_t)lv[l].N * sizeof(float);
+      double** d64[] = {&L.D, &L.mu, &L.cx, &L.cy, &L.cz, &L.b0, &L.diag, &L.sd, &L.sx, &L.sy,
+                        &L.sz};
+      float** d32[] = {&L.sx32, &L.sy32, &L.sz32};
+      for (double** p : d64) DOT_HIP(hipMalloc(p, n8));
+      for (float** p : d32) DOT_HIP(hipMalloc(p, n4));
+    }
+    for (int l = 0; l + 1 < n; ++l) {
+      DOT_HIP(hipMalloc(&op->mg[l].q, (size_t)lv[l].N * sizeof(double)));
+      DOT_HIP(hipMalloc(&op->mg[l].q32, (size_t)lv[l].N * sizeof(float)));
+    }
+    DOT_HIP(hipMalloc(&op->mg_flag, sizeof(int)));
+  }
+  BC6 bc;
+  for (int f = 0; f < 6; ++f) bc.f[f] = op->bc[f];
+  for (int l = 1; l < n; ++l) {
+    MgLevel& F = op->mg[l - 1];
+    MgLevel& L = op->mg[l];
+    const GridDims& gc = L.g;
+    hipLaunchKernelGGL(mg_coarsen_kernel, dim3(nblk(gc.N, 256)), dim3(256), 0, s, F.g, gc, F.D,
+                       F.mu, L.D, L.mu);
+    DOT_LAUNCH_CHECK();
+    hipLaunchKernelGGL(build_coef_kernel, dim3(nblk(gc.N, 256)), dim3(256), 0, s, gc, bc, L.D,
+                       L.cx, L.cy, L.cz, L.b0);
+    DOT_LAUNCH_CHECK();
+    hipLaunchKernelGGL(diag_kernel, dim3(nblk(gc.N, 256)), dim3(256), 0, s, gc, L.cx, L.cy, L.cz,
+                       L.b0, L.mu, L.diag, L.sd);
+    DOT_LAUNCH_CHECK();
+    hipLaunchKernelGGL(scale_kernel, dim3(nblk(gc.N, 256)), dim3(256), 0, s, gc, L.cx, L.cy,
+                       L.cz, L.sd, L.sx, L.sy, L.sz, L.sx32, L.sy32, L.sz32);
+    DOT_LAUNCH_CHECK();
+    hipLaunchKernelGGL(mg_q_kernel, dim3(nblk(F.g.N, 256)), dim3(256), 0, s, F.g, gc, F.sd, L.sd,
+                       F.q, F.q32);
+    DOT_LAUNCH_CHECK();
+  }
+  // the V-cycle is a valid (positive definite) preconditioner only if every
+  // level's diagonal is positive; otherwise the solver falls back to Jacobi
+  hipLaunchKernelGGL(mg_flag_clear_kernel, dim3(1), dim3(1), 0, s, op->mg_flag);
+  DOT_LAUNCH_CHECK();
+  for (int l = 0; l < n; ++l) {
+    hipLaunchKernelGGL(mg_check_kernel, dim3(nblk(lv[l].N, 256)), dim3(256), 0, s, lv[l].N,
+                       op->mg[l].diag, op->mg_flag);
+    DOT_LAUNCH_CHECK();
+  }
+  DOT_HIP(hipMemcpyAsync(op->pinned, op->mg_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  DOT_HIP(hipStreamSynchronize(s));
+  op->mg_ok = op->pinned[0] == 0;
+  return DOT_OK;
+}
+
 static int refresh_diag(dot_op* op, const double* mua, hipStream_t s) {
   const GridDims& g = op->g;
   hipLaunchKernelGGL(diag_kernel, dim3(nblk(g.N, 256)), dim3(256), 0, s, g, op->cx, op->cy,
@@ -320,7 +482,14 @@ static int refresh_diag(dot_op* op, const double* mua, hipStream_t s) {
   hipLaunchKernelGGL(scale_kernel, dim3(nblk(g.N, 256)), dim3(256), 0, s, g, op->cx, op->cy,
                      op->cz, op->sd, op->sx, op->sy, op->sz, op->sx32, op->sy32, op->sz32);
   DOT_LAUNCH_CHECK();
-  return DOT_OK;
+  // the absorption the diagonal was formed with, for the coarse levels
+  if (mua) {
+    if (mua != op->mu0)
+      DOT_HIP(hipMemcpyAsync(op->mu0, mua, (size_t)g.N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  } else {
+    DOT_HIP(hipMemsetAsync(op->mu0, 0, (size_t)g.N * sizeof(double), s));
+  }
+  return mg_refresh(op, s);
 }
 
 // ------------------------------------------------------------------ RBF cell lists
@@ -450,7 +619,7 @@ int dot_build_operator(const dot_grid* grid, const double* D_dev, void* stream, 
   op->device = dev;
   const size_t n8 = (size_t)g.N * sizeof(double), n4 = (size_t)g.N * sizeof(float);
   double** d64[] = {&op->cx, &op->cy, &op->cz, &op->b0, &op->diag, &op->sd,
-                    &op->sx, &op->sy, &op->sz, &op->phi};
+                    &op->sx, &op->sy, &op->sz, &op->phi, &op->D0, &op->mu0};
   float** d32[] = {&op->sx32, &op->sy32, &op->sz32};
   for (double** p : d64)
     if (e == hipSuccess) e = hipMalloc(p, n8);
@@ -471,6 +640,7 @@ int dot_build_operator(const dot_grid* grid, const double* D_dev, void* stream, 
                      op->cx, op->cy, op->cz, op->b0);
   int rc = DOT_OK;
   e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(op->D0, D_dev, n8, hipMemcpyDeviceToDevice, s);
   if (e == hipSuccess) rc = refresh_diag(op, nullptr, s);
   if (e != hipSuccess || rc != DOT_OK) {
     if (e != hipSuccess) set_error("build_coef_kernel: %s", hipGetErrorString(e));
@@ -490,7 +660,8 @@ int dot_destroy_operator(dot_op* op) {
                   op->sy32,      op->sz32,       op->phi,         op->theta,     op->pair_cell,
                   op->rbf_start, op->chunk_rbf,  op->chunk_begin, op->rbf_chunk0, op->cells_dev,  op->small_dev,
                   op->pair_g,    op->pair_g32,   op->pair_band,   op->band_idx,   op->band_cells,
-                  op->band_part};
+                  op->band_part, op->D0,         op->mu0};
+  mg_free(op);
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (op->pinned) (void)hipHostFree(op->pinned);
@@ -532,9 +703,8 @@ int dot_pals_mua(dot_op* op, const dot_pals* pals, const double* theta_dev, doub
   DOT_HIP(hipMemcpyAsync(op->theta, theta_dev, (size_t)m0 * stride * sizeof(double),
                          hipMemcpyDeviceToDevice, s));
   // mu and phi, then the diagonal.  Without a caller buffer, mu is written
-  // into the diagonal array itself: diag_kernel reads mu[c] and writes
-  // diag[c] from the same thread, so the update is safe in place.
-  double* tmp_mu = mua_dev ? mua_dev : op->diag;
+  // into the handle's absorption array (kept for the multigrid levels).
+  double* tmp_mu = mua_dev ? mua_dev : op->mu0;
   rc = launch_pals(g, pals, op->theta, 0.0, tmp_mu, nullptr, op->phi, s);
   if (rc) return rc;
   rc = refresh_diag(op, tmp_mu, s);

@@ -14,6 +14,12 @@
 // alpha, beta, norms and the convergence mask live on the device; the host
 // polls the number of active columns every few iterations.
 //
+// Preconditioner: on 3D grids whose sides halve, a geometric multigrid
+// V-cycle on the scaled system (mg.hip) by default: pass 1 then forms
+// p = z + beta p_old from z = M^-1 r, the V-cycle runs after pass 2 and its
+// last kernel forms r.z, so an iteration is the two sweeps plus one V-cycle.
+// Elsewhere (and on request) the Jacobi preconditioning of the scaling alone.
+//
 // Mixed precision: binary32 CG on the scaled system with binary64 reliable
 // updates (solve_mixed below): the binary32 correction is folded into the
 // binary64 x^ and the binary32 residual is replaced by the binary64 b^ - A^ x^
@@ -80,7 +86,11 @@ enum FinMode {
   F_BETA_RU = 3,   // binary32 CG: beta, reliable-update schedule
   F_RESID = 4,     // true binary64 residual: convergence
   F_REPLACE = 5,   // residual replaced: rho, beta
-  F_TRUE = 6       // final true relres
+  F_TRUE = 6,      // final true relres
+  F_RHO_MG = 7,    // multigrid: rho = r.z, beta = rho / rho_old (0 on the first)
+  F_BETA_MG = 8,   // multigrid, binary64: relres and convergence only
+  F_RU_MG = 9,     // multigrid, binary32: reliable-update schedule only
+  F_REPLACE_MG = 10  // multigrid: residual replaced (rho and beta follow from r.z)
 };
 
 enum { FLAG_BREAKDOWN = 1, FLAG_NONFINITE = 2 };
@@ -532,7 +542,7 @@ struct FinArgs {
   const int* live;
   ColState st;
   double rtol, delta;
-  int have_s;   // F_BETA_RU: the sweep accumulated the unscaled norm |S r|^2
+  int have_s;   // F_BETA_RU / F_RU_MG: the sweep accumulated |S r|^2; F_RHO_MG: first
 };
 
 __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
@@ -658,6 +668,57 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
       st.relres[j] = bn > 0.0 ? sqrt(s0) / bn : sqrt(s0);
       break;
     }
+    case F_RHO_MG: {  // r.z of the preconditioned residual
+      if (!fin || !(s0 > 0.0)) {
+        st.flags[j] |= fin ? FLAG_BREAKDOWN : FLAG_NONFINITE;
+        st.active[j] = 0;
+        st.upd[j] = 0;
+      } else {
+        st.beta[j] = a.have_s ? 0.0 : s0 / st.rho[j];
+        st.rho[j] = s0;
+      }
+      break;
+    }
+    case F_BETA_MG: {
+      st.iters[j] += 1;
+      const double rel = sqrt(s1) / st.bnorm[j];
+      st.relres[j] = rel;
+      if (!fin) {
+        st.flags[j] |= FLAG_NONFINITE;
+        st.active[j] = 0;
+      } else if (rel <= a.rtol) {
+        st.active[j] = 0;
+      }
+      break;
+    }
+    case F_RU_MG: {
+      st.iters[j] += 1;
+      if (!fin) {
+        st.flags[j] |= FLAG_NONFINITE;
+        st.active[j] = 0;
+        break;
+      }
+      const double rn = sqrt(s0);
+      bool claims = false;
+      if (a.have_s) {
+        const double est = st.scale[j] * sqrt(s1) / st.bnorm[j];
+        st.relres[j] = est;
+        claims = est <= a.rtol;
+      }
+      st.rmax[j] = fmax(st.rmax[j], rn);
+      if (rn < a.delta * st.rmax[j] || claims) st.upd[j] = 1;
+      break;
+    }
+    case F_REPLACE_MG: {
+      if (!fin) {
+        st.flags[j] |= FLAG_NONFINITE;
+        st.active[j] = 0;
+      } else {
+        st.rmax[j] = sqrt(s0);
+      }
+      st.upd[j] = 0;
+      break;
+    }
   }
 }
 
@@ -698,13 +759,21 @@ struct Workspace {
   float* r32;
   float* p32[2];
   float* d32;
+  // multigrid (when the operator has a hierarchy): z = M^-1 r and the V-cycle
+  double* z64;
+  float* z32;
+  MgWork<double> mg64;
+  MgWork<float> mg32;
+  int mg_slots;      // partial slots per column of the V-cycle's r.z
   double* partial;
   ColState st;
   size_t bytes;
 };
 
-static size_t layout_workspace(const Geom& G, int precision, char* base, Workspace* w) {
+static size_t layout_workspace(const dot_op* op, const Geom& G, int precision, char* base,
+                               Workspace* w) {
   const size_t Nk = (size_t)G.ldw * G.k;
+  const bool mg = op->mg_nlev >= 2;
   size_t off = 0;
   auto take = [&](size_t bytes) -> char* {
     char* p = base ? base + off : nullptr;
@@ -716,14 +785,25 @@ static size_t layout_workspace(const Geom& G, int precision, char* base, Workspa
     ws.r64 = (double*)take(Nk * 8);
     ws.p64[0] = (double*)take(Nk * 8);
     ws.p64[1] = (double*)take(Nk * 8);
+    if (mg) {
+      ws.z64 = (double*)take(Nk * 8);
+      char* m = take(mg_work_bytes(op, G.k, G.ldw, 8));
+      if (base) mg_work_layout<double>(op, G.k, G.ldw, m, &ws.mg64);
+    }
   } else {
     ws.r64 = (double*)take(Nk * 8);
     ws.r32 = (float*)take(Nk * 4);
     ws.p32[0] = (float*)take(Nk * 4);
     ws.p32[1] = (float*)take(Nk * 4);
     ws.d32 = (float*)take(Nk * 4);
+    if (mg) {
+      ws.z32 = (float*)take(Nk * 4);
+      char* m = take(mg_work_bytes(op, G.k, G.ldw, 4));
+      if (base) mg_work_layout<float>(op, G.k, G.ldw, m, &ws.mg32);
+    }
   }
-  ws.partial = (double*)take((size_t)2 * G.k * G.nblk_col * 8);
+  ws.mg_slots = mg ? mg_partial_slots(op, G.k) : 0;
+  ws.partial = (double*)take((size_t)2 * G.k * std::max(G.nblk_col, ws.mg_slots) * 8);
   const size_t k = (size_t)G.k;
   ws.st.rho = (double*)take(k * 8);
   ws.st.rho_prev = (double*)take(k * 8);
@@ -825,7 +905,7 @@ static int launch_fin(int mode, const Geom& G, const Workspace& ws, const int* l
   f.have_s = have_s;
   f.mode = mode;
   f.k = G.k;
-  f.nblk = G.nblk_col;
+  f.nblk = mode == F_RHO_MG ? ws.mg_slots : G.nblk_col;
   f.partial = ws.partial;
   f.live = live;
   f.st = ws.st;
@@ -896,7 +976,7 @@ static int finish_true(dot_op* op, const Geom& G, const Workspace& ws, const dou
 }
 
 static int solve_fp64(dot_op* op, const Geom& G, const Workspace& ws, const double* rhs, double* x,
-                      const dot_solve_opts& o, hipStream_t s, int* iters_done) {
+                      const dot_solve_opts& o, bool mg, hipStream_t s, int* iters_done) {
   EltArgs e{};
   e.G = G;
   e.sd = op->sd;
@@ -907,6 +987,16 @@ static int solve_fp64(dot_op* op, const Geom& G, const Workspace& ws, const doub
   e.partial = ws.partial;
   DOT_TRY(launch_elt<E_INIT>(e, s));
   DOT_TRY(launch_fin(F_INIT, G, ws, nullptr, o.rtol, 0.0, s));
+  // z = M^-1 r and rho = r.z (the first beta is zero)
+  auto precondition = [&](int first) -> int {
+    hipEvent_t e0, e1;
+    unsigned long long* cols;
+    DOT_TRY(prof_begin(op, DOT_PROF_VCYCLE_FP64, s, &e0, &e1, &cols));
+    DOT_TRY(mg_vcycle<double>(op, ws.mg64, G.k, ws.r64, G.ldw, ws.z64, ws.st.active, ws.partial, s));
+    DOT_TRY(prof_end(op, DOT_PROF_VCYCLE_FP64, s, e0, e1));
+    return launch_fin(F_RHO_MG, G, ws, ws.st.active, o.rtol, 0.0, s, first);
+  };
+  if (mg) DOT_TRY(precondition(1));
   int n_active = 0;
   DOT_TRY(poll(op, ws, G.k, s, &n_active, nullptr));
   int it = 0;
@@ -915,7 +1005,7 @@ static int solve_fp64(dot_op* op, const Geom& G, const Workspace& ws, const doub
     SweepArgs<double> p1 = base_args64(op, G);
     p1.active = ws.st.active;
     p1.coef = ws.st.beta;
-    p1.in0 = ws.r64;
+    p1.in0 = mg ? ws.z64 : ws.r64;
     p1.in1 = ws.p64[cur];
     p1.out0 = ws.p64[cur ^ 1];
     p1.ld_in0 = p1.ld_in1 = p1.ld_out0 = G.ldw;
@@ -933,7 +1023,8 @@ static int solve_fp64(dot_op* op, const Geom& G, const Workspace& ws, const doub
     p2.norm_s = true;
     p2.partial = ws.partial;
     DOT_TRY(launch_sweep<M_PCG2, double>(op, p2, s, DOT_PROF_PCG2_FP64));
-    DOT_TRY(launch_fin(F_BETA, G, ws, ws.st.active, o.rtol, 0.0, s));
+    DOT_TRY(launch_fin(mg ? F_BETA_MG : F_BETA, G, ws, ws.st.active, o.rtol, 0.0, s));
+    if (mg) DOT_TRY(precondition(0));
     ++it;
     if (it % o.check_every == 0 || it == o.max_iter) DOT_TRY(poll(op, ws, G.k, s, &n_active, nullptr));
   }
@@ -947,9 +1038,11 @@ static int solve_fp64(dot_op* op, const Geom& G, const Workspace& ws, const doub
 // into x^ in binary64 (x^ += s d), the true residual b^ - A^ x^ is recomputed
 // in binary64 and replaces the binary32 residual.  The search direction is
 // kept, so the Krylov information is not discarded as in a restart.  Every
-// convergence decision is made on the binary64 residual.
+// convergence decision is made on the binary64 residual.  With multigrid the
+// binary32 V-cycle preconditions the binary32 residual (after a replacement,
+// the replaced one).
 static int solve_mixed(dot_op* op, const Geom& G, const Workspace& ws, const double* rhs,
-                       double* x, const dot_solve_opts& o, hipStream_t s, int* iters_done,
+                       double* x, const dot_solve_opts& o, bool mg, hipStream_t s, int* iters_done,
                        int* outer_done) {
   const double delta = o.inner_rtol;
   EltArgs e{};
@@ -969,7 +1062,16 @@ static int solve_mixed(dot_op* op, const Geom& G, const Workspace& ws, const dou
   EltArgs er = e;
   er.mask = ws.st.active;
   DOT_TRY(launch_elt<E_REPLACE>(er, s));
-  DOT_TRY(launch_fin(F_REPLACE, G, ws, ws.st.active, o.rtol, delta, s));
+  DOT_TRY(launch_fin(mg ? F_REPLACE_MG : F_REPLACE, G, ws, ws.st.active, o.rtol, delta, s));
+  auto precondition = [&](int first) -> int {
+    hipEvent_t e0, e1;
+    unsigned long long* cols;
+    DOT_TRY(prof_begin(op, DOT_PROF_VCYCLE_FP32, s, &e0, &e1, &cols));
+    DOT_TRY(mg_vcycle<float>(op, ws.mg32, G.k, ws.r32, G.ldw, ws.z32, ws.st.active, ws.partial, s));
+    DOT_TRY(prof_end(op, DOT_PROF_VCYCLE_FP32, s, e0, e1));
+    return launch_fin(F_RHO_MG, G, ws, ws.st.active, o.rtol, delta, s, first);
+  };
+  if (mg) DOT_TRY(precondition(1));
   int n_active = 0, n_upd = 0;
   DOT_TRY(poll(op, ws, G.k, s, &n_active, nullptr));
   int it = 0, updates = 0, cur = 0;
@@ -977,7 +1079,7 @@ static int solve_mixed(dot_op* op, const Geom& G, const Workspace& ws, const dou
     SweepArgs<float> p1 = base_args32(op, G);
     p1.active = ws.st.active;
     p1.coef = ws.st.beta;
-    p1.in0 = ws.r32;
+    p1.in0 = mg ? ws.z32 : ws.r32;
     p1.in1 = ws.p32[cur];
     p1.out0 = ws.p32[cur ^ 1];
     p1.ld_in0 = p1.ld_in1 = p1.ld_out0 = G.ldw;
@@ -996,28 +1098,35 @@ static int solve_mixed(dot_op* op, const Geom& G, const Workspace& ws, const dou
     const bool polled = (it + 1) % o.check_every == 0 || it + 1 == o.max_iter;
     p2.norm_s = polled;
     DOT_TRY(launch_sweep<M_PCG2, float>(op, p2, s, DOT_PROF_PCG2_FP32));
-    DOT_TRY(launch_fin(F_BETA_RU, G, ws, ws.st.active, o.rtol, delta, s, polled ? 1 : 0));
+    DOT_TRY(launch_fin(mg ? F_RU_MG : F_BETA_RU, G, ws, ws.st.active, o.rtol, delta, s,
+                       polled ? 1 : 0));
     ++it;
-    if (it % o.check_every != 0 && it != o.max_iter) continue;
-    DOT_TRY(poll(op, ws, G.k, s, &n_active, &n_upd));
-    if (n_upd == 0) continue;
-    // reliable update of the flagged columns
-    EltArgs ef = e;
-    ef.mask = ws.st.upd;
-    DOT_TRY(launch_elt<E_FOLD>(ef, s));
-    SweepArgs<double> rs = base_args64(op, G);
-    rs.active = ws.st.upd;
-    rs.in0 = x;
-    rs.b = rhs;
-    rs.out0 = ws.r64;
-    rs.ld_out0 = G.ldw;
-    rs.partial = ws.partial;
-    DOT_TRY(launch_sweep<M_RESID, double>(op, rs, s, DOT_PROF_RESID));
-    DOT_TRY(launch_fin(F_RESID, G, ws, ws.st.upd, o.rtol, delta, s));
-    DOT_TRY(launch_elt<E_REPLACE>(ef, s));
-    DOT_TRY(launch_fin(F_REPLACE, G, ws, ws.st.upd, o.rtol, delta, s));
-    ++updates;
-    DOT_TRY(poll(op, ws, G.k, s, &n_active, nullptr));
+    if (polled) {
+      DOT_TRY(poll(op, ws, G.k, s, &n_active, &n_upd));
+      if (n_upd > 0) {
+        // reliable update of the flagged columns
+        EltArgs ef = e;
+        ef.mask = ws.st.upd;
+        DOT_TRY(launch_elt<E_FOLD>(ef, s));
+        SweepArgs<double> rs = base_args64(op, G);
+        rs.active = ws.st.upd;
+        rs.in0 = x;
+        rs.b = rhs;
+        rs.out0 = ws.r64;
+        rs.ld_out0 = G.ldw;
+        rs.partial = ws.partial;
+        DOT_TRY(launch_sweep<M_RESID, double>(op, rs, s, DOT_PROF_RESID));
+        DOT_TRY(launch_fin(F_RESID, G, ws, ws.st.upd, o.rtol, delta, s));
+        DOT_TRY(launch_elt<E_REPLACE>(ef, s));
+        DOT_TRY(launch_fin(mg ? F_REPLACE_MG : F_REPLACE, G, ws, ws.st.upd, o.rtol, delta, s));
+        ++updates;
+        if (!mg) DOT_TRY(poll(op, ws, G.k, s, &n_active, nullptr));
+      }
+    }
+    if (mg) {
+      DOT_TRY(precondition(0));
+      if (polled && n_upd > 0) DOT_TRY(poll(op, ws, G.k, s, &n_active, nullptr));
+    }
   }
   // columns stopped by the iteration cap: fold their pending correction
   if (n_active > 0) {
@@ -1040,7 +1149,7 @@ size_t dot_solve_workspace_bytes(const dot_op* op, int k, int precision) {
   if (!op || k < 1 || k > DOT_MAX_COLUMNS || (precision != DOT_FP64 && precision != DOT_MIXED))
     return 0;
   Geom G = make_geom(op->g, k);
-  return layout_workspace(G, precision, nullptr, nullptr);
+  return layout_workspace(op, G, precision, nullptr, nullptr);
 }
 
 int dot_apply(dot_op* op, int k, const double* X_dev, double* Y_dev, void* stream) {
@@ -1064,6 +1173,70 @@ int dot_apply(dot_op* op, int k, const double* X_dev, double* Y_dev, void* strea
   return launch_sweep<M_APPLY, double>(op, a, as_stream(stream));
 }
 
+int dot_multigrid_levels(const dot_op* op) {
+  return (op && op->mg_nlev >= 2 && op->mg_ok) ? op->mg_nlev : 0;
+}
+
+// scaled vectors, r^ and z^, then the V-cycle's work vectors and dot slots
+static size_t mg_apply_layout(const dot_op* op, int k, char* base, double** rh, double** zh,
+                              MgWork<double>* w, double** partial) {
+  const size_t nk = (size_t)op->g.N * k * sizeof(double);
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off += align256(bytes);
+    return p;
+  };
+  char* a = take(nk);
+  char* b = take(nk);
+  char* m = take(mg_work_bytes(op, k, op->g.N, sizeof(double)));
+  char* p = take((size_t)2 * k * std::max(1, mg_partial_slots(op, k)) * sizeof(double));
+  if (base) {
+    *rh = (double*)a;
+    *zh = (double*)b;
+    mg_work_layout<double>(op, k, op->g.N, m, w);
+    *partial = (double*)p;
+  }
+  return off;
+}
+
+size_t dot_multigrid_workspace_bytes(const dot_op* op, int k) {
+  if (dot_multigrid_levels(op) == 0 || k < 1 || k > DOT_MAX_COLUMNS) return 0;
+  return mg_apply_layout(op, k, nullptr, nullptr, nullptr, nullptr, nullptr);
+}
+
+// out[c + N j] = in[c + N j] / sd[c]
+__global__ void div_sd_kernel(int64_t N, int k, const double* __restrict__ in,
+                              const double* __restrict__ sd, double* __restrict__ out) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= N * k) return;
+  out[t] = in[t] / sd[t % N];
+}
+
+int dot_multigrid_apply(dot_op* op, int k, const double* R_dev, double* Z_dev, void* work_dev,
+                        size_t work_bytes, void* stream) {
+  clear_error();
+  if (!op) DOT_FAIL(DOT_EINVAL, "op is NULL");
+  if (dot_multigrid_levels(op) == 0) DOT_FAIL(DOT_EINVAL, "no multigrid hierarchy for this operator");
+  if (k < 1 || k > DOT_MAX_COLUMNS) DOT_FAIL(DOT_EINVAL, "k must be in [1, %d]", DOT_MAX_COLUMNS);
+  if (!R_dev || !Z_dev) DOT_FAIL(DOT_EINVAL, "R_dev/Z_dev is NULL");
+  const size_t need = mg_apply_layout(op, k, nullptr, nullptr, nullptr, nullptr, nullptr);
+  if (!work_dev || work_bytes < need)
+    DOT_FAIL(DOT_ENOMEM, "workspace too small: need %zu bytes, got %zu", need, work_bytes);
+  if (((uintptr_t)work_dev & 255) != 0) DOT_FAIL(DOT_EINVAL, "work_dev must be 256-byte aligned");
+  double *rh = nullptr, *zh = nullptr, *partial = nullptr;
+  MgWork<double> w;
+  mg_apply_layout(op, k, (char*)work_dev, &rh, &zh, &w, &partial);
+  hipStream_t s = as_stream(stream);
+  const unsigned blocks = (unsigned)((op->g.N * k + 255) / 256);
+  hipLaunchKernelGGL(div_sd_kernel, dim3(blocks), dim3(256), 0, s, op->g.N, k, R_dev, op->sd, rh);
+  DOT_LAUNCH_CHECK();
+  DOT_TRY(mg_vcycle<double>(op, w, k, rh, op->g.N, zh, nullptr, partial, s));
+  hipLaunchKernelGGL(div_sd_kernel, dim3(blocks), dim3(256), 0, s, op->g.N, k, zh, op->sd, Z_dev);
+  DOT_LAUNCH_CHECK();
+  return DOT_OK;
+}
+
 int dot_solve_multi_rhs(dot_op* op, int trans, int k, const double* rhs_dev, double* x_dev,
                         const dot_solve_opts* opts, void* work_dev, size_t work_bytes,
                         dot_solve_info* info, void* stream) {
@@ -1084,8 +1257,16 @@ int dot_solve_multi_rhs(dot_op* op, int trans, int k, const double* rhs_dev, dou
   const char* ra = (const char*)rhs_dev;
   const char* xa = (const char*)x_dev;
   if (ra < xa + bytes && xa < ra + bytes) DOT_FAIL(DOT_EINVAL, "rhs_dev and x_dev overlap");
+  if (opts->precond != DOT_PRECOND_AUTO && opts->precond != DOT_PRECOND_JACOBI &&
+      opts->precond != DOT_PRECOND_MG)
+    DOT_FAIL(DOT_EINVAL, "opts.precond must be DOT_PRECOND_AUTO, _JACOBI or _MG");
+  if (opts->precond == DOT_PRECOND_MG && op->mg_nlev < 2)
+    DOT_FAIL(DOT_EINVAL, "no multigrid hierarchy for this grid (3D, sides that halve to >= 4)");
+  if (opts->precond == DOT_PRECOND_MG && !op->mg_ok)
+    DOT_FAIL(DOT_EINVAL, "multigrid hierarchy has a non-positive diagonal on some level");
+  const bool mg = op->mg_nlev >= 2 && op->mg_ok && opts->precond != DOT_PRECOND_JACOBI;
   Geom G = make_geom(op->g, k);
-  const size_t need = layout_workspace(G, opts->precision, nullptr, nullptr);
+  const size_t need = layout_workspace(op, G, opts->precision, nullptr, nullptr);
   if (!work_dev || work_bytes < need)
     DOT_FAIL(DOT_ENOMEM, "workspace too small: need %zu bytes, got %zu", need, work_bytes);
   if (((uintptr_t)work_dev & 255) != 0) DOT_FAIL(DOT_EINVAL, "work_dev must be 256-byte aligned");
@@ -1093,11 +1274,12 @@ int dot_solve_multi_rhs(dot_op* op, int trans, int k, const double* rhs_dev, dou
   if ((wa < xa + bytes && xa < wa + need) || (wa < ra + bytes && ra < wa + need))
     DOT_FAIL(DOT_EINVAL, "workspace overlaps rhs_dev or x_dev");
   Workspace ws;
-  layout_workspace(G, opts->precision, (char*)work_dev, &ws);
+  layout_workspace(op, G, opts->precision, (char*)work_dev, &ws);
   hipStream_t s = as_stream(stream);
   int iters = 0, outer = 0;
-  int rc = opts->precision == DOT_FP64 ? solve_fp64(op, G, ws, rhs_dev, x_dev, *opts, s, &iters)
-                                       : solve_mixed(op, G, ws, rhs_dev, x_dev, *opts, s, &iters, &outer);
+  int rc = opts->precision == DOT_FP64
+               ? solve_fp64(op, G, ws, rhs_dev, x_dev, *opts, mg, s, &iters)
+               : solve_mixed(op, G, ws, rhs_dev, x_dev, *opts, mg, s, &iters, &outer);
   if (rc != DOT_OK) return rc;
   // per-column results
   std::vector<int> it_col(k), flags(k);
@@ -1123,7 +1305,7 @@ int dot_solve_multi_rhs(dot_op* op, int trans, int k, const double* rhs_dev, dou
       for (int j = 0; j < k; ++j) info->relres_host[j] = rel[j];
   }
   if (fl & FLAG_NONFINITE) DOT_FAIL(DOT_ENONFINITE, "non-finite values in the solve");
-  if (fl & FLAG_BREAKDOWN) DOT_FAIL(DOT_EBREAKDOWN, "CG breakdown: p^T A p <= 0");
+  if (fl & FLAG_BREAKDOWN) DOT_FAIL(DOT_EBREAKDOWN, "CG breakdown: p^T A p <= 0 or r^T M^-1 r <= 0");
   if (!conv) {
     set_error("not converged: max relres above rtol after %d iterations", iters);
     return DOT_NOT_CONVERGED;

@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported(L):
 
 
 def test_abi_version(L):
-    assert L.lib.dot_abi_version() == 1
+    assert L.lib.dot_abi_version() == 2
 
 
 def _grid(L, dim=3, n=(8, 8, 8), bc=(0, 0, 0, 0, 1, 1)):
