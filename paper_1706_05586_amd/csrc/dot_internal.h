@@ -171,8 +171,7 @@ int mg_refresh(dot_op* op, hipStream_t s);
 void mg_free(dot_op* op);
 
 // Work vectors of one V-cycle: per level l >= 1 a right-hand side, an
-// iterate and a result (N_l columns apart); level 0 an iterate x0 in the
-// solver's layout.
+// iterate and a result (N_l columns apart).
 template <typename T>
 struct MgWork {
   int nlev = 0;
@@ -182,7 +181,7 @@ struct MgWork {
   int64_t ld[DOT_MG_MAXLEV] = {};
 };
 // bytes of MgWork<T> for k columns on op's hierarchy (0 without one);
-// carve the vectors from base (256-aligned), level-0 iterate with stride ld0
+// carve the vectors from base (256-aligned); ld0: the level-0 stride
 size_t mg_work_bytes(const dot_op* op, int k, int64_t ld0, size_t elem);
 template <typename T>
 void mg_work_layout(const dot_op* op, int k, int64_t ld0, char* base, MgWork<T>* w);

@@ -12,7 +12,8 @@
 // coarse cells (D and mu averaged over the children).  One V-cycle:
 //     down, level l:  x = w b;  b_{l+1} = R (b - A^ x)          (one kernel)
 //     coarsest:       NU_C damped Jacobi steps from zero
-//     up, level l:    y = x + P z_{l+1};  z = y + w (b - A^ y)   (one kernel)
+//     up, level l:    y = x + P z_{l+1};  z = y + w (b - A^ y)   (one kernel,
+//                     forming x = w b again rather than reading it back)
 // with w = MG_OMEGA.  Pre- and post-smoothing are the same symmetric Jacobi
 // step and R = P^T, so the preconditioner is symmetric; it is positive
 // definite because w < 2 / lambda_max(A^) for these diagonally dominant
@@ -63,9 +64,8 @@ struct MgArgs {
   const T* q;          // up: sd / sd_coarse(parent)
   const int* active;   // columns to process (NULL = all)
   const T* b;          // right-hand side of this level (ld)
-  const T* xin;        // up: iterate after the down step (ld)
   const T* xc;         // up: coarse correction (cld)
-  T* out;              // down: iterate x (ld); up: result z (ld)
+  T* out;              // up: result z (ld)
   T* bc;               // down: coarse right-hand side (cld)
   int64_t ld, cld;
   double* partial;     // up on level 0: [2][k][nblk] slots of b . z (else NULL)
@@ -154,24 +154,49 @@ __global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T> a) {
   const int64_t pbase = in ? (x >> 1) + (int64_t)G.cnx * (y >> 1) : 0;
   const int64_t phbase = hin ? (hx >> 1) + (int64_t)G.cnx * (hy >> 1) : 0;
 
-  // staged value of a cell at plane z: down w b, up x + q xc(parent)
-  auto stage = [&](int r, int64_t c, int64_t p) -> T {
+  // The pre-smoothed iterate x = w b is never stored: both kernels form it
+  // from b.  Raw loads of a cell's staged value (down: b, staged x = w b;
+  // up: b, q, xc(parent), staged y = w b + q xc) are combined only where the
+  // value is used: the own cell's next plane after the barrier, the halo
+  // cell's next plane at the following plane's LDS store, so no load is
+  // waited for before the barrier that follows it.  The own cell's raw b of
+  // plane z is carried to the residual b - A^ v of that plane.
+  struct Raw {
+    T v[MRG];
+    T xc[MRG];
+    T q;
+  };
+  auto load_raw = [&](int64_t c, int64_t p, Raw& o) {
+#pragma unroll
+    for (int r = 0; r < MRG; ++r) {
+      o.v[r] = mg_ld(a.b, c + a.ld * col[r]);
+      if constexpr (MODE == MG_UP) o.xc[r] = mg_ld(a.xc, p + a.cld * col[r]);
+    }
+    if constexpr (MODE == MG_UP) o.q = mg_ld(a.q, c);
+  };
+  auto staged = [&](const Raw& o, int r) -> T {
     if constexpr (MODE == MG_DOWN) {
-      return w * mg_ld(a.b, c + a.ld * col[r]);
+      return w * o.v[r];
     } else {
-      return mg_ld(a.xin, c + a.ld * col[r]) + mg_ld(a.q, c) * mg_ld(a.xc, p + a.cld * col[r]);
+      return w * o.v[r] + o.q * o.xc[r];
     }
   };
 
-  T vm[MRG], vc[MRG];
-#pragma unroll
-  for (int r = 0; r < MRG; ++r) {
+  T vm[MRG], vc[MRG], bcur[MRG];
+  {
+    Raw om, oc;
     const int zm = z0 > 0 ? z0 - 1 : z0;
-    const T m = stage(r, base + zm * G.nxy, pbase + (zm >> 1) * G.cnxy);
-    const T c0 = stage(r, base + z0 * G.nxy, pbase + (z0 >> 1) * G.cnxy);
-    vm[r] = (z0 > 0 && in) ? m : T(0);
-    vc[r] = in ? c0 : T(0);
+    load_raw(base + zm * G.nxy, pbase + (zm >> 1) * G.cnxy, om);
+    load_raw(base + z0 * G.nxy, pbase + (z0 >> 1) * G.cnxy, oc);
+#pragma unroll
+    for (int r = 0; r < MRG; ++r) {
+      vm[r] = (z0 > 0 && in) ? staged(om, r) : T(0);
+      vc[r] = in ? staged(oc, r) : T(0);
+      bcur[r] = oc.v[r];
+    }
   }
+  Raw hr;  // halo cell, plane z
+  load_raw(hbase + z0 * G.nxy, phbase + (z0 >> 1) * G.cnxy, hr);
   T cD = z0 > 0 ? mg_ld(a.sz, base + (z0 - 1) * G.nxy) : T(0);
   T zacc[MRG];
   double acc[MRG];
@@ -190,37 +215,36 @@ __global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T> a) {
     for (int r = 0; r < MRG; ++r) sm[buf][r][ty + 1][tx + 1] = vc[r];
     if (hthread) {
 #pragma unroll
-      for (int r = 0; r < MRG; ++r) {
-        const T h = stage(r, hbase + z * G.nxy, phbase + (z >> 1) * G.cnxy);
-        sm[buf][r][hsy][hsx] = hin ? h : T(0);
-      }
+      for (int r = 0; r < MRG; ++r) sm[buf][r][hsy][hsx] = hin ? staged(hr, r) : T(0);
     }
-    T vp[MRG], bv[MRG];
-#pragma unroll
-    for (int r = 0; r < MRG; ++r) {
-      const T v = stage(r, base + zu * G.nxy, pbase + (zu >> 1) * G.cnxy);
-      vp[r] = (has_up && in) ? v : T(0);
-      bv[r] = mg_ld(a.b, c + a.ld * col[r]);
-    }
+    // loads for after the barrier: own cell of plane z + 1, this plane's
+    // right-hand side and coefficients; then the halo of plane z + 1
+    Raw pr;
+    load_raw(base + zu * G.nxy, pbase + (zu >> 1) * G.cnxy, pr);
     const bool has_w = in && x > 0, has_s = in && y > 0;
     const T cE = mg_ld(a.sx, c);
     const T cWl = mg_ld(a.sx, has_w ? c - 1 : c);
     const T cN = mg_ld(a.sy, c);
     const T cSl = mg_ld(a.sy, has_s ? c - G.nx : c);
     const T cU = mg_ld(a.sz, c);
+    const T sdv = MODE == MG_DOWN ? (T)mg_ld(a.sd, c) : T(0);
+    load_raw(hbase + zu * G.nxy, phbase + (zu >> 1) * G.cnxy, hr);
+    __syncthreads();
     const T cW = has_w ? cWl : T(0);
     const T cS = has_s ? cSl : T(0);
-    __syncthreads();
+    T vp[MRG];
+#pragma unroll
+    for (int r = 0; r < MRG; ++r) vp[r] = (has_up && in) ? staged(pr, r) : T(0);
 #pragma unroll
     for (int r = 0; r < MRG; ++r) {
       if (!act[r]) continue;  // block-uniform
       const T vW = sm[buf][r][ty + 1][tx], vE = sm[buf][r][ty + 1][tx + 2];
       const T vS = sm[buf][r][ty][tx + 1], vN = sm[buf][r][ty + 2][tx + 1];
       const T Av = vc[r] - cW * vW - cE * vE - cS * vS - cN * vN - cD * vm[r] - cU * vp[r];
+      const T bv = bcur[r];
       if constexpr (MODE == MG_DOWN) {
-        if (in) a.out[c + a.ld * col[r]] = vc[r];
         // restriction: S_l (b - A^ x) summed over the 2 x 2 x 2 aggregate
-        const T e = in ? (T)mg_ld(a.sd, c) * (bv[r] - Av) : T(0);
+        const T e = in ? sdv * (bv - Av) : T(0);
         T s2 = e + __shfl_xor(e, 1, 64);
         s2 += __shfl_xor(s2, 32, 64);
         if ((z & 1) == 0) {
@@ -233,10 +257,10 @@ __global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T> a) {
           }
         }
       } else {
-        const T zv = vc[r] + w * (bv[r] - Av);
+        const T zv = vc[r] + w * (bv - Av);
         if (in) {
           a.out[c + a.ld * col[r]] = zv;
-          acc[r] += (double)bv[r] * (double)zv;
+          acc[r] += (double)bv * (double)zv;
         }
       }
     }
@@ -245,6 +269,7 @@ __global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T> a) {
     for (int r = 0; r < MRG; ++r) {
       vm[r] = vc[r];
       vc[r] = vp[r];
+      bcur[r] = pr.v[r];
     }
   }
   if constexpr (MODE == MG_UP) {
@@ -309,8 +334,9 @@ __global__ __launch_bounds__(256) void mg_jacobi_kernel(GridDims g, int k, const
 static size_t mg_al(size_t v) { return (v + 255) & ~(size_t)255; }
 
 size_t mg_work_bytes(const dot_op* op, int k, int64_t ld0, size_t elem) {
+  (void)ld0;
   if (op->mg_nlev < 2) return 0;
-  size_t off = mg_al((size_t)ld0 * k * elem);  // level-0 iterate
+  size_t off = 0;
   for (int l = 1; l < op->mg_nlev; ++l) off += 3 * mg_al((size_t)op->mg[l].g.N * k * elem);
   return off;
 }
@@ -320,10 +346,8 @@ void mg_work_layout(const dot_op* op, int k, int64_t ld0, char* base, MgWork<T>*
   *w = MgWork<T>{};
   if (op->mg_nlev < 2) return;
   w->nlev = op->mg_nlev;
-  size_t off = 0;
-  w->x[0] = reinterpret_cast<T*>(base + off);
   w->ld[0] = ld0;
-  off += mg_al((size_t)ld0 * k * sizeof(T));
+  size_t off = 0;
   for (int l = 1; l < op->mg_nlev; ++l) {
     const size_t bytes = mg_al((size_t)op->mg[l].g.N * k * sizeof(T));
     w->ld[l] = op->mg[l].g.N;
@@ -384,7 +408,6 @@ int mg_vcycle(dot_op* op, const MgWork<T>& w, int k, const T* r0, int64_t ld0, T
     a.sdc = Lc.sd;
     a.active = active;
     a.b = bl(l);
-    a.out = w.x[l];
     a.bc = w.b[l + 1];
     a.ld = l == 0 ? ld0 : w.ld[l];
     a.cld = w.ld[l + 1];
@@ -422,7 +445,6 @@ int mg_vcycle(dot_op* op, const MgWork<T>& w, int k, const T* r0, int64_t ld0, T
     a.q = MgCoef<T>::q(L);
     a.active = active;
     a.b = bl(l);
-    a.xin = w.x[l];
     a.xc = w.z[l + 1];
     a.out = zl(l);
     a.ld = l == 0 ? ld0 : w.ld[l];
