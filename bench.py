@@ -52,7 +52,7 @@ PASS_BYTES = {
 # runs summarized in profiles/sweep_pcg_fp32_128cube_40rhs_hbm_traffic.md; valid
 # while the sweep kernel sources hash to the value recorded with them.
 TRAFFIC = {
-    "sources": ("paper_1706_05586_amd/csrc/solve.hip", "paper_1706_05586_amd/csrc/dot_internal.h"),
+    "sources": ("paper_1706_05586_amd/csrc/solve.hip",),
     "sha256": "ea8961cdeb2013e7841f5cf185a773853487ddc9c61e7b7fe0dde9e7bac6925d",
     "config": "C3",
     "pcg2_fp32_bytes_per_launch": 1.6773e9,
@@ -85,6 +85,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-leg", action="store_true")
     ap.add_argument("--no-jacobian-leg", action="store_true")
+    ap.add_argument("--no-jacobi-leg", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=120)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB between two device buffers 5 times (reference "
@@ -251,17 +252,19 @@ def main():
     # ------------------------------------------- Jacobi-preconditioned leg
     # the same mixed solve with the Jacobi scaling alone (the preconditioner
     # the oracle's CG uses), for the multigrid comparison and the CPU baseline
-    step(th_ref, precision=L.DOT_MIXED, full_path=False, precond=L.DOT_PRECOND_JACOBI)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    step(th_ref, precision=L.DOT_MIXED, full_path=False, precond=L.DOT_PRECOND_JACOBI)
-    torch.cuda.synchronize()
-    ejac = time.perf_counter() - t1
-    rj = state["res"]
-    jacobi = {"ms_per_solve": round(ejac * 1e3, 2), "rhs_per_s": round(k / ejac, 3),
-              "iters": int(rj.iters_max), "updates": int(rj.outer),
-              "relres_max": float(rj.relres.max())}
-    log(f"[bench] Jacobi-preconditioned mixed solve: {ejac * 1e3:.1f} ms, iters={rj.iters_max}")
+    jacobi, rj = None, None
+    if not args.no_jacobi_leg:
+        step(th_ref, precision=L.DOT_MIXED, full_path=False, precond=L.DOT_PRECOND_JACOBI)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        step(th_ref, precision=L.DOT_MIXED, full_path=False, precond=L.DOT_PRECOND_JACOBI)
+        torch.cuda.synchronize()
+        ejac = time.perf_counter() - t1
+        rj = state["res"]
+        jacobi = {"ms_per_solve": round(ejac * 1e3, 2), "rhs_per_s": round(k / ejac, 3),
+                  "iters": int(rj.iters_max), "updates": int(rj.outer),
+                  "relres_max": float(rj.relres.max())}
+        log(f"[bench] Jacobi-preconditioned mixed solve: {ejac * 1e3:.1f} ms, iters={rj.iters_max}")
 
     # ---------------------------------------------------------- FP64 leg
     fp64 = None
@@ -298,7 +301,7 @@ def main():
     # ---------------------------------------------------------- CPU baseline
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(wl, args.cpu_iters, rj)
+        cpu = cpu_baseline(wl, args.cpu_iters, rj if rj is not None else res)
         log(f"[bench] cpu baseline: {cpu}")
 
     traffic = measured_traffic(cfg.name)
@@ -346,7 +349,8 @@ def main():
                   "preconditioner": f"multigrid V-cycle, {op.multigrid_levels} levels",
                   "vcycle_avg_us": round(msv / max(nv, 1) * 1e3, 1), "vcycles": nv},
         "jacobi_mixed": jacobi,
-        "speedup_multigrid_vs_jacobi_solve": round(jacobi["ms_per_solve"] / solve_ms, 3),
+        "speedup_multigrid_vs_jacobi_solve": (round(jacobi["ms_per_solve"] / solve_ms, 3)
+                                              if jacobi else None),
         "fp64": fp64,
         "speedup_mixed_vs_fp64_solve": (round(fp64["ms_per_solve"] / solve_ms, 3)
                                         if fp64 else None),
