@@ -16,11 +16,12 @@ with this plain implementation.  The reading, written out:
     copied to its 8 children), in scaled variables
         prolongation  x^_l += S_l P S_{l+1}^-1 x^_{l+1}
         restriction   b^_{l+1} = S_{l+1}^-1 P^T S_l r^_l
-  * one cycle on level l with right-hand side b:
-        x = w b;  b_{l+1} = restriction of (b - A^ x);  x_{l+1} = cycle(b_{l+1});
-        y = x + prolongation of x_{l+1};  result y + w (b - A^ y)
-    and on the coarsest level NU_C steps x <- x + w (b - A^ x) from x = 0,
-    with w = OMEGA;
+  * one cycle on level l with right-hand side b, J(v) = v + w (b - A^ v)
+    the damped Jacobi step and nu = NU0 on level 0, NU1 below:
+        x = J applied nu - 1 times to w b;
+        b_{l+1} = restriction of (b - A^ x);  x_{l+1} = cycle(b_{l+1});
+        result: J applied nu times to x + prolongation of x_{l+1}
+    and on the coarsest level NU_C steps J from x = 0, with w = OMEGA;
   * as an approximate inverse of A: M R = S_0^-1 V(S_0^-1 R).
 
 Pinned (tests/test_oracle_multigrid.py) by properties a mistake in a
@@ -38,6 +39,8 @@ import scipy.sparse as sp
 from . import discretization as disc
 
 OMEGA = 0.9
+NU0 = 2
+NU1 = 3
 NU_C = 8
 
 
@@ -96,11 +99,16 @@ def vcycle_scaled(levels: list, b: np.ndarray, level: int = 0) -> np.ndarray:
             x = x + OMEGA * (b - Ah @ x)
         return x
     C = levels[level + 1]
+    nu = NU0 if level == 0 else NU1
     x = OMEGA * b
+    for _ in range(nu - 1):
+        x = x + OMEGA * (b - Ah @ x)
     bc = _sum_children(L["sd"] * (b - Ah @ x), L["n"]) / C["sd"]
     xc = vcycle_scaled(levels, bc, level + 1)
     y = x + L["sd"] * _copy_to_children(xc / C["sd"], L["n"])
-    return y + OMEGA * (b - Ah @ y)
+    for _ in range(nu):
+        y = y + OMEGA * (b - Ah @ y)
+    return y
 
 
 def apply(levels: list, R: np.ndarray) -> np.ndarray:

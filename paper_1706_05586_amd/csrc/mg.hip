@@ -9,16 +9,19 @@
 //     prolongation  x^_l += S_l P S_{l+1}^-1 x^_{l+1}   (weight q = sd / sd_parent)
 //     restriction   b^_{l+1} = S_{l+1}^-1 P^T S_l r^_l   (its transpose)
 // and the coarse operator is the same finite-volume discretization on the
-// coarse cells (D and mu averaged over the children).  One V-cycle:
-//     down, level l:  x = w b;  b_{l+1} = R (b - A^ x)          (one kernel)
-//     coarsest:       NU_C damped Jacobi steps from zero
-//     up, level l:    y = x + P z_{l+1};  z = y + w (b - A^ y)   (one kernel,
-//                     forming x = w b again rather than reading it back)
-// with w = MG_OMEGA.  Pre- and post-smoothing are the same symmetric Jacobi
-// step and R = P^T, so the preconditioner is symmetric; it is positive
-// definite because w < 2 / lambda_max(A^) for these diagonally dominant
-// operators (lambda_max <= 2) and every coarse correction is positive
-// semidefinite.  The up kernel of level 0 also forms r . z per column.
+// coarse cells (D and mu averaged over the children).  One V-cycle, with
+// nu_l damped Jacobi steps J(v) = v + w (b - A^ v) each way on level l:
+//     down, level l:  x = J^(nu_l - 1)(w b);  b_{l+1} = R (b - A^ x)
+//     coarsest:       NU_C Jacobi steps from zero
+//     up, level l:    z = J^nu_l(x + P z_{l+1})
+// with w = MG_OMEGA.  Every kernel does one step or the restriction, forming
+// w b from b rather than storing it.  Pre- and post-smoothing are the same
+// symmetric Jacobi step, equally many, and R = P^T, so the preconditioner is
+// symmetric; it is positive definite because w < 2 / lambda_max(A^) for
+// these diagonally dominant operators (lambda_max <= 2) and every coarse
+// correction is positive semidefinite.  The coarse levels, where steps cost
+// little, take more of them.  The last step on level 0 also forms r . z per
+// column.
 //
 // Kernel layout: a block is a 32 x 8 (x, y) tile (each wave two rows of 32,
 // so the 2 x 2 aggregates of a plane are pairs of lanes l, l ^ 1 and l, l ^ 32)
@@ -40,9 +43,16 @@ constexpr int MNH = 2 * MTX + 2 * MTY;  // halo cells of a tile
 static_assert(MNT >= MNH, "every halo cell needs a thread");
 constexpr int MRG = 4;                  // columns per block
 constexpr int MG_NU_C = 8;              // Jacobi steps on the coarsest level
+
+constexpr int MG_NU0 = 2;               // smoothing steps each way on the finest level
+constexpr int MG_NU1 = 3;               // ... and on the coarser levels above the coarsest
 #define MG_OMEGA 0.9
 
-enum MgMode { MG_DOWN = 0, MG_UP = 1 };
+static inline int mg_nu(int level) { return level == 0 ? MG_NU0 : MG_NU1; }
+
+// MG_DOWN: restriction of the residual of the staged iterate;
+// MG_SMOOTH: one damped Jacobi step from the staged iterate
+enum MgMode { MG_DOWN = 0, MG_SMOOTH = 1 };
 
 struct MgGeom {
   int nx, ny, nz;
@@ -61,14 +71,15 @@ struct MgArgs {
   const T* sz;
   const double* sd;    // down: sqrt(diag) of this level
   const double* sdc;   // down: sqrt(diag) of the coarse level
-  const T* q;          // up: sd / sd_coarse(parent)
+  const T* q;          // prolongation: sd / sd_coarse(parent)
   const int* active;   // columns to process (NULL = all)
   const T* b;          // right-hand side of this level (ld)
-  const T* xc;         // up: coarse correction (cld)
-  T* out;              // up: result z (ld)
+  const T* x;          // staged iterate (ld; the kernels without it form w b)
+  const T* xc;         // coarse correction added to it (cld)
+  T* out;              // smoothing: result (ld)
   T* bc;               // down: coarse right-hand side (cld)
   int64_t ld, cld;
-  double* partial;     // up on level 0: [2][k][nblk] slots of b . z (else NULL)
+  double* partial;     // smoothing: [2][k][nblk] slots of b . out (or NULL)
   int nblk;
 };
 
@@ -101,7 +112,10 @@ __device__ __forceinline__ T mg_ld(const T* p, int64_t i) {
   return p[i];
 }
 
-template <int MODE, typename T>
+// The staged iterate v of a level kernel is x (HX) or w b, plus q xc(parent)
+// with the prolongation (HC).  MG_DOWN writes the restriction of b - A^ v,
+// MG_SMOOTH writes v + w (b - A^ v).
+template <int MODE, bool HX, bool HC, typename T>
 __global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T> a) {
   const MgGeom& G = a.G;
   const int groups = (a.k + MRG - 1) / MRG;
@@ -154,15 +168,15 @@ __global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T> a) {
   const int64_t pbase = in ? (x >> 1) + (int64_t)G.cnx * (y >> 1) : 0;
   const int64_t phbase = hin ? (hx >> 1) + (int64_t)G.cnx * (hy >> 1) : 0;
 
-  // The pre-smoothed iterate x = w b is never stored: both kernels form it
-  // from b.  Raw loads of a cell's staged value (down: b, staged x = w b;
-  // up: b, q, xc(parent), staged y = w b + q xc) are combined only where the
-  // value is used: the own cell's next plane after the barrier, the halo
-  // cell's next plane at the following plane's LDS store, so no load is
-  // waited for before the barrier that follows it.  The own cell's raw b of
-  // plane z is carried to the residual b - A^ v of that plane.
+  // Raw loads of a cell's staged value (b, and x, q and xc(parent) where the
+  // kernel has them) are combined only where the value is used: the own
+  // cell's next plane after the barrier, the halo cell's next plane at the
+  // following plane's LDS store, so no load is waited for before the barrier
+  // that follows it.  The own cell's raw b of plane z is carried to the
+  // residual b - A^ v of that plane.
   struct Raw {
     T v[MRG];
+    T x[MRG];
     T xc[MRG];
     T q;
   };
@@ -170,16 +184,20 @@ __global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T> a) {
 #pragma unroll
     for (int r = 0; r < MRG; ++r) {
       o.v[r] = mg_ld(a.b, c + a.ld * col[r]);
-      if constexpr (MODE == MG_UP) o.xc[r] = mg_ld(a.xc, p + a.cld * col[r]);
+      if constexpr (HX) o.x[r] = mg_ld(a.x, c + a.ld * col[r]);
+      if constexpr (HC) o.xc[r] = mg_ld(a.xc, p + a.cld * col[r]);
     }
-    if constexpr (MODE == MG_UP) o.q = mg_ld(a.q, c);
+    if constexpr (HC) o.q = mg_ld(a.q, c);
   };
   auto staged = [&](const Raw& o, int r) -> T {
-    if constexpr (MODE == MG_DOWN) {
-      return w * o.v[r];
+    T v;
+    if constexpr (HX) {
+      v = o.x[r];
     } else {
-      return w * o.v[r] + o.q * o.xc[r];
+      v = w * o.v[r];
     }
+    if constexpr (HC) v += o.q * o.xc[r];
+    return v;
   };
 
   T vm[MRG], vc[MRG], bcur[MRG];
@@ -272,7 +290,7 @@ __global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T> a) {
       bcur[r] = pr.v[r];
     }
   }
-  if constexpr (MODE == MG_UP) {
+  if constexpr (MODE == MG_SMOOTH) {
     if (a.partial) {
       __shared__ double red[MNT / 64][MRG];
 #pragma unroll
@@ -333,11 +351,15 @@ __global__ __launch_bounds__(256) void mg_jacobi_kernel(GridDims g, int k, const
 
 static size_t mg_al(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// Column stride of a coarse level's vectors: a larger level's columns are
+// padded so that the columns of a block's group do not sit a power of two
+// apart.
+static int64_t mg_ld_of(int64_t N) { return N >= 8192 ? N + 1088 : N; }
+
 size_t mg_work_bytes(const dot_op* op, int k, int64_t ld0, size_t elem) {
-  (void)ld0;
   if (op->mg_nlev < 2) return 0;
-  size_t off = 0;
-  for (int l = 1; l < op->mg_nlev; ++l) off += 3 * mg_al((size_t)op->mg[l].g.N * k * elem);
+  size_t off = MG_NU0 >= 2 ? mg_al((size_t)ld0 * k * elem) : 0;
+  for (int l = 1; l < op->mg_nlev; ++l) off += 3 * mg_al((size_t)mg_ld_of(op->mg[l].g.N) * k * elem);
   return off;
 }
 
@@ -348,9 +370,13 @@ void mg_work_layout(const dot_op* op, int k, int64_t ld0, char* base, MgWork<T>*
   w->nlev = op->mg_nlev;
   w->ld[0] = ld0;
   size_t off = 0;
+  if (MG_NU0 >= 2) {
+    w->x[0] = reinterpret_cast<T*>(base);
+    off += mg_al((size_t)ld0 * k * sizeof(T));
+  }
   for (int l = 1; l < op->mg_nlev; ++l) {
-    const size_t bytes = mg_al((size_t)op->mg[l].g.N * k * sizeof(T));
-    w->ld[l] = op->mg[l].g.N;
+    w->ld[l] = mg_ld_of(op->mg[l].g.N);
+    const size_t bytes = mg_al((size_t)w->ld[l] * k * sizeof(T));
     w->b[l] = reinterpret_cast<T*>(base + off);
     off += bytes;
     w->x[l] = reinterpret_cast<T*>(base + off);
@@ -385,34 +411,73 @@ struct MgCoef<float> {
   static const float* q(const MgLevel& L) { return L.q32; }
 };
 
+template <int MODE, bool HX, bool HC, typename T>
+static void mg_launch(const MgArgs<T>& a, int groups, hipStream_t s) {
+  const int blocks = a.G.ntiles * a.G.nzc * groups;
+  hipLaunchKernelGGL((mg_level_kernel<MODE, HX, HC, T>), dim3(blocks), dim3(MNT), 0, s, a);
+}
+
 template <typename T>
 int mg_vcycle(dot_op* op, const MgWork<T>& w, int k, const T* r0, int64_t ld0, T* z0,
               const int* active, double* partial, hipStream_t s) {
   const int nl = op->mg_nlev;
   if (nl < 2 || w.nlev != nl) DOT_FAIL(DOT_EINVAL, "multigrid hierarchy not available");
+  if (MG_NU0 >= 2 && !w.x[0]) DOT_FAIL(DOT_EINVAL, "multigrid work vectors missing");
   const int groups = (k + MRG - 1) / MRG;
-  // right-hand side, iterate and result of level l
+  // right-hand side of level l; its smoothing results alternate between
+  // res(l) and alt(l), the first and the last (an odd count, 2 nu - 1) in
+  // res(l), where the level above reads the correction
   auto bl = [&](int l) -> const T* { return l == 0 ? r0 : w.b[l]; };
-  auto zl = [&](int l) -> T* { return l == 0 ? z0 : w.z[l]; };
-  // down the hierarchy
-  for (int l = 0; l + 1 < nl; ++l) {
+  auto res = [&](int l) -> T* { return l == 0 ? z0 : w.z[l]; };
+  auto alt = [&](int l) -> T* { return w.x[l]; };
+  auto args = [&](int l) {
     const MgLevel& L = op->mg[l];
-    const MgLevel& Lc = op->mg[l + 1];
     MgArgs<T> a{};
-    a.G = mg_geom(L.g, &Lc.g, k);
+    a.G = mg_geom(L.g, l + 1 < nl ? &op->mg[l + 1].g : nullptr, k);
     a.k = k;
     a.sx = MgCoef<T>::sx(L);
     a.sy = MgCoef<T>::sy(L);
     a.sz = MgCoef<T>::sz(L);
-    a.sd = L.sd;
-    a.sdc = Lc.sd;
     a.active = active;
     a.b = bl(l);
-    a.bc = w.b[l + 1];
     a.ld = l == 0 ? ld0 : w.ld[l];
-    a.cld = w.ld[l + 1];
-    const int blocks = a.G.ntiles * a.G.nzc * groups;
-    hipLaunchKernelGGL((mg_level_kernel<MG_DOWN, T>), dim3(blocks), dim3(MNT), 0, s, a);
+    if (l + 1 < nl) a.cld = w.ld[l + 1];
+    return a;
+  };
+  // one smoothing step on level l from x (NULL: w b) plus, with xc, the
+  // prolongation of xc; returns the buffer written
+  int outputs[DOT_MG_MAXLEV] = {};
+  auto smooth = [&](int l, const T* x, const T* xc, double* part) -> T* {
+    MgArgs<T> a = args(l);
+    T* o = (outputs[l]++ & 1) ? alt(l) : res(l);
+    a.x = x;
+    a.xc = xc;
+    a.q = MgCoef<T>::q(op->mg[l]);
+    a.out = o;
+    a.partial = part;
+    a.nblk = a.G.ntiles * a.G.nzc;
+    if (x && xc) mg_launch<MG_SMOOTH, true, true>(a, groups, s);
+    else if (x) mg_launch<MG_SMOOTH, true, false>(a, groups, s);
+    else if (xc) mg_launch<MG_SMOOTH, false, true>(a, groups, s);
+    else mg_launch<MG_SMOOTH, false, false>(a, groups, s);
+    return o;
+  };
+  // down the hierarchy: nu - 1 steps after x = w b, then the restriction
+  const T* pre[DOT_MG_MAXLEV] = {};
+  for (int l = 0; l + 1 < nl; ++l) {
+    const T* x = nullptr;
+    for (int i = 1; i < mg_nu(l); ++i) {
+      x = smooth(l, x, nullptr, nullptr);
+      DOT_LAUNCH_CHECK();
+    }
+    pre[l] = x;
+    MgArgs<T> a = args(l);
+    a.sd = op->mg[l].sd;
+    a.sdc = op->mg[l + 1].sd;
+    a.x = x;
+    a.bc = w.b[l + 1];
+    if (x) mg_launch<MG_DOWN, true, false>(a, groups, s);
+    else mg_launch<MG_DOWN, false, false>(a, groups, s);
     DOT_LAUNCH_CHECK();
   }
   // coarsest level: MG_NU_C Jacobi steps from zero, ending in z
@@ -432,28 +497,15 @@ int mg_vcycle(dot_op* op, const MgWork<T>& w, int k, const T* r0, int64_t ld0, T
       prev = o;
     }
   }
-  // up the hierarchy
+  // up the hierarchy: the prolongation with the first of nu steps; on level
+  // 0 the last step also forms r0 . z0
   for (int l = nl - 2; l >= 0; --l) {
-    const MgLevel& L = op->mg[l];
-    const MgLevel& Lc = op->mg[l + 1];
-    MgArgs<T> a{};
-    a.G = mg_geom(L.g, &Lc.g, k);
-    a.k = k;
-    a.sx = MgCoef<T>::sx(L);
-    a.sy = MgCoef<T>::sy(L);
-    a.sz = MgCoef<T>::sz(L);
-    a.q = MgCoef<T>::q(L);
-    a.active = active;
-    a.b = bl(l);
-    a.xc = w.z[l + 1];
-    a.out = zl(l);
-    a.ld = l == 0 ? ld0 : w.ld[l];
-    a.cld = w.ld[l + 1];
-    a.partial = l == 0 ? partial : nullptr;
-    a.nblk = a.G.ntiles * a.G.nzc;
-    const int blocks = a.G.ntiles * a.G.nzc * groups;
-    hipLaunchKernelGGL((mg_level_kernel<MG_UP, T>), dim3(blocks), dim3(MNT), 0, s, a);
-    DOT_LAUNCH_CHECK();
+    const T* x = pre[l];
+    const int nu = mg_nu(l);
+    for (int i = 0; i < nu; ++i) {
+      x = smooth(l, x, i == 0 ? w.z[l + 1] : nullptr, (l == 0 && i == nu - 1) ? partial : nullptr);
+      DOT_LAUNCH_CHECK();
+    }
   }
   return DOT_OK;
 }

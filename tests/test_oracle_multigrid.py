@@ -64,7 +64,7 @@ def test_preconditioned_operator_well_conditioned(small):
     evj = np.linalg.eigvalsh(A / np.outer(d, d))
     kappa_mg, kappa_j = ev.max() / ev.min(), evj.max() / evj.min()
     # the coarse correction removes the smooth modes Jacobi leaves behind
-    assert kappa_mg < 0.25 * kappa_j, (kappa_mg, kappa_j)
+    assert kappa_mg < 0.1 * kappa_j, (kappa_mg, kappa_j)
     # symmetric smoothing with w < 1 on an operator with lambda_max(D^-1 A) <= 2:
     # M A has no eigenvalue beyond 2
     assert ev.max() < 2.0
@@ -106,4 +106,4 @@ def test_pcg_iterations_far_below_jacobi():
     xm, itm = pcg(A, b, lambda r: omg.apply(lv, r), 1e-10)
     assert np.linalg.norm(b - A @ xm) <= 1e-10 * np.linalg.norm(b)
     assert np.linalg.norm(xm - xj) <= 1e-8 * np.linalg.norm(xj)
-    assert itm * 4 <= itj, (itm, itj)
+    assert itm * 8 <= itj, (itm, itj)
