@@ -195,4 +195,14 @@ int mg_vcycle(dot_op* op, const MgWork<T>& w, int k, const T* r0, int64_t ld0, T
 
 constexpr int kWave = 64;
 
+// The hardware deals a grid's blocks to the 8 XCDs in turn (block b runs on
+// XCD b mod 8).  Maps block b to a logical block so that each XCD runs one
+// contiguous range of the logical order and neighbours in that order share
+// the XCD's L2.
+__device__ __forceinline__ int xcd_remap_block(int b, int total) {
+  const int per = total >> 3, rem = total & 7;
+  const int xcd = b & 7, idx = b >> 3;
+  return xcd * per + min(xcd, rem) + idx;
+}
+
 }  // namespace dot

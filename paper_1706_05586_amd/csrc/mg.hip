@@ -119,8 +119,11 @@ template <int MODE, bool HX, bool HC, typename T>
 __global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T> a) {
   const MgGeom& G = a.G;
   const int groups = (a.k + MRG - 1) / MRG;
-  const int grp = blockIdx.x % groups;
-  const int rest = blockIdx.x / groups;
+  // column groups fastest, then tiles: the blocks of one tile and its x
+  // neighbours run on one XCD and share coefficient and halo lines in its L2
+  const int logical = xcd_remap_block((int)blockIdx.x, (int)gridDim.x);
+  const int grp = logical % groups;
+  const int rest = logical / groups;
   const int tile = rest % G.ntiles, zci = rest / G.ntiles;
   const int slot = tile + G.ntiles * zci;
   const int x0 = (tile % G.tiles_x) * MTX, y0 = (tile / G.tiles_x) * MTY;

@@ -148,12 +148,6 @@ struct SweepArgs {
   unsigned long long* prof_cols;  // optional: sum of active columns over launches
 };
 
-__device__ __forceinline__ int remap_block(int L, int total) {
-  const int per = total >> 3, rem = total & 7;
-  const int xcd = L & 7, idx = L >> 3;
-  return xcd * per + min(xcd, rem) + idx;
-}
-
 // Logical block -> (tile, z chunk, column group).  The column group varies
 // fastest: the blocks of all groups of one tile and z chunk are neighbours in
 // the logical order, so they run together on one XCD and share that tile's
@@ -234,7 +228,7 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs<T> a) {
   // per plane suffices
   __shared__ T sm[2][RG][TY + 2][TX + 2];
   const Geom& G = a.G;
-  const int logical = remap_block((int)blockIdx.x, (int)gridDim.x);
+  const int logical = xcd_remap_block((int)blockIdx.x, (int)gridDim.x);
   int tile, zci, grp;
   block_coords(logical, G, ngroups, &tile, &zci, &grp);
   const int slot = tile + G.ntiles * zci;
@@ -471,7 +465,7 @@ template <int MODE>
 __global__ __launch_bounds__(NT) void elt_kernel(EltArgs a) {
   const Geom& G = a.G;
   const int ngroups = (G.k + RG - 1) / RG;
-  const int logical = remap_block((int)blockIdx.x, (int)gridDim.x);
+  const int logical = xcd_remap_block((int)blockIdx.x, (int)gridDim.x);
   int tile, zci, grp;
   block_coords(logical, G, ngroups, &tile, &zci, &grp);
   const int slot = tile + G.ntiles * zci;
