@@ -144,6 +144,7 @@ struct dot_op {
   void* prof = nullptr;           // kernel timing state (solve.hip)
   int32_t* pinned = nullptr;      // pinned host mailbox (counters/flags)
   double* pinned_d = nullptr;     // pinned host doubles (misfit, small results)
+  hipEvent_t poll_ev[2] = {};     // the solver's pending flag snapshots
   // multigrid hierarchy (levels 0 .. mg_nlev - 1; mg_nlev < 2: not available)
   double* D0 = nullptr;           // copy of the frozen diffusion field
   double* mu0 = nullptr;          // absorption of the current diagonal
@@ -160,7 +161,7 @@ void destroy_profile(dot_op* op);
 int profile_begin(dot_op* op, int kind, hipStream_t s, hipEvent_t* e0, hipEvent_t* e1,
                   unsigned long long** cols);
 int profile_end(dot_op* op, int kind, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
-constexpr int kPinnedInts = 2 * DOT_MAX_COLUMNS + 64;
+constexpr int kPinnedInts = 4 * DOT_MAX_COLUMNS + 64;
 int ensure_cells_dev(dot_op* op, int n, const int32_t* cells_host, hipStream_t s);
 // after the pair lists of dot_pals_mua: per-pair d mu / d p and band rows
 int jac_prepare(dot_op* op, hipStream_t s);

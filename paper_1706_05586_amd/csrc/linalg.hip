@@ -678,7 +678,11 @@ static int symeig(int n, const double* A, int lda, double* w, double* V, int ldv
     // E of that size moves the eigenvalues by about ||E||_2 ~ 2 sqrt(n) eps
     // ||A||_F, within the n eps ||A|| backward error of the tile updates.
     if (sweep == 0) floor = BJ_TOL * sqrt(tots);
-    if (!(offs > 1e-30 * tots) || offs == 0.0 || hflag == 0 || sweep >= max_sweeps) break;
+    // stop once off(A) <= n eps ||A||_F: the eigenvalues are then within
+    // ||off(A)||_2 <= n eps ||A||_F of the diagonal, the size of the
+    // backward error of the rotations themselves
+    const double stop = (double)n * BJ_TOL;
+    if (!(offs > stop * stop * tots) || offs == 0.0 || hflag == 0 || sweep >= max_sweeps) break;
     // Reorder the first n indices by decreasing diagonal before each sweep
     // (a symmetric permutation of G and the same permutation of V's
     // columns; the padding stays in place): blocks then pair indices of

@@ -352,6 +352,177 @@ __global__ __launch_bounds__(256) void mg_jacobi_kernel(GridDims g, int k, const
   oj[c] = xj[c] + w * (bj[c] - Av);
 }
 
+// The coarse tail of the V-cycle in one launch: the levels from the first
+// one of at most MG_TAIL_MAXN cells down to the coarsest, one block per
+// column with every vector of those levels in LDS (b, and two iterates per
+// level).  Each thread owns the cells tid + MG_TAIL_THREADS i of a level
+// and keeps their coefficients in registers while it works on that level.
+// The arithmetic is that of the level kernels (the same steps, the
+// restriction summed over the eight children in a fixed order).
+constexpr int MG_TAIL_THREADS = 512;
+constexpr int MG_TAIL_CPT = 8;
+constexpr int MG_TAIL_MAXN = MG_TAIL_THREADS * MG_TAIL_CPT;
+constexpr size_t MG_TAIL_MAXBYTES = 144 * 1024;
+
+template <typename T>
+struct MgTailLevel {
+  int nx, ny, nz, N;
+  const T* sx;
+  const T* sy;
+  const T* sz;
+  const double* sd;  // sqrt(diag)
+  const T* q;        // prolongation weights (all but the coarsest)
+  int off;           // LDS element offset of b; the iterates follow at off + N, off + 2 N
+};
+
+template <typename T>
+struct MgTailArgs {
+  int nl;  // tail levels; L[nl - 1] is the coarsest
+  MgTailLevel<T> L[DOT_MG_MAXLEV];
+  int k;
+  const int* active;
+  const T* b;  // right-hand side of L[0] (global, ldb)
+  T* z;        // result of L[0] (global, ldz)
+  int64_t ldb, ldz;
+};
+
+template <typename T>
+__global__ __launch_bounds__(MG_TAIL_THREADS) void mg_tail_kernel(MgTailArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char mg_tail_smem[];
+  T* S = reinterpret_cast<T*>(mg_tail_smem);
+  const int j = blockIdx.x;
+  if (j >= a.k || (a.active && a.active[j] == 0)) return;  // uniform
+  const int t = threadIdx.x;
+  const T w = (T)MG_OMEGA;
+
+  // per-thread cells of the current level: coefficients and neighbour flags
+  T cE[MG_TAIL_CPT], cW[MG_TAIL_CPT], cN[MG_TAIL_CPT], cS[MG_TAIL_CPT], cU[MG_TAIL_CPT],
+      cD[MG_TAIL_CPT];
+  int fl[MG_TAIL_CPT];  // bit 0..5: has -x, +x, -y, +y, -z, +z neighbour
+  auto prepare = [&](const MgTailLevel<T>& L) {
+#pragma unroll
+    for (int i = 0; i < MG_TAIL_CPT; ++i) {
+      const int c = t + MG_TAIL_THREADS * i;
+      fl[i] = 0;
+      cE[i] = cW[i] = cN[i] = cS[i] = cU[i] = cD[i] = T(0);
+      if (c < L.N) {
+        const int x = c % L.nx, y = (c / L.nx) % L.ny, z = c / (L.nx * L.ny);
+        const int nxy = L.nx * L.ny;
+        fl[i] = (x > 0) | ((x + 1 < L.nx) << 1) | ((y > 0) << 2) | ((y + 1 < L.ny) << 3) |
+                ((z > 0) << 4) | ((z + 1 < L.nz) << 5);
+        cE[i] = L.sx[c];
+        cN[i] = L.sy[c];
+        cU[i] = L.sz[c];
+        if (x > 0) cW[i] = L.sx[c - 1];
+        if (y > 0) cS[i] = L.sy[c - L.nx];
+        if (z > 0) cD[i] = L.sz[c - nxy];
+      }
+    }
+  };
+  // A^ v at owned cell i (c) of a level from the LDS vector v
+  auto apply = [&](const MgTailLevel<T>& L, const T* v, int i, int c) -> T {
+    const int nxy = L.nx * L.ny;
+    const int f = fl[i];
+    const T vW = v[(f & 1) ? c - 1 : c], vE = v[(f & 2) ? c + 1 : c];
+    const T vS = v[(f & 4) ? c - L.nx : c], vN = v[(f & 8) ? c + L.nx : c];
+    const T vD = v[(f & 16) ? c - nxy : c], vU = v[(f & 32) ? c + nxy : c];
+    return v[c] - cW[i] * vW - cE[i] * vE - cS[i] * vS - cN[i] * vN - cD[i] * vD - cU[i] * vU;
+  };
+  // out = J(in) = in + w (b - A^ in); in == NULL: in = w b
+  auto jstep = [&](const MgTailLevel<T>& L, const T* b, const T* in, T* out) {
+    if (in == nullptr) {
+      for (int c = t; c < L.N; c += MG_TAIL_THREADS) out[c] = w * b[c];
+      __syncthreads();
+      return;
+    }
+#pragma unroll
+    for (int i = 0; i < MG_TAIL_CPT; ++i) {
+      const int c = t + MG_TAIL_THREADS * i;
+      if (c < L.N) out[c] = in[c] + w * (b[c] - apply(L, in, i, c));
+    }
+    __syncthreads();
+  };
+
+  const MgTailLevel<T>& L0 = a.L[0];
+  for (int c = t; c < L0.N; c += MG_TAIL_THREADS) S[L0.off + c] = a.b[c + a.ldb * j];
+  __syncthreads();
+  const T* pre[DOT_MG_MAXLEV];
+  // down: x = J^(nu - 1)(w b), restriction of b - A^ x
+  for (int l = 0; l + 1 < a.nl; ++l) {
+    const MgTailLevel<T>& L = a.L[l];
+    const MgTailLevel<T>& C = a.L[l + 1];
+    T* b = S + L.off;
+    T* buf[2] = {S + L.off + L.N, S + L.off + 2 * L.N};
+    prepare(L);
+    jstep(L, b, nullptr, buf[0]);
+    int cur = 0;
+    for (int s = 1; s < MG_NU1; ++s) {
+      jstep(L, b, buf[cur], buf[cur ^ 1]);
+      cur ^= 1;
+    }
+    const T* x = buf[cur];
+    T* r = buf[cur ^ 1];
+#pragma unroll
+    for (int i = 0; i < MG_TAIL_CPT; ++i) {
+      const int c = t + MG_TAIL_THREADS * i;
+      if (c < L.N) r[c] = (T)L.sd[c] * (b[c] - apply(L, x, i, c));
+    }
+    __syncthreads();
+    T* bc = S + C.off;
+    const int nxy = L.nx * L.ny;
+    for (int cc = t; cc < C.N; cc += MG_TAIL_THREADS) {
+      const int X = cc % C.nx, Y = (cc / C.nx) % C.ny, Z = cc / (C.nx * C.ny);
+      const int f0 = 2 * X + L.nx * (2 * Y) + nxy * (2 * Z);
+      T s = T(0);
+      for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+          for (int dx = 0; dx < 2; ++dx) s += r[f0 + dx + L.nx * dy + nxy * dz];
+      bc[cc] = s / (T)C.sd[cc];
+    }
+    __syncthreads();
+    pre[l] = x;
+  }
+  // coarsest: MG_NU_C steps from zero
+  const T* zc;
+  {
+    const MgTailLevel<T>& L = a.L[a.nl - 1];
+    T* b = S + L.off;
+    T* buf[2] = {S + L.off + L.N, S + L.off + 2 * L.N};
+    prepare(L);
+    jstep(L, b, nullptr, buf[0]);
+    int cur = 0;
+    for (int s = 1; s < MG_NU_C; ++s) {
+      jstep(L, b, buf[cur], buf[cur ^ 1]);
+      cur ^= 1;
+    }
+    zc = buf[cur];
+  }
+  // up: y = x + P z_{l+1}, then nu steps
+  for (int l = a.nl - 2; l >= 0; --l) {
+    const MgTailLevel<T>& L = a.L[l];
+    const MgTailLevel<T>& C = a.L[l + 1];
+    T* b = S + L.off;
+    T* buf[2] = {S + L.off + L.N, S + L.off + 2 * L.N};
+    const int xi = pre[l] == buf[0] ? 0 : 1;
+    T* y = buf[xi ^ 1];
+    const int nxy = L.nx * L.ny;
+    for (int c = t; c < L.N; c += MG_TAIL_THREADS) {
+      const int x = c % L.nx, yy = (c / L.nx) % L.ny, z = c / nxy;
+      const int p = (x >> 1) + C.nx * ((yy >> 1) + C.ny * (z >> 1));
+      y[c] = pre[l][c] + L.q[c] * zc[p];
+    }
+    __syncthreads();
+    prepare(L);
+    int cur = xi ^ 1;
+    for (int s = 0; s < MG_NU1; ++s) {
+      jstep(L, b, buf[cur], buf[cur ^ 1]);
+      cur ^= 1;
+    }
+    zc = buf[cur];
+  }
+  for (int c = t; c < L0.N; c += MG_TAIL_THREADS) a.z[c + a.ldz * j] = zc[c];
+}
+
 static size_t mg_al(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // Column stride of a coarse level's vectors: a larger level's columns are
@@ -447,6 +618,17 @@ int mg_vcycle(dot_op* op, const MgWork<T>& w, int k, const T* r0, int64_t ld0, T
     if (l + 1 < nl) a.cld = w.ld[l + 1];
     return a;
   };
+  // the coarse tail run by mg_tail_kernel: levels t0 .. nl - 1 (t0 >= 1;
+  // t0 = nl: none, the coarsest level then takes MG_NU_C Jacobi launches)
+  int t0 = nl;
+  size_t tail_bytes = 0;
+  for (int l = nl - 1; l >= 1; --l) {
+    const size_t bytes = tail_bytes + 3 * (size_t)op->mg[l].g.N * sizeof(T);
+    if (op->mg[l].g.N > MG_TAIL_MAXN || bytes > MG_TAIL_MAXBYTES) break;
+    tail_bytes = bytes;
+    t0 = l;
+  }
+  const int ndown = t0 < nl ? t0 : nl - 1;  // levels with a down and an up pass
   // one smoothing step on level l from x (NULL: w b) plus, with xc, the
   // prolongation of xc; returns the buffer written
   int outputs[DOT_MG_MAXLEV] = {};
@@ -467,7 +649,7 @@ int mg_vcycle(dot_op* op, const MgWork<T>& w, int k, const T* r0, int64_t ld0, T
   };
   // down the hierarchy: nu - 1 steps after x = w b, then the restriction
   const T* pre[DOT_MG_MAXLEV] = {};
-  for (int l = 0; l + 1 < nl; ++l) {
+  for (int l = 0; l < ndown; ++l) {
     const T* x = nullptr;
     for (int i = 1; i < mg_nu(l); ++i) {
       x = smooth(l, x, nullptr, nullptr);
@@ -483,8 +665,38 @@ int mg_vcycle(dot_op* op, const MgWork<T>& w, int k, const T* r0, int64_t ld0, T
     else mg_launch<MG_DOWN, false, false>(a, groups, s);
     DOT_LAUNCH_CHECK();
   }
-  // coarsest level: MG_NU_C Jacobi steps from zero, ending in z
-  {
+  if (t0 < nl) {
+    MgTailArgs<T> ta{};
+    ta.nl = nl - t0;
+    int off = 0;
+    for (int i = 0; i < ta.nl; ++i) {
+      const MgLevel& L = op->mg[t0 + i];
+      MgTailLevel<T>& d = ta.L[i];
+      d.nx = L.g.nx;
+      d.ny = L.g.ny;
+      d.nz = L.g.nz;
+      d.N = (int)L.g.N;
+      d.sx = MgCoef<T>::sx(L);
+      d.sy = MgCoef<T>::sy(L);
+      d.sz = MgCoef<T>::sz(L);
+      d.sd = L.sd;
+      d.q = MgCoef<T>::q(L);
+      d.off = off;
+      off += 3 * d.N;
+    }
+    ta.k = k;
+    ta.active = active;
+    ta.b = w.b[t0];
+    ta.ldb = w.ld[t0];
+    ta.z = w.z[t0];
+    ta.ldz = w.ld[t0];
+    if (tail_bytes > 65536)
+      DOT_HIP(hipFuncSetAttribute((const void*)mg_tail_kernel<T>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)tail_bytes));
+    hipLaunchKernelGGL((mg_tail_kernel<T>), dim3(k), dim3(MG_TAIL_THREADS), tail_bytes, s, ta);
+    DOT_LAUNCH_CHECK();
+  } else {
+    // coarsest level: MG_NU_C Jacobi steps from zero, ending in z
     const int l = nl - 1;
     const MgLevel& L = op->mg[l];
     const unsigned blocks = (unsigned)((L.g.N * k + 255) / 256);
@@ -502,7 +714,7 @@ int mg_vcycle(dot_op* op, const MgWork<T>& w, int k, const T* r0, int64_t ld0, T
   }
   // up the hierarchy: the prolongation with the first of nu steps; on level
   // 0 the last step also forms r0 . z0
-  for (int l = nl - 2; l >= 0; --l) {
+  for (int l = ndown - 1; l >= 0; --l) {
     const T* x = pre[l];
     const int nu = mg_nu(l);
     for (int i = 0; i < nu; ++i) {

@@ -629,6 +629,8 @@ int dot_build_operator(const dot_grid* grid, const double* D_dev, void* stream, 
   if (e == hipSuccess) e = hipHostMalloc(&op->pinned, kPinnedInts * sizeof(int32_t), hipHostMallocDefault);
   if (e == hipSuccess)
     e = hipHostMalloc(&op->pinned_d, 64 * sizeof(double), hipHostMallocDefault);
+  for (int i = 0; i < 2; ++i)
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&op->poll_ev[i], hipEventDisableTiming);
   if (e != hipSuccess) {
     set_error("device allocation failed: %s", hipGetErrorString(e));
     dot_destroy_operator(op);
@@ -666,6 +668,8 @@ int dot_destroy_operator(dot_op* op) {
     if (p) (void)hipFree(p);
   if (op->pinned) (void)hipHostFree(op->pinned);
   if (op->pinned_d) (void)hipHostFree(op->pinned_d);
+  for (hipEvent_t ev : op->poll_ev)
+    if (ev) (void)hipEventDestroy(ev);
   delete op;
   return DOT_OK;
 }

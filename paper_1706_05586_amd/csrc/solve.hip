@@ -928,6 +928,43 @@ static int poll(dot_op* op, const Workspace& ws, int k, hipStream_t s, int* n_ac
   return DOT_OK;
 }
 
+// Flag snapshots read one poll late: at a poll the activity and update
+// flags are copied to one of two pinned slots behind an event, and the
+// previous poll's slot is then read, so the host waits for the stream only
+// when it is a poll interval behind and the GPU keeps the next iterations
+// queued.  Iterations enqueued after the last column has stopped run with
+// every column masked off and cost a few microseconds per launch.
+struct LagPoll {
+  int pending = -1;  // slot of the snapshot not read yet (-1: none)
+  int next = 0;
+};
+
+static int poll_snapshot(dot_op* op, const Workspace& ws, int k, hipStream_t s, LagPoll& lp) {
+  int32_t* slot = op->pinned + 2 * k * lp.next;
+  DOT_HIP(hipMemcpyAsync(slot, ws.st.active, k * sizeof(int), hipMemcpyDeviceToHost, s));
+  DOT_HIP(hipMemcpyAsync(slot + k, ws.st.upd, k * sizeof(int), hipMemcpyDeviceToHost, s));
+  DOT_HIP(hipEventRecord(op->poll_ev[lp.next], s));
+  return DOT_OK;
+}
+
+// reads the pending snapshot (waiting for it) and makes the one just taken pending
+static int poll_read(dot_op* op, int k, LagPoll& lp, bool advance, int* n_active, int* n_upd) {
+  if (lp.pending >= 0) {
+    DOT_HIP(hipEventSynchronize(op->poll_ev[lp.pending]));
+    const int32_t* slot = op->pinned + 2 * k * lp.pending;
+    int na = 0, nu = 0;
+    for (int j = 0; j < k; ++j) {
+      na += slot[j] != 0;
+      nu += slot[k + j] != 0;
+    }
+    *n_active = na;
+    *n_upd = nu;
+  }
+  lp.pending = advance ? lp.next : -1;
+  if (advance) lp.next ^= 1;
+  return DOT_OK;
+}
+
 static SweepArgs<double> base_args64(dot_op* op, const Geom& G) {
   SweepArgs<double> a{};
   a.G = G;
@@ -993,6 +1030,7 @@ static int solve_fp64(dot_op* op, const Geom& G, const Workspace& ws, const doub
   if (mg) DOT_TRY(precondition(1));
   int n_active = 0;
   DOT_TRY(poll(op, ws, G.k, s, &n_active, nullptr));
+  LagPoll lp;
   int it = 0;
   int cur = 0;
   while (n_active > 0 && it < o.max_iter) {
@@ -1020,7 +1058,11 @@ static int solve_fp64(dot_op* op, const Geom& G, const Workspace& ws, const doub
     DOT_TRY(launch_fin(mg ? F_BETA_MG : F_BETA, G, ws, ws.st.active, o.rtol, 0.0, s));
     if (mg) DOT_TRY(precondition(0));
     ++it;
-    if (it % o.check_every == 0 || it == o.max_iter) DOT_TRY(poll(op, ws, G.k, s, &n_active, nullptr));
+    if (it % o.check_every == 0 || it == o.max_iter) {
+      int nu = 0;
+      DOT_TRY(poll_snapshot(op, ws, G.k, s, lp));
+      DOT_TRY(poll_read(op, G.k, lp, true, &n_active, &nu));
+    }
   }
   *iters_done = it;
   return finish_true(op, G, ws, rhs, x, s);
@@ -1068,7 +1110,14 @@ static int solve_mixed(dot_op* op, const Geom& G, const Workspace& ws, const dou
   if (mg) DOT_TRY(precondition(1));
   int n_active = 0, n_upd = 0;
   DOT_TRY(poll(op, ws, G.k, s, &n_active, nullptr));
+  LagPoll lp;
   int it = 0, updates = 0, cur = 0;
+  auto count = [&](bool advance) -> int {
+    n_upd = 0;
+    DOT_TRY(poll_read(op, G.k, lp, advance, &n_active, &n_upd));
+    if (n_upd > 0) ++updates;
+    return DOT_OK;
+  };
   while (n_active > 0 && it < o.max_iter) {
     SweepArgs<float> p1 = base_args32(op, G);
     p1.active = ws.st.active;
@@ -1096,34 +1145,31 @@ static int solve_mixed(dot_op* op, const Geom& G, const Workspace& ws, const dou
                        polled ? 1 : 0));
     ++it;
     if (polled) {
-      DOT_TRY(poll(op, ws, G.k, s, &n_active, &n_upd));
-      if (n_upd > 0) {
-        // reliable update of the flagged columns
-        EltArgs ef = e;
-        ef.mask = ws.st.upd;
-        DOT_TRY(launch_elt<E_FOLD>(ef, s));
-        SweepArgs<double> rs = base_args64(op, G);
-        rs.active = ws.st.upd;
-        rs.in0 = x;
-        rs.b = rhs;
-        rs.out0 = ws.r64;
-        rs.ld_out0 = G.ldw;
-        rs.partial = ws.partial;
-        DOT_TRY(launch_sweep<M_RESID, double>(op, rs, s, DOT_PROF_RESID));
-        DOT_TRY(launch_fin(F_RESID, G, ws, ws.st.upd, o.rtol, delta, s));
-        DOT_TRY(launch_elt<E_REPLACE>(ef, s));
-        DOT_TRY(launch_fin(mg ? F_REPLACE_MG : F_REPLACE, G, ws, ws.st.upd, o.rtol, delta, s));
-        ++updates;
-        if (!mg) DOT_TRY(poll(op, ws, G.k, s, &n_active, nullptr));
-      }
+      DOT_TRY(poll_snapshot(op, ws, G.k, s, lp));
+      // reliable update of the flagged columns (every kernel masked by the
+      // update flags: a no-op where none is set)
+      EltArgs ef = e;
+      ef.mask = ws.st.upd;
+      DOT_TRY(launch_elt<E_FOLD>(ef, s));
+      SweepArgs<double> rs = base_args64(op, G);
+      rs.active = ws.st.upd;
+      rs.in0 = x;
+      rs.b = rhs;
+      rs.out0 = ws.r64;
+      rs.ld_out0 = G.ldw;
+      rs.partial = ws.partial;
+      DOT_TRY(launch_sweep<M_RESID, double>(op, rs, s, DOT_PROF_RESID));
+      DOT_TRY(launch_fin(F_RESID, G, ws, ws.st.upd, o.rtol, delta, s));
+      DOT_TRY(launch_elt<E_REPLACE>(ef, s));
+      DOT_TRY(launch_fin(mg ? F_REPLACE_MG : F_REPLACE, G, ws, ws.st.upd, o.rtol, delta, s));
     }
-    if (mg) {
-      DOT_TRY(precondition(0));
-      if (polled && n_upd > 0) DOT_TRY(poll(op, ws, G.k, s, &n_active, nullptr));
-    }
+    if (mg) DOT_TRY(precondition(0));
+    if (polled) DOT_TRY(count(true));
   }
+  DOT_TRY(count(false));
   // columns stopped by the iteration cap: fold their pending correction
-  if (n_active > 0) {
+  // (masked by the activity flags: a no-op where every column converged)
+  {
     EltArgs ef = e;
     ef.mask = ws.st.active;
     DOT_TRY(launch_elt<E_FOLD>(ef, s));
