@@ -801,6 +801,119 @@ __global__ __launch_bounds__(1024) void householder_qr_kernel(int n, int q, doub
   }
 }
 
+// Fast path for n <= HQ_MAXN: the factorization in one block with a wave
+// per trailing column (wave reductions, two block barriers per step), and
+// the complete Q with one wave per column of Q applying the reflectors to
+// a unit vector held in registers (the columns are independent).
+constexpr int HQ_RPL = 16;
+constexpr int HQ_MAXN = 64 * HQ_RPL;
+
+__device__ __forceinline__ double hq_wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(1024) void hh_factor_kernel(int n, int q, double* __restrict__ X,
+                                                         double* __restrict__ tau) {
+  __shared__ double sh_tau, sh_beta, sh_scale;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, nw = blockDim.x >> 6;
+  for (int k = 0; k < q; ++k) {
+    double* xk = X + (int64_t)n * k;
+    if (wave == 0) {
+      double s = 0.0;
+      for (int i = k + 1 + lane; i < n; i += 64) s += xk[i] * xk[i];
+      s = hq_wave_sum(s);
+      if (lane == 0) {
+        const double alpha = xk[k];
+        if (s == 0.0) {
+          sh_tau = 0.0;
+          sh_beta = alpha;
+          sh_scale = 0.0;
+        } else {
+          const double nr = sqrt(alpha * alpha + s);
+          const double beta = alpha >= 0.0 ? -nr : nr;
+          sh_tau = (beta - alpha) / beta;
+          sh_scale = 1.0 / (alpha - beta);
+          sh_beta = beta;
+        }
+        tau[k] = sh_tau;
+      }
+    }
+    __syncthreads();
+    const double tk = sh_tau, sc = sh_scale;
+    double v[HQ_RPL];
+#pragma unroll
+    for (int r = 0; r < HQ_RPL; ++r) {
+      const int i = lane + 64 * r;
+      v[r] = (i > k && i < n) ? xk[i] * sc : 0.0;
+    }
+    __syncthreads();  // every wave holds v before column k is overwritten
+    if (wave == 0) {
+#pragma unroll
+      for (int r = 0; r < HQ_RPL; ++r) {
+        const int i = lane + 64 * r;
+        if (i > k && i < n) xk[i] = v[r];
+      }
+      if (lane == 0) xk[k] = sh_beta;
+    }
+    for (int j = k + 1 + wave; j < q; j += nw) {
+      double* xj = X + (int64_t)n * j;
+      double xv[HQ_RPL];
+      double d = lane == 0 ? xj[k] : 0.0;
+#pragma unroll
+      for (int r = 0; r < HQ_RPL; ++r) {
+        const int i = lane + 64 * r;
+        xv[r] = (i > k && i < n) ? xj[i] : 0.0;
+        d += v[r] * xv[r];
+      }
+      d = hq_wave_sum(d);
+      const double f = tk * d;
+#pragma unroll
+      for (int r = 0; r < HQ_RPL; ++r) {
+        const int i = lane + 64 * r;
+        if (i > k && i < n) xj[i] = xv[r] - f * v[r];
+      }
+      if (lane == 0) xj[k] -= f;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void hh_form_q_kernel(int n, int q, const double* __restrict__ X,
+                                                        const double* __restrict__ tau,
+                                                        double* __restrict__ Q, int ldq) {
+  const int lane = threadIdx.x & 63;
+  const int c = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
+  if (c >= n) return;  // uniform over the wave
+  double u[HQ_RPL];
+#pragma unroll
+  for (int r = 0; r < HQ_RPL; ++r) u[r] = (lane + 64 * r == c) ? 1.0 : 0.0;
+  for (int k = q - 1; k >= 0; --k) {
+    const double tk = tau[k];
+    if (tk == 0.0) continue;  // uniform
+    const double* vk = X + (int64_t)n * k;
+    double vv[HQ_RPL];
+    double d = 0.0;
+#pragma unroll
+    for (int r = 0; r < HQ_RPL; ++r) {
+      const int i = lane + 64 * r;
+      vv[r] = i == k ? 1.0 : ((i > k && i < n) ? vk[i] : 0.0);
+      d += vv[r] * u[r];
+    }
+    d = hq_wave_sum(d);
+    const double f = tk * d;
+#pragma unroll
+    for (int r = 0; r < HQ_RPL; ++r) u[r] -= f * vv[r];
+  }
+  double* qc = Q + (int64_t)ldq * c;
+#pragma unroll
+  for (int r = 0; r < HQ_RPL; ++r) {
+    const int i = lane + 64 * r;
+    if (i < n) qc[i] = u[r];
+  }
+}
+
 static size_t qr_work_bytes(int n, int q) {
   return al256((size_t)n * q * 8) + al256((size_t)q * 8) + al256((size_t)n * 8);
 }
@@ -814,6 +927,16 @@ static int qr_complete(int n, int q, const double* X, int ldx, double* Q, int ld
     const unsigned b = (unsigned)(((int64_t)n * q + 255) / 256);
     hipLaunchKernelGGL(copy_matrix_kernel, dim3(b), dim3(256), 0, s, n, q, X, ldx, Xw, n);
     DOT_LAUNCH_CHECK();
+  }
+  if (n <= HQ_MAXN) {
+    if (q > 0) {
+      hipLaunchKernelGGL(hh_factor_kernel, dim3(1), dim3(1024), 0, s, n, q, Xw, tau);
+      DOT_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(hh_form_q_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, n, q, Xw, tau,
+                       Q, ldq);
+    DOT_LAUNCH_CHECK();
+    return DOT_OK;
   }
   hipLaunchKernelGGL(householder_qr_kernel, dim3(1), dim3(1024), 0, s, n, q, Xw, n, tau, Q, ldq, wb);
   DOT_LAUNCH_CHECK();
