@@ -38,9 +38,9 @@ import scipy.sparse as sp
 
 from . import discretization as disc
 
-OMEGA = 0.9
+OMEGA = 0.85
 NU0 = 2
-NU1 = 3
+NU1 = 4
 NU_C = 8
 
 

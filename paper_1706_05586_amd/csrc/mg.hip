@@ -45,8 +45,8 @@ constexpr int MRG = 4;                  // columns per block
 constexpr int MG_NU_C = 8;              // Jacobi steps on the coarsest level
 
 constexpr int MG_NU0 = 2;               // smoothing steps each way on the finest level
-constexpr int MG_NU1 = 3;               // ... and on the coarser levels above the coarsest
-#define MG_OMEGA 0.9
+constexpr int MG_NU1 = 4;               // ... and on the coarser levels above the coarsest
+#define MG_OMEGA 0.85
 
 static inline int mg_nu(int level) { return level == 0 ? MG_NU0 : MG_NU1; }
 
@@ -219,6 +219,7 @@ __global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T> a) {
   Raw hr;  // halo cell, plane z
   load_raw(hbase + z0 * G.nxy, phbase + (z0 >> 1) * G.cnxy, hr);
   T cD = z0 > 0 ? mg_ld(a.sz, base + (z0 - 1) * G.nxy) : T(0);
+  T sdc_next = T(1);
   T zacc[MRG];
   double acc[MRG];
 #pragma unroll
@@ -249,6 +250,10 @@ __global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T> a) {
     const T cSl = mg_ld(a.sy, has_s ? c - G.nx : c);
     const T cU = mg_ld(a.sz, c);
     const T sdv = MODE == MG_DOWN ? (T)mg_ld(a.sd, c) : T(0);
+    // the aggregate's coarse sqrt(diag), loaded on the even plane for the
+    // odd plane's write
+    if (MODE == MG_DOWN && (z & 1) == 0)
+      sdc_next = (T)mg_ld(a.sdc, in ? (x >> 1) + (int64_t)G.cnx * (y >> 1) + G.cnxy * (z >> 1) : 0);
     load_raw(hbase + zu * G.nxy, phbase + (zu >> 1) * G.cnxy, hr);
     __syncthreads();
     const T cW = has_w ? cWl : T(0);
@@ -274,7 +279,7 @@ __global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T> a) {
           zacc[r] += s2;
           if (in && (lane & 33) == 0) {
             const int64_t C = (x >> 1) + (int64_t)G.cnx * (y >> 1) + G.cnxy * (z >> 1);
-            a.bc[C + a.cld * col[r]] = zacc[r] / (T)mg_ld(a.sdc, C);
+            a.bc[C + a.cld * col[r]] = zacc[r] / sdc_next;
           }
         }
       } else {
