@@ -165,8 +165,10 @@ __device__ __forceinline__ void jacobi_angle(double app, double aqq, double apq,
 // t^2 + 2 (d / e) t - 1 = 0, and c = (1 + t^2)^(-1/2), s = t c.
 __device__ __forceinline__ void jacobi_angle_1div(double app, double aqq, double apq, double* c,
                                                   double* s) {
+  // d^2 + e^2 neither overflows nor underflows: the block solver scales its
+  // matrix to ||A||_F ~ 1 and rotates only |a_pq| > eps ||A||_F
   const double d = aqq - app, e = 2.0 * apq;
-  double t = e / (fabs(d) + hypot(d, e));
+  double t = e / (fabs(d) + sqrt(d * d + e * e));
   if (d < 0.0) t = -t;
   const double cc = rsqrt(1.0 + t * t);
   *c = cc;
@@ -323,7 +325,7 @@ __global__ __launch_bounds__(64) void bj_eig_kernel(int ld, int nbk, int round,
         tournament(BJ_S, r, t, &p, &q);
         const double app = a[p][p], aqq = a[q][q], apq = a[p][q];
         double c = 1.0, s = 0.0;
-        if (fabs(apq) > fmax(BJ_TOL * sqrt(fabs(app * aqq)), floor)) {
+        if (apq * apq > fmax(BJ_TOL * BJ_TOL * fabs(app * aqq), floor * floor)) {
           jacobi_angle_1div(app, aqq, apq, &c, &s);
           any = 1;
         }
@@ -580,7 +582,7 @@ __global__ void copy_matrix_kernel(int m, int n, const double* __restrict__ X, i
 // descending order of the first n diagonal entries of G (ld): the rank of
 // entry i counts the larger entries and the equal ones with a smaller index
 __global__ void eig_rank_kernel(int n, int ld, const double* __restrict__ G, int* __restrict__ order,
-                                double* __restrict__ w) {
+                                double* __restrict__ w, double wscale) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double di = G[i + (int64_t)ld * i];
@@ -590,7 +592,12 @@ __global__ void eig_rank_kernel(int n, int ld, const double* __restrict__ G, int
     rank += (dj > di || (dj == di && j < i)) ? 1 : 0;
   }
   order[rank] = i;
-  w[rank] = di;
+  w[rank] = di * wscale;
+}
+
+__global__ void scale_array_kernel(int64_t n, double f, double* __restrict__ a) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e < n) a[e] *= f;
 }
 
 __global__ void permute_cols_kernel(int n, int ld, const double* __restrict__ V,
@@ -659,7 +666,7 @@ static int symeig(int n, const double* A, int lda, double* w, double* V, int ldv
   const int ntiles = npairs * (npairs + 1) / 2 + (ld / BJ_S) * npairs;
   std::vector<double> hp(1024);
   int hflag = 1, sweep = 0;
-  double floor = 0.0;
+  double floor = 0.0, gscale = 1.0;
   for (;; ++sweep) {
     hipLaunchKernelGGL(offnorm_kernel, dim3(nblk_off), dim3(256), 0, s, ld, Gw, part);
     DOT_LAUNCH_CHECK();
@@ -677,6 +684,18 @@ static int symeig(int n, const double* A, int lda, double* w, double* V, int ldv
     // rotating on graded spectra such as J_s J_s^T.  A random-like remainder
     // E of that size moves the eigenvalues by about ||E||_2 ~ 2 sqrt(n) eps
     // ||A||_F, within the n eps ||A|| backward error of the tile updates.
+    if (sweep == 0 && tots > 0.0) {
+      // scale by a power of two to ||A||_F ~ 1 (exact; undone on the
+      // eigenvalues), which keeps the squares in the rotation angles and
+      // the threshold test in range
+      const int ex = (int)std::lround(std::log2(std::sqrt(tots)));
+      gscale = std::ldexp(1.0, -ex);
+      hipLaunchKernelGGL(scale_array_kernel, dim3((unsigned)((ll + 255) / 256)), dim3(256), 0, s,
+                         (int64_t)ll, gscale, Gw);
+      DOT_LAUNCH_CHECK();
+      offs *= gscale * gscale;
+      tots *= gscale * gscale;
+    }
     if (sweep == 0) floor = BJ_TOL * sqrt(tots);
     // stop once off(A) <= n eps ||A||_F: the eigenvalues are then within
     // ||off(A)||_2 <= n eps ||A||_F of the diagonal, the size of the
@@ -688,7 +707,7 @@ static int symeig(int n, const double* A, int lda, double* w, double* V, int ldv
     // columns; the padding stays in place): blocks then pair indices of
     // similar size, which takes a quarter fewer sweeps on graded spectra.
     hipLaunchKernelGGL(eig_rank_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, ld, Gw, order,
-                       wtmp);
+                       wtmp, 1.0);
     DOT_LAUNCH_CHECK();
     hipLaunchKernelGGL(bj_permute_kernel, dim3((unsigned)((ll + 255) / 256)), dim3(256), 0, s, n, ld,
                        order, Gw, Vw, Gt, Vt);
@@ -707,7 +726,8 @@ static int symeig(int n, const double* A, int lda, double* w, double* V, int ldv
     }
   }
   if (sweeps) *sweeps = sweep;
-  hipLaunchKernelGGL(eig_rank_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, ld, Gw, order, w);
+  hipLaunchKernelGGL(eig_rank_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, ld, Gw, order, w,
+                     1.0 / gscale);
   DOT_LAUNCH_CHECK();
   hipLaunchKernelGGL(permute_cols_kernel, dim3((unsigned)(((int64_t)n * n + 255) / 256)), dim3(256), 0,
                      s, n, ld, Vw, order, V, ldv);
