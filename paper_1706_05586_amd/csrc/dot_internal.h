@@ -122,6 +122,8 @@ struct dot_op {
   int64_t chunk_cap = 0;
   int64_t n_chunks = 0;            // chunks hold at most DOT_PAIR_CHUNK pairs
   int64_t rbf_cap = 0;
+  int64_t* rbf_sub = nullptr;    // device: per (RBF, scan range) counts, then starts
+  int64_t rbf_sub_cap = 0;
   // per pair: h^d d mu / d p of its RBF's active parameters (pair-major), and
   // its row in the band-cell list (every cell of any list, in cell order),
   // through which the contraction reads U and Z rows packed cell-major

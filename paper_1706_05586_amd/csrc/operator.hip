@@ -523,6 +523,19 @@ __device__ __forceinline__ void rbf_box(const GridDims& g, const double* th, dou
   }
 }
 
+// RBF m's bounding box is scanned by kRbfSplit blocks, each a contiguous
+// range of the box's cells in increasing cell order: a counting pass, then,
+// at offsets from the prefix sums over (RBF, range), a filling pass, so each
+// RBF's list comes out in increasing cell order.
+constexpr int kRbfSplit = 16;
+
+__device__ __forceinline__ void rbf_range(int64_t box, int s, int64_t* q0, int64_t* q1) {
+  int64_t per = (box + kRbfSplit - 1) / kRbfSplit;
+  per = (per + 255) / 256 * 256;
+  *q0 = std::min<int64_t>(box, per * s);
+  *q1 = std::min<int64_t>(box, per * (s + 1));
+}
+
 template <bool kFill>
 __global__ __launch_bounds__(256) void rbf_cells_kernel(GridDims g, PalsK p,
                                                         const double* __restrict__ theta,
@@ -531,19 +544,21 @@ __global__ __launch_bounds__(256) void rbf_cells_kernel(GridDims g, PalsK p,
                                                         const int64_t* __restrict__ start,
                                                         int32_t* __restrict__ cells) {
   __shared__ int s_wave[4];
-  const int m = blockIdx.x;
+  const int m = blockIdx.x / kRbfSplit, part = blockIdx.x % kRbfSplit;
   const double* th = theta + (int64_t)m * p.stride;
   int lo[3], ext[3];
   rbf_box(g, th, p.gamma, lo, ext);
   const int64_t box = (int64_t)ext[0] * ext[1] * ext[2];
+  int64_t q0, q1;
+  rbf_range(box, part, &q0, &q1);
   const double beta = th[1], g2 = p.gamma * p.gamma;
   int64_t total = 0;
-  int64_t out = kFill ? start[m] : 0;
-  for (int64_t base = 0; base < box; base += 256) {
+  int64_t out = kFill ? start[blockIdx.x] : 0;
+  for (int64_t base = q0; base < q1; base += 256) {
     const int64_t q = base + threadIdx.x;
     int flag = 0;
     int64_t c = 0;
-    if (q < box) {
+    if (q < q1) {
       const int ix = (int)(q % ext[0]);
       const int iy = (int)((q / ext[0]) % ext[1]);
       const int iz = (int)(q / ((int64_t)ext[0] * ext[1]));
@@ -566,7 +581,7 @@ __global__ __launch_bounds__(256) void rbf_cells_kernel(GridDims g, PalsK p,
     total += tot;
     __syncthreads();
   }
-  if (!kFill && threadIdx.x == 0) counts[m] = total;
+  if (!kFill && threadIdx.x == 0) counts[blockIdx.x] = total;
 }
 
 }  // namespace dot
@@ -662,7 +677,7 @@ int dot_destroy_operator(dot_op* op) {
                   op->sy32,      op->sz32,       op->phi,         op->theta,     op->pair_cell,
                   op->rbf_start, op->chunk_rbf,  op->chunk_begin, op->rbf_chunk0, op->cells_dev,  op->small_dev,
                   op->pair_g,    op->pair_g32,   op->pair_band,   op->band_idx,   op->band_cells,
-                  op->band_part, op->D0,         op->mu0};
+                  op->band_part, op->D0,         op->mu0,         op->rbf_sub};
   mg_free(op);
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -725,15 +740,31 @@ int dot_pals_mua(dot_op* op, const dot_pals* pals, const double* theta_dev, doub
     op->rbf_cap = m0 + 1;
   }
   PalsK p{pals->mu_in, pals->mu_out, pals->cutoff, pals->eps, pals->gamma, m0, g.dim, stride};
-  hipLaunchKernelGGL(rbf_cells_kernel<false>, dim3(m0), dim3(256), 0, s, g, p, op->theta, op->phi,
-                     op->rbf_start, nullptr, nullptr);
+  const int64_t nsub = (int64_t)m0 * kRbfSplit;
+  if (nsub > op->rbf_sub_cap) {
+    if (op->rbf_sub) DOT_HIP(hipFree(op->rbf_sub));
+    op->rbf_sub = nullptr;
+    op->rbf_sub_cap = 0;
+    DOT_HIP(hipMalloc(&op->rbf_sub, (size_t)nsub * sizeof(int64_t)));
+    op->rbf_sub_cap = nsub;
+  }
+  hipLaunchKernelGGL(rbf_cells_kernel<false>, dim3((unsigned)nsub), dim3(256), 0, s, g, p, op->theta,
+                     op->phi, op->rbf_sub, nullptr, nullptr);
   DOT_LAUNCH_CHECK();
-  std::vector<int64_t> counts(m0 + 1, 0);
-  DOT_HIP(hipMemcpyAsync(counts.data(), op->rbf_start, (size_t)m0 * sizeof(int64_t),
+  std::vector<int64_t> sub(nsub, 0);
+  DOT_HIP(hipMemcpyAsync(sub.data(), op->rbf_sub, (size_t)nsub * sizeof(int64_t),
                          hipMemcpyDeviceToHost, s));
   DOT_HIP(hipStreamSynchronize(s));
-  std::vector<int64_t> start(m0 + 1, 0);
-  for (int m = 0; m < m0; ++m) start[m + 1] = start[m] + counts[m];
+  // RBF starts, and each range's start, in (RBF, range) order
+  std::vector<int64_t> start(m0 + 1, 0), sub_start(nsub, 0);
+  for (int m = 0; m < m0; ++m) {
+    int64_t at = start[m];
+    for (int r = 0; r < kRbfSplit; ++r) {
+      sub_start[(int64_t)m * kRbfSplit + r] = at;
+      at += sub[(int64_t)m * kRbfSplit + r];
+    }
+    start[m + 1] = at;
+  }
   const int64_t total = start[m0];
   // chunk table: each RBF's list split into chunks of at most DOT_PAIR_CHUNK cells
   const int64_t kPairChunk = DOT_PAIR_CHUNK;
@@ -779,8 +810,10 @@ int dot_pals_mua(dot_op* op, const dot_pals* pals, const double* theta_dev, doub
   }
   DOT_HIP(hipMemcpyAsync(op->chunk_begin, chunk_begin.data(), (size_t)(nch + 1) * sizeof(int64_t),
                          hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(rbf_cells_kernel<true>, dim3(m0), dim3(256), 0, s, g, p, op->theta, op->phi,
-                     nullptr, op->rbf_start, op->pair_cell);
+  DOT_HIP(hipMemcpyAsync(op->rbf_sub, sub_start.data(), (size_t)nsub * sizeof(int64_t),
+                         hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(rbf_cells_kernel<true>, dim3((unsigned)nsub), dim3(256), 0, s, g, p, op->theta,
+                     op->phi, nullptr, op->rbf_sub, op->pair_cell);
   DOT_LAUNCH_CHECK();
   // the host vectors above are read by the asynchronous copies: wait for them
   DOT_HIP(hipStreamSynchronize(s));
