@@ -192,9 +192,11 @@ void mg_work_layout(const dot_op* op, int k, int64_t ld0, char* base, MgWork<T>*
 int mg_partial_slots(const dot_op* op, int k);
 // z0 = V-cycle applied to r0 (both k columns ld0 apart; columns outside
 // `active` are skipped); partial[0][j][slot] receives r0_j . z0_j
+// (prof_cols: optional, receives the number of active columns)
 template <typename T>
 int mg_vcycle(dot_op* op, const MgWork<T>& w, int k, const T* r0, int64_t ld0, T* z0,
-              const int* active, double* partial, hipStream_t s);
+              const int* active, double* partial, hipStream_t s,
+              unsigned long long* prof_cols = nullptr);
 
 constexpr int kWave = 64;
 

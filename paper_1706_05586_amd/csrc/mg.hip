@@ -80,6 +80,7 @@ struct MgArgs {
   T* bc;               // down: coarse right-hand side (cld)
   int64_t ld, cld;
   double* partial;     // smoothing: [2][k][nblk] slots of b . out (or NULL)
+  unsigned long long* prof_cols;  // optional: += active columns of the launch
   int nblk;
 };
 
@@ -146,6 +147,12 @@ __global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T> a) {
     any |= act[r];
   }
   if (!any) return;  // uniform over the block
+  if (a.prof_cols && tile == 0 && zci == 0 && threadIdx.x == 0) {
+    int n = 0;
+#pragma unroll
+    for (int r = 0; r < MRG; ++r) n += act[r] ? 1 : 0;
+    atomicAdd(a.prof_cols, (unsigned long long)n);
+  }
 
   // halo cell owned by this thread (if any)
   int hx = -1, hy = -1, hsy = 0, hsx = 0;
@@ -598,7 +605,7 @@ static void mg_launch(const MgArgs<T>& a, int groups, hipStream_t s) {
 
 template <typename T>
 int mg_vcycle(dot_op* op, const MgWork<T>& w, int k, const T* r0, int64_t ld0, T* z0,
-              const int* active, double* partial, hipStream_t s) {
+              const int* active, double* partial, hipStream_t s, unsigned long long* prof_cols) {
   const int nl = op->mg_nlev;
   if (nl < 2 || w.nlev != nl) DOT_FAIL(DOT_EINVAL, "multigrid hierarchy not available");
   if (MG_NU0 >= 2 && !w.x[0]) DOT_FAIL(DOT_EINVAL, "multigrid work vectors missing");
@@ -645,6 +652,7 @@ int mg_vcycle(dot_op* op, const MgWork<T>& w, int k, const T* r0, int64_t ld0, T
     a.q = MgCoef<T>::q(op->mg[l]);
     a.out = o;
     a.partial = part;
+    a.prof_cols = part ? prof_cols : nullptr;
     a.nblk = a.G.ntiles * a.G.nzc;
     if (x && xc) mg_launch<MG_SMOOTH, true, true>(a, groups, s);
     else if (x) mg_launch<MG_SMOOTH, true, false>(a, groups, s);
@@ -730,8 +738,8 @@ int mg_vcycle(dot_op* op, const MgWork<T>& w, int k, const T* r0, int64_t ld0, T
   return DOT_OK;
 }
 template int mg_vcycle<float>(dot_op*, const MgWork<float>&, int, const float*, int64_t, float*,
-                              const int*, double*, hipStream_t);
+                              const int*, double*, hipStream_t, unsigned long long*);
 template int mg_vcycle<double>(dot_op*, const MgWork<double>&, int, const double*, int64_t,
-                               double*, const int*, double*, hipStream_t);
+                               double*, const int*, double*, hipStream_t, unsigned long long*);
 
 }  // namespace dot

@@ -817,17 +817,24 @@ static size_t layout_workspace(const dot_op* op, const Geom& G, int precision, c
 }
 
 // ------------------------------------------------------------ profiling
+// Timed launches: an event pair each and, for launches whose kernels count
+// their active columns, a device slot of that count.  A counted launch that
+// found no active column (a launch queued after every column had stopped,
+// see LagPoll) is left out of the totals.
+constexpr int kProfSlots = 2048;
 struct ProfState {
   bool on = false;
   std::vector<hipEvent_t> pool;
   struct Pending {
     int kind;
     hipEvent_t e0, e1;
+    bool counted;
   };
   std::vector<Pending> pending;
   double ms[DOT_PROF_KINDS] = {};
   int64_t launches[DOT_PROF_KINDS] = {};
-  unsigned long long* cols_dev = nullptr;
+  unsigned long long cols[DOT_PROF_KINDS] = {};
+  unsigned long long* cols_dev = nullptr;  // kProfSlots, slot i for pending[i]
 };
 
 static ProfState* prof_of(dot_op* op) { return reinterpret_cast<ProfState*>(op->prof); }
@@ -835,12 +842,21 @@ static ProfState* prof_of(dot_op* op) { return reinterpret_cast<ProfState*>(op->
 static int prof_drain(dot_op* op) {
   ProfState* p = prof_of(op);
   if (!p) return DOT_OK;
-  for (auto& q : p->pending) {
-    float ms = 0.0f;
-    DOT_HIP(hipEventSynchronize(q.e1));
-    DOT_HIP(hipEventElapsedTime(&ms, q.e0, q.e1));
-    p->ms[q.kind] += ms;
-    p->launches[q.kind] += 1;
+  const size_t n = p->pending.size();
+  if (n == 0) return DOT_OK;
+  for (auto& q : p->pending) DOT_HIP(hipEventSynchronize(q.e1));
+  std::vector<unsigned long long> slot(n);
+  DOT_HIP(hipMemcpy(slot.data(), p->cols_dev, n * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+  DOT_HIP(hipMemset(p->cols_dev, 0, n * sizeof(unsigned long long)));
+  for (size_t i = 0; i < n; ++i) {
+    const auto& q = p->pending[i];
+    if (!q.counted || slot[i] > 0) {
+      float ms = 0.0f;
+      DOT_HIP(hipEventElapsedTime(&ms, q.e0, q.e1));
+      p->ms[q.kind] += ms;
+      p->launches[q.kind] += 1;
+      p->cols[q.kind] += slot[i];
+    }
     p->pool.push_back(q.e0);
     p->pool.push_back(q.e1);
   }
@@ -854,7 +870,7 @@ static int prof_begin(dot_op* op, int kind, hipStream_t s, hipEvent_t* e0, hipEv
   *cols = nullptr;
   ProfState* p = prof_of(op);
   if (!p || !p->on || kind < 0) return DOT_OK;
-  if (p->pending.size() >= 2048) DOT_TRY(prof_drain(op));
+  if (p->pending.size() >= (size_t)kProfSlots) DOT_TRY(prof_drain(op));
   for (hipEvent_t* e : {e0, e1}) {
     if (p->pool.empty()) {
       hipEvent_t ev;
@@ -864,15 +880,16 @@ static int prof_begin(dot_op* op, int kind, hipStream_t s, hipEvent_t* e0, hipEv
     *e = p->pool.back();
     p->pool.pop_back();
   }
-  *cols = p->cols_dev + kind;
+  *cols = p->cols_dev + p->pending.size();
   DOT_HIP(hipEventRecord(*e0, s));
   return DOT_OK;
 }
 
-static int prof_end(dot_op* op, int kind, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+static int prof_end(dot_op* op, int kind, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                    bool counted = false) {
   if (!e0) return DOT_OK;
   DOT_HIP(hipEventRecord(e1, s));
-  prof_of(op)->pending.push_back({kind, e0, e1});
+  prof_of(op)->pending.push_back({kind, e0, e1, counted});
   return DOT_OK;
 }
 
@@ -883,7 +900,7 @@ static int launch_sweep(dot_op* op, SweepArgs<T> a, hipStream_t s, int kind = -1
   const int blocks = a.G.nblk_col * n_groups(a.G, ColsPerBlock<T>::value);
   hipLaunchKernelGGL((sweep_kernel<MODE, T>), dim3(blocks), dim3(NT), 0, s, a);
   DOT_LAUNCH_CHECK();
-  return prof_end(op, kind, s, e0, e1);
+  return prof_end(op, kind, s, e0, e1, true);
 }
 
 template <int MODE>
@@ -1023,8 +1040,9 @@ static int solve_fp64(dot_op* op, const Geom& G, const Workspace& ws, const doub
     hipEvent_t e0, e1;
     unsigned long long* cols;
     DOT_TRY(prof_begin(op, DOT_PROF_VCYCLE_FP64, s, &e0, &e1, &cols));
-    DOT_TRY(mg_vcycle<double>(op, ws.mg64, G.k, ws.r64, G.ldw, ws.z64, ws.st.active, ws.partial, s));
-    DOT_TRY(prof_end(op, DOT_PROF_VCYCLE_FP64, s, e0, e1));
+    DOT_TRY(mg_vcycle<double>(op, ws.mg64, G.k, ws.r64, G.ldw, ws.z64, ws.st.active, ws.partial, s,
+                              cols));
+    DOT_TRY(prof_end(op, DOT_PROF_VCYCLE_FP64, s, e0, e1, true));
     return launch_fin(F_RHO_MG, G, ws, ws.st.active, o.rtol, 0.0, s, first);
   };
   if (mg) DOT_TRY(precondition(1));
@@ -1103,8 +1121,9 @@ static int solve_mixed(dot_op* op, const Geom& G, const Workspace& ws, const dou
     hipEvent_t e0, e1;
     unsigned long long* cols;
     DOT_TRY(prof_begin(op, DOT_PROF_VCYCLE_FP32, s, &e0, &e1, &cols));
-    DOT_TRY(mg_vcycle<float>(op, ws.mg32, G.k, ws.r32, G.ldw, ws.z32, ws.st.active, ws.partial, s));
-    DOT_TRY(prof_end(op, DOT_PROF_VCYCLE_FP32, s, e0, e1));
+    DOT_TRY(mg_vcycle<float>(op, ws.mg32, G.k, ws.r32, G.ldw, ws.z32, ws.st.active, ws.partial, s,
+                             cols));
+    DOT_TRY(prof_end(op, DOT_PROF_VCYCLE_FP32, s, e0, e1, true));
     return launch_fin(F_RHO_MG, G, ws, ws.st.active, o.rtol, delta, s, first);
   };
   if (mg) DOT_TRY(precondition(1));
@@ -1360,7 +1379,8 @@ int dot_profile_enable(dot_op* op, int enable) {
   if (!p) {
     p = new ProfState();
     op->prof = p;
-    hipError_t e = hipMalloc(&p->cols_dev, DOT_PROF_KINDS * sizeof(unsigned long long));
+    hipError_t e = hipMalloc(&p->cols_dev, kProfSlots * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMemset(p->cols_dev, 0, kProfSlots * sizeof(unsigned long long));
     if (e != hipSuccess) DOT_FAIL(DOT_EHIP, "hipMalloc: %s", hipGetErrorString(e));
   }
   DOT_TRY(prof_drain(op));
@@ -1368,8 +1388,8 @@ int dot_profile_enable(dot_op* op, int enable) {
   for (int i = 0; i < DOT_PROF_KINDS; ++i) {
     p->ms[i] = 0.0;
     p->launches[i] = 0;
+    p->cols[i] = 0;
   }
-  DOT_HIP(hipMemset(p->cols_dev, 0, DOT_PROF_KINDS * sizeof(unsigned long long)));
   return DOT_OK;
 }
 
@@ -1382,11 +1402,9 @@ int dot_profile_read(dot_op* op, int kind, double* ms_total, int64_t* launches,
   if (!p) DOT_FAIL(DOT_EINVAL, "profiling was never enabled on this handle");
   DOT_HIP(hipDeviceSynchronize());
   DOT_TRY(prof_drain(op));
-  unsigned long long cols = 0;
-  DOT_HIP(hipMemcpy(&cols, p->cols_dev + kind, sizeof(cols), hipMemcpyDeviceToHost));
   if (ms_total) *ms_total = p->ms[kind];
   if (launches) *launches = p->launches[kind];
-  if (column_sweeps) *column_sweeps = (int64_t)cols;
+  if (column_sweeps) *column_sweeps = (int64_t)p->cols[kind];
   return DOT_OK;
 }
 
