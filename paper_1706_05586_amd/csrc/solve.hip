@@ -146,6 +146,13 @@ struct SweepArgs {
   T* out1;             // PCG2: r (in place)
   double* partial;     // [2][k][nblk_col]
   unsigned long long* prof_cols;  // optional: sum of active columns over launches
+  // RESID with out2: instead of r64, the binary32 residual r / scale[j] (column
+  // stride ld_out2) and its norms (as the replacement pass forms them) into
+  // partial2
+  float* out2;
+  const double* scale;
+  int64_t ld_out2;
+  double* partial2;
 };
 
 // Logical block -> (tile, z chunk, column group).  The column group varies
@@ -248,6 +255,8 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs<T> a) {
   T* out0[RG];
   T* out1[RG];
   const double* bcol[RG];
+  float* out2c[RG];
+  double scl[RG];
   bool any = false;
 #pragma unroll
   for (int r = 0; r < RG; ++r) {
@@ -260,6 +269,8 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs<T> a) {
     out0[r] = a.out0 ? a.out0 + (a.ld_out0 ? a.ld_out0 : G.N) * jj : nullptr;
     out1[r] = a.out1 ? a.out1 + (a.ld_out1 ? a.ld_out1 : G.N) * jj : nullptr;
     bcol[r] = a.b ? a.b + G.N * jj : nullptr;
+    out2c[r] = a.out2 ? a.out2 + a.ld_out2 * jj : nullptr;
+    scl[r] = (act[r] && a.scale) ? a.scale[j] : 1.0;
     any |= act[r];
   }
   if (!any) return;  // uniform over the block
@@ -295,10 +306,11 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs<T> a) {
   T vm[RG], vc[RG];        // staged values of planes z-1 and z
   T pr0[RG], pr1[RG];      // raw loads of the own cell, plane z+1
   T hr0[RG], hr1[RG];      // raw loads of the halo cell, next plane
-  double acc[RG][2];
+  double acc[RG][2], acc2[RG][2];
 #pragma unroll
   for (int r = 0; r < RG; ++r) {
     acc[r][0] = acc[r][1] = 0.0;
+    acc2[r][0] = acc2[r][1] = 0.0;
     const uint32_t cm = base + (uint32_t)(z0 > 0 ? z0 - 1 : z0) * nxy;
     const uint32_t c0 = base + (uint32_t)z0 * nxy;
     const uint32_t h0 = hbase + (uint32_t)z0 * nxy;
@@ -428,10 +440,19 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs<T> a) {
       } else if constexpr (MODE == M_RESID) {
         const double rr = bo[r] / sdc - (double)Av;
         if (in) {
-          st(out0[r], c, (T)rr);
           acc[r][0] += rr * rr;
           const double t = sdc * rr;
           acc[r][1] += t * t;
+          if (out2c[r]) {
+            const float rv = (float)(rr / scl[r]);
+            out2c[r][c] = rv;
+            const double rd = (double)rv;
+            acc2[r][0] += rd * rd;
+            const double t2 = sdc * rd;
+            acc2[r][1] += t2 * t2;
+          } else {
+            st(out0[r], c, (T)rr);
+          }
         }
       }
     }
@@ -443,6 +464,12 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs<T> a) {
     }
   }
   if constexpr (MODE != M_APPLY) block_partials<RG>(acc, G, grp, slot, a.partial);
+  if constexpr (MODE == M_RESID) {
+    if (a.out2) {  // uniform
+      __syncthreads();  // block_partials' LDS is read above
+      block_partials<RG>(acc2, G, grp, slot, a.partial2);
+    }
+  }
 }
 
 // Elementwise passes on the same block decomposition (same partial slots).
@@ -760,6 +787,7 @@ struct Workspace {
   MgWork<float> mg32;
   int mg_slots;      // partial slots per column of the V-cycle's r.z
   double* partial;
+  size_t partial_stride;  // elements; the second set starts there
   ColState st;
   size_t bytes;
 };
@@ -797,7 +825,10 @@ static size_t layout_workspace(const dot_op* op, const Geom& G, int precision, c
     }
   }
   ws.mg_slots = mg ? mg_partial_slots(op, G.k) : 0;
-  ws.partial = (double*)take((size_t)2 * G.k * std::max(G.nblk_col, ws.mg_slots) * 8);
+  // two sets of [2][k][slots] partials: the residual sweep of a reliable
+  // update fills both (its own norms and those of the replaced residual)
+  ws.partial_stride = (size_t)2 * G.k * std::max(G.nblk_col, ws.mg_slots);
+  ws.partial = (double*)take(2 * ws.partial_stride * 8);
   const size_t k = (size_t)G.k;
   ws.st.rho = (double*)take(k * 8);
   ws.st.rho_prev = (double*)take(k * 8);
@@ -911,13 +942,13 @@ static int launch_elt(const EltArgs& a, hipStream_t s) {
 }
 
 static int launch_fin(int mode, const Geom& G, const Workspace& ws, const int* live, double rtol,
-                      double delta, hipStream_t s, int have_s = 1) {
+                      double delta, hipStream_t s, int have_s = 1, int set = 0) {
   FinArgs f;
   f.have_s = have_s;
   f.mode = mode;
   f.k = G.k;
   f.nblk = mode == F_RHO_MG ? ws.mg_slots : G.nblk_col;
-  f.partial = ws.partial;
+  f.partial = ws.partial + (set ? ws.partial_stride : 0);
   f.live = live;
   f.st = ws.st;
   f.rtol = rtol;
@@ -1170,17 +1201,20 @@ static int solve_mixed(dot_op* op, const Geom& G, const Workspace& ws, const dou
       EltArgs ef = e;
       ef.mask = ws.st.upd;
       DOT_TRY(launch_elt<E_FOLD>(ef, s));
+      // binary64 residual and, in the same sweep, the binary32 residual
+      // that replaces the recurrence's (r / scale) with the norms of both
       SweepArgs<double> rs = base_args64(op, G);
       rs.active = ws.st.upd;
       rs.in0 = x;
       rs.b = rhs;
-      rs.out0 = ws.r64;
-      rs.ld_out0 = G.ldw;
+      rs.out2 = ws.r32;
+      rs.ld_out2 = G.ldw;
+      rs.scale = ws.st.scale;
       rs.partial = ws.partial;
+      rs.partial2 = ws.partial + ws.partial_stride;
       DOT_TRY(launch_sweep<M_RESID, double>(op, rs, s, DOT_PROF_RESID));
       DOT_TRY(launch_fin(F_RESID, G, ws, ws.st.upd, o.rtol, delta, s));
-      DOT_TRY(launch_elt<E_REPLACE>(ef, s));
-      DOT_TRY(launch_fin(mg ? F_REPLACE_MG : F_REPLACE, G, ws, ws.st.upd, o.rtol, delta, s));
+      DOT_TRY(launch_fin(mg ? F_REPLACE_MG : F_REPLACE, G, ws, ws.st.upd, o.rtol, delta, s, 1, 1));
     }
     if (mg) DOT_TRY(precondition(0));
     if (polled) DOT_TRY(count(true));
