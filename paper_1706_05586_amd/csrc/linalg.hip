@@ -178,10 +178,7 @@ __device__ __forceinline__ void jacobi_angle_1div(double app, double aqq, double
 constexpr int EIG_SMALL = 64;
 
 // One block: A (n x n, lda) -> eigenvalues w (descending) and eigenvectors V.
-// NTH threads: 64 (one wave: its barriers cost nothing, the norms are wave
-// sums) for n <= 32, 256 above.
-template <int NTH>
-__global__ __launch_bounds__(NTH) void symeig_small_kernel(int n, const double* __restrict__ Ain,
+__global__ __launch_bounds__(256) void symeig_small_kernel(int n, const double* __restrict__ Ain,
                                                            int lda, double* __restrict__ w,
                                                            double* __restrict__ Vout, int ldv,
                                                            int max_sweeps, int* sweeps_out) {
@@ -189,10 +186,10 @@ __global__ __launch_bounds__(NTH) void symeig_small_kernel(int n, const double* 
   __shared__ double v[EIG_SMALL][EIG_SMALL + 1];
   __shared__ double cs[EIG_SMALL / 2][2];
   __shared__ int pq[EIG_SMALL / 2][2];
-  __shared__ double red[NTH];
+  __shared__ double red[256];
   __shared__ int order[EIG_SMALL];
   const int np = n + (n & 1);
-  for (int e = threadIdx.x; e < np * np; e += NTH) {
+  for (int e = threadIdx.x; e < np * np; e += 256) {
     const int i = e % np, j = e / np;
     a[i][j] = (i < n && j < n) ? Ain[i + (int64_t)lda * j] : 0.0;
     v[i][j] = i == j ? 1.0 : 0.0;
@@ -201,39 +198,28 @@ __global__ __launch_bounds__(NTH) void symeig_small_kernel(int n, const double* 
   int sweep = 0;
   for (; sweep < max_sweeps; ++sweep) {
     double off = 0.0, tot = 0.0;
-    for (int e = threadIdx.x; e < n * n; e += NTH) {
+    for (int e = threadIdx.x; e < n * n; e += 256) {
       const int i = e % n, j = e / n;
       const double x = a[i][j] * a[i][j];
       tot += x;
       if (i != j) off += x;
     }
-    double offs, tots;
-    if constexpr (NTH == 64) {
-#pragma unroll
-      for (int o = 32; o >= 1; o >>= 1) {
-        off += __shfl_xor(off, o, 64);
-        tot += __shfl_xor(tot, o, 64);
-      }
-      offs = off;
-      tots = tot;
-    } else {
-      red[threadIdx.x] = off;
-      __syncthreads();
-      for (int s = NTH / 2; s >= 1; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
-      }
-      offs = red[0];
-      __syncthreads();
-      red[threadIdx.x] = tot;
-      __syncthreads();
-      for (int s = NTH / 2; s >= 1; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
-      }
-      tots = red[0];
+    red[threadIdx.x] = off;
+    __syncthreads();
+    for (int s = 128; s >= 1; s >>= 1) {
+      if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
       __syncthreads();
     }
+    const double offs = red[0];
+    __syncthreads();
+    red[threadIdx.x] = tot;
+    __syncthreads();
+    for (int s = 128; s >= 1; s >>= 1) {
+      if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    const double tots = red[0];
+    __syncthreads();
     if (!(offs > 1e-30 * tots) || offs == 0.0) break;
     for (int round = 0; round < np - 1; ++round) {
       if ((int)threadIdx.x < np / 2) {
@@ -248,7 +234,7 @@ __global__ __launch_bounds__(NTH) void symeig_small_kernel(int n, const double* 
       }
       __syncthreads();
       // columns: A <- A J, V <- V J
-      for (int e = threadIdx.x; e < (np / 2) * np; e += NTH) {
+      for (int e = threadIdx.x; e < (np / 2) * np; e += 256) {
         const int k = e / np, r = e % np;
         const int p = pq[k][0], q = pq[k][1];
         const double c = cs[k][0], s = cs[k][1];
@@ -261,7 +247,7 @@ __global__ __launch_bounds__(NTH) void symeig_small_kernel(int n, const double* 
       }
       __syncthreads();
       // rows: A <- J^T A
-      for (int e = threadIdx.x; e < (np / 2) * np; e += NTH) {
+      for (int e = threadIdx.x; e < (np / 2) * np; e += 256) {
         const int k = e / np, r = e % np;
         const int p = pq[k][0], q = pq[k][1];
         const double c = cs[k][0], s = cs[k][1];
@@ -285,11 +271,11 @@ __global__ __launch_bounds__(NTH) void symeig_small_kernel(int n, const double* 
     if (sweeps_out) *sweeps_out = sweep;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < n * n; e += NTH) {
+  for (int e = threadIdx.x; e < n * n; e += 256) {
     const int r = e % n, j = e / n;
     Vout[r + (int64_t)ldv * j] = v[r][order[j]];
   }
-  for (int j = threadIdx.x; j < n; j += NTH) w[j] = a[order[j]][order[j]];
+  for (int j = threadIdx.x; j < n; j += 256) w[j] = a[order[j]][order[j]];
 }
 
 // Larger n: block Jacobi.  The (padded) index range is cut into blocks of
@@ -645,11 +631,7 @@ static size_t symeig_work_bytes(int n) {
 static int symeig(int n, const double* A, int lda, double* w, double* V, int ldv, char* work,
                   hipStream_t s, int max_sweeps, int* sweeps) {
   if (n <= EIG_SMALL) {
-if (n <= 32)
-      hipLaunchKernelGGL(symeig_small_kernel<64>, dim3(1), dim3(64), 0, s, n, A, lda, w, V, ldv,
-                       max_sweeps, (int*)nullptr);
-    else
-      hipLaunchKernelGGL(symeig_small_kernel<256>, dim3(1), dim3(256), 0, s, n, A, lda, w, V, ldv,
+    hipLaunchKernelGGL(symeig_small_kernel, dim3(1), dim3(256), 0, s, n, A, lda, w, V, ldv,
                        max_sweeps, (int*)nullptr);
     DOT_LAUNCH_CHECK();
     if (sweeps) *sweeps = -1;
