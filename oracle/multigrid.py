@@ -17,7 +17,8 @@ with this plain implementation.  The reading, written out:
         prolongation  x^_l += S_l P S_{l+1}^-1 x^_{l+1}
         restriction   b^_{l+1} = S_{l+1}^-1 P^T S_l r^_l
   * one cycle on level l with right-hand side b, J(v) = v + w (b - A^ v)
-    the damped Jacobi step and nu = NU0 on level 0, NU1 below:
+    the damped Jacobi step and nu = NU0 on level 0, NU1 on level 1, NU2
+    below:
         x = J applied nu - 1 times to w b;
         b_{l+1} = restriction of (b - A^ x);  x_{l+1} = cycle(b_{l+1});
         result: J applied nu times to x + prolongation of x_{l+1}
@@ -40,7 +41,8 @@ from . import discretization as disc
 
 OMEGA = 0.85
 NU0 = 2
-NU1 = 4
+NU1 = 3
+NU2 = 5
 NU_C = 8
 
 
@@ -99,7 +101,7 @@ def vcycle_scaled(levels: list, b: np.ndarray, level: int = 0) -> np.ndarray:
             x = x + OMEGA * (b - Ah @ x)
         return x
     C = levels[level + 1]
-    nu = NU0 if level == 0 else NU1
+    nu = NU0 if level == 0 else (NU1 if level == 1 else NU2)
     x = OMEGA * b
     for _ in range(nu - 1):
         x = x + OMEGA * (b - Ah @ x)

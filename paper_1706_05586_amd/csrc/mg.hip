@@ -45,10 +45,13 @@ constexpr int MRG = 4;                  // columns per block
 constexpr int MG_NU_C = 8;              // Jacobi steps on the coarsest level
 
 constexpr int MG_NU0 = 2;               // smoothing steps each way on the finest level
-constexpr int MG_NU1 = 4;               // ... and on the coarser levels above the coarsest
+constexpr int MG_NU1 = 3;               // ... on level 1
+constexpr int MG_NU2 = 5;               // ... and on the coarser levels above the coarsest
 #define MG_OMEGA 0.85
 
-static inline int mg_nu(int level) { return level == 0 ? MG_NU0 : MG_NU1; }
+__host__ __device__ inline int mg_nu(int level) {
+  return level == 0 ? MG_NU0 : (level == 1 ? MG_NU1 : MG_NU2);
+}
 
 // MG_DOWN: restriction of the residual of the staged iterate;
 // MG_SMOOTH: one damped Jacobi step from the staged iterate
@@ -385,6 +388,7 @@ struct MgTailLevel {
   const double* sd;  // sqrt(diag)
   const T* q;        // prolongation weights (all but the coarsest)
   int off;           // LDS element offset of b; the iterates follow at off + N, off + 2 N
+  int nu;            // smoothing steps each way
 };
 
 template <typename T>
@@ -468,7 +472,7 @@ __global__ __launch_bounds__(MG_TAIL_THREADS) void mg_tail_kernel(MgTailArgs<T> 
     prepare(L);
     jstep(L, b, nullptr, buf[0]);
     int cur = 0;
-    for (int s = 1; s < MG_NU1; ++s) {
+    for (int s = 1; s < L.nu; ++s) {
       jstep(L, b, buf[cur], buf[cur ^ 1]);
       cur ^= 1;
     }
@@ -526,7 +530,7 @@ __global__ __launch_bounds__(MG_TAIL_THREADS) void mg_tail_kernel(MgTailArgs<T> 
     __syncthreads();
     prepare(L);
     int cur = xi ^ 1;
-    for (int s = 0; s < MG_NU1; ++s) {
+    for (int s = 0; s < L.nu; ++s) {
       jstep(L, b, buf[cur], buf[cur ^ 1]);
       cur ^= 1;
     }
@@ -695,6 +699,7 @@ int mg_vcycle(dot_op* op, const MgWork<T>& w, int k, const T* r0, int64_t ld0, T
       d.sd = L.sd;
       d.q = MgCoef<T>::q(L);
       d.off = off;
+      d.nu = mg_nu(t0 + i);
       off += 3 * d.N;
     }
     ta.k = k;

@@ -107,3 +107,19 @@ def test_pcg_iterations_far_below_jacobi():
     assert np.linalg.norm(b - A @ xm) <= 1e-10 * np.linalg.norm(b)
     assert np.linalg.norm(xm - xj) <= 1e-8 * np.linalg.norm(xj)
     assert itm * 8 <= itj, (itm, itj)
+
+
+def test_four_level_cycle_symmetric_positive():
+    """On a grid with four levels (every smoothing count in use) the cycle is
+    still symmetric and positive: u^T M v = v^T M u and v^T M v > 0 for
+    random u, v."""
+    n = (32, 32, 32)
+    bc = (DIRICHLET, DIRICHLET, DIRICHLET, ROBIN, ROBIN, ROBIN)
+    D, mu = smooth_fields(n, 3)
+    lv = omg.hierarchy(n, bc, D, mu)
+    assert len(lv) == 4
+    rng = np.random.default_rng(9)
+    u, v = rng.standard_normal((2, lv[0]["sd"].size))
+    Mu, Mv = omg.apply(lv, u), omg.apply(lv, v)
+    assert abs(u @ Mv - v @ Mu) <= 1e-13 * abs(u @ Mv)
+    assert v @ Mv > 0.0 and u @ Mu > 0.0
