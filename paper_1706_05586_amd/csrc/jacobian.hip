@@ -858,6 +858,40 @@ __global__ __launch_bounds__(256) void grad_cell_kernel(GridDims g, JacParams P,
   sc[c] = s;
 }
 
+// The same sums with each Z[c, j] loaded once (l_s <= MAXS): lam[i] is
+// accumulated over j in the same order, so the result is identical.
+template <int MAXS>
+__global__ __launch_bounds__(256) void grad_cell_small_kernel(GridDims g, JacParams P,
+                                                              const double* __restrict__ phi,
+                                                              int l_s, const double* __restrict__ U,
+                                                              int l_d, const double* __restrict__ Z,
+                                                              const double* __restrict__ Rs,
+                                                              double* __restrict__ sc) {
+  extern __shared__ double sR[];  // l_d x l_s
+  for (int t = threadIdx.x; t < l_d * l_s; t += blockDim.x) sR[t] = Rs[t];
+  __syncthreads();
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= g.N) return;
+  if (fabs(phi[c] - P.cutoff) > P.eps) {
+    sc[c] = 0.0;
+    return;
+  }
+  double lam[MAXS];
+#pragma unroll
+  for (int i = 0; i < MAXS; ++i) lam[i] = 0.0;
+  for (int j = 0; j < l_d; ++j) {
+    const double zj = Z[c + P.N * j];
+#pragma unroll
+    for (int i = 0; i < MAXS; ++i)
+      if (i < l_s) lam[i] += zj * sR[j + l_d * i];
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < MAXS; ++i)
+    if (i < l_s) s += U[c + P.N * i] * lam[i];
+  sc[c] = s;
+}
+
 __global__ __launch_bounds__(256) void grad_chunk_kernel(int na, const int32_t* __restrict__ pair_cell,
                                                          const double* __restrict__ pair_g,
                                                          const int64_t* __restrict__ chunk_begin,
@@ -1168,9 +1202,14 @@ int dot_grad_misfit(dot_op* op, int l_s, const double* U_dev, int l_d, const dou
   const int m0 = op->pals.m0;
   double* sc = (double*)work_dev;
   double* partial = sc + ((op->g.N + 31) / 32) * 32;
-  hipLaunchKernelGGL(grad_cell_kernel, dim3((unsigned)((op->g.N + 255) / 256)), dim3(256),
-                     (size_t)l_s * l_d * sizeof(double), s, op->g, P, op->phi, l_s, U_dev, l_d,
-                     Z_dev, Rs_dev, sc);
+  if (l_s <= 32)
+    hipLaunchKernelGGL(grad_cell_small_kernel<32>, dim3((unsigned)((op->g.N + 255) / 256)), dim3(256),
+                       (size_t)l_s * l_d * sizeof(double), s, op->g, P, op->phi, l_s, U_dev, l_d,
+                       Z_dev, Rs_dev, sc);
+  else
+    hipLaunchKernelGGL(grad_cell_kernel, dim3((unsigned)((op->g.N + 255) / 256)), dim3(256),
+                       (size_t)l_s * l_d * sizeof(double), s, op->g, P, op->phi, l_s, U_dev, l_d,
+                       Z_dev, Rs_dev, sc);
   DOT_LAUNCH_CHECK();
   if (op->n_chunks > 0) {
     hipLaunchKernelGGL(grad_chunk_kernel, dim3((unsigned)op->n_chunks), dim3(256), 0, s, na,
