@@ -193,9 +193,10 @@ size_t dot_solve_workspace_bytes(const dot_op* op, int k, int precision);
  * ||b||_2, on the symmetrically Jacobi-scaled system.  Preconditioner
  * (opts.precond): a geometric multigrid V-cycle on 3D grids whose sides
  * halve down to at least 4 cells (2 x 2 x 2 aggregation, the same
- * finite-volume operator on every level with D and mu averaged, one damped
- * Jacobi pre- and post-smoothing step, piecewise-constant transfers, damped
- * Jacobi steps on the coarsest level), or the Jacobi scaling alone.  The
+ * finite-volume operator on every level with D and mu averaged, damped
+ * Jacobi smoothing with w = 0.85, 2 steps each way on the finest level, 3 on
+ * the next and 5 below, piecewise-constant transfers, 8 damped Jacobi steps
+ * on the coarsest level), or the Jacobi scaling alone.  The
  * hierarchy is rebuilt by dot_build_operator, dot_set_mua and dot_pals_mua.
  * DOT_MIXED runs the CG recurrences (stencil,
  * vectors) in binary32 inside binary64 iterative refinement: the binary32
@@ -203,6 +204,9 @@ size_t dot_solve_workspace_bytes(const dot_op* op, int k, int precision);
  * recomputed in binary64 and replaces the binary32 one whenever the latter
  * has dropped by inner_rtol (the search direction is kept); convergence is
  * decided on the binary64 residual; the V-cycle then runs in binary32.
+ * The host reads the column flags every check_every iterations, one such
+ * poll late: iterations launched after the last column converged run with
+ * every column masked off.
  * rhs_dev, x_dev: N x k, must not overlap.  work_dev: >= the size from
  * dot_solve_workspace_bytes, 256-byte aligned.  Synchronizes the stream.
  * Returns DOT_OK, DOT_NOT_CONVERGED (outputs valid), or an error.
@@ -278,7 +282,9 @@ int dot_grad_misfit(dot_op* op, int l_s, const double* U_dev, int l_d, const dou
  * and the contraction; dot_profile_read returns, for one kernel kind, the
  * summed event time (ms), the number of launches and the sum over launches
  * of the number of active columns each launch processed (a contraction
- * launch counts 1).  Reading synchronizes the device.
+ * launch counts 1).  Solver launches that found no active column (those
+ * queued after convergence) are left out of all three.  Reading
+ * synchronizes the device.
  */
 #define DOT_PROF_PCG1_FP64 0   /* CG pass 1 (p = r + beta p, A p, p.Ap), binary64 */
 #define DOT_PROF_PCG2_FP64 1   /* CG pass 2 (A p, x += alpha p, r -= alpha A p, norms) */
