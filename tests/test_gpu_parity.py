@@ -391,3 +391,48 @@ def test_jacobian_split_bf16_error(dotlib, dev, name):
     print(f"{name}: split-bf16 rel err {e2:.3e}, 3-part {e3:.3e}")
     assert e2 <= 2e-5
     assert e3 <= 1e-6
+
+
+@pytest.mark.parametrize("check_every", [1, 2])
+def test_mixed_multigrid_iteration_cap(dotlib, dev, check_every):
+    """Binary32 CG with the multigrid preconditioner stopped by the iteration
+    cap: the flags are read one poll late and the last correction is folded
+    into x at the end, so the returned x carries every iteration (its
+    residual, recomputed by the oracle's operator, is far below the first
+    one's and equals the reported one) and the status is "not converged"."""
+    wl, prob, W, V, data, ref = case("t3d_b")
+    op, grid, pals, th = gpu_operator(dotlib, dev, wl)
+    with op:
+        op.pals_mua(pals, th)
+        assert op.multigrid_levels == 3
+        rhs = np.hstack([ref["BW"], ref["CV"]])
+        with pytest.warns(dotlib.NotConverged):
+            capped = op.solve(torch.tensor(rhs, device=dev), rtol=1e-14, max_iter=3,
+                              precision=dotlib.DOT_MIXED, check_every=check_every)
+        X = capped.x.cpu().numpy()
+    assert not capped.converged and capped.iters_max == 3
+    true_rel = osol.relative_residuals(ref["A"], X, rhs)
+    assert np.allclose(true_rel, capped.relres, rtol=1e-6, atol=1e-15)
+    # the oracle's V-cycle-preconditioned CG after the same 3 iterations
+    from oracle import multigrid as omg
+    A = ref["A"]
+    lv = omg.hierarchy(prob.n, prob.bc, prob.D, prob.mua(wl.theta_ref))
+    want = []
+    for j in range(rhs.shape[1]):
+        b = rhs[:, j]
+        x = np.zeros_like(b)
+        r = b.copy()
+        z = omg.apply(lv, r)
+        p = z.copy()
+        rho = r @ z
+        for _ in range(3):
+            w = A @ p
+            al = rho / (p @ w)
+            x += al * p
+            r -= al * w
+            z = omg.apply(lv, r)
+            rn = r @ z
+            p = z + (rn / rho) * p
+            rho = rn
+        want.append(np.linalg.norm(b - A @ x) / np.linalg.norm(b))
+    assert np.allclose(true_rel, want, rtol=1e-3), (true_rel.max(), max(want))
