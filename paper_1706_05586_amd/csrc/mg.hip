@@ -193,12 +193,16 @@ __global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T> a) {
     T xc[MRG];
     T q;
   };
-  auto load_raw = [&](int64_t c, int64_t p, Raw& o) {
+  // with_xc false: the plane has the parent plane of the previous one, whose
+  // coarse values o.xc still holds (block-uniform)
+  auto load_raw = [&](int64_t c, int64_t p, Raw& o, bool with_xc) {
 #pragma unroll
     for (int r = 0; r < MRG; ++r) {
       o.v[r] = mg_ld(a.b, c + a.ld * col[r]);
       if constexpr (HX) o.x[r] = mg_ld(a.x, c + a.ld * col[r]);
-      if constexpr (HC) o.xc[r] = mg_ld(a.xc, p + a.cld * col[r]);
+      if constexpr (HC) {
+        if (with_xc) o.xc[r] = mg_ld(a.xc, p + a.cld * col[r]);
+      }
     }
     if constexpr (HC) o.q = mg_ld(a.q, c);
   };
@@ -214,20 +218,21 @@ __global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T> a) {
   };
 
   T vm[MRG], vc[MRG], bcur[MRG];
+  Raw pr;  // own cell, plane z + 1 (its coarse values carried between planes)
   {
-    Raw om, oc;
+    Raw om;
     const int zm = z0 > 0 ? z0 - 1 : z0;
-    load_raw(base + zm * G.nxy, pbase + (zm >> 1) * G.cnxy, om);
-    load_raw(base + z0 * G.nxy, pbase + (z0 >> 1) * G.cnxy, oc);
+    load_raw(base + zm * G.nxy, pbase + (zm >> 1) * G.cnxy, om, true);
+    load_raw(base + z0 * G.nxy, pbase + (z0 >> 1) * G.cnxy, pr, true);
 #pragma unroll
     for (int r = 0; r < MRG; ++r) {
       vm[r] = (z0 > 0 && in) ? staged(om, r) : T(0);
-      vc[r] = in ? staged(oc, r) : T(0);
-      bcur[r] = oc.v[r];
+      vc[r] = in ? staged(pr, r) : T(0);
+      bcur[r] = pr.v[r];
     }
   }
   Raw hr;  // halo cell, plane z
-  load_raw(hbase + z0 * G.nxy, phbase + (z0 >> 1) * G.cnxy, hr);
+  load_raw(hbase + z0 * G.nxy, phbase + (z0 >> 1) * G.cnxy, hr, true);
   T cD = z0 > 0 ? mg_ld(a.sz, base + (z0 - 1) * G.nxy) : T(0);
   T sdc_next = T(1);
   T zacc[MRG];
@@ -251,8 +256,8 @@ __global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T> a) {
     }
     // loads for after the barrier: own cell of plane z + 1, this plane's
     // right-hand side and coefficients; then the halo of plane z + 1
-    Raw pr;
-    load_raw(base + zu * G.nxy, pbase + (zu >> 1) * G.cnxy, pr);
+    const bool new_parent = (zu >> 1) != (z >> 1);
+    load_raw(base + zu * G.nxy, pbase + (zu >> 1) * G.cnxy, pr, new_parent);
     const bool has_w = in && x > 0, has_s = in && y > 0;
     const T cE = mg_ld(a.sx, c);
     const T cWl = mg_ld(a.sx, has_w ? c - 1 : c);
@@ -264,7 +269,7 @@ __global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T> a) {
     // odd plane's write
     if (MODE == MG_DOWN && (z & 1) == 0)
       sdc_next = (T)mg_ld(a.sdc, in ? (x >> 1) + (int64_t)G.cnx * (y >> 1) + G.cnxy * (z >> 1) : 0);
-    load_raw(hbase + zu * G.nxy, phbase + (zu >> 1) * G.cnxy, hr);
+    load_raw(hbase + zu * G.nxy, phbase + (zu >> 1) * G.cnxy, hr, new_parent);
     __syncthreads();
     const T cW = has_w ? cWl : T(0);
     const T cS = has_s ? cSl : T(0);
