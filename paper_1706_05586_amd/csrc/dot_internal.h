@@ -71,6 +71,7 @@ struct MgLevel {
   double* b0 = nullptr;
   double* diag = nullptr;
   double* sd = nullptr;    // sqrt(diag)
+  float* sd32 = nullptr;   // sd rounded to binary32 (owned on every level)
   double* sx = nullptr;
   double* sy = nullptr;
   double* sz = nullptr;

@@ -72,8 +72,8 @@ struct MgArgs {
   const T* sx;
   const T* sy;
   const T* sz;
-  const double* sd;    // down: sqrt(diag) of this level
-  const double* sdc;   // down: sqrt(diag) of the coarse level
+  const T* sd;         // down: sqrt(diag) of this level
+  const T* sdc;        // down: sqrt(diag) of the coarse level
   const T* q;          // prolongation: sd / sd_coarse(parent)
   const int* active;   // columns to process (NULL = all)
   const T* b;          // right-hand side of this level (ld)
@@ -264,11 +264,11 @@ __global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T> a) {
     const T cN = mg_ld(a.sy, c);
     const T cSl = mg_ld(a.sy, has_s ? c - G.nx : c);
     const T cU = mg_ld(a.sz, c);
-    const T sdv = MODE == MG_DOWN ? (T)mg_ld(a.sd, c) : T(0);
+    const T sdv = MODE == MG_DOWN ? mg_ld(a.sd, c) : T(0);
     // the aggregate's coarse sqrt(diag), loaded on the even plane for the
     // odd plane's write
     if (MODE == MG_DOWN && (z & 1) == 0)
-      sdc_next = (T)mg_ld(a.sdc, in ? (x >> 1) + (int64_t)G.cnx * (y >> 1) + G.cnxy * (z >> 1) : 0);
+      sdc_next = mg_ld(a.sdc, in ? (x >> 1) + (int64_t)G.cnx * (y >> 1) + G.cnxy * (z >> 1) : 0);
     load_raw(hbase + zu * G.nxy, phbase + (zu >> 1) * G.cnxy, hr, new_parent);
     __syncthreads();
     const T cW = has_w ? cWl : T(0);
@@ -597,6 +597,7 @@ struct MgCoef<double> {
   static const double* sy(const MgLevel& L) { return L.sy; }
   static const double* sz(const MgLevel& L) { return L.sz; }
   static const double* q(const MgLevel& L) { return L.q; }
+  static const double* sd(const MgLevel& L) { return L.sd; }
 };
 template <>
 struct MgCoef<float> {
@@ -604,6 +605,7 @@ struct MgCoef<float> {
   static const float* sy(const MgLevel& L) { return L.sy32; }
   static const float* sz(const MgLevel& L) { return L.sz32; }
   static const float* q(const MgLevel& L) { return L.q32; }
+  static const float* sd(const MgLevel& L) { return L.sd32; }
 };
 
 template <int MODE, bool HX, bool HC, typename T>
@@ -679,8 +681,8 @@ int mg_vcycle(dot_op* op, const MgWork<T>& w, int k, const T* r0, int64_t ld0, T
     }
     pre[l] = x;
     MgArgs<T> a = args(l);
-    a.sd = op->mg[l].sd;
-    a.sdc = op->mg[l + 1].sd;
+    a.sd = MgCoef<T>::sd(op->mg[l]);
+    a.sdc = MgCoef<T>::sd(op->mg[l + 1]);
     a.x = x;
     a.bc = w.b[l + 1];
     if (x) mg_launch<MG_DOWN, true, false>(a, groups, s);

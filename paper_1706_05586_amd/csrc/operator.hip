@@ -349,6 +349,11 @@ __global__ void mg_q_kernel(GridDims gf, GridDims gc, const double* __restrict__
   q32[c] = (float)v;
 }
 
+__global__ void mg_round_kernel(int64_t N, const double* __restrict__ v, float* __restrict__ v32) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c < N) v32[c] = (float)v[c];
+}
+
 // flag = 1 if some diagonal entry is not positive (or not finite)
 __global__ void mg_check_kernel(int64_t N, const double* __restrict__ diag, int* __restrict__ flag) {
   const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -387,6 +392,7 @@ void mg_free(dot_op* op) {
       for (void* p : ptrs)
         if (p) (void)hipFree(p);
     }
+    if (L.sd32) (void)hipFree(L.sd32);
     if (L.q) (void)hipFree(L.q);
     if (L.q32) (void)hipFree(L.q32);
     L = MgLevel{};
@@ -431,6 +437,8 @@ int mg_refresh(dot_op* op, hipStream_t s) {
       for (double** p : d64) DOT_HIP(hipMalloc(p, n8));
       for (float** p : d32) DOT_HIP(hipMalloc(p, n4));
     }
+    for (int l = 0; l < n; ++l)
+      DOT_HIP(hipMalloc(&op->mg[l].sd32, (size_t)lv[l].N * sizeof(float)));
     for (int l = 0; l + 1 < n; ++l) {
       DOT_HIP(hipMalloc(&op->mg[l].q, (size_t)lv[l].N * sizeof(double)));
       DOT_HIP(hipMalloc(&op->mg[l].q32, (size_t)lv[l].N * sizeof(float)));
@@ -457,6 +465,12 @@ int mg_refresh(dot_op* op, hipStream_t s) {
     DOT_LAUNCH_CHECK();
     hipLaunchKernelGGL(mg_q_kernel, dim3(nblk(F.g.N, 256)), dim3(256), 0, s, F.g, gc, F.sd, L.sd,
                        F.q, F.q32);
+    DOT_LAUNCH_CHECK();
+  }
+  for (int l = 0; l < n; ++l) {
+    const MgLevel& L = op->mg[l];
+    hipLaunchKernelGGL(mg_round_kernel, dim3(nblk(L.g.N, 256)), dim3(256), 0, s, L.g.N, L.sd,
+                       L.sd32);
     DOT_LAUNCH_CHECK();
   }
   // the V-cycle is a valid (positive definite) preconditioner only if every
