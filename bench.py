@@ -56,8 +56,8 @@ TRAFFIC = {
     "sources": ("paper_1706_05586_amd/csrc/solve.hip",),
     "sha256": "012b47953557bbfc08522b98cfd08eb6e9128a34dd7f3a132ab2107f644e02bf",
     "config": "C3",
-    "pcg2_fp32_bytes_per_launch": 1825300000.0,
-    "pcg1_fp32_bytes_per_launch": 1409700000.0,
+    "pcg2_fp32_bytes_per_launch": 1825000000.0,
+    "pcg1_fp32_bytes_per_launch": 1408600000.0,
 }
 
 
