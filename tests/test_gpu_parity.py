@@ -436,3 +436,38 @@ def test_mixed_multigrid_iteration_cap(dotlib, dev, check_every):
             rho = rn
         want.append(np.linalg.norm(b - A @ x) / np.linalg.norm(b))
     assert np.allclose(true_rel, want, rtol=1e-3), (true_rel.max(), max(want))
+
+
+def test_multigrid_refreshed_by_new_parameters(dotlib, dev):
+    """A second dot_pals_mua on the same operator rebuilds every level of the
+    hierarchy (coefficients, sqrt(diag) in both precisions, prolongation
+    weights): an iteration-capped mixed multigrid solve after it equals the
+    same solve on a fresh operator built for the new parameters, and differs
+    from the solve before the update."""
+    wl, prob, W, V, data, ref = case("t3d_b")
+    rhs = torch.tensor(np.hstack([ref["BW"], ref["CV"]]), device=dev)
+
+    def capped(op):
+        with pytest.warns(dotlib.NotConverged):
+            return op.solve(rhs, rtol=1e-14, max_iter=3, precision=dotlib.DOT_MIXED,
+                            precond=dotlib.DOT_PRECOND_MG).x.cpu().numpy()
+
+    op, grid, pals, th = gpu_operator(dotlib, dev, wl)
+    # moved RBF centres: a different absorption on every level
+    th2 = th.clone().reshape(-1, 2 + grid.dim)
+    th2[:, 2:] += 0.05
+    th2 = th2.reshape(-1)
+    with op:
+        op.pals_mua(pals, th)
+        X1 = capped(op)
+        op.pals_mua(pals, th2)
+        X2 = capped(op)
+    fresh, *_ = gpu_operator(dotlib, dev, wl)
+    with fresh:
+        fresh.pals_mua(pals, th2)
+        Xf = capped(fresh)
+    scale = np.linalg.norm(Xf)
+    print(f"[mg refresh] |X2 - Xf| {np.linalg.norm(X2 - Xf) / scale:.2e} "
+          f"|X1 - Xf| {np.linalg.norm(X1 - Xf) / scale:.2e}", flush=True)
+    assert np.linalg.norm(X2 - Xf) <= 1e-12 * scale
+    assert np.linalg.norm(X1 - Xf) > 1e-4 * scale
