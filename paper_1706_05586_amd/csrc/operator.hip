@@ -349,6 +349,7 @@ __global__ void mg_q_kernel(GridDims gf, GridDims gc, const double* __restrict__
   q32[c] = (float)v;
 }
 
+// v rounded to binary32
 __global__ void mg_round_kernel(int64_t N, const double* __restrict__ v, float* __restrict__ v32) {
   const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (c < N) v32[c] = (float)v[c];
