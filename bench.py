@@ -10,7 +10,7 @@ hot path:
   PaLS absorption and A(theta) -> B W and C V -> the 40 forward + adjoint
   solves to per-column relative residual 1e-8 (binary32 CG with a multigrid
   V-cycle preconditioner, in binary64 refinement) -> sampled misfit ->
-  split-bfloat16 sampled Jacobian (400 x 320)
+  3-part split-bfloat16 sampled Jacobian (400 x 320)
   -> adjoint gradient -> Alg. 1 + lift + complement (next optimized design)
   -> thin SVD of the sampled Jacobian and the truncated-SVD Gauss-Newton
   step.
@@ -45,6 +45,7 @@ PASS_BYTES = {
     "pcg2_fp32": 20,   # read p, d, r; write d, r    (binary32)
     "pcg1_fp64": 24,
     "pcg2_fp64": 40,
+    "resid": 28,       # binary64 b - A x: read b, x; write r; binary32 residual write
 }
 
 
@@ -87,7 +88,9 @@ def parse():
     ap.add_argument("--no-fp64-leg", action="store_true")
     ap.add_argument("--no-jacobian-leg", action="store_true")
     ap.add_argument("--no-jacobi-leg", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=120)
+    ap.add_argument("--cpu-repeats", type=int, default=3)
+    ap.add_argument("--cpu-baseline-only", action="store_true",
+                    help="only run the CPU baseline of --config and print it as JSON")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB between two device buffers 5 times (reference "
                          "kernel for scaling the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -126,6 +129,22 @@ def main():
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy)
         return
+
+    if args.cpu_baseline_only:
+        import synthetic
+        print(json.dumps(cpu_baseline(synthetic.make_workload(synthetic.get_config(args.config)),
+                                      args.cpu_repeats)), flush=True)
+        return
+
+    # the CPU baseline (oracle on the host, one core) runs in a child process
+    # beside the GPU legs; started before this process touches the GPU
+    cpu_proc = None
+    if not args.no_cpu_baseline:
+        import subprocess
+        cpu_proc = subprocess.Popen(
+            [sys.executable, os.path.abspath(__file__), "--cpu-baseline-only", "--config",
+             args.config, "--cpu-repeats", str(args.cpu_repeats)],
+            stdout=subprocess.PIPE, text=True)
 
     import torch
 
@@ -209,7 +228,7 @@ def main():
         if full_path:
             U, Z = x[:, :ls], x[:, ls:]
             Rs, f = op.sampled_misfit(wl.det_cells, U, V, DW)
-            Js = op.jacobian(U, Z, L.DOT_JAC_SPLIT_BF16)
+            Js = op.jacobian(U, Z, L.DOT_JAC_SPLIT_BF16X3)
             g = op.grad_misfit(U, Z, Rs)
             # the next design (Alg. 1) and the Gauss-Newton model both read
             # J_s only: the design runs on a second stream from a worker
@@ -246,7 +265,8 @@ def main():
     ms2, n2, cols2 = op.profile_read(L.DOT_PROF_PCG2_FP32)
     ms1, n1, cols1 = op.profile_read(L.DOT_PROF_PCG1_FP32)
     msj, nj, _ = op.profile_read(L.DOT_PROF_JACOBIAN)
-    msv, nv, _ = op.profile_read(L.DOT_PROF_VCYCLE_FP32)
+    msv, nv, colsv = op.profile_read(L.DOT_PROF_VCYCLE_FP32)
+    msr, nr, colsr = op.profile_read(L.DOT_PROF_RESID)
     op.profile_enable(False)
     # error of the step's split-bf16 J_s against binary64 on the same fields
     J64 = op.jacobian(x[:, :ls], x[:, ls:], L.DOT_JAC_FP64)
@@ -261,8 +281,26 @@ def main():
     achieved2 = bytes2 / (ms2 * 1e-3) / 1e9 if ms2 > 0 else 0.0
     bytes1 = cols1 * N * PASS_BYTES["pcg1_fp32"]
     achieved1 = bytes1 / (ms1 * 1e-3) / 1e9 if ms1 > 0 else 0.0
+    # the whole solve's HBM-bound kernels: both CG passes, the V-cycles and
+    # the binary64 residual replacements, algorithmic bytes over summed time
+    vbytes = colsv * op.multigrid_cycle_bytes(L.DOT_MIXED)
+    rbytes = colsr * N * PASS_BYTES["resid"]
+    solve_bytes = bytes1 + bytes2 + vbytes + rbytes
+    solve_ms = ms1 + ms2 + msv + msr
+    solve_kernels = {
+        "bytes": solve_bytes, "ms": round(solve_ms, 3),
+        "achieved_gbs": round(solve_bytes / (solve_ms * 1e-3) / 1e9, 1) if solve_ms > 0 else None,
+        "frac": round(solve_bytes / (solve_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if solve_ms > 0 else None,
+        "vcycle_bytes_per_column": op.multigrid_cycle_bytes(L.DOT_MIXED),
+        "vcycle_gbs": round(vbytes / (msv * 1e-3) / 1e9, 1) if msv > 0 else None,
+        "resid_gbs": round(rbytes / (msr * 1e-3) / 1e9, 1) if msr > 0 else None,
+        "what": "CG pass 1 (12 B/cell/col) + pass 2 (20) + V-cycles (vector streams of every "
+                "level kernel) + binary64 residual replacements (28), binary32 vectors; summed "
+                "HIP-event time of those launches over the timed steps",
+    }
 
     # solve-only timing of the mixed form (same 40 RHS) for the comparison
+    solve_ms = None
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     nrep = max(1, args.steps // 2)
@@ -322,8 +360,12 @@ def main():
 
     # ---------------------------------------------------------- CPU baseline
     cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(wl, args.cpu_iters, rj)
+    if cpu_proc is not None:
+        log("[bench] waiting for the CPU baseline")
+        outs, _ = cpu_proc.communicate(timeout=900)
+        if cpu_proc.returncode != 0:
+            raise RuntimeError(f"CPU baseline failed with code {cpu_proc.returncode}")
+        cpu = json.loads(outs.strip().splitlines()[-1])
         log(f"[bench] cpu baseline: {cpu}")
 
     traffic = measured_traffic(cfg.name)
@@ -345,7 +387,7 @@ def main():
                         f"{cfg.n_s} sources / {cfg.n_d} detectors, {ls}+{ld} simultaneous RHS "
                         f"({cfg.q_s} optimized + {ls - cfg.q_s} complementary random each), "
                         f"{cfg.m0} RBFs ({cfg.n_p} params), binary32 CG in binary64 refinement "
-                        "to relres 1e-8; step = PaLS, RHS, solves, misfit, split-bf16 Jacobian, "
+                        "to relres 1e-8; step = PaLS, RHS, solves, misfit, 3-part split-bf16 Jacobian, "
                         "gradient, Alg. 1 design, thin SVD and truncated-SVD Gauss-Newton step",
             "grid": list(cfg.n), "rhs_per_step": k, "rtol": 1e-8, "n_params": cfg.n_p,
         },
@@ -364,6 +406,7 @@ def main():
             "launches": n2,
             "pass1_achieved_gbs": round(achieved1, 1),
             "pass1_avg_launch_us": round(ms1 / max(n1, 1) * 1e3, 2),
+            "solve_kernels": solve_kernels,
         },
         "mixed": {"iters": int(res.iters_max), "updates": int(res.outer),
                   "relres_max": float(res.relres.max()), "ms_per_solve": round(solve_ms, 2),
@@ -386,9 +429,11 @@ def main():
 
 
 def jacobian_leg(dl, L, torch, dev):
-    """1600 x 5000 sampled Jacobian on 128^3 with 1000 RBFs: split-bf16 vs binary64,
-    algorithmic TFLOP/s = 2 l_s l_d n_act (band pairs) / time; error vs binary64
-    and, on a sample of columns, vs the oracle's loop nest."""
+    """1600 x 5000 sampled Jacobian on 128^3 with 1000 RBFs: the 3-part
+    split-bf16 product form, the 2-part option and binary64; algorithmic
+    TFLOP/s = 2 l_s l_d n_act (band pairs) / time, algorithmic HBM bytes =
+    the fields at the band cells read once plus J_s written; error against
+    binary64 on the same fields."""
     import synthetic
 
     cfg = synthetic.get_config("C5")
@@ -403,13 +448,16 @@ def jacobian_leg(dl, L, torch, dev):
     # binary64 solves, so every binary32 CG pass of the run belongs to the
     # timed 128^3, 64-RBF workload
     U, Z = setup_fields(dl, L, torch, dev, cfg, wl, op, pals, W, V, L.DOT_FP64, 1e-8)
-    pairs = op.n_pairs
+    pairs, nband = op.n_pairs, op.n_band_cells
     na = pals.n_act(grid.dim)
     flops = 2.0 * cfg.l_s * cfg.l_d * na * pairs
+    hbm = 8.0 * nband * (cfg.l_s + cfg.l_d) + 8.0 * cfg.l_s * cfg.l_d * cfg.n_p
     out = {"workload": f"C5: 128^3, {cfg.m0} RBFs, {cfg.l_s}x{cfg.l_d} sampled rows, "
-                       f"{cfg.n_p} params", "band_pairs": pairs, "algorithmic_gflop": flops / 1e9}
+                       f"{cfg.n_p} params", "band_pairs": pairs, "band_cells": nband,
+           "algorithmic_gflop": flops / 1e9, "algorithmic_hbm_bytes": hbm,
+           "intensity_flop_per_byte": round(flops / hbm, 1)}
     Js = {}
-    for prec, name in ((L.DOT_JAC_SPLIT_BF16, "split_bf16"), (L.DOT_JAC_SPLIT_BF16X3, "split_bf16x3"),
+    for prec, name in ((L.DOT_JAC_SPLIT_BF16X3, "split_bf16x3"), (L.DOT_JAC_SPLIT_BF16, "split_bf16"),
                        (L.DOT_JAC_FP64, "fp64")):
         Js[name] = op.jacobian(U, Z, prec)
         torch.cuda.synchronize()
@@ -419,71 +467,46 @@ def jacobian_leg(dl, L, torch, dev):
         ms, n, _ = op.profile_read(L.DOT_PROF_JACOBIAN)
         op.profile_enable(False)
         t = ms / n * 1e-3
-        out[name] = {"ms": round(ms / n, 3), "tflops_algorithmic": round(flops / t / 1e12, 3)}
+        out[name] = {"ms": round(ms / n, 3), "tflops_algorithmic": round(flops / t / 1e12, 3),
+                     "hbm_gbs_algorithmic": round(hbm / t / 1e9, 1),
+                     "hbm_frac_algorithmic": round(hbm / t / 1e9 / HBM_PEAK_GBS, 4)}
     ref = Js["fp64"]
-    for name in ("split_bf16", "split_bf16x3"):
+    for name in ("split_bf16x3", "split_bf16"):
         out[name]["rel_err_vs_fp64"] = float(torch.linalg.norm(Js[name] - ref) / torch.linalg.norm(ref))
-    out["split_bf16"]["frac_of_bf16_peak_algorithmic"] = round(
-        out["split_bf16"]["tflops_algorithmic"] / BF16_PEAK_TFLOPS, 5)
+        out[name]["frac_of_bf16_peak_algorithmic"] = round(
+            out[name]["tflops_algorithmic"] / BF16_PEAK_TFLOPS, 5)
+    out["split_bf16x3"]["role"] = "product form (error bound 1e-6)"
+    out["split_bf16"]["role"] = "option (error bound 2e-5)"
     out["fp64"]["frac_of_fp64_peak"] = round(out["fp64"]["tflops_algorithmic"] / FP64_PEAK_TFLOPS, 4)
-    # sampled oracle check on the columns of three RBFs
-    out["sampled_oracle_rel_err"] = sampled_oracle_columns(wl, U, Z, Js["split_bf16"], [0, 417, 999])
     # thin SVD of the 1600 x 5000 sampled Jacobian (Gauss-Newton model)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    s, _, _ = dl.svd_thin(Js["split_bf16"], rcut=1e-10)
+    s, _, _ = dl.svd_thin(Js["split_bf16x3"], rcut=1e-10)
     torch.cuda.synchronize()
     out["svd_1600x5000_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
     op.close()
     return out
 
 
-def sampled_oracle_columns(wl, U, Z, Js, rbfs):
-    """Oracle loop nest for the Jacobian columns of a few RBFs at full size: the
-    columns of h^3 d mu / d p for RBF m on its support box, then the oracle's
-    sparse loop nest on the fields gathered there."""
-    from oracle import discretization as odisc
-    from oracle import estimators as oest
-    from oracle import pals as opals
-
-    cfg = wl.cfg
-    th = wl.theta_ref
-    cols = opals.active_columns(cfg.active, cfg.dim)
-    na = len(cols)
-    n = tuple(cfg.n)
-    h = odisc.spacing(n)
-    errs = []
-    for m in rbfs:
-        R = 1.0 / th[m, 1]
-        lo = np.maximum(0, np.floor((th[m, 2:] - R) / h - 0.5).astype(int))
-        hi = np.minimum(np.array(n) - 1, np.ceil((th[m, 2:] + R) / h - 0.5).astype(int))
-        axes = [np.arange(lo[a], hi[a] + 1) for a in range(3)]
-        gz, gy, gx = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
-        cells = (gx + n[0] * (gy + n[1] * gz)).ravel()
-        x = np.stack([(gx.ravel() + 0.5) * h, (gy.ravel() + 0.5) * h, (gz.ravel() + 0.5) * h], 1)
-        band = (cfg.mu_in - cfg.mu_out) * opals.delta_eps(
-            opals.phi(x, th, cfg.gamma) - cfg.cutoff, cfg.eps)
-        G = h ** 3 * band[:, None] * opals.dphi_dtheta_j(x, th[m], cfg.gamma)[:, cols]
-        keep = np.any(G != 0, axis=1)
-        idx = torch_index(cells[keep], U.device)
-        Jref = oest.jacobian_sparse_loops(U[idx, :].cpu().numpy(), Z[idx, :].cpu().numpy(),
-                                          G[keep])
-        Jgpu = Js[:, m * na:(m + 1) * na].cpu().numpy()
-        errs.append(np.linalg.norm(Jgpu - Jref) / np.linalg.norm(Jref))
-    return float(max(errs))
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
-def torch_index(a, device):
-    import torch
-    return torch.tensor(np.asarray(a, dtype=np.int64), device=device)
+def cpu_baseline(wl, repeats):
+    """The oracle's Jacobi-PCG (scipy CSR SpMV, numpy vector updates) solving
+    one right-hand side of the same workload to relative residual 1e-8,
+    timed end to end, median of `repeats` runs.  BLAS is held to one thread
+    (the CSR product is single-threaded anyway), so the baseline runs on one
+    core; the host's core count and model are recorded beside it."""
+    from threadpoolctl import threadpool_limits
 
-
-def cpu_baseline(wl, iters, jacobi_res):
-    """The oracle's Jacobi-PCG (scipy CSR) on one right-hand side of the same
-    workload, run for a bounded number of iterations and scaled to the
-    iteration count a Jacobi-PCG solve to 1e-8 needs (the GPU's
-    Jacobi-preconditioned count, which follows the oracle's); without that
-    count (the Jacobi leg skipped) the oracle solves to 1e-8 itself."""
     from oracle import estimators as oest
     from oracle import problem as oprob
     from oracle import solvers as osol
@@ -494,21 +517,22 @@ def cpu_baseline(wl, iters, jacobi_res):
     W = oest.sample_matrix(wl.w_signs)
     b = oest.simultaneous_rhs(prob.N, wl.src_cells, W[:, :1])[:, 0]
     t_setup = time.perf_counter() - t0
-    t1 = time.perf_counter()
-    if jacobi_res is not None:
-        _, it, rel = osol.pcg_jacobi(A, b, rtol=1e-30, maxiter=iters)
-        t_it = (time.perf_counter() - t1) / it
-        need = int(jacobi_res.iters_max)
-        how = f"{it} iterations timed ({t_it * 1e3:.1f} ms each), scaled to the {need} iterations"
-    else:
-        _, need, rel = osol.pcg_jacobi(A, b, rtol=1e-8, maxiter=5000)
-        t_it = (time.perf_counter() - t1) / need
-        how = f"solved to 1e-8 in {need} iterations ({t_it * 1e3:.1f} ms each), the iterations"
-    per_rhs = t_it * need
+    times, iters, rels = [], [], []
+    with threadpool_limits(limits=1):
+        for _ in range(repeats):
+            t1 = time.perf_counter()
+            _, it, rel = osol.pcg_jacobi(A, b, rtol=1e-8, maxiter=5000)
+            times.append(time.perf_counter() - t1)
+            iters.append(it)
+            rels.append(rel)
+    per_rhs = float(np.median(times))
     return {"value": round(1.0 / per_rhs, 5), "unit": "RHS/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle Jacobi-PCG (scipy CSR SpMV, one thread) on 1 RHS of the 128^3 "
-                      f"workload: {how} a Jacobi-PCG solve to 1e-8 takes; oracle assembly "
-                      f"({t_setup:.1f} s) not included"}
+            "host_cpus": os.cpu_count(), "host_cpu_model": _cpu_model(),
+            "seconds_per_solve": [round(t, 3) for t in times], "iters": iters[0],
+            "relres": float(rels[0]),
+            "sample": f"oracle Jacobi-PCG (scipy CSR SpMV, one thread) solving 1 of the 40 "
+                      f"RHS of the 128^3 workload to relres 1e-8 ({iters[0]} iterations), "
+                      f"median of {repeats} runs; oracle assembly ({t_setup:.1f} s) not timed"}
 
 
 if __name__ == "__main__":

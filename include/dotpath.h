@@ -72,8 +72,12 @@ extern "C" {
 
 /* Jacobian precision */
 #define DOT_JAC_FP64 0        /* binary64 products and sums */
-#define DOT_JAC_SPLIT_BF16 1  /* hi/lo bfloat16 operands, 3 MFMA products, fp32 accumulate */
-#define DOT_JAC_SPLIT_BF16X3 2  /* hi/mid/lo bfloat16 operands, 6 MFMA products */
+#define DOT_JAC_SPLIT_BF16 1  /* hi/lo bfloat16 operands, 3 MFMA products, fp32 accumulate:
+                                 each product carries a relative error up to about 2^-16,
+                                 so J_s is within 2e-5 relative Frobenius error of binary64
+                                 (a faster option, not within the 1e-6 bound) */
+#define DOT_JAC_SPLIT_BF16X3 2  /* hi/mid/lo bfloat16 operands, 6 MFMA products: binary32-level
+                                 operands, within 1e-6 relative Frobenius error of binary64 */
 
 /* PaLS parameter activity bits */
 #define DOT_ACT_ALPHA 1u
@@ -122,7 +126,8 @@ int dot_abi_version(void);
 /* Thread-local description of the last error ("" if none). */
 const char* dot_last_error(void);
 
-/* Number of cells N of a grid descriptor, or -1 if it is invalid. */
+/* Number of cells N of a grid descriptor, or -1 if it is invalid (at most
+ * 2^29 cells: the solver addresses one binary64 column with 32-bit offsets). */
 int64_t dot_grid_cells(const dot_grid* grid);
 
 /*
@@ -169,6 +174,10 @@ int dot_pals_mua(dot_op* op, const dot_pals* pals, const double* theta_dev, doub
  * the nonzeros of G = h^d d mu / d p per active parameter kind, i.e. the cells
  * the contraction visits summed over RBFs (-1 if no PaLS state). */
 int64_t dot_pals_pairs(const dot_op* op);
+
+/* Number of distinct cells in the band lists of the last dot_pals_mua call:
+ * the rows of U and Z the contraction reads (-1 if no PaLS state). */
+int64_t dot_pals_band_cells(const dot_op* op);
 
 /* Y = A X for k columns (X_dev and Y_dev are N x k and must not overlap). */
 int dot_apply(dot_op* op, int k, const double* X_dev, double* Y_dev, void* stream);
@@ -219,6 +228,13 @@ int dot_solve_multi_rhs(dot_op* op, int trans, int k, const double* rhs_dev, dou
  * when it preconditions with Jacobi (2D grids, sides that do not halve to at
  * least 4 cells, or a level whose diagonal is not positive). */
 int dot_multigrid_levels(const dot_op* op);
+
+/* Algorithmic HBM bytes per column of one V-cycle of the solver's
+ * preconditioner in the given precision (DOT_FP64: binary64 vectors,
+ * DOT_MIXED: binary32): every vector each level's kernels must read or write
+ * once (right-hand sides, iterates, coarse values, results), the operator's
+ * coefficients not counted; 0 without a hierarchy.  For roofline figures. */
+double dot_multigrid_cycle_bytes(const dot_op* op, int precision);
 
 /* Workspace bytes for dot_multigrid_apply with k columns (0 without a hierarchy). */
 size_t dot_multigrid_workspace_bytes(const dot_op* op, int k);

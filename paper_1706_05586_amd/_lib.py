@@ -81,10 +81,12 @@ SIGNATURES = {
     "dot_destroy_operator": (_i, [_vp]),
     "dot_operator_cells": (_i64, [_vp]),
     "dot_pals_pairs": (_i64, [_vp]),
+    "dot_pals_band_cells": (_i64, [_vp]),
     "dot_set_mua": (_i, [_vp, _vp, _vp]),
     "dot_pals_mua": (_i, [_vp, C.POINTER(DotPals), _vp, _vp, _vp]),
     "dot_apply": (_i, [_vp, _i, _vp, _vp, _vp]),
     "dot_multigrid_levels": (_i, [_vp]),
+    "dot_multigrid_cycle_bytes": (_d, [_vp, _i]),
     "dot_multigrid_workspace_bytes": (_sz, [_vp, _i]),
     "dot_multigrid_apply": (_i, [_vp, _i, _vp, _vp, _vp, _sz, _vp]),
     "dot_form_rhs": (_i, [_vp, _i, _pi32, _i, _vp, _vp, _vp]),

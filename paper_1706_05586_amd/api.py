@@ -21,6 +21,7 @@ from . import _lib as L
 from ._lib import check, lib
 
 __all__ = ["Grid", "Pals", "Operator", "SolveResult", "pals_field", "gemm", "colmajor",
+           "check_field_block",
            "empty_colmajor", "mode_gram", "symeig", "qr_complete", "hooi", "svd_thin",
            "tsvd_step", "optimized_design"]
 
@@ -122,6 +123,21 @@ def pals_field(grid: Grid, pals: Pals, theta: torch.Tensor, mus_prime: float | N
                              _ptr(diff) if diff is not None else None, _stream()),
           "dot_pals_field")
     return (mua, diff) if diff is not None else mua
+
+
+def check_field_block(t: torch.Tensor, rows: int, cols: int, name: str = "out"):
+    """A caller-supplied (rows, cols) block that the library writes whole: float64,
+    on the GPU, column-major with leading dimension rows (t.t() contiguous)."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if tuple(t.shape) != (rows, cols):
+        raise ValueError(f"{name} must have shape ({rows}, {cols}), got {tuple(t.shape)}")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64, got {t.dtype}")
+    if not t.t().is_contiguous():
+        raise ValueError(f"{name} must be column-major: {name}.t() contiguous")
+    if not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
 
 
 def _check_colmajor_out(out: torch.Tensor, rows: int, cols: int):
@@ -339,9 +355,18 @@ class Operator:
         return int(lib.dot_pals_pairs(self._handle))
 
     @property
+    def n_band_cells(self) -> int:
+        """Distinct cells of those band lists (rows of U and Z the contraction reads)."""
+        return int(lib.dot_pals_band_cells(self._handle))
+
+    @property
     def multigrid_levels(self) -> int:
         """Levels of the V-cycle hierarchy the solver uses (0: Jacobi)."""
         return int(lib.dot_multigrid_levels(self._handle))
+
+    def multigrid_cycle_bytes(self, precision: int) -> float:
+        """Algorithmic HBM bytes per column of one V-cycle (0: no hierarchy)."""
+        return float(lib.dot_multigrid_cycle_bytes(self._handle, int(precision)))
 
     def multigrid_apply(self, R: torch.Tensor) -> torch.Tensor:
         """One binary64 V-cycle as an approximate inverse of A (N x k in and out)."""
@@ -371,8 +396,7 @@ class Operator:
         if cells.size != n_pts:
             raise ValueError("one cell per weight row")
         if out is not None:
-            if out.shape != (self.N, k) or not out.t().is_contiguous() or out.dtype != torch.float64:
-                raise ValueError("out must be a column-major (N, k) float64 block")
+            check_field_block(out, self.N, k)
             rhs = out
         else:
             rhs = empty_colmajor(self.N, k, self.device)
@@ -390,6 +414,10 @@ class Operator:
               precond: int = L.DOT_PRECOND_AUTO) -> SolveResult:
         Bm = colmajor(rhs, "rhs")
         k = rhs.shape[1]
+        if rhs.shape[0] != self.N:
+            raise ValueError(f"rhs must have {self.N} rows")
+        if out is not None:
+            check_field_block(out, self.N, k)
         x = out if out is not None else empty_colmajor(self.N, k, self.device)
         nbytes = self.solve_workspace_bytes(k, precision)
         if work is None or work.numel() < nbytes or work.data_ptr() % 256:

@@ -189,6 +189,8 @@ struct MgWork {
 size_t mg_work_bytes(const dot_op* op, int k, int64_t ld0, size_t elem);
 template <typename T>
 void mg_work_layout(const dot_op* op, int k, int64_t ld0, char* base, MgWork<T>* w);
+// algorithmic bytes per column of one V-cycle with elements of elem bytes
+double mg_cycle_stream_bytes(const dot_op* op, size_t elem);
 // partial slots per column of the level-0 smoothing kernel (the dot (r, z))
 int mg_partial_slots(const dot_op* op, int k);
 // z0 = V-cycle applied to r0 (both k columns ld0 apart; columns outside

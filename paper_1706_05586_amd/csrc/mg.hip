@@ -614,6 +614,24 @@ static void mg_launch(const MgArgs<T>& a, int groups, hipStream_t s) {
   hipLaunchKernelGGL((mg_level_kernel<MODE, HX, HC, T>), dim3(blocks), dim3(MNT), 0, s, a);
 }
 
+// The coarse tail run by mg_tail_kernel: levels t0 .. nl - 1 (t0 >= 1), the
+// levels of at most MG_TAIL_MAXN cells whose three vectors fit in LDS
+// together; t0 = nl: none, the coarsest level then takes MG_NU_C Jacobi
+// launches.  *tail_bytes receives the LDS bytes of the tail.
+static int mg_tail_start(const dot_op* op, size_t elem, size_t* tail_bytes) {
+  const int nl = op->mg_nlev;
+  int t0 = nl;
+  size_t tb = 0;
+  for (int l = nl - 1; l >= 1; --l) {
+    const size_t bytes = tb + 3 * (size_t)op->mg[l].g.N * elem;
+    if (op->mg[l].g.N > MG_TAIL_MAXN || bytes > MG_TAIL_MAXBYTES) break;
+    tb = bytes;
+    t0 = l;
+  }
+  *tail_bytes = tb;
+  return t0;
+}
+
 template <typename T>
 int mg_vcycle(dot_op* op, const MgWork<T>& w, int k, const T* r0, int64_t ld0, T* z0,
               const int* active, double* partial, hipStream_t s, unsigned long long* prof_cols) {
@@ -641,16 +659,8 @@ int mg_vcycle(dot_op* op, const MgWork<T>& w, int k, const T* r0, int64_t ld0, T
     if (l + 1 < nl) a.cld = w.ld[l + 1];
     return a;
   };
-  // the coarse tail run by mg_tail_kernel: levels t0 .. nl - 1 (t0 >= 1;
-  // t0 = nl: none, the coarsest level then takes MG_NU_C Jacobi launches)
-  int t0 = nl;
   size_t tail_bytes = 0;
-  for (int l = nl - 1; l >= 1; --l) {
-    const size_t bytes = tail_bytes + 3 * (size_t)op->mg[l].g.N * sizeof(T);
-    if (op->mg[l].g.N > MG_TAIL_MAXN || bytes > MG_TAIL_MAXBYTES) break;
-    tail_bytes = bytes;
-    t0 = l;
-  }
+  const int t0 = mg_tail_start(op, sizeof(T), &tail_bytes);
   const int ndown = t0 < nl ? t0 : nl - 1;  // levels with a down and an up pass
   // one smoothing step on level l from x (NULL: w b) plus, with xc, the
   // prolongation of xc; returns the buffer written
@@ -749,6 +759,45 @@ int mg_vcycle(dot_op* op, const MgWork<T>& w, int k, const T* r0, int64_t ld0, T
   }
   return DOT_OK;
 }
+// Algorithmic HBM bytes per column of one V-cycle (mg_vcycle's launches):
+// every vector a level kernel must read or write once, the operator's
+// coefficients (shared by the columns of a block) not counted.  A smoothing
+// step reads b and, except the first, the staged iterate, reads the parent
+// values with the prolongation, and writes its result; the restriction reads
+// b and the iterate and writes the coarse right-hand side; the tail kernel
+// reads its top level's right-hand side and writes its result (the deeper
+// levels live in LDS); the Jacobi steps of a coarsest level without a tail
+// read b and the previous iterate and write.
+double mg_cycle_stream_bytes(const dot_op* op, size_t elem) {
+  const int nl = op->mg_nlev;
+  if (nl < 2) return 0.0;
+  size_t tail_bytes = 0;
+  const int t0 = mg_tail_start(op, elem, &tail_bytes);
+  const int ndown = t0 < nl ? t0 : nl - 1;
+  double v = 0.0;   // vector streams, in cells
+  for (int l = 0; l < ndown; ++l) {
+    const double n = (double)op->mg[l].g.N, nc = (double)op->mg[l + 1].g.N;
+    const int nu = mg_nu(l);
+    bool have_x = false;
+    for (int i = 1; i < nu; ++i) {
+      v += (have_x ? 3.0 : 2.0) * n;
+      have_x = true;
+    }
+    v += (have_x ? 2.0 : 1.0) * n + nc;            // restriction
+    for (int i = 0; i < nu; ++i) {
+      v += (have_x ? 3.0 : 2.0) * n + (i == 0 ? nc : 0.0);
+      have_x = true;
+    }
+  }
+  if (t0 < nl) {
+    v += 2.0 * (double)op->mg[t0].g.N;
+  } else {
+    const double n = (double)op->mg[nl - 1].g.N;
+    v += 2.0 * n + (MG_NU_C - 1) * 3.0 * n;
+  }
+  return v * (double)elem;
+}
+
 template int mg_vcycle<float>(dot_op*, const MgWork<float>&, int, const float*, int64_t, float*,
                               const int*, double*, hipStream_t, unsigned long long*);
 template int mg_vcycle<double>(dot_op*, const MgWork<double>&, int, const double*, int64_t,

@@ -41,8 +41,10 @@ int validate_grid(const dot_grid* g, GridDims* out, const char** why) {
     return DOT_EINVAL;
   }
   const int64_t N = (int64_t)g->n[0] * g->n[1] * nz;
-  if (N > ((int64_t)1 << 31) - 1) {
-    *why = "grid has more than 2^31-1 cells";
+  // the stencil sweeps address a column with 32-bit byte offsets, so a
+  // binary64 column of N cells must span less than 4 GiB
+  if (N > ((int64_t)1 << 29)) {
+    *why = "grid has more than 2^29 cells";
     return DOT_EINVAL;
   }
   for (int f = 0; f < 2 * g->dim; ++f) {
@@ -518,7 +520,9 @@ struct BoxK {
 
 __device__ __forceinline__ void rbf_box(const GridDims& g, const double* th, double gamma, int* lo,
                                         int* ext) {
-  const double beta = th[1];
+  // the support depends on beta^2 only, so its radius uses |beta| (beta = 0
+  // gives an infinite radius: the whole grid)
+  const double beta = fabs(th[1]);
   const double R = sqrt(fmax(0.0, 1.0 - gamma * gamma)) / beta;
   const int n[3] = {g.nx, g.ny, g.nz};
   for (int a = 0; a < 3; ++a) {
@@ -707,6 +711,8 @@ int dot_destroy_operator(dot_op* op) {
 int64_t dot_operator_cells(const dot_op* op) { return op ? op->g.N : -1; }
 
 int64_t dot_pals_pairs(const dot_op* op) { return (op && op->have_pals) ? op->n_pairs : -1; }
+
+int64_t dot_pals_band_cells(const dot_op* op) { return (op && op->have_pals) ? op->n_band : -1; }
 
 int dot_set_mua(dot_op* op, const double* mua_dev, void* stream) {
   clear_error();

@@ -43,38 +43,25 @@
 
 namespace dot {
 
-// Launch geometry (compile-time; the defaults are the tuned values)
-#ifndef DOT_TY
-#define DOT_TY 4
-#endif
-#ifndef DOT_RG64
-#define DOT_RG64 4
-#endif
-#ifndef DOT_RG32
-#define DOT_RG32 4
-#endif
-#ifndef DOT_ZWANT
-#define DOT_ZWANT 2048
-#endif
-#ifndef DOT_ZMIN
-#define DOT_ZMIN 8
-#endif
-#ifndef DOT_PADW
-#define DOT_PADW 1088
-#endif
+// Launch geometry
+constexpr int kTileRows = 4;        // rows per tile
+constexpr int kColsPerBlock = 4;    // columns per block (both precisions)
+constexpr int64_t kZWant = 2048;    // blocks aimed at per column group when choosing z chunks
+constexpr int kZMin = 8;            // fewest planes per z chunk
+constexpr int64_t kColumnPad = 1088;  // work-vector column stride is N + kColumnPad
 constexpr int TX = 64;              // one wave per x row
-constexpr int TY = DOT_TY;          // rows per tile
+constexpr int TY = kTileRows;
 constexpr int NT = TX * TY;
 constexpr int NHALO = 2 * TX + 2 * TY;
 static_assert(NT >= NHALO, "every halo cell of a tile needs a thread of its block");
-constexpr int RG = DOT_RG64;        // columns per block, binary64 sweeps and elementwise passes
+constexpr int RG = kColsPerBlock;  // columns per block, binary64 sweeps and elementwise passes
 template <typename T>
 struct ColsPerBlock {
-  static constexpr int value = DOT_RG64;
+  static constexpr int value = kColsPerBlock;
 };
 template <>
 struct ColsPerBlock<float> {
-  static constexpr int value = DOT_RG32;
+  static constexpr int value = kColsPerBlock;
 };
 
 enum SweepMode { M_APPLY = 0, M_TRUE = 1, M_PCG1 = 2, M_PCG2 = 3, M_RESID = 4 };
@@ -159,25 +146,12 @@ struct SweepArgs {
 // fastest: the blocks of all groups of one tile and z chunk are neighbours in
 // the logical order, so they run together on one XCD and share that tile's
 // coefficient and halo cache lines in its L2.
-#ifndef DOT_HALO_UNCOND
-#define DOT_HALO_UNCOND 1
-#endif
-#ifndef DOT_GROUP_FASTEST
-#define DOT_GROUP_FASTEST 1
-#endif
 __device__ __forceinline__ void block_coords(int logical, const Geom& G, int ngroups, int* tile,
                                              int* zci, int* grp) {
-#if DOT_GROUP_FASTEST
   *grp = logical % ngroups;
   const int rest = logical / ngroups;
   *tile = rest % G.ntiles;
   *zci = rest / G.ntiles;
-#else
-  *tile = logical % G.ntiles;
-  const int rest = logical / G.ntiles;
-  *zci = rest % G.nzc;
-  *grp = rest / G.nzc;
-#endif
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -380,7 +354,6 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs<T> a) {
       }
       if constexpr (MODE == M_RESID || MODE == M_TRUE) bo[r] = ld(bcol[r], c);
     }
-#if DOT_HALO_UNCOND
     {
       const uint32_t hc = hbase + (uint32_t)min(z + 1, G.nz - 1) * nxy;
 #pragma unroll
@@ -389,16 +362,6 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs<T> a) {
         if constexpr (TWO) hr1[r] = ld(in1[r], hc);
       }
     }
-#else
-    if (z + 1 < z1) {
-      const uint32_t hc = hbase + (uint32_t)(z + 1) * nxy;
-#pragma unroll
-      for (int r = 0; r < RG; ++r) {
-        hr0[r] = ld(in0[r], hc);
-        if constexpr (TWO) hr1[r] = ld(in1[r], hc);
-      }
-    }
-#endif
     __syncthreads();
     T vp[RG];
 #pragma unroll
@@ -753,21 +716,21 @@ static Geom make_geom(const GridDims& g, int k) {
   G.nz = g.nz;
   G.nxy = g.nxy;
   G.N = g.N;
-  // work-vector columns DOT_PADW elements apart beyond N, so that the columns
+  // work-vector columns kColumnPad elements apart beyond N, so that the columns
   // of a group and the vectors of one sweep do not sit a power of two apart
-  G.ldw = g.N + DOT_PADW;
+  G.ldw = g.N + kColumnPad;
   G.k = k;
   G.tiles_x = (g.nx + TX - 1) / TX;
   const int tiles_y = (g.ny + TY - 1) / TY;
   G.ntiles = G.tiles_x * tiles_y;
-  // z chunk: aim for DOT_ZWANT blocks of DOT_RG64 columns, chunks of at least
-  // DOT_ZMIN planes.  The chunking does not depend on the column group size,
+  // z chunk: aim for kZWant blocks of kColsPerBlock columns, chunks of at least
+  // kZMin planes.  The chunking does not depend on the column group size,
   // so every kernel of a solve shares the partial slots.
-  const int64_t want = DOT_ZWANT;
-  const int64_t per_z = (int64_t)G.ntiles * n_groups(G, DOT_RG64);
+  const int64_t want = kZWant;
+  const int64_t per_z = (int64_t)G.ntiles * n_groups(G, kColsPerBlock);
   int nzc = (int)std::min<int64_t>(g.nz, std::max<int64_t>(1, (want + per_z - 1) / per_z));
   int zc = (g.nz + nzc - 1) / nzc;
-  zc = std::max(zc, std::min(DOT_ZMIN, g.nz));
+  zc = std::max(zc, std::min(kZMin, g.nz));
   G.zc = zc;
   G.nzc = (g.nz + zc - 1) / zc;
   G.nblk_col = G.ntiles * G.nzc;
@@ -1268,6 +1231,12 @@ int dot_apply(dot_op* op, int k, const double* X_dev, double* Y_dev, void* strea
 
 int dot_multigrid_levels(const dot_op* op) {
   return (op && op->mg_nlev >= 2 && op->mg_ok) ? op->mg_nlev : 0;
+}
+
+double dot_multigrid_cycle_bytes(const dot_op* op, int precision) {
+  if (dot_multigrid_levels(op) == 0 || (precision != DOT_FP64 && precision != DOT_MIXED))
+    return 0.0;
+  return mg_cycle_stream_bytes(op, precision == DOT_FP64 ? sizeof(double) : sizeof(float));
 }
 
 // scaled vectors, r^ and z^, then the V-cycle's work vectors and dot slots

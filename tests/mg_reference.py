@@ -1,15 +1,22 @@
-"""Geometric multigrid V-cycle: the preconditioner of the solver's CG.
+"""Reference model of the solver's multigrid preconditioner (test support).
 
-Test infrastructure only.  Section 3.3 leaves the iterative solver open; the
-GPU solver preconditions its CG with the V-cycle below on 3D grids whose
-sides halve, and the tests compare one application of it element by element
-with this plain implementation.  The reading, written out:
+This is not part of the oracle: the paper leaves the iterative solver open
+(Section 3.3: iterative or sparse direct solvers), so nothing here is the
+paper's arithmetic.  It is a plain scipy model of the geometric multigrid
+V-cycle that this build chose as the preconditioner of its CG, written so
+that the GPU V-cycle can be compared with it element by element and so that
+the design itself (symmetry, definiteness, its effect on CG) can be pinned
+on the CPU.  The solves themselves are checked against the oracle by other
+means: residuals recomputed with the oracle's CSR matrix and the forward
+error against its direct solve.
+
+The design, written out:
 
   * levels: level l + 1 aggregates the 2 x 2 x 2 cells of level l, while
     all three sides are even and the smallest is at least 8; every level is
-    the finite-volume operator of `discretization.assemble` on its own grid,
-    with D and mu the means over the children (so the coarse mass is the sum
-    of the fine masses);
+    the finite-volume operator of `oracle.discretization.assemble` on its own
+    grid, with D and mu the means over the children (so the coarse mass is
+    the sum of the fine masses);
   * each level in the symmetrically scaled form A^_l = S_l^-1 A_l S_l^-1,
     S_l = diag(A_l)^(1/2);
   * transfers with the piecewise-constant prolongation P (a coarse value
@@ -25,11 +32,11 @@ with this plain implementation.  The reading, written out:
     and on the coarsest level NU_C steps J from x = 0, with w = OMEGA;
   * as an approximate inverse of A: M R = S_0^-1 V(S_0^-1 R).
 
-Pinned (tests/test_oracle_multigrid.py) by properties a mistake in a
-transfer, a scaling or the smoothing would break: M is symmetric and
-positive definite (dense on a small grid), M A has a condition number far
-below that of the Jacobi-scaled A, and CG preconditioned with M needs a
-fraction of the iterations of Jacobi-PCG.
+Pinned (tests/test_mg_reference.py) by properties a mistake in a transfer, a
+scaling or the smoothing would break: M is symmetric and positive definite
+(dense on a small grid), M A has a condition number far below that of the
+Jacobi-scaled A, and CG preconditioned with M needs a fraction of the
+iterations of Jacobi-PCG.
 """
 
 from __future__ import annotations
@@ -37,7 +44,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
-from . import discretization as disc
+from oracle import discretization as disc
 
 OMEGA = 0.85
 NU0 = 2

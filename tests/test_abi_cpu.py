@@ -107,3 +107,34 @@ def test_product_path_has_no_oracle_dependency():
             if fn.endswith((".py", ".hip", ".h", ".cpp")):
                 text = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in text and "from oracle" not in text, fn
+
+
+def test_grid_cell_cap(L):
+    """The sweeps address one binary64 column with 32-bit byte offsets: grids
+    of more than 2^29 cells are refused on the host."""
+    assert L.lib.dot_grid_cells(C.byref(_grid(L, n=(1024, 1024, 512)))) == 1 << 29
+    assert L.lib.dot_grid_cells(C.byref(_grid(L, n=(1024, 1024, 513)))) == -1
+    out = C.c_void_p()
+    rc = L.lib.dot_build_operator(C.byref(_grid(L, n=(1024, 1024, 513))), C.c_void_p(1), None,
+                                  C.byref(out))
+    assert rc == L.DOT_EINVAL and b"2^29" in L.lib.dot_last_error()
+
+
+def test_output_block_checks():
+    """Caller-supplied output blocks (solve's out, form_rhs's out) are checked
+    for shape, dtype and column-major layout before the library writes them."""
+    import torch
+
+    from paper_1706_05586_amd.api import check_field_block
+    good = torch.empty((3, 10), dtype=torch.float64).t()          # (10, 3) column-major
+    with pytest.raises(ValueError, match="shape"):
+        check_field_block(good[:9], 10, 3)
+    with pytest.raises(TypeError, match="float64"):
+        check_field_block(torch.empty((3, 10), dtype=torch.float32).t(), 10, 3)
+    with pytest.raises(ValueError, match="column-major"):
+        check_field_block(torch.empty((10, 3), dtype=torch.float64), 10, 3)
+    with pytest.raises(TypeError, match="CUDA"):
+        check_field_block(good, 10, 3)   # layout right, but host memory
+    # a column slice of a column-major block is itself column-major
+    with pytest.raises(TypeError, match="CUDA"):
+        check_field_block(good[:, 1:], 10, 2)

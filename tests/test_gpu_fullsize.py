@@ -4,7 +4,7 @@ times, on outputs the oracle can compute piece by piece:
   * 40-RHS binary32-in-binary64 solve to 1e-8: every column's true relative
     residual recomputed with the oracle's CSR operator;
   * sampled misfit from the GPU fields against the oracle's definition;
-  * binary64 and split-bfloat16 J_s on the columns of sampled RBFs against
+  * binary64 and 3-part split-bfloat16 J_s on the columns of sampled RBFs against
     the oracle's sparse loop nest over that RBF's support box;
   * gradient entries of sampled RBFs against the oracle's adjoint form;
   * 1000-RBF workload: the same Jacobian check at 1600 x 5000, and the thin
@@ -17,10 +17,9 @@ import pytest
 import torch
 
 import synthetic
-from oracle import discretization as odisc
 from oracle import estimators as oest
-from oracle import pals as opals
 from oracle import problem as oprob
+from oracle_columns import support_columns
 
 pytestmark = pytest.mark.gpu
 
@@ -34,28 +33,6 @@ def dl():
 @pytest.fixture(scope="module")
 def dev():
     return torch.device("cuda:0")
-
-
-def support_columns(wl, m):
-    """Cells of RBF m's support box and the oracle's h^3 dmu/dp columns of
-    its active parameters there (rows that are zero are dropped)."""
-    cfg = wl.cfg
-    th = wl.theta_ref
-    cols = opals.active_columns(cfg.active, cfg.dim)
-    n = tuple(cfg.n)
-    h = odisc.spacing(n)
-    R = 1.0 / th[m, 1]
-    lo = np.maximum(0, np.floor((th[m, 2:] - R) / h - 0.5).astype(int))
-    hi = np.minimum(np.array(n) - 1, np.ceil((th[m, 2:] + R) / h - 0.5).astype(int))
-    axes = [np.arange(lo[a], hi[a] + 1) for a in range(3)]
-    gz, gy, gx = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
-    cells = (gx + n[0] * (gy + n[1] * gz)).ravel()
-    x = np.stack([(gx.ravel() + 0.5) * h, (gy.ravel() + 0.5) * h, (gz.ravel() + 0.5) * h], 1)
-    band = (cfg.mu_in - cfg.mu_out) * opals.delta_eps(
-        opals.phi(x, th, cfg.gamma) - cfg.cutoff, cfg.eps)
-    G = h ** 3 * band[:, None] * opals.dphi_dtheta_j(x, th[m], cfg.gamma)[:, cols]
-    keep = np.any(G != 0, axis=1)
-    return cells[keep], G[keep], len(cols)
 
 
 def gpu_setup(dl, dev, name, precision, rtol):
@@ -103,7 +80,7 @@ def test_128cubed_40rhs_mixed_solve_misfit_jacobian_gradient(dl, dev):
         assert np.linalg.norm(Rs.cpu().numpy() - Rs_ref) <= 1e-12 * np.linalg.norm(Rs_ref)
         assert f == pytest.approx(oest.misfit(Rs_ref), rel=1e-12)
         J64 = op.jacobian(U, Z, L.DOT_JAC_FP64).cpu().numpy()
-        J2 = op.jacobian(U, Z, L.DOT_JAC_SPLIT_BF16).cpu().numpy()
+        J3 = op.jacobian(U, Z, L.DOT_JAC_SPLIT_BF16X3).cpu().numpy()
         g = op.grad_misfit(U, Z, Rs).cpu().numpy()
         Rn = Rs.cpu().numpy()
         for m in (0, 21, 42, 63):
@@ -112,12 +89,12 @@ def test_128cubed_40rhs_mixed_solve_misfit_jacobian_gradient(dl, dev):
             Jr = oest.jacobian_sparse_loops(Uc, Zc, G)
             sl = slice(m * na, (m + 1) * na)
             e64 = np.linalg.norm(J64[:, sl] - Jr) / np.linalg.norm(Jr)
-            e2 = np.linalg.norm(J2[:, sl] - Jr) / np.linalg.norm(Jr)
+            e3 = np.linalg.norm(J3[:, sl] - Jr) / np.linalg.norm(Jr)
             gr = oest.gradient_adjoint(Uc, Zc, Rn, G)
             eg = np.linalg.norm(g[sl] - gr) / np.linalg.norm(gr)
-            print(f"[fullsize] C3 RBF {m}: J64 {e64:.2e} split {e2:.2e} grad {eg:.2e}", flush=True)
+            print(f"[fullsize] C3 RBF {m}: J64 {e64:.2e} 3-part {e3:.2e} grad {eg:.2e}", flush=True)
             assert e64 <= 1e-11
-            assert e2 <= 1e-6
+            assert e3 <= 1e-6
             assert eg <= 1e-11
 
 
@@ -132,8 +109,8 @@ def test_1000rbf_jacobian_and_thin_svd(dl, dev):
         J3 = op.jacobian(U, Z, L.DOT_JAC_SPLIT_BF16X3)
         e2 = float(torch.linalg.norm(J2 - J64) / torch.linalg.norm(J64))
         e3 = float(torch.linalg.norm(J3 - J64) / torch.linalg.norm(J64))
-        print(f"[fullsize] C5 split-bf16 {e2:.2e}, 3-part {e3:.2e} vs binary64", flush=True)
-        assert e2 <= 1e-6 and e3 <= 1e-6
+        print(f"[fullsize] C5 3-part {e3:.2e}, 2-part option {e2:.2e} vs binary64", flush=True)
+        assert e3 <= 1e-6 and e2 <= 2e-5
         X = res.x
         J64n = J64.cpu().numpy()
         for m in (0, 417, 999):
@@ -145,9 +122,9 @@ def test_1000rbf_jacobian_and_thin_svd(dl, dev):
             e = np.linalg.norm(J64n[:, sl] - Jr) / np.linalg.norm(Jr)
             print(f"[fullsize] C5 RBF {m}: J64 {e:.2e}", flush=True)
             assert e <= 1e-11
-        s, Us, Ys = dl.svd_thin(J2, rcut=1e-10)
+        s, Us, Ys = dl.svd_thin(J3, rcut=1e-10)
         s, Us, Ys = s.cpu().numpy(), Us.cpu().numpy(), Ys.cpu().numpy()
-        Jn = J2.cpu().numpy()
+        Jn = J3.cpu().numpy()
         m_, n_ = Jn.shape
         assert np.all(np.diff(s) <= 0.0) and s[-1] >= 0.0
         eps = np.finfo(np.float64).eps

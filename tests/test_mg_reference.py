@@ -1,5 +1,5 @@
-"""Pins of the oracle's multigrid V-cycle (the CG preconditioner on 3D grids
-that halve) by properties a mistake in a transfer, a scaling or a smoothing
+"""Pins of the scipy model of the solver's multigrid V-cycle (the CG
+preconditioner this build chose; tests/mg_reference.py) by properties a mistake in a transfer, a scaling or a smoothing
 step breaks: symmetry and positive definiteness of the preconditioner, the
 conditioning of the preconditioned operator, and the CG iteration count.
 """
@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from oracle import discretization as disc
-from oracle import multigrid as omg
+import mg_reference as omg
 
 ROBIN, DIRICHLET = 1, 0
 
