@@ -185,6 +185,11 @@ def test_96cubed_gradient_sampled_columns_and_central_differences(dl, dev):
         order = np.argsort(-np.abs(g))
         sample = [int(k) for k in list(order[:4]) + list(order[100:103]) + list(order[250:252])]
         h = 1e-6
+        # each evaluation of f carries a relative error of about the solver's
+        # tolerance (1e-12), so the central difference has an absolute noise
+        # floor of about 1e-12 |f| / h besides its relative truncation error
+        noise = 1e-12 * abs(f0) / h
+        say(f"[C4 96^3] f {f0:.6e}, central-difference noise floor {noise:.2e}")
         for k in sample:
             e = torch.zeros_like(params)
             e[k] = h
@@ -192,7 +197,7 @@ def test_96cubed_gradient_sampled_columns_and_central_differences(dl, dev):
             fm = dl.misfit(params - e, prob).item()
             fd = (fp - fm) / (2 * h)
             say(f"[C4 96^3] FD param {k}: g {g[k]:.9e} fd {fd:.9e} rel {abs(fd - g[k]) / abs(g[k]):.2e}")
-            assert abs(fd - g[k]) <= 2e-5 * abs(g[k]) + 1e-8 * np.abs(g).max(), (k, fd, g[k])
+            assert abs(fd - g[k]) <= 2e-5 * abs(g[k]) + noise, (k, fd, g[k])
 
 
 def _signs(n):
