@@ -7,14 +7,16 @@ Rademacher signs.  Both the CPU oracle and the HIP path consume exactly the
 arrays produced here.
 """
 
-from .configs import CONFIGS, TEST_CONFIGS, WorkloadConfig, get_config
-from .inputs import Workload, make_workload
+from .configs import CONFIGS, INVERSION_CONFIGS, TEST_CONFIGS, WorkloadConfig, get_config
+from .inputs import Workload, make_workload, sketch_draws
 
 __all__ = [
     "CONFIGS",
     "TEST_CONFIGS",
+    "INVERSION_CONFIGS",
     "WorkloadConfig",
     "get_config",
     "Workload",
     "make_workload",
+    "sketch_draws",
 ]

@@ -59,6 +59,7 @@ class WorkloadConfig:
     rtol: float = 1e-10
     theta_true_alpha_scale: float = 0.25
     theta_true_shift: float = 0.02
+    theta_true_flip: int = 0      # RBFs whose expansion coefficient changes sign in the truth
 
     @property
     def N(self) -> int:
@@ -167,11 +168,43 @@ TEST_CONFIGS = {
 }
 
 
+# Inversion workloads (the outer Gauss-Newton driver of Sections 3.2 and 4).
+# The unit box stands for a 60 mm slab: with x = L x', L = 60 mm, the diffusion
+# equation and its Robin condition keep their form on [0, 1]^3 with D' = D / L
+# and mu' = L mu, which is D = 1 / (3 (mu + mus')) with mu and mus' both scaled
+# by L.  Background absorption 0.01 / mm, anomaly 0.05 / mm and reduced
+# scattering 1 / mm (breast-tissue values) then give a diffusion length of
+# about 6 mm, so absorption anomalies are visible in the data; the initial
+# guess is the reference lattice (Fig. 3 layout: mixed-sign expansion
+# coefficients) and the truth rescales, moves and flips some of its RBFs.
+_L_MM = 60.0
+INVERSION_CONFIGS = {
+    # parity-test size for the driver (the oracle replays it with direct solves)
+    "inv_t": WorkloadConfig(
+        name="inv_t", config_id=201, dim=3, n=(24, 24, 24), bc=_ROBIN_Z, lattice=(3, 3, 3),
+        width=0.3, centre_jitter=0.03, src_lattice=(6, 6), det_lattice=(6, 6), l_s=6, l_d=6,
+        q_s=2, q_d=2, mu_out=0.01 * _L_MM, mu_in=0.05 * _L_MM, mus_prime=1.0 * _L_MM,
+        theta_true_alpha_scale=0.5, theta_true_shift=0.05, theta_true_flip=3, rtol=1e-12,
+    ),
+    # Example 2's shape (table T3): 32^3, 225 sources on top, 225 detectors on
+    # the bottom, 27 RBFs with five parameters each (135), 12 simultaneous
+    # sources and detectors, 2 of them optimized after the SAA phase
+    "inv_x2": WorkloadConfig(
+        name="inv_x2", config_id=202, dim=3, n=(32, 32, 32), bc=_ROBIN_Z, lattice=(3, 3, 3),
+        width=0.3, centre_jitter=0.03, src_lattice=(15, 15), det_lattice=(15, 15), l_s=12,
+        l_d=12, q_s=2, q_d=2, mu_out=0.01 * _L_MM, mu_in=0.05 * _L_MM, mus_prime=1.0 * _L_MM,
+        theta_true_alpha_scale=0.5, theta_true_shift=0.05, theta_true_flip=3, rtol=1e-10,
+    ),
+}
+
+
 def get_config(name: str, **overrides) -> WorkloadConfig:
     if name in CONFIGS:
         cfg = CONFIGS[name]
     elif name in TEST_CONFIGS:
         cfg = TEST_CONFIGS[name]
+    elif name in INVERSION_CONFIGS:
+        cfg = INVERSION_CONFIGS[name]
     else:
         raise KeyError(f"unknown workload {name!r}")
     return replace(cfg, **overrides) if overrides else cfg

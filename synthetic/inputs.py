@@ -75,6 +75,9 @@ def _theta_true(cfg: WorkloadConfig, theta_ref: np.ndarray, rng: np.random.Gener
     theta = theta_ref.copy()
     theta[:, 0] *= 1.0 + rng.uniform(-cfg.theta_true_alpha_scale, cfg.theta_true_alpha_scale, size=cfg.m0)
     theta[:, 2:] += rng.uniform(-cfg.theta_true_shift, cfg.theta_true_shift, size=theta[:, 2:].shape)
+    if cfg.theta_true_flip > 0:
+        # basis functions that change sides (visible <-> invisible) in the truth
+        theta[rng.permutation(cfg.m0)[: cfg.theta_true_flip], 0] *= -1.0
     return theta
 
 
@@ -139,3 +142,21 @@ def make_workload(cfg: WorkloadConfig) -> Workload:
     z = _rademacher(rng[6], (n_d - cfg.q_d, cfg.l_d - cfg.q_d))
     return Workload(cfg=cfg, theta_ref=theta_ref, theta_true=theta_true, src_cells=src,
                     det_cells=det, w_signs=w, v_signs=v, y_signs=y, z_signs=z, xi=xi)
+
+
+def sketch_draws(n_s: int, n_d: int, n_p: int, q_s: int, q_d: int, k: int, sweeps: int,
+                 seed: int) -> dict:
+    """Random test vectors of the sketched optimized design: Rademacher source
+    signs w1 (n_s x k), and standard normal parameter directions t1, t2[s],
+    t3[s] (n_p x k) and coefficient vectors a2[s] (q_d x k), a3[s] (q_s x k)
+    per sweep s.  Raw draws only."""
+    rng = np.random.default_rng(np.random.SeedSequence(BASE_SEED + 7919 * seed))
+    out = {"w1": _rademacher(rng, (n_s, k)).astype(np.float64),
+           "t1": rng.standard_normal((n_p, k)), "a2": [], "t2": [], "a3": [], "t3": []}
+    for _ in range(sweeps):
+        out["a2"].append(rng.standard_normal((q_d, k)))
+        out["t2"].append(rng.standard_normal((n_p, k)))
+        out["a3"].append(rng.standard_normal((q_s, k)))
+        out["t3"].append(rng.standard_normal((n_p, k)))
+    return out
+
