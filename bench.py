@@ -88,6 +88,9 @@ def parse():
     ap.add_argument("--no-fp64-leg", action="store_true")
     ap.add_argument("--no-jacobian-leg", action="store_true")
     ap.add_argument("--no-jacobi-leg", action="store_true")
+    ap.add_argument("--no-inversion-leg", action="store_true")
+    ap.add_argument("--no-frequency-leg", action="store_true")
+    ap.add_argument("--no-diffusion-leg", action="store_true")
     ap.add_argument("--cpu-repeats", type=int, default=3)
     ap.add_argument("--cpu-baseline-only", action="store_true",
                     help="only run the CPU baseline of --config and print it as JSON")
@@ -358,6 +361,24 @@ def main():
         jac = jacobian_leg(dl, L, torch, dev)
         log(f"[bench] jacobian leg: {jac}")
 
+    # ------------------------------------------------ frequency-domain leg
+    frequency = None
+    if not args.no_frequency_leg:
+        frequency = frequency_leg(dl, L, torch, dev, op, cfg, wl, W, V)
+        log(f"[bench] frequency leg: {frequency}")
+
+    # ------------------------------------------------------- diffusion leg
+    diffusion = None
+    if not args.no_diffusion_leg:
+        diffusion = diffusion_leg(dl, L, torch, dev, op, cfg, wl, pals, W, V)
+        log(f"[bench] diffusion leg: {diffusion}")
+
+    # ---------------------------------------------------------- inversion leg
+    inversion = None
+    if not args.no_inversion_leg:
+        inversion = inversion_leg(dl, L, torch, dev)
+        log(f"[bench] inversion leg: {inversion}")
+
     # ---------------------------------------------------------- CPU baseline
     cpu = None
     if cpu_proc is not None:
@@ -422,6 +443,9 @@ def main():
         "step_jacobian_ms": round(msj / max(nj, 1), 3),
         "step_jacobian_rel_err_vs_fp64": jac_err,
         "jacobian": jac,
+        "frequency": frequency,
+        "diffusion": diffusion,
+        "inversion": inversion,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -486,6 +510,159 @@ def jacobian_leg(dl, L, torch, dev):
     out["svd_1600x5000_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
     op.close()
     return out
+
+
+# modulation frequency of the frequency-domain leg: kappa = omega / nu with
+# omega = 2 pi 100 MHz and nu = c / 1.4 in tissue, in the unit box's length unit
+# (1 mm for the 128^3 workload): kappa / mu_out is about 0.3, as in a 60 mm slab
+KAPPA_100MHZ_PER_MM = 2.0 * np.pi * 100e6 / (3.0e11 / 1.4)
+
+
+def frequency_leg(dl, L, torch, dev, op, cfg, wl, W, V, reps=3):
+    """The step's 40 right-hand sides solved at 100 MHz modulation:
+    (A + i kappa h^d I) X = [B W, C V] by COCG with the multigrid V-cycle
+    (binary64, relres 1e-8).  Algorithmic bytes per cell, complex column and
+    iteration: apply 32 (read p, write q), update 96 (read p, q, x, r; write
+    x, r), r^T z 32, direction 48, plus the binary64 V-cycle on both parts."""
+    ls, ld = cfg.l_s, cfg.l_d
+    k = ls + ld
+    N = op.N
+    rhs = torch.zeros((N, k), dtype=torch.complex128, device=dev)
+    rhs[:, :ls] = op.form_rhs(wl.src_cells, W)
+    rhs[:, ls:] = op.form_rhs(wl.det_cells, V)
+    kappa = KAPPA_100MHZ_PER_MM
+    res = op.solve_complex(rhs, kappa, rtol=1e-8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        res = op.solve_complex(rhs, kappa, rtol=1e-8)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    it = int(res.iters_max)
+    per = 32 + 96 + 32 + 48 + 2 * op.multigrid_cycle_bytes(L.DOT_FP64) / N
+    gbs = per * N * k * it / t / 1e9
+    return {"kappa": kappa, "columns_complex": k, "ms_per_solve": round(t * 1e3, 2),
+            "rhs_per_s": round(k / t, 2), "iters": it, "relres_max": float(res.relres.max()),
+            "bytes_per_cell_column_iteration": round(per, 1),
+            "achieved_gbs_algorithmic": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "preconditioner": f"multigrid V-cycle on real and imaginary parts, "
+                              f"{op.multigrid_levels} levels"}
+
+
+def diffusion_leg(dl, L, torch, dev, op, cfg, wl, pals, W, V):
+    """The sampled Jacobian with the diffusion inverted as well (face terms of
+    dA/dp) on the step's fields: scattering contrast 2x inside the anomaly;
+    binary64 and 3-part split-bf16, error of the latter against the former;
+    algorithmic flop = 2 l_s l_d n_act (pairs x 7 rows)."""
+    ls, ld = cfg.l_s, cfg.l_d
+    th = torch.tensor(wl.theta_ref, device=dev)
+    op.pals_mua_diffusion(pals, th, 2.0 * cfg.mus_prime, cfg.mus_prime)
+    rhs = dl.empty_colmajor(op.N, ls + ld, dev)
+    op.form_rhs(wl.src_cells, W, out=rhs[:, :ls])
+    op.form_rhs(wl.det_cells, V, out=rhs[:, ls:])
+    res = op.solve(rhs, rtol=1e-8, precision=L.DOT_MIXED, inner_rtol=0.01, check_every=2)
+    U, Z = res.x[:, :ls], res.x[:, ls:]
+    na = pals.n_act(op.grid.dim)
+    rows = 1 + 2 * op.grid.dim
+    flops = 2.0 * ls * ld * na * op.n_pairs * rows
+    out = {"scattering_in_over_out": 2.0, "solve_iters": int(res.iters_max),
+           "rows_per_pair": rows, "pairs": op.n_pairs, "algorithmic_gflop": flops / 1e9}
+    Js = {}
+    for prec, name in ((L.DOT_JAC_FP64, "fp64"), (L.DOT_JAC_SPLIT_BF16X3, "split_bf16x3")):
+        Js[name] = op.jacobian(U, Z, prec)
+        torch.cuda.synchronize()
+        op.profile_enable(True)
+        for _ in range(3):
+            Js[name] = op.jacobian(U, Z, prec)
+        ms, n, _ = op.profile_read(L.DOT_PROF_JACOBIAN)
+        op.profile_enable(False)
+        out[name] = {"ms": round(ms / n, 3), "tflops_algorithmic": round(flops / (ms / n * 1e-3) / 1e12, 2)}
+    out["split_bf16x3"]["rel_err_vs_fp64"] = float(
+        torch.linalg.norm(Js["split_bf16x3"] - Js["fp64"]) / torch.linalg.norm(Js["fp64"]))
+    op.pals_mua(pals, th)
+    return out
+
+
+# Table T3 of the paper (Example 2: 32^3, 225 sources / 225 detectors, 27
+# RBFs, 135 parameters, l = 12): iterations / function / Jacobian evaluations
+# and total large solves, MATLAB, hardware not stated.
+PAPER_T3 = {"all_sources_detectors": {"it": 25, "fe": 26, "je": 15, "solves": 9225},
+            "saa_to_intermediate_tol": {"it": 4, "fe": 5, "je": 6, "solves": 132},
+            "saa_plus_2_optimized": {"it": 12, "fe": 13, "je": 6, "solves": 726},
+            "saa_plus_4_optimized": {"it": 9, "fe": 10, "je": 3, "solves": 762}}
+
+
+def inversion_leg(dl, L, torch, dev, max_iter=30):
+    """The outer driver on Example 2's shape (32^3 slab of 60 mm, 225 sources on
+    top, 225 detectors at the bottom, 27 RBFs x 5 parameters, l = 12, 2
+    optimized sources and detectors after the SAA phase, 0.1% noise): SAA
+    Gauss-Newton to the intermediate tolerance, the full Jacobian (450
+    solves) with Alg. 1 and the complement, then Gauss-Newton towards the
+    final tolerance; counts beside table T3 and the wall time.  The data come
+    from the library's own binary64 solves at the true parameters; the true
+    misfit of each phase's end point is a check on the side (not counted)."""
+    import synthetic
+
+    cfg = synthetic.get_config("inv_x2")
+    wl = synthetic.make_workload(cfg)
+    grid, pals = dl.Grid.from_config(cfg), dl.Pals.from_config(cfg)
+    T = lambda a: torch.tensor(np.asarray(a, dtype=np.float64), device=dev)  # noqa: E731
+    _, D = dl.pals_field(grid, pals, T(wl.theta_ref), cfg.mus_prime)
+    op = dl.Operator(grid, D)
+    eye_s = torch.eye(cfg.n_s, dtype=torch.float64, device=dev)
+
+    def measurements(theta):
+        op.pals_mua(pals, theta)
+        B = op.form_rhs(wl.src_cells, eye_s)
+        return op.solve(B, rtol=1e-12).x[wl.det_cells.astype(np.int64), :]
+
+    M_true = measurements(T(wl.theta_true))
+    data = M_true * (1.0 + cfg.noise * T(wl.xi))
+    dn2 = float(torch.sum(data * data).item())
+    inv = dl.inversion
+    sd = inv.SampledDOT(op, pals, T(wl.theta_ref), wl.src_cells, wl.det_cells, data,
+                        rtol=cfg.rtol)
+    p0 = sd.params_of(T(wl.theta_ref))
+    opts = inv.TrustRegionOptions(radius0=0.5, max_iter=max_iter)
+
+    def true_rel(p):
+        R = measurements(sd.theta_of(p)) - data
+        return float(torch.sum(R * R).item()) / dn2
+
+    k_sk, sweeps = 8, 2
+    draws = synthetic.sketch_draws(cfg.n_s, cfg.n_d, cfg.n_p, cfg.q_s, cfg.q_d, k_sk, sweeps, 1)
+    draws = {key: ([T(x) for x in v] if isinstance(v, list) else T(v)) for key, v in draws.items()}
+    runs = {}
+    for design, sketch in (("full_jacobian", None), ("sketched", draws)):
+        sd.solves = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = inv.invert(sd, p0, T(wl.w_signs / np.sqrt(cfg.l_s)),
+                         T(wl.v_signs / np.sqrt(cfg.l_d)), cfg.q_s, cfg.q_d, T(wl.y_signs),
+                         T(wl.z_signs), cfg.noise, opts, sketch=sketch)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        phases = {}
+        for name in ("saa", "opt"):
+            ph = out.get(name)
+            if ph is None:
+                continue
+            phases[name] = {"it": ph.it, "fe": ph.fe, "je": ph.je, "converged": ph.converged,
+                            "sampled_rel_misfit": 2.0 * ph.f / dn2,
+                            "true_rel_misfit": true_rel(ph.p)}
+        n_up = cfg.n_s + cfg.n_d if sketch is None else inv.sketch_solves(k_sk, sweeps)
+        runs[design] = {"phases": phases, "update_solves": n_up, "solves": out["solves"],
+                        "solves_counted": out["counted"], "wall_s": round(wall, 3)}
+        log(f"[bench] inversion ({design}): {runs[design]}")
+    res = {"workload": f"inv_x2: 32^3, {cfg.n_s} sources / {cfg.n_d} detectors, {cfg.m0} RBFs "
+                       f"({cfg.n_p} params), l = {cfg.l_s}, {cfg.q_s} optimized after SAA, "
+                       f"delta = {cfg.noise}, binary64 solves to relres {cfg.rtol}",
+           "tolerances_rel_misfit": {"intermediate": cfg.noise, "final": cfg.noise ** 2},
+           "start_true_rel_misfit": true_rel(p0), "max_trial_steps_per_phase": max_iter,
+           "sketch": {"test_vectors": k_sk, "sweeps": sweeps}, "runs": runs,
+           "paper_T3": PAPER_T3}
+    op.close()
+    return res
 
 
 def _cpu_model():

@@ -170,6 +170,27 @@ int dot_set_mua(dot_op* op, const double* mua_dev, void* stream);
 int dot_pals_mua(dot_op* op, const dot_pals* pals, const double* theta_dev, double* mua_dev,
                  void* stream);
 
+/*
+ * Set A(theta) with the diffusion coefficient an unknown as well (Section
+ * 3.3, last paragraph: dA/dp_k then has 5 (2D) or 7 (3D) diagonals).  The
+ * level set describes an anomaly in both optical properties:
+ * mu = mu_out + (mu_in - mu_out) H, mu_s = mus_out + (mus_in - mus_out) H with
+ * H = H_eps(phi - cutoff), and D = 1 / (3 (mu + mu_s)) (the diffusion
+ * approximation) replaces the D given to dot_build_operator.  The face
+ * coefficients, diagonal and multigrid hierarchy are rebuilt; dot_jacobian
+ * and dot_grad_misfit then contract with the full dA/dp_k (the face terms
+ * dT_f/dp_k (z_c - z_c')(u_c - u_c') through dD/dp_k = -3 D^2 (mu_in - mu_out +
+ * mus_in - mus_out) delta_eps(phi - cutoff) d phi / d p_k, besides the diagonal
+ * h^d d mu / d p_k), with the same parameters and band lists.  Needs
+ * mu_in != mu_out.  mua_dev and diff_dev (may be NULL) receive mu and D.
+ * dot_pals_mua and dot_set_mua return to the diffusion given at build time;
+ * dot_dadp_apply covers the absorption-only model and returns DOT_EINVAL in
+ * this mode.  Synchronizes the stream.
+ */
+int dot_pals_mua_diffusion(dot_op* op, const dot_pals* pals, double mus_in, double mus_out,
+                           const double* theta_dev, double* mua_dev, double* diff_dev,
+                           void* stream);
+
 /* Number of (RBF, cell) pairs in the band lists of the last dot_pals_mua call:
  * the nonzeros of G = h^d d mu / d p per active parameter kind, i.e. the cells
  * the contraction visits summed over RBFs (-1 if no PaLS state). */
@@ -200,9 +221,11 @@ size_t dot_solve_workspace_bytes(const dot_op* op, int k, int precision);
  * z_i of A z_i = B w_i and the adjoint fields y_j of A^T y_j = C v_j.
  * Preconditioned CG from x0 = 0 per column until ||b - A x||_2 <= rtol
  * ||b||_2, on the symmetrically Jacobi-scaled system.  Preconditioner
- * (opts.precond): a geometric multigrid V-cycle on 3D grids whose sides
- * halve down to at least 4 cells (2 x 2 x 2 aggregation, the same
- * finite-volume operator on every level with D and mu averaged, damped
+ * (opts.precond): a geometric multigrid V-cycle on 2D and 3D grids whose
+ * sides all have at least 5 cells (2 x 2 x 2 aggregation, 2 x 2 in 2D, each
+ * side halved rounding up while every coarse side keeps at least 3 cells;
+ * the same finite-volume operator on every level, h = 1 / n_x, with D and
+ * mu averaged over the children of an aggregate, damped
  * Jacobi smoothing with w = 0.85, 2 steps each way on the finest level, 3 on
  * the next and 5 below, piecewise-constant transfers, 8 damped Jacobi steps
  * on the coarsest level), or the Jacobi scaling alone.  The
@@ -224,9 +247,33 @@ int dot_solve_multi_rhs(dot_op* op, int trans, int k, const double* rhs_dev, dou
                         const dot_solve_opts* opts, void* work_dev, size_t work_bytes,
                         dot_solve_info* info, void* stream);
 
+/*
+ * Frequency-domain multi-right-hand-side solve (Section 2, eq. PDE with
+ * omega > 0, and eq. compmeas): (A + i kappa E) X = RHS with kappa =
+ * omega / nu and E = h^d I, the cell volumes (every unknown of the
+ * cell-centred scheme is a cell average, so no row of E is zero; the zero
+ * rows of the paper's E belong to the boundary nodes of its vertex-centred
+ * scheme).  A + i kappa E is complex symmetric, so the adjoint solves of
+ * Section 3.3 use the same call.  Conjugate orthogonal CG (COCG) from x0 = 0
+ * on the symmetrically scaled system, preconditioned by the real multigrid
+ * V-cycle of dot_solve_multi_rhs applied to the real and imaginary parts (or
+ * the Jacobi scaling alone), per column until ||b - A_w x||_2 <= rtol
+ * ||b||_2 (conjugated norms).  Complex N x k blocks are N x 2k binary64
+ * arrays: real parts in columns 0 .. k-1, imaginary parts in k .. 2k-1.
+ * opts: rtol, max_iter, check_every and precond as for dot_solve_multi_rhs,
+ * precision must be DOT_FP64.  info.relres_host (k values) receives the true
+ * relative residual recomputed in binary64; DOT_NOT_CONVERGED when one
+ * exceeds 1.01 rtol.  kappa = 0 solves the real system.  k <= 2048.
+ * Synchronizes the stream.
+ */
+size_t dot_solve_complex_workspace_bytes(const dot_op* op, int k, int precond);
+int dot_solve_complex(dot_op* op, double kappa, int k, const double* rhs_dev, double* x_dev,
+                      const dot_solve_opts* opts, void* work_dev, size_t work_bytes,
+                      dot_solve_info* info, void* stream);
+
 /* Levels of the multigrid hierarchy the solver uses for this operator, or 0
- * when it preconditions with Jacobi (2D grids, sides that do not halve to at
- * least 4 cells, or a level whose diagonal is not positive). */
+ * when it preconditions with Jacobi (a side shorter than 5 cells, or a level
+ * whose diagonal is not positive). */
 int dot_multigrid_levels(const dot_op* op);
 
 /* Algorithmic HBM bytes per column of one V-cycle of the solver's
@@ -272,15 +319,32 @@ size_t dot_jacobian_workspace_bytes(const dot_op* op, int l_s, int l_d);
  * DOT_JAC_SPLIT_BF16X3 (operands rounded to binary32 and split into 2 or 3
  * bfloat16 parts, products on the matrix cores with binary32 accumulation
  * over 512-cell runs, binary64 sums across runs and chunks).  U_dev: N x l_s,
- * Z_dev: N x l_d, l_s <= 1024.  The binary64 matrix-core kernel needs
- * ceil(l_s / 16) ceil(l_d n_act / 16) <= 64 and l_s + l_d <= 128, beyond
- * that DOT_JAC_FP64 runs a plain binary64 kernel; the split forms need
- * l_s <= 64 and l_d <= 64 and return DOT_EINVAL beyond.  The workspace holds
- * per-chunk partial blocks and the packed rows of U and Z at the listed
- * cells (for the split forms U already split into its bfloat16 parts).
+ * Z_dev: N x l_d, l_s, l_d <= DOT_MAX_COLUMNS.  Samples larger than the
+ * matrix-core kernels hold in one pass (binary64: ceil(l_s / 16)
+ * ceil(l_d n_act / 16) <= 64 and l_s + l_d <= 128; split forms: l_s, l_d <=
+ * 64) run as tiles of at most 64 sources and as many detectors as fit, each
+ * written into its rows of Js_dev; with l_s = n_s and l_d = n_d (W, V
+ * identities) this is the full Jacobian J of eq. Jtensor.  The workspace
+ * holds one tile's per-chunk partial blocks and packed rows of U and Z at
+ * the listed cells (for the split forms U already split into its bfloat16
+ * parts).
  */
 int dot_jacobian(dot_op* op, int l_s, const double* U_dev, int l_d, const double* Z_dev,
                  int precision, double* Js_dev, void* work_dev, size_t work_bytes, void* stream);
+
+/*
+ * Derivative of A(p) along parameter directions, applied to fields (Section
+ * 3.3: with the absorption the unknown, dA/dp_k = h^d diag(d mu / d p_k)):
+ * Y_dev[:, j] = (sum_k Theta_dev[k, j] dA/dp_k) X_dev[:, j] for j < k, at the
+ * parameters of the last dot_pals_mua call.  Theta_dev: n_p x k column-major
+ * (one direction per column, parameter order as in dot_jacobian); X_dev,
+ * Y_dev: N x k, must not overlap; Y is zero outside the level-set band.
+ * This is the matrix-free product with the Jacobian: for u = A^-1 b and
+ * z = A^-T c, c^T A^-1 (dA/d theta) A^-1 b = z^T Y(theta, u), so a sketch
+ * J (w kron theta) needs one forward and one adjoint solve.
+ */
+int dot_dadp_apply(dot_op* op, int k, const double* Theta_dev, const double* X_dev, double* Y_dev,
+                 void* stream);
 
 /*
  * Gradient of f = 1/2 ||Rs||_F^2 (Section 3.1, eq. UnbiasedGrad):
@@ -291,6 +355,7 @@ int dot_jacobian(dot_op* op, int l_s, const double* U_dev, int l_d, const double
 int dot_grad_misfit(dot_op* op, int l_s, const double* U_dev, int l_d, const double* Z_dev,
                     const double* Rs_dev, double* g_dev, void* work_dev, size_t work_bytes,
                     void* stream);
+
 
 /*
  * Kernel timing with HIP events on the caller's stream (off by default).

@@ -12,11 +12,12 @@ from .api import (Grid, Operator, Pals, SolveResult, colmajor, empty_colmajor, g
                   mode_gram, optimized_design, pals_field, qr_complete, svd_thin, symeig,
                   tsvd_step)
 from .autograd import MisfitFn, MisfitProblem, misfit
+from . import inversion  # noqa: E402  (outer Gauss-Newton driver on the ABI calls)
 
 __all__ = [
     "DOT_ACT_ALPHA", "DOT_ACT_BETA", "DOT_ACT_CHI", "DOT_BC_DIRICHLET", "DOT_BC_ROBIN",
     "DOT_FP64", "DOT_MIXED", "DOT_PRECOND_AUTO", "DOT_PRECOND_JACOBI", "DOT_PRECOND_MG", "DOT_JAC_FP64", "DOT_JAC_SPLIT_BF16", "DOT_JAC_SPLIT_BF16X3", "DotError", "NotConverged",
     "LIB_PATH", "Grid", "Operator", "Pals", "SolveResult", "colmajor", "empty_colmajor",
     "gemm", "pals_field", "MisfitFn", "MisfitProblem", "misfit", "mode_gram", "symeig",
-    "qr_complete", "hooi", "svd_thin", "tsvd_step", "optimized_design",
+    "qr_complete", "hooi", "svd_thin", "tsvd_step", "optimized_design", "inversion",
 ]

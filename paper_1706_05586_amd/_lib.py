@@ -84,7 +84,11 @@ SIGNATURES = {
     "dot_pals_band_cells": (_i64, [_vp]),
     "dot_set_mua": (_i, [_vp, _vp, _vp]),
     "dot_pals_mua": (_i, [_vp, C.POINTER(DotPals), _vp, _vp, _vp]),
+    "dot_pals_mua_diffusion": (_i, [_vp, C.POINTER(DotPals), _d, _d, _vp, _vp, _vp, _vp]),
     "dot_apply": (_i, [_vp, _i, _vp, _vp, _vp]),
+    "dot_solve_complex_workspace_bytes": (_sz, [_vp, _i, _i]),
+    "dot_solve_complex": (_i, [_vp, _d, _i, _vp, _vp, C.POINTER(DotSolveOpts), _vp, _sz,
+                               C.POINTER(DotSolveInfo), _vp]),
     "dot_multigrid_levels": (_i, [_vp]),
     "dot_multigrid_cycle_bytes": (_d, [_vp, _i]),
     "dot_multigrid_workspace_bytes": (_sz, [_vp, _i]),
@@ -97,6 +101,7 @@ SIGNATURES = {
                                 C.POINTER(C.c_double), _vp]),
     "dot_jacobian_workspace_bytes": (_sz, [_vp, _i, _i]),
     "dot_jacobian": (_i, [_vp, _i, _vp, _i, _vp, _i, _vp, _vp, _sz, _vp]),
+    "dot_dadp_apply": (_i, [_vp, _i, _vp, _vp, _vp, _vp]),
     "dot_grad_misfit": (_i, [_vp, _i, _vp, _i, _vp, _vp, _vp, _vp, _sz, _vp]),
     "dot_gemm": (_i, [_i, _i, _i, _i, _i, _d, _vp, _i, _vp, _i, _d, _vp, _i, _vp]),
     "dot_mode_gram_workspace_bytes": (_sz, [_i, _i, _i, _i]),

@@ -23,7 +23,7 @@ from ._lib import check, lib
 __all__ = ["Grid", "Pals", "Operator", "SolveResult", "pals_field", "gemm", "colmajor",
            "check_field_block",
            "empty_colmajor", "mode_gram", "symeig", "qr_complete", "hooi", "svd_thin",
-           "tsvd_step", "optimized_design"]
+           "tsvd_step", "optimized_design", "complemented_sample"]
 
 
 def _stream() -> C.c_void_p:
@@ -148,9 +148,10 @@ def _check_colmajor_out(out: torch.Tensor, rows: int, cols: int):
 
 
 def gemm(A: torch.Tensor, B: torch.Tensor, transa: bool = False, transb: bool = False,
-         alpha: float = 1.0, out: torch.Tensor | None = None) -> torch.Tensor:
-    """alpha op(A) op(B) for logical matrices, computed by the library's FP64 kernel.
-    ``out`` may be a column block of a column-major matrix."""
+         alpha: float = 1.0, out: torch.Tensor | None = None, beta: float = 0.0) -> torch.Tensor:
+    """alpha op(A) op(B) + beta out for logical matrices, computed by the library's
+    FP64 kernel.  ``out`` may be a column block of a column-major matrix; it is
+    required when beta is not zero."""
     Am, Bm = colmajor(A, "A"), colmajor(B, "B")
     ar, ac = A.shape
     br, bc = B.shape
@@ -159,13 +160,15 @@ def gemm(A: torch.Tensor, B: torch.Tensor, transa: bool = False, transb: bool = 
     if kd != kb:
         raise ValueError("inner dimensions differ")
     if out is None:
+        if beta != 0.0:
+            raise ValueError("beta != 0 needs out")
         out = empty_colmajor(m, n, A.device)
         ldc = max(m, 1)
     else:
         _check_colmajor_out(out, m, n)
         ldc = out.stride(1) if n > 1 else max(m, 1)
     check(lib.dot_gemm(int(transa), int(transb), m, n, kd, float(alpha), _ptr(Am), max(ar, 1),
-                       _ptr(Bm), max(br, 1), 0.0, _ptr(out), ldc, _stream()), "dot_gemm")
+                       _ptr(Bm), max(br, 1), float(beta), _ptr(out), ldc, _stream()), "dot_gemm")
     return out
 
 
@@ -270,21 +273,32 @@ def optimized_design(Js: torch.Tensor, W: torch.Tensor, V: torch.Tensor, q_s: in
     orth(W W~), V_hat = orth(V V~) by Householder QR, whose complete Q also
     gives the complements W_c, V_c; the new samples are W = [W_hat, W_c Y]
     and V = [V_hat, V_c Z] with Y = (l_s - q_s)^{-1/2} y_signs (eqs. newW, newV).
+    The new samples have q + (columns of the signs) columns each; with W and V
+    identities, J_s is the full Jacobian and the design is the paper's.
     Returns (W_new, V_new, info)."""
     n_s, l_s = W.shape
     n_d, l_d = V.shape
     Wt, Vt, it, obj = hooi(Js, l_d, l_s, q_d, q_s, tol, maxit)
-    out = []
-    for S, T, q, l, signs in ((W, Wt, q_s, l_s, y_signs), (V, Vt, q_d, l_d, z_signs)):
-        n = S.shape[0]
-        X = gemm(S, T)                          # n x q
-        Q = qr_complete(X)                      # [S_hat, S_c]
-        new = empty_colmajor(n, l, S.device)
-        new[:, :q].copy_(Q[:, :q])
-        if l > q:
-            gemm(Q[:, q:], signs, alpha=1.0 / np.sqrt(l - q), out=new[:, q:])
-        out.append(new)
-    return out[0], out[1], {"hooi_iters": it, "objective": obj, "W_tilde": Wt, "V_tilde": Vt}
+    Wn = complemented_sample(gemm(W, Wt), y_signs)
+    Vn = complemented_sample(gemm(V, Vt), z_signs)
+    return Wn, Vn, {"hooi_iters": it, "objective": obj, "W_tilde": Wt, "V_tilde": Vt}
+
+
+def complemented_sample(X: torch.Tensor, signs: torch.Tensor) -> torch.Tensor:
+    """New simultaneous sources (or detectors) from optimized directions
+    (eqs. newW, newV): X (n x q) spans them; Householder QR gives the complete
+    Q = [X_hat, X_c]; returns [X_hat, X_c Y], Y = signs / sqrt(l - q), signs
+    (n - q) x (l - q)."""
+    n, q = X.shape
+    if signs.shape[0] != n - q:
+        raise ValueError(f"complement signs must have {n - q} rows")
+    l = q + signs.shape[1]
+    Q = qr_complete(X)
+    new = empty_colmajor(n, l, X.device)
+    new[:, :q].copy_(Q[:, :q])
+    if l > q:
+        gemm(Q[:, q:], signs, alpha=1.0 / np.sqrt(l - q), out=new[:, q:])
+    return new
 
 
 @dataclass
@@ -348,6 +362,20 @@ class Operator:
                                _stream()), "dot_pals_mua")
         self.pals = pals
         return mua
+
+    def pals_mua_diffusion(self, pals: Pals, theta: torch.Tensor, mus_in: float,
+                           mus_out: float):
+        """A(theta) with mu and D = 1 / (3 (mu + mu_s)) both from the level set
+        (diffusion inverted as well).  Returns (mu, D)."""
+        _need_cuda_f64(theta, "theta")
+        mua = torch.empty(self.N, dtype=torch.float64, device=self.device)
+        D = torch.empty_like(mua)
+        p = pals.c()
+        check(lib.dot_pals_mua_diffusion(self._handle, C.byref(p), float(mus_in), float(mus_out),
+                                         _ptr(theta.contiguous()), _ptr(mua), _ptr(D), _stream()),
+              "dot_pals_mua_diffusion")
+        self.pals = pals
+        return mua, D
 
     @property
     def n_pairs(self) -> int:
@@ -436,6 +464,40 @@ class Operator:
         return SolveResult(x=x, iters=iters, relres=rel, iters_max=info.iters_max,
                            outer=info.outer, converged=code == L.DOT_OK)
 
+    def solve_complex(self, rhs: torch.Tensor, kappa: float, rtol: float = 1e-10,
+                      max_iter: int = 20000, check_every: int = 8,
+                      precond: int = L.DOT_PRECOND_AUTO, warn: bool = True) -> SolveResult:
+        """(A + i kappa h^d I) X = rhs for a complex128 (N, k) block (COCG).
+        The result's x is complex128 (N, k)."""
+        if not isinstance(rhs, torch.Tensor) or rhs.dtype != torch.complex128 or not rhs.is_cuda:
+            raise TypeError("rhs must be a complex128 CUDA tensor")
+        R2 = rhs.reshape(-1, 1) if rhs.dim() == 1 else rhs
+        if R2.shape[0] != self.N:
+            raise ValueError(f"rhs must have {self.N} rows")
+        k = R2.shape[1]
+        # N x 2k real block: real parts, then imaginary parts (column-major)
+        B = empty_colmajor(self.N, 2 * k, self.device)
+        B[:, :k].copy_(R2.real)
+        B[:, k:].copy_(R2.imag)
+        X = empty_colmajor(self.N, 2 * k, self.device)
+        nbytes = int(lib.dot_solve_complex_workspace_bytes(self._handle, k, precond))
+        work = _workspace(nbytes, self.device)
+        opts = L.DotSolveOpts(rtol, max_iter, L.DOT_FP64, 0.1, check_every, precond)
+        iters = np.zeros(k, dtype=np.int32)
+        rel = np.zeros(k, dtype=np.float64)
+        info = L.DotSolveInfo(0, 0, iters.ctypes.data_as(C.POINTER(C.c_int32)),
+                              rel.ctypes.data_as(C.POINTER(C.c_double)))
+        code = lib.dot_solve_complex(self._handle, float(kappa), k, _ptr(B), _ptr(X),
+                                     C.byref(opts), _ptr(work), work.numel(), C.byref(info),
+                                     _stream())
+        check(code, "dot_solve_complex")
+        if code == L.DOT_NOT_CONVERGED and warn:
+            warnings.warn(f"complex solve did not reach rtol={rtol}: max relres {rel.max():.3e}",
+                          L.NotConverged)
+        x = torch.complex(X[:, :k], X[:, k:])
+        return SolveResult(x=x.reshape(-1) if rhs.dim() == 1 else x, iters=iters, relres=rel,
+                           iters_max=info.iters_max, outer=0, converged=code == L.DOT_OK)
+
     # ------------------------------------------------------------ profiling
     def profile_enable(self, on: bool = True):
         check(lib.dot_profile_enable(self._handle, int(on)), "dot_profile_enable")
@@ -481,6 +543,22 @@ class Operator:
                                _ptr(work), work.numel(), _stream()), "dot_jacobian")
         return Js
 
+    def dadp_apply(self, Theta: torch.Tensor, X: torch.Tensor) -> torch.Tensor:
+        """(sum_k Theta[k, j] dA/dp_k) X[:, j] for each column j (Theta: n_p x k)."""
+        if self.pals is None:
+            raise RuntimeError("call pals_mua before dadp_apply")
+        n_p = self.pals.m0 * self.pals.n_act(self.grid.dim)
+        Th2 = Theta.reshape(-1, 1) if Theta.dim() == 1 else Theta
+        X2 = X.reshape(-1, 1) if X.dim() == 1 else X
+        if Th2.shape[0] != n_p or X2.shape != (self.N, Th2.shape[1]):
+            raise ValueError(f"Theta must be ({n_p}, k) and X ({self.N}, k)")
+        Tm, Xm = colmajor(Th2, "Theta"), colmajor(X2, "X")
+        k = X2.shape[1]
+        Y = empty_colmajor(self.N, k, self.device)
+        check(lib.dot_dadp_apply(self._handle, k, _ptr(Tm), _ptr(Xm), _ptr(Y), _stream()),
+              "dot_dadp_apply")
+        return Y.reshape(-1) if X.dim() == 1 else Y
+
     def grad_misfit(self, U: torch.Tensor, Z: torch.Tensor, Rs: torch.Tensor,
                     work: torch.Tensor | None = None) -> torch.Tensor:
         if self.pals is None:
@@ -495,3 +573,4 @@ class Operator:
         check(lib.dot_grad_misfit(self._handle, l_s, _ptr(Um), l_d, _ptr(Zm), _ptr(Rm), _ptr(g),
                                   _ptr(work), work.numel(), _stream()), "dot_grad_misfit")
         return g
+

@@ -41,6 +41,24 @@ void clear_error();
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Block-wide exclusive prefix sum of a 0/1 flag over 256 threads; returns the
+// position and sets *total.  Order follows threadIdx.x, so compaction is
+// deterministic.
+__device__ __forceinline__ int block_scan_flag256(int flag, int* s_wave, int* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const unsigned long long bal = __ballot(flag);
+  const int before = __popcll(bal & ((1ull << lane) - 1ull));
+  if (lane == 0) s_wave[wave] = __popcll(bal);
+  __syncthreads();
+  int off = 0, tot = 0;
+  for (int w = 0; w < 4; ++w) {
+    if (w < wave) off += s_wave[w];
+    tot += s_wave[w];
+  }
+  *total = tot;
+  return off + before;
+}
+
 // ---------------------------------------------------------------- handle
 struct GridDims {
   int dim;
@@ -53,8 +71,9 @@ struct GridDims {
 struct dot_state_arrays;
 
 // ---------------------------------------------------------------- multigrid
-// Geometric hierarchy for the V-cycle preconditioner (3D grids whose sides
-// halve): level l + 1 aggregates 2 x 2 x 2 cells of level l and is the same
+// Geometric hierarchy for the V-cycle preconditioner (2D and 3D grids):
+// level l + 1 aggregates 2 x 2 x 2 cells of level l (2 x 2 in 2D; the last
+// aggregate of an odd side is one cell thick along it) and is the same
 // finite-volume discretization on the coarse cells, with D and mu averaged
 // over the children.  Every level is kept in the symmetrically scaled form
 // (unit diagonal): couplings to +x, +y, +z in binary64 and binary32.
@@ -105,6 +124,28 @@ struct dot_op {
   float* sx32 = nullptr;
   float* sy32 = nullptr;
   float* sz32 = nullptr;
+  // diffusion from the level set (dot_pals_mua_diffusion): D0 then holds
+  // D(theta), Dbuild the coefficient given to dot_build_operator, restored by
+  // dot_pals_mua and dot_set_mua
+  bool diff_mode = false;
+  double mus_in = 0.0, mus_out = 0.0;
+  double* Dbuild = nullptr;
+  // contraction rows and pairs with the face terms of dA/dp (diffusion mode):
+  // 1 + 2 dim rows per band cell (the cell, then its faces -x, +x, -y, +y,
+  // -z, +z): row cell, neighbour across the face (-1: none) and the weight of
+  // the adjoint-field difference; every (RBF, cell) pair repeated per row
+  int32_t* vrow_cell = nullptr;
+  int32_t* vrow_nbr = nullptr;
+  double* vrow_w = nullptr;
+  int64_t vrow_cap = 0, n_vrows = 0;
+  int32_t* vpair_band = nullptr;
+  double* vpair_g = nullptr;
+  float* vpair_g32 = nullptr;
+  int64_t vpair_cap = 0, n_vpairs = 0;
+  int64_t* vchunk_begin = nullptr;
+  int32_t* vrbf_chunk0 = nullptr;
+  int64_t vchunk_cap = 0, n_vchunks = 0;
+  int vrbf_cap = 0;
   // level-set state from the last dot_pals_mua call
   double* phi = nullptr;
   double* theta = nullptr;      // copy of theta (m0 x (2 + dim))
@@ -168,6 +209,8 @@ constexpr int kPinnedInts = 4 * DOT_MAX_COLUMNS + 64;
 int ensure_cells_dev(dot_op* op, int n, const int32_t* cells_host, hipStream_t s);
 // after the pair lists of dot_pals_mua: per-pair d mu / d p and band rows
 int jac_prepare(dot_op* op, hipStream_t s);
+// the face rows and pairs of diffusion mode (after jac_prepare)
+int jac_prepare_faces(dot_op* op, hipStream_t s);
 // multigrid: levels of the grid (0 or 1: none), hierarchy (re)build after
 // the diagonal changed, and one V-cycle z = M^-1 r on the scaled system
 int mg_levels_for(const GridDims& g, GridDims* levels);

@@ -72,69 +72,91 @@ __device__ __forceinline__ void cell_xyz(const GridDims& g, int64_t c, double* x
   *x2 = (z + 0.5) * g.h;
 }
 
-constexpr int JB = 32;     // cells staged per batch
-constexpr int JOUT = 32;   // outputs per thread per output pass
-constexpr int JT = 256;    // threads
+// ----------------------------------------------------------------------
+// Directional derivative of A(p) applied to fields:
+//     Y[c, j] = h^d (mu_in - mu_out) delta_eps(phi_c - cutoff)
+//               sum_m sum_a Theta[m n_act + a, j] d phi_c / d p_{m,a}  X[c, j],
+// i.e. (sum_k Theta[k, j] dA/dp_k) X[:, j] with dA/dp_k = h^d diag(d mu / d p_k).
+// One block of 256 threads per cell tile (8 x 8 x 4 in 3D, 16 x 16 in 2D);
+// the RBFs whose support reaches the tile are listed in RBF order and summed
+// in that order at every cell (deterministic), DIRK columns at a time.
+constexpr int DIRK = 8;
 
-// Partial contraction of one chunk, binary64.  Output element e of the
-// chunk's block is (i, j, a) with e = (j + l_d i) + l_s l_d a.
-__global__ __launch_bounds__(JT) void jac_chunk_fp64_kernel(
-    GridDims g, JacParams P, const double* __restrict__ theta, const double* __restrict__ phi,
-    const int32_t* __restrict__ pair_cell, const int64_t* __restrict__ chunk_begin,
-    const int32_t* __restrict__ chunk_rbf, int l_s, const double* __restrict__ U, int l_d,
-    const double* __restrict__ Z, double* __restrict__ partial) {
-  extern __shared__ double smem[];
-  const int ch = blockIdx.x;
-  const int64_t b0 = chunk_begin[ch], b1 = chunk_begin[ch + 1];
-  const int m = chunk_rbf[ch];
-  const double* th = theta + (int64_t)m * P.stride;
+__global__ __launch_bounds__(256) void dA_dir_kernel(GridDims g, JacParams P,
+                                                     const double* __restrict__ theta,
+                                                     const double* __restrict__ phi, int m0,
+                                                     int k, const double* __restrict__ Th,
+                                                     int n_p, const double* __restrict__ X,
+                                                     double* __restrict__ Y) {
+  __shared__ int s_wave[4];
+  __shared__ int s_list[256];
+  const bool d3 = g.dim == 3;
+  const int TX = d3 ? 8 : 16, TY = d3 ? 8 : 16, TZ = d3 ? 4 : 1;
+  const int tiles_x = (g.nx + TX - 1) / TX, tiles_y = (g.ny + TY - 1) / TY;
+  const int tile = blockIdx.x;
+  const int bx = tile % tiles_x, by = (tile / tiles_x) % tiles_y, bz = tile / (tiles_x * tiles_y);
+  const int t = threadIdx.x;
+  const int lx = t % TX, ly = (t / TX) % TY, lz = t / (TX * TY);
+  const int x = bx * TX + lx, y = by * TY + ly, z = bz * TZ + lz;
+  const bool inside = x < g.nx && y < g.ny && z < g.nz;
+  const double h = g.h;
+  const double xc0 = (x + 0.5) * h, xc1 = (y + 0.5) * h, xc2 = (z + 0.5) * h;
+  const double lo0 = (bx * TX + 0.5) * h, hi0 = (min(g.nx, bx * TX + TX) - 0.5) * h;
+  const double lo1 = (by * TY + 0.5) * h, hi1 = (min(g.ny, by * TY + TY) - 0.5) * h;
+  const double lo2 = (bz * TZ + 0.5) * h, hi2 = (min(g.nz, bz * TZ + TZ) - 0.5) * h;
+  const double g2 = P.gamma * P.gamma;
+  const int64_t c = inside ? x + (int64_t)g.nx * (y + (int64_t)g.ny * z) : 0;
+  const double w = inside ? P.hd * band_weight(P, phi[c]) : 0.0;
   const int na = P.n_act;
-  double* Us = smem;                   // [JB][l_s]
-  double* Zs = Us + JB * l_s;          // [JB][l_d]
-  double* Gs = Zs + JB * l_d;          // [JB][na]
-  const int nout = l_s * l_d * na;
-  const int lsld = l_s * l_d;
-  double* out = partial + (int64_t)ch * nout;
-  for (int ob = 0; ob < nout; ob += JT * JOUT) {
-    double acc[JOUT];
+  for (int j0 = 0; j0 < k; j0 += DIRK) {
+    double acc[DIRK];
 #pragma unroll
-    for (int q = 0; q < JOUT; ++q) acc[q] = 0.0;
-    for (int64_t cb = b0; cb < b1; cb += JB) {
-      const int nb = (int)min<int64_t>(JB, b1 - cb);
+    for (int q = 0; q < DIRK; ++q) acc[q] = 0.0;
+    for (int base = 0; base < m0; base += 256) {
+      const int m = base + t;
+      int flag = 0;
+      if (m < m0) {
+        const double* th = theta + (int64_t)m * P.stride;
+        const double beta = th[1];
+        const double d0 = fmax(0.0, fmax(lo0 - th[2], th[2] - hi0));
+        const double d1 = fmax(0.0, fmax(lo1 - th[3], th[3] - hi1));
+        double dist2 = d0 * d0 + d1 * d1;
+        if (d3) {
+          const double dd = fmax(0.0, fmax(lo2 - th[4], th[4] - hi2));
+          dist2 += dd * dd;
+        }
+        flag = (beta * beta * dist2 + g2 < 1.0) ? 1 : 0;
+      }
+      int total;
+      const int pos = block_scan_flag256(flag, s_wave, &total);
+      if (flag) s_list[pos] = m;
       __syncthreads();
-      for (int t = threadIdx.x; t < nb * l_s; t += JT) {
-        const int cc = t % nb, i = t / nb;
-        Us[cc * l_s + i] = U[pair_cell[cb + cc] + P.N * i];
-      }
-      for (int t = threadIdx.x; t < nb * l_d; t += JT) {
-        const int cc = t % nb, j = t / nb;
-        Zs[cc * l_d + j] = Z[pair_cell[cb + cc] + P.N * j];
-      }
-      if (threadIdx.x < nb) {
-        const int64_t c = pair_cell[cb + threadIdx.x];
-        double x0, x1, x2, d[5];
-        cell_xyz(g, c, &x0, &x1, &x2);
-        rbf_dphi(P, th, x0, x1, x2, d);
-        const double w = band_weight(P, phi[c]);
-        for (int a = 0; a < na; ++a) Gs[threadIdx.x * na + a] = P.hd * (w * d[a]);
-      }
-      __syncthreads();
+      if (inside && w != 0.0) {
+        for (int q = 0; q < total; ++q) {
+          const int mm = s_list[q];
+          double d[5];
+          rbf_dphi(P, theta + (int64_t)mm * P.stride, xc0, xc1, xc2, d);
+          const double* tk = Th + (int64_t)mm * na;
 #pragma unroll
-      for (int q = 0; q < JOUT; ++q) {
-        const int e = ob + q * JT + threadIdx.x;
-        if (e < nout) {
-          const int a = e / lsld, rem = e % lsld;
-          const int j = rem % l_d, i = rem / l_d;
-          double s = acc[q];
-          for (int cc = 0; cc < nb; ++cc) s += Us[cc * l_s + i] * Zs[cc * l_d + j] * Gs[cc * na + a];
-          acc[q] = s;
+          for (int jj = 0; jj < DIRK; ++jj) {
+            if (j0 + jj < k) {
+              const double* tc = tk + (int64_t)n_p * (j0 + jj);
+              double s = 0.0;
+              for (int a = 0; a < na; ++a) s += d[a] * tc[a];
+              acc[jj] += s;
+            }
+          }
         }
       }
+      __syncthreads();
     }
+    if (inside) {
 #pragma unroll
-    for (int q = 0; q < JOUT; ++q) {
-      const int e = ob + q * JT + threadIdx.x;
-      if (e < nout) out[e] = acc[q];
+      for (int jj = 0; jj < DIRK; ++jj)
+        if (j0 + jj < k) {
+          const int64_t e = c + P.N * (int64_t)(j0 + jj);
+          Y[e] = w == 0.0 ? 0.0 : w * acc[jj] * X[e];
+        }
     }
   }
 }
@@ -274,12 +296,94 @@ __global__ void pair_band_kernel(int64_t n_pairs, const int32_t* __restrict__ pa
   if (p < n_pairs) pair_band[p] = idx[pair_cell[p]];
 }
 
+// Diffusion mode (dot_pals_mua_diffusion): dA/dp_k also has the face terms
+// sum_f dT_f/dp_k (e_c - e_c')(e_c - e_c')^T + boundary faces, with
+// dT_f/dp_k = dT_f/dD_c dD_c/dp_k + dT_f/dD_c' dD_c'/dp_k and
+// dD_c/dp_k = s_c h^d d mu_c / d p_k, s_c = -3 D_c^2 (1 + (mus_in - mus_out) /
+// (mu_in - mu_out)) / h^d.  Each half of a face term belongs to one cell, so
+// per (RBF, cell) pair the contraction gains 2 dim rows beside the cell's own:
+// row 1 + f (face f = 2 axis + side: -x, +x, -y, +y, -z, +z) is
+// (U_c - U_c', w (Z_c - Z_c')) across an interior face and (U_c, w Z_c) on a
+// boundary face, w = s_c dT_f/dD_c, all under the same pair weight
+// h^d d mu / d p_k:
+//   interior   dT/dD_c = h^(d-2) 2 D_c'^2 / (D_c + D_c')^2
+//   Dirichlet  dT/dD_c = h^(d-2) 2
+//   Robin      dT/dD_c = h^(d-1) 2 h / (h + 4 D_c)^2
+struct Faces6 {
+  int bc[6];
+};
+
+__global__ __launch_bounds__(256) void vrow_kernel(GridDims g, Faces6 fb, int64_t n_band,
+                                                   const int32_t* __restrict__ band_cells,
+                                                   const double* __restrict__ D, double ratio,
+                                                   int R, int32_t* __restrict__ rcell,
+                                                   int32_t* __restrict__ rnbr,
+                                                   double* __restrict__ rw) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= n_band * R) return;
+  const int64_t b = q / R;
+  const int r = (int)(q - b * R);
+  const int64_t c = band_cells[b];
+  rcell[q] = (int32_t)c;
+  if (r == 0) {
+    rnbr[q] = -1;
+    rw[q] = 1.0;
+    return;
+  }
+  const int f = r - 1, axis = f >> 1, side = f & 1;
+  const int x = (int)(c % g.nx), y = (int)((c / g.nx) % g.ny), z = (int)(c / g.nxy);
+  const int pos[3] = {x, y, z};
+  const int n[3] = {g.nx, g.ny, g.nz};
+  const int64_t stride[3] = {1, g.nx, g.nxy};
+  const double h = g.h;
+  const double hd2 = g.dim == 3 ? h : 1.0, hd1 = g.dim == 3 ? h * h : h;
+  const double Dc = D[c];
+  const double sc = -3.0 * Dc * Dc * ratio / g.hd;
+  const bool interior = side == 0 ? pos[axis] > 0 : pos[axis] + 1 < n[axis];
+  if (interior) {
+    const int64_t cn = side == 0 ? c - stride[axis] : c + stride[axis];
+    const double Dn = D[cn];
+    const double s2 = Dc + Dn;
+    rnbr[q] = (int32_t)cn;
+    rw[q] = sc * hd2 * 2.0 * Dn * Dn / (s2 * s2);
+  } else {
+    const int code = fb.bc[f];
+    const double t = code == DOT_BC_DIRICHLET ? hd2 * 2.0
+                                              : hd1 * 2.0 * h / ((h + 4.0 * Dc) * (h + 4.0 * Dc));
+    rnbr[q] = -1;
+    rw[q] = sc * t;
+  }
+}
+
+// virtual pair p R + r: band row of pair p times R plus r, its weights
+__global__ __launch_bounds__(256) void vpair_kernel(int64_t n_pairs, int R, int na,
+                                                    const int32_t* __restrict__ pair_band,
+                                                    const double* __restrict__ pair_g,
+                                                    int32_t* __restrict__ vband,
+                                                    double* __restrict__ vg,
+                                                    float* __restrict__ vg32) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= n_pairs * R) return;
+  const int64_t p = q / R;
+  const int r = (int)(q - p * R);
+  vband[q] = pair_band[p] * R + r;
+  for (int a = 0; a < na; ++a) {
+    const double v = pair_g[p * na + a];
+    vg[q * na + a] = v;
+    vg32[q * na + a] = (float)v;
+  }
+}
+
 // Packed rows: packed[b * L + i] = U[c_b, i] (i < l_s) or Z[c_b, i - l_s],
 // L = l_s + l_d, through a 64-row x 64-column LDS tile so that both the
 // column reads and the row writes are contiguous.
-template <typename T>
+// FACE (diffusion mode): row b is (U_c - U_nbr, w (Z_c - Z_nbr)) with the
+// neighbour rnbr[b] (-1: none, the plain values) and weight rw[b].
+template <typename T, bool FACE>
 __global__ __launch_bounds__(256) void pack_rows_kernel(int64_t N, int64_t n_band,
                                                         const int32_t* __restrict__ band_cells,
+                                                        const int32_t* __restrict__ rnbr,
+                                                        const double* __restrict__ rw,
                                                         int l_s, const double* __restrict__ U,
                                                         int l_d, const double* __restrict__ Z,
                                                         T* __restrict__ packed) {
@@ -290,12 +394,22 @@ __global__ __launch_bounds__(256) void pack_rows_kernel(int64_t N, int64_t n_ban
   const int t = threadIdx.x, bl = t & 63;
   const int64_t b = b0 + bl;
   const int64_t c = b < n_band ? band_cells[b] : 0;
+  const int64_t cn = (FACE && b < n_band) ? rnbr[b] : -1;
+  const double wz = (FACE && b < n_band) ? rw[b] : 1.0;
 #pragma unroll 4
   for (int r = 0; r < 16; ++r) {
     const int il = (t >> 6) + 4 * r;
     const int i = i0 + il;
     T v = T(0);
-    if (b < n_band && i < L) v = (T)(i < l_s ? U[c + N * (int64_t)i] : Z[c + N * (int64_t)(i - l_s)]);
+    if (b < n_band && i < L) {
+      const double* src = i < l_s ? U + N * (int64_t)i : Z + N * (int64_t)(i - l_s);
+      double val = src[c];
+      if (FACE) {
+        if (cn >= 0) val -= src[cn];
+        if (i >= l_s) val *= wz;
+      }
+      v = (T)val;
+    }
     tile[bl][il] = v;
   }
   __syncthreads();
@@ -564,9 +678,11 @@ __device__ __forceinline__ uint32_t word_part(const typename SplitWord<TERMS>::t
   }
 }
 
-template <int TERMS>
+template <int TERMS, bool FACE>
 __global__ __launch_bounds__(256) void pack_split_kernel(int64_t N, int64_t n_band,
                                                          const int32_t* __restrict__ band_cells,
+                                                         const int32_t* __restrict__ rnbr,
+                                                         const double* __restrict__ rw,
                                                          int l_s, const double* __restrict__ U,
                                                          int l_d, const double* __restrict__ Z,
                                                          int mt16, int ldj,
@@ -578,6 +694,12 @@ __global__ __launch_bounds__(256) void pack_split_kernel(int64_t N, int64_t n_ba
   const int t = threadIdx.x, bl = t & 63;
   const int64_t b = b0 + bl;
   const int64_t c = b < n_band ? band_cells[b] : 0;
+  // FACE: the neighbour's values are subtracted (clamped to the cell itself
+  // and multiplied by zero where there is none) and Z is weighted
+  const int64_t cr = (FACE && b < n_band) ? rnbr[b] : -1;
+  const int64_t cn = cr >= 0 ? cr : c;
+  const double fl = cr >= 0 ? 1.0 : 0.0;
+  const double wz = (FACE && b < n_band) ? rw[b] : 1.0;
   // columns i = t / 64 + 4 k, eight loads in flight per thread (a row of
   // band cells is a gather: latency, not bandwidth, bounds one load at a
   // time).  Loads and stores are unconditional (a guarded load is waited
@@ -590,6 +712,7 @@ __global__ __launch_bounds__(256) void pack_split_kernel(int64_t N, int64_t n_ba
       const int i = min(i0 + 4 * k, L - 1);
       const double* src = i < l_s ? U + N * (int64_t)i : Z + N * (int64_t)(i - l_s);
       v[k] = src[c];
+      if (FACE) v[k] = (v[k] - fl * src[cn]) * (i < l_s ? 1.0 : wz);
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) ptile[bl * LP + min(i0 + 4 * k, L)] = (float)v[k];
@@ -779,11 +902,24 @@ __global__ __launch_bounds__(JS_THREADS) void jac_split_kernel(
   if (kstep % JFLUSH != 0) flush(kstep / JFLUSH);
 }
 
-// Js[(j + l_d i) + l_s l_d (m na + a)] = - sum over the chunks of RBF m and
-// their runs of JFLUSH K-steps (binary32 blocks), in order, in binary64.
+// Where a tile of t_i sources x t_j detectors lands in J_s: the tile's row
+// j + t_j i (detector fastest) and column k go to
+// Js[base + j + ldi i + ldk k], so a tile at sources i0.., detectors j0.. of
+// an l_s x l_d sample has base j0 + l_d i0, ldi = l_d, ldk = l_s l_d.
+struct JacOut {
+  int tj;
+  int64_t base, ldi, ldk;
+  __device__ __forceinline__ int64_t at(int row, int k) const {
+    return base + (row % tj) + ldi * (row / tj) + ldk * (int64_t)k;
+  }
+};
+
+// J_s entry (j, i, m na + a) of the tile = - sum over the chunks of RBF m
+// and their runs of JFLUSH K-steps (binary32 blocks), in order, in binary64.
 __global__ void jac_reduce_runs_kernel(int m0, const int32_t* __restrict__ rbf_chunk0,
                                        const int64_t* __restrict__ chunk_begin, int lsld, int na,
-                                       const float* __restrict__ partial, double* __restrict__ Js) {
+                                       const float* __restrict__ partial, JacOut o,
+                                       double* __restrict__ Js) {
   const int m = blockIdx.y;
   const int nout = lsld * na;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -808,12 +944,13 @@ __global__ void jac_reduce_runs_kernel(int m0, const int32_t* __restrict__ rbf_c
     }
   }
   const int a = e / lsld, row = e % lsld;
-  Js[row + (int64_t)lsld * (m * na + a)] = -s;
+  Js[o.at(row, m * na + a)] = -s;
 }
 
-// Js[(j + l_d i) + l_s l_d (m na + a)] = - sum over chunks of RBF m.
+// J_s entry (j, i, m na + a) of the tile = - sum over chunks of RBF m.
 __global__ void jac_reduce_kernel(int m0, const int32_t* __restrict__ rbf_chunk0, int lsld, int na,
-                                  const double* __restrict__ partial, double* __restrict__ Js) {
+                                  const double* __restrict__ partial, JacOut o,
+                                  double* __restrict__ Js) {
   const int m = blockIdx.y;
   const int nout = lsld * na;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -830,7 +967,7 @@ __global__ void jac_reduce_kernel(int m0, const int32_t* __restrict__ rbf_chunk0
     for (int k = 0; k < 4; ++k) s += v[k] * (double)(ch + k < c1);
   }
   const int a = e / lsld, row = e % lsld;
-  Js[row + (int64_t)lsld * (m * na + a)] = -s;
+  Js[o.at(row, m * na + a)] = -s;
 }
 
 // s_c = sum_i U[c,i] sum_j Z[c,j] Rs[j,i] on band cells, 0 elsewhere.
@@ -890,6 +1027,48 @@ __global__ __launch_bounds__(256) void grad_cell_small_kernel(GridDims g, JacPar
   for (int i = 0; i < MAXS; ++i)
     if (i < l_s) s += U[c + P.N * i] * lam[i];
   sc[c] = s;
+}
+
+// Diffusion mode: Lambda = Z R_s (N x l_s), then per face row q (cell c,
+// neighbour c', weight w) e_q = sum_i (U_ci - U_c'i) w (Lambda_ci - Lambda_c'i)
+// (the plain values where there is no neighbour), which the virtual pairs
+// weight by h^d d mu / d p like the cell sums of the absorption-only mode.
+__global__ __launch_bounds__(256) void lambda_kernel(int64_t N, int l_s, int l_d,
+                                                     const double* __restrict__ Z,
+                                                     const double* __restrict__ Rs,
+                                                     double* __restrict__ Lam) {
+  extern __shared__ double sR[];  // l_d x l_s
+  for (int t = threadIdx.x; t < l_d * l_s; t += blockDim.x) sR[t] = Rs[t];
+  __syncthreads();
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= N) return;
+  for (int i = 0; i < l_s; ++i) {
+    double v = 0.0;
+    for (int j = 0; j < l_d; ++j) v += Z[c + N * j] * sR[j + l_d * i];
+    Lam[c + N * i] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void grad_vrow_kernel(int64_t N, int64_t n_rows, int l_s,
+                                                        const int32_t* __restrict__ rcell,
+                                                        const int32_t* __restrict__ rnbr,
+                                                        const double* __restrict__ rw,
+                                                        const double* __restrict__ U,
+                                                        const double* __restrict__ Lam,
+                                                        double* __restrict__ e) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= n_rows) return;
+  const int64_t c = rcell[q], cn = rnbr[q];
+  double s = 0.0;
+  for (int i = 0; i < l_s; ++i) {
+    double du = U[c + N * i], dl = Lam[c + N * i];
+    if (cn >= 0) {
+      du -= U[cn + N * i];
+      dl -= Lam[cn + N * i];
+    }
+    s += du * dl;
+  }
+  e[q] = rw[q] * s;
 }
 
 __global__ __launch_bounds__(256) void grad_chunk_kernel(int na, const int32_t* __restrict__ pair_cell,
@@ -957,28 +1136,125 @@ static size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 // Workspace of dot_jacobian / dot_grad_misfit: per-chunk partial blocks, then
 // the packed band rows (binary64, which also holds the binary32 packing).
 // binary64 per chunk, or binary32 per run of JSLOT pairs (JSPC per chunk)
+// The rows and pairs the contraction runs over: the band cells and the
+// (RBF, cell) pairs, or in diffusion mode the face rows and virtual pairs.
+struct JacTables {
+  int64_t n_rows;
+  const int32_t* row_cell;
+  const int32_t* row_nbr;    // diffusion mode only
+  const double* row_w;       // diffusion mode only
+  const int32_t* pair_band;
+  const double* pair_g;
+  const float* pair_g32;
+  int64_t n_pairs;
+  const int64_t* chunk_begin;
+  int64_t n_chunks;
+  const int32_t* rbf_chunk0;
+  bool face;
+};
+
+static JacTables jac_tables(const dot_op* op) {
+  JacTables t;
+  t.face = op->diff_mode;
+  if (!t.face) {
+    t.n_rows = op->n_band;
+    t.row_cell = op->band_cells;
+    t.row_nbr = nullptr;
+    t.row_w = nullptr;
+    t.pair_band = op->pair_band;
+    t.pair_g = op->pair_g;
+    t.pair_g32 = op->pair_g32;
+    t.n_pairs = op->n_pairs;
+    t.chunk_begin = op->chunk_begin;
+    t.n_chunks = op->n_chunks;
+    t.rbf_chunk0 = op->rbf_chunk0;
+  } else {
+    t.n_rows = op->n_vrows;
+    t.row_cell = op->vrow_cell;
+    t.row_nbr = op->vrow_nbr;
+    t.row_w = op->vrow_w;
+    t.pair_band = op->vpair_band;
+    t.pair_g = op->vpair_g;
+    t.pair_g32 = op->vpair_g32;
+    t.n_pairs = op->n_vpairs;
+    t.chunk_begin = op->vchunk_begin;
+    t.n_chunks = op->n_vchunks;
+    t.rbf_chunk0 = op->vrbf_chunk0;
+  }
+  return t;
+}
+
+// binary64 per chunk, or binary32 per run of JSLOT pairs (JSPC per chunk)
 static size_t jac_partial_bytes(const dot_op* op, int l_s, int l_d) {
   const int na = n_active_bits(op->pals.active, op->g.dim);
-  return al256((size_t)std::max<int64_t>(op->n_chunks, 1) * l_s * l_d * na *
+  return al256((size_t)std::max<int64_t>(jac_tables(op).n_chunks, 1) * l_s * l_d * na *
                std::max(sizeof(double), JSPC * sizeof(float)));
 }
 
-// packed band rows: binary64 rows of l_s + l_d values, or for the split
-// forms the split words of U (at most 8 bytes, l_s rounded up to 16 per row)
-// followed by binary32 rows of Z (l_d rounded up to 16)
+// packed rows: binary64 rows of l_s + l_d values, or for the split forms the
+// split words of U (at most 8 bytes, l_s rounded up to 16 per row) followed
+// by binary32 rows of Z (l_d rounded up to 16)
 static size_t packed_split_u_bytes(const dot_op* op, int l_s) {
-  return al256((size_t)std::max<int64_t>(op->n_band, 1) * ((l_s + 15) / 16) * 16 * 8);
+  return al256((size_t)std::max<int64_t>(jac_tables(op).n_rows, 1) * ((l_s + 15) / 16) * 16 * 8);
+}
+
+// Source x detector tile of one contraction pass: the whole sample when the
+// matrix-core kernels hold it (binary64: at most 64 output tiles of 16 x 16
+// over 8 waves, l_s + l_d <= 16 JRMAX and the LDS staging within 160 KB;
+// split forms: l_s, l_d <= 64),
+// otherwise tiles of at most 64 sources and as many detectors as fit.
+static void jac_tile_shape(int precision, int l_s, int l_d, int na, int* ts, int* td) {
+  if (precision == DOT_JAC_FP64) {
+    // at most 8 output tiles per wave, JRMAX staged values per thread, and
+    // the staged operands within the 160 KB of LDS
+    auto fits = [na](int a, int b) {
+      const int mt = (a + 15) / 16, tiles = mt * ((b * na + 15) / 16);
+      if (tiles > 64 || a + b > 16 * JRMAX) return false;
+      const int ncp = ((8 * ((tiles + 7) / 8) - 1) / mt + 1) * 16;
+      return jac_lds_bytes(mt * 16, ncp) <= (size_t)160 * 1024;
+    };
+    if (fits(l_s, l_d)) {
+      *ts = l_s;
+      *td = l_d;
+      return;
+    }
+    const int a = std::min(l_s, 64);
+    int b = std::min(l_d, 16 * JRMAX - a);
+    while (b > 1 && !fits(a, b)) --b;
+    *ts = a;
+    *td = b;
+  } else {
+    *ts = std::min(l_s, 64);
+    *td = std::min(l_d, 64);
+  }
+}
+
+static size_t jac_tile_bytes(const dot_op* op, int l_s, int l_d) {
+  const size_t nb = (size_t)std::max<int64_t>(jac_tables(op).n_rows, 1);
+  const size_t packed = std::max(al256(nb * (l_s + l_d) * sizeof(double)),
+                                 packed_split_u_bytes(op, l_s) +
+                                     al256(nb * ((l_d + 15) / 16) * 16 * sizeof(float)));
+  return jac_partial_bytes(op, l_s, l_d) + packed;
+}
+
+// gradient scratch in diffusion mode: Lambda = Z R_s (N x l_s), one value
+// per face row, one partial per (chunk, active parameter)
+static size_t grad_face_bytes(const dot_op* op, int l_s) {
+  const int na = n_active_bits(op->pals.active, op->g.dim);
+  return al256((size_t)op->g.N * l_s * sizeof(double)) +
+         al256((size_t)std::max<int64_t>(op->n_vrows, 1) * sizeof(double)) +
+         al256((size_t)std::max<int64_t>(op->n_vchunks, 1) * na * sizeof(double));
 }
 
 static size_t jac_bytes(const dot_op* op, int l_s, int l_d) {
   const int na = n_active_bits(op->pals.active, op->g.dim);
-  const size_t nb = (size_t)std::max<int64_t>(op->n_band, 1);
-  const size_t packed = std::max(al256(nb * (l_s + l_d) * sizeof(double)),
-                                 packed_split_u_bytes(op, l_s) +
-                                     al256(nb * ((l_d + 15) / 16) * 16 * sizeof(float)));
-  const size_t jac = jac_partial_bytes(op, l_s, l_d) + packed;
-  const size_t grad = (size_t)op->g.N * sizeof(double) +
-                      (size_t)std::max<int64_t>(op->n_chunks, 1) * na * sizeof(double) + 256;
+  int a = 0, b = 0, c = 0, d = 0;
+  jac_tile_shape(DOT_JAC_FP64, l_s, l_d, na, &a, &b);
+  jac_tile_shape(DOT_JAC_SPLIT_BF16, l_s, l_d, na, &c, &d);
+  const size_t jac = std::max(jac_tile_bytes(op, a, b), jac_tile_bytes(op, c, d));
+  size_t grad = (size_t)op->g.N * sizeof(double) +
+                (size_t)std::max<int64_t>(op->n_chunks, 1) * na * sizeof(double) + 256;
+  if (op->diff_mode) grad = std::max(grad, grad_face_bytes(op, l_s));
   return al256(std::max(jac, grad));
 }
 
@@ -1049,6 +1325,199 @@ int jac_prepare(dot_op* op, hipStream_t s) {
   return DOT_OK;
 }
 
+int jac_prepare_faces(dot_op* op, hipStream_t s) {
+  const GridDims& g = op->g;
+  const int R = 1 + 2 * g.dim;
+  const int na = n_active_bits(op->pals.active, g.dim);
+  const int m0 = op->pals.m0;
+  const int64_t nr = op->n_band * R, nv = op->n_pairs * R;
+  // the three row arrays share one capacity
+  const int64_t old_cap = op->vrow_cap;
+  int rc = grow(&op->vrow_cell, &op->vrow_cap, std::max<int64_t>(nr, 1));
+  if (rc) return rc;
+  if (op->vrow_nbr == nullptr || op->vrow_cap != old_cap) {
+    if (op->vrow_nbr) DOT_HIP(hipFree(op->vrow_nbr));
+    if (op->vrow_w) DOT_HIP(hipFree(op->vrow_w));
+    op->vrow_nbr = nullptr;
+    op->vrow_w = nullptr;
+    DOT_HIP(hipMalloc(&op->vrow_nbr, (size_t)op->vrow_cap * sizeof(int32_t)));
+    DOT_HIP(hipMalloc(&op->vrow_w, (size_t)op->vrow_cap * sizeof(double)));
+  }
+  Faces6 fb;
+  for (int f = 0; f < 6; ++f) fb.bc[f] = op->bc[f];
+  const double ratio = 1.0 + (op->mus_in - op->mus_out) / (op->pals.mu_in - op->pals.mu_out);
+  if (nr > 0) {
+    hipLaunchKernelGGL(vrow_kernel, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s, g, fb,
+                       op->n_band, op->band_cells, op->D0, ratio, R, op->vrow_cell, op->vrow_nbr,
+                       op->vrow_w);
+    DOT_LAUNCH_CHECK();
+  }
+  // virtual pairs (with one zero weight record past the last, as for pairs)
+  int64_t cap = op->vpair_cap;
+  rc = grow(&op->vpair_band, &cap, std::max<int64_t>(nv, 1));
+  if (rc) return rc;
+  if (cap != op->vpair_cap || !op->vpair_g) {
+    if (op->vpair_g) DOT_HIP(hipFree(op->vpair_g));
+    if (op->vpair_g32) DOT_HIP(hipFree(op->vpair_g32));
+    op->vpair_g = nullptr;
+    op->vpair_g32 = nullptr;
+    DOT_HIP(hipMalloc(&op->vpair_g, (size_t)((cap + 1) * na + 8) * sizeof(double)));
+    DOT_HIP(hipMalloc(&op->vpair_g32, (size_t)((cap + 1) * na + 8) * sizeof(float)));
+    op->vpair_cap = cap;
+  }
+  hipLaunchKernelGGL(fill_double_kernel, dim3(1), dim3(64), 0, s, op->vpair_g + nv * na, 8, 0.0);
+  DOT_LAUNCH_CHECK();
+  hipLaunchKernelGGL(fill_float_kernel, dim3(1), dim3(64), 0, s, op->vpair_g32 + nv * na, 8, 0.f);
+  DOT_LAUNCH_CHECK();
+  if (nv > 0) {
+    hipLaunchKernelGGL(vpair_kernel, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s,
+                       op->n_pairs, R, na, op->pair_band, op->pair_g, op->vpair_band, op->vpair_g,
+                       op->vpair_g32);
+    DOT_LAUNCH_CHECK();
+  }
+  // chunks of at most DOT_PAIR_CHUNK virtual pairs within each RBF
+  std::vector<int64_t> start(m0 + 1);
+  DOT_HIP(hipMemcpyAsync(start.data(), op->rbf_start, (size_t)(m0 + 1) * sizeof(int64_t),
+                         hipMemcpyDeviceToHost, s));
+  DOT_HIP(hipStreamSynchronize(s));
+  std::vector<int64_t> vbegin;
+  std::vector<int32_t> vrc(m0 + 1, 0);
+  for (int m = 0; m < m0; ++m) {
+    vrc[m] = (int32_t)vbegin.size();
+    for (int64_t b = start[m] * R; b < start[m + 1] * R; b += DOT_PAIR_CHUNK) vbegin.push_back(b);
+  }
+  vrc[m0] = (int32_t)vbegin.size();
+  const int64_t nch = (int64_t)vbegin.size();
+  vbegin.push_back(nv);
+  rc = grow(&op->vchunk_begin, &op->vchunk_cap, nch + 1);
+  if (rc) return rc;
+  if (op->vrbf_cap < m0 + 1) {
+    if (op->vrbf_chunk0) DOT_HIP(hipFree(op->vrbf_chunk0));
+    op->vrbf_chunk0 = nullptr;
+    DOT_HIP(hipMalloc(&op->vrbf_chunk0, (size_t)(m0 + 1) * sizeof(int32_t)));
+    op->vrbf_cap = m0 + 1;
+  }
+  DOT_HIP(hipMemcpyAsync(op->vchunk_begin, vbegin.data(), (size_t)(nch + 1) * sizeof(int64_t),
+                         hipMemcpyHostToDevice, s));
+  DOT_HIP(hipMemcpyAsync(op->vrbf_chunk0, vrc.data(), (size_t)(m0 + 1) * sizeof(int32_t),
+                         hipMemcpyHostToDevice, s));
+  DOT_HIP(hipStreamSynchronize(s));
+  op->n_vrows = nr;
+  op->n_vpairs = nv;
+  op->n_vchunks = nch;
+  return DOT_OK;
+}
+
+// One tile of the contraction: t_s sources (U columns) x t_d detectors (Z
+// columns) that the matrix-core kernels hold (see jac_tile_shape), reduced
+// into J_s at the tile's place.
+static int jac_tile(dot_op* op, const JacParams& P, int precision, int l_s, const double* U_dev,
+                    int l_d, const double* Z_dev, double* partial, char* packed, const JacOut& o,
+                    double* Js_dev, hipStream_t s) {
+  const int na = P.n_act;
+  const int m0 = op->pals.m0;
+  const int lsld = l_s * l_d;
+  const int L = l_s + l_d;
+  const int MT = (l_s + 15) / 16, NT = (l_d * na + 15) / 16;
+  const int tiles = MT * NT;
+  const int JRs = (l_d + 15) / 16;
+  if (precision == DOT_JAC_FP64 ? !(tiles <= 64 && L <= 16 * JRMAX) : !(MT <= 4 && JRs <= 4))
+    DOT_FAIL(DOT_EINVAL, "internal: contraction tile %d x %d does not fit the kernels", l_s, l_d);
+  const JacTables tab = jac_tables(op);
+  if (tab.n_chunks > 0 && precision == DOT_JAC_FP64) {
+    const dim3 pgrid((unsigned)((tab.n_rows + 63) / 64), (unsigned)((L + 63) / 64));
+    if (tab.face)
+      hipLaunchKernelGGL((pack_rows_kernel<double, true>), pgrid, dim3(256), 0, s, op->g.N,
+                         tab.n_rows, tab.row_cell, tab.row_nbr, tab.row_w, l_s, U_dev, l_d, Z_dev,
+                         (double*)packed);
+    else
+      hipLaunchKernelGGL((pack_rows_kernel<double, false>), pgrid, dim3(256), 0, s, op->g.N,
+                         tab.n_rows, tab.row_cell, tab.row_nbr, tab.row_w, l_s, U_dev, l_d, Z_dev,
+                         (double*)packed);
+    DOT_LAUNCH_CHECK();
+    // tiles per wave, and the columns the padded tiles reach
+    const int qmax = (tiles + 7) / 8;
+    const int ncp = ((8 * qmax - 1) / MT + 1) * 16;
+    const size_t shm = jac_lds_bytes(MT * 16, ncp);
+    int rc = DOT_EINVAL;
+#define DOT_JAC_F64(Q)                                                                           \
+  case Q: {                                                                                      \
+    auto kern = jac_mfma_kernel<Q>;                                                              \
+    DOT_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,   \
+                                (int)shm));                                                      \
+    hipLaunchKernelGGL(kern, dim3((unsigned)tab.n_chunks), dim3(JTHREADS), shm, s, tab.pair_band,   \
+                       tab.pair_g, tab.n_pairs, tab.chunk_begin, l_s, l_d, na,                         \
+                       (const double*)packed, partial, ncp);                                     \
+    DOT_LAUNCH_CHECK();                                                                          \
+    rc = DOT_OK;                                                                                 \
+  } break;
+    switch (qmax) {
+      DOT_JAC_F64(1) DOT_JAC_F64(2) DOT_JAC_F64(3) DOT_JAC_F64(4)
+      DOT_JAC_F64(5) DOT_JAC_F64(6) DOT_JAC_F64(7) DOT_JAC_F64(8)
+    }
+#undef DOT_JAC_F64
+    if (rc) return rc;
+  } else if (tab.n_chunks > 0) {
+    const int terms = precision == DOT_JAC_SPLIT_BF16 ? 2 : 3;
+    char* pu = packed;
+    float* pz = reinterpret_cast<float*>(packed + packed_split_u_bytes(op, l_s));
+    const size_t pshm = (size_t)64 * (L + 1) * sizeof(float);
+    const unsigned pblocks = (unsigned)((tab.n_rows + 63) / 64);
+#define DOT_PACK_SPLIT(TT, FF, W)                                                                \
+  hipLaunchKernelGGL((pack_split_kernel<TT, FF>), dim3(pblocks), dim3(256), pshm, s, op->g.N,   \
+                     tab.n_rows, tab.row_cell, tab.row_nbr, tab.row_w, l_s, U_dev, l_d, Z_dev, MT * 16, \
+                     JRs * 16, reinterpret_cast<W*>(pu), pz)
+    if (terms == 2) {
+      if (tab.face)
+        DOT_PACK_SPLIT(2, true, uint32_t);
+      else
+        DOT_PACK_SPLIT(2, false, uint32_t);
+    } else {
+      if (tab.face)
+        DOT_PACK_SPLIT(3, true, uint2);
+      else
+        DOT_PACK_SPLIT(3, false, uint2);
+    }
+#undef DOT_PACK_SPLIT
+    DOT_LAUNCH_CHECK();
+    const size_t shm = jac_split_lds_bytes(terms, MT, JRs, na);
+    int rc = DOT_EINVAL;
+#define DOT_JS_LAUNCH(T, M, J)                                                                   \
+  if (terms == T && MT == M && JRs == J) {                                                       \
+    auto kern = jac_split_kernel<T, M, J>;                                                       \
+    DOT_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,   \
+                                (int)shm));                                                      \
+    hipLaunchKernelGGL(kern, dim3((unsigned)tab.n_chunks), dim3(JS_THREADS), shm, s,              \
+                       tab.pair_band, tab.pair_g32, tab.n_pairs, tab.chunk_begin, l_s, l_d, na,          \
+                       reinterpret_cast<const typename SplitWord<T>::type*>(pu), pz,             \
+                       reinterpret_cast<float*>(partial));                                       \
+    DOT_LAUNCH_CHECK();                                                                          \
+    rc = DOT_OK;                                                                                 \
+  }
+#define DOT_JS_MT(T)                                                                             \
+  DOT_JS_LAUNCH(T, 1, 1) DOT_JS_LAUNCH(T, 1, 2) DOT_JS_LAUNCH(T, 1, 3) DOT_JS_LAUNCH(T, 1, 4)    \
+  DOT_JS_LAUNCH(T, 2, 1) DOT_JS_LAUNCH(T, 2, 2) DOT_JS_LAUNCH(T, 2, 3) DOT_JS_LAUNCH(T, 2, 4)    \
+  DOT_JS_LAUNCH(T, 3, 1) DOT_JS_LAUNCH(T, 3, 2) DOT_JS_LAUNCH(T, 3, 3) DOT_JS_LAUNCH(T, 3, 4)    \
+  DOT_JS_LAUNCH(T, 4, 1) DOT_JS_LAUNCH(T, 4, 2) DOT_JS_LAUNCH(T, 4, 3) DOT_JS_LAUNCH(T, 4, 4)
+    DOT_JS_MT(2)
+    DOT_JS_MT(3)
+#undef DOT_JS_MT
+#undef DOT_JS_LAUNCH
+    if (rc) return rc;
+  }
+  dim3 grid((lsld * na + 255) / 256, m0);
+  if (precision != DOT_JAC_FP64 && tab.n_chunks > 0) {
+    hipLaunchKernelGGL(jac_reduce_runs_kernel, grid, dim3(256), 0, s, m0, tab.rbf_chunk0,
+                       tab.chunk_begin, lsld, na, reinterpret_cast<const float*>(partial), o,
+                       Js_dev);
+  } else {
+    hipLaunchKernelGGL(jac_reduce_kernel, grid, dim3(256), 0, s, m0, tab.rbf_chunk0, lsld, na,
+                       partial, o, Js_dev);
+  }
+  DOT_LAUNCH_CHECK();
+  return DOT_OK;
+}
+
 }  // namespace dot
 
 using namespace dot;
@@ -1070,137 +1539,81 @@ int dot_jacobian(dot_op* op, int l_s, const double* U_dev, int l_d, const double
   if (precision != DOT_JAC_FP64 && precision != DOT_JAC_SPLIT_BF16 &&
       precision != DOT_JAC_SPLIT_BF16X3)
     DOT_FAIL(DOT_EINVAL, "precision must be DOT_JAC_FP64, DOT_JAC_SPLIT_BF16 or _BF16X3");
-  if (l_s > 1024) DOT_FAIL(DOT_EINVAL, "l_s must be <= 1024");
+  if (l_s > DOT_MAX_COLUMNS || l_d > DOT_MAX_COLUMNS)
+    DOT_FAIL(DOT_EINVAL, "l_s and l_d must be <= %d", DOT_MAX_COLUMNS);
   const size_t need = jac_bytes(op, l_s, l_d);
   if (!work_dev || work_bytes < need)
     DOT_FAIL(DOT_ENOMEM, "workspace too small: need %zu bytes, got %zu", need, work_bytes);
   hipStream_t s = as_stream(stream);
   const JacParams P = make_params(op);
-  const int na = P.n_act;
-  const int m0 = op->pals.m0;
-  const int lsld = l_s * l_d;
-  const int L = l_s + l_d;
-  const int MT = (l_s + 15) / 16, NT = (l_d * na + 15) / 16;
-  const int tiles = MT * NT;
-  // binary64: at most 8 tiles per wave and JRMAX staged values per thread,
-  // beyond that the plain kernel.  Split forms: l_s <= 64 and l_d <= 64.
-  const int JRs = (l_d + 15) / 16;
-  const bool mfma_fits = precision == DOT_JAC_FP64 ? tiles <= 64 && L <= 16 * JRMAX
-                                                   : MT <= 4 && JRs <= 4;
-  if (precision != DOT_JAC_FP64 && !mfma_fits)
-    DOT_FAIL(DOT_EINVAL, "l_s, l_d and n_act too large for the split-bf16 kernel");
-  if (precision == DOT_JAC_FP64 && !mfma_fits &&
-      (size_t)JB * (l_s + l_d + 5) * sizeof(double) > 64 * 1024)
-    DOT_FAIL(DOT_EINVAL, "l_s + l_d too large for the contraction kernel");
+  int ts = 0, td = 0;
+  jac_tile_shape(precision, l_s, l_d, P.n_act, &ts, &td);
   double* partial = (double*)work_dev;
-  char* packed = (char*)work_dev + jac_partial_bytes(op, l_s, l_d);
+  char* packed = (char*)work_dev + jac_partial_bytes(op, ts, td);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   unsigned long long* cols = nullptr;
   DOT_TRY_J(profile_begin(op, DOT_PROF_JACOBIAN, s, &e0, &e1, &cols));
-  if (op->n_chunks > 0 && !mfma_fits) {
-    const size_t shm = (size_t)JB * (l_s + l_d + na) * sizeof(double);
-    hipLaunchKernelGGL(jac_chunk_fp64_kernel, dim3((unsigned)op->n_chunks), dim3(JT), shm, s, op->g,
-                       P, op->theta, op->phi, op->pair_cell, op->chunk_begin, op->chunk_rbf, l_s,
-                       U_dev, l_d, Z_dev, partial);
-    DOT_LAUNCH_CHECK();
-  } else if (op->n_chunks > 0 && precision == DOT_JAC_FP64) {
-    const dim3 pgrid((unsigned)((op->n_band + 63) / 64), (unsigned)((L + 63) / 64));
-    hipLaunchKernelGGL(pack_rows_kernel<double>, pgrid, dim3(256), 0, s, op->g.N, op->n_band,
-                       op->band_cells, l_s, U_dev, l_d, Z_dev, (double*)packed);
-    DOT_LAUNCH_CHECK();
-    // tiles per wave, and the columns the padded tiles reach
-    const int qmax = (tiles + 7) / 8;
-    const int ncp = ((8 * qmax - 1) / MT + 1) * 16;
-    const size_t shm = jac_lds_bytes(MT * 16, ncp);
-    int rc = DOT_EINVAL;
-#define DOT_JAC_F64(Q)                                                                           \
-  case Q: {                                                                                      \
-    auto kern = jac_mfma_kernel<Q>;                                                              \
-    DOT_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,   \
-                                (int)shm));                                                      \
-    hipLaunchKernelGGL(kern, dim3((unsigned)op->n_chunks), dim3(JTHREADS), shm, s, op->pair_band, \
-                       op->pair_g, op->n_pairs, op->chunk_begin, l_s, l_d, na,                   \
-                       (const double*)packed, partial, ncp);                                     \
-    DOT_LAUNCH_CHECK();                                                                          \
-    rc = DOT_OK;                                                                                 \
-  } break;
-    switch (qmax) {
-      DOT_JAC_F64(1) DOT_JAC_F64(2) DOT_JAC_F64(3) DOT_JAC_F64(4)
-      DOT_JAC_F64(5) DOT_JAC_F64(6) DOT_JAC_F64(7) DOT_JAC_F64(8)
+  for (int i0 = 0; i0 < l_s; i0 += ts)
+    for (int j0 = 0; j0 < l_d; j0 += td) {
+      const int ti = std::min(ts, l_s - i0), tj = std::min(td, l_d - j0);
+      JacOut o;
+      o.tj = tj;
+      o.base = j0 + (int64_t)l_d * i0;
+      o.ldi = l_d;
+      o.ldk = (int64_t)l_s * l_d;
+      DOT_TRY_J(jac_tile(op, P, precision, ti, U_dev + op->g.N * (int64_t)i0, tj,
+                         Z_dev + op->g.N * (int64_t)j0, partial, packed, o, Js_dev, s));
     }
-#undef DOT_JAC_F64
-    if (rc) return rc;
-  } else if (op->n_chunks > 0) {
-    const int terms = precision == DOT_JAC_SPLIT_BF16 ? 2 : 3;
-    char* pu = packed;
-    float* pz = reinterpret_cast<float*>(packed + packed_split_u_bytes(op, l_s));
-    const size_t pshm = (size_t)64 * (L + 1) * sizeof(float);
-    const unsigned pblocks = (unsigned)((op->n_band + 63) / 64);
-    if (terms == 2) {
-      hipLaunchKernelGGL(pack_split_kernel<2>, dim3(pblocks), dim3(256), pshm, s, op->g.N,
-                         op->n_band, op->band_cells, l_s, U_dev, l_d, Z_dev, MT * 16, JRs * 16,
-                         reinterpret_cast<uint32_t*>(pu), pz);
-    } else {
-      hipLaunchKernelGGL(pack_split_kernel<3>, dim3(pblocks), dim3(256), pshm, s, op->g.N,
-                         op->n_band, op->band_cells, l_s, U_dev, l_d, Z_dev, MT * 16, JRs * 16,
-                         reinterpret_cast<uint2*>(pu), pz);
-    }
-    DOT_LAUNCH_CHECK();
-    const size_t shm = jac_split_lds_bytes(terms, MT, JRs, na);
-    int rc = DOT_EINVAL;
-#define DOT_JS_LAUNCH(T, M, J)                                                                   \
-  if (terms == T && MT == M && JRs == J) {                                                       \
-    auto kern = jac_split_kernel<T, M, J>;                                                       \
-    DOT_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,   \
-                                (int)shm));                                                      \
-    hipLaunchKernelGGL(kern, dim3((unsigned)op->n_chunks), dim3(JS_THREADS), shm, s,             \
-                       op->pair_band, op->pair_g32, op->n_pairs, op->chunk_begin, l_s, l_d, na,  \
-                       reinterpret_cast<const typename SplitWord<T>::type*>(pu), pz,             \
-                       reinterpret_cast<float*>(partial));                                       \
-    DOT_LAUNCH_CHECK();                                                                          \
-    rc = DOT_OK;                                                                                 \
-  }
-#define DOT_JS_MT(T)                                                                             \
-  DOT_JS_LAUNCH(T, 1, 1) DOT_JS_LAUNCH(T, 1, 2) DOT_JS_LAUNCH(T, 1, 3) DOT_JS_LAUNCH(T, 1, 4)    \
-  DOT_JS_LAUNCH(T, 2, 1) DOT_JS_LAUNCH(T, 2, 2) DOT_JS_LAUNCH(T, 2, 3) DOT_JS_LAUNCH(T, 2, 4)    \
-  DOT_JS_LAUNCH(T, 3, 1) DOT_JS_LAUNCH(T, 3, 2) DOT_JS_LAUNCH(T, 3, 3) DOT_JS_LAUNCH(T, 3, 4)    \
-  DOT_JS_LAUNCH(T, 4, 1) DOT_JS_LAUNCH(T, 4, 2) DOT_JS_LAUNCH(T, 4, 3) DOT_JS_LAUNCH(T, 4, 4)
-    DOT_JS_MT(2)
-    DOT_JS_MT(3)
-#undef DOT_JS_MT
-#undef DOT_JS_LAUNCH
-    if (rc) return rc;
-  }
-  dim3 grid((lsld * na + 255) / 256, m0);
-  if (precision != DOT_JAC_FP64 && op->n_chunks > 0) {
-    hipLaunchKernelGGL(jac_reduce_runs_kernel, grid, dim3(256), 0, s, m0, op->rbf_chunk0,
-                       op->chunk_begin, lsld, na, reinterpret_cast<const float*>(partial), Js_dev);
-  } else {
-    hipLaunchKernelGGL(jac_reduce_kernel, grid, dim3(256), 0, s, m0, op->rbf_chunk0, lsld, na,
-                       partial, Js_dev);
-  }
-  DOT_LAUNCH_CHECK();
   return profile_end(op, DOT_PROF_JACOBIAN, s, e0, e1);
 }
 
-int dot_grad_misfit(dot_op* op, int l_s, const double* U_dev, int l_d, const double* Z_dev,
-                    const double* Rs_dev, double* g_dev, void* work_dev, size_t work_bytes,
-                    void* stream) {
-  clear_error();
+}  // extern "C"
+
+namespace dot {
+
+static int grad_check_args(const dot_op* op, int l_s, int l_d, const double* U_dev,
+                           const double* Z_dev, const double* Rs_dev, const double* g_dev) {
   if (!op) DOT_FAIL(DOT_EINVAL, "op is NULL");
   if (!op->have_pals) DOT_FAIL(DOT_EINVAL, "dot_pals_mua has not been called on this handle");
   if (l_s < 1 || l_d < 1) DOT_FAIL(DOT_EINVAL, "l_s and l_d must be >= 1");
   if (!U_dev || !Z_dev || !Rs_dev || !g_dev) DOT_FAIL(DOT_EINVAL, "NULL argument");
   if ((size_t)l_s * l_d * sizeof(double) > 48 * 1024)
     DOT_FAIL(DOT_EINVAL, "l_s * l_d too large for the gradient kernel");
-  const size_t need = jac_bytes(op, l_s, l_d);
-  if (!work_dev || work_bytes < need)
-    DOT_FAIL(DOT_ENOMEM, "workspace too small: need %zu bytes, got %zu", need, work_bytes);
-  hipStream_t s = as_stream(stream);
+  return DOT_OK;
+}
+
+// The gradient's launches on scratch memory sc: per-cell sums s_c (N values,
+// padded to 32), then one partial per (chunk, active parameter).
+static int grad_run(dot_op* op, int l_s, const double* U_dev, int l_d, const double* Z_dev,
+                    const double* Rs_dev, double* g_dev, double* sc, hipStream_t s) {
   const JacParams P = make_params(op);
   const int na = P.n_act;
   const int m0 = op->pals.m0;
-  double* sc = (double*)work_dev;
+  if (op->diff_mode) {
+    double* lam = sc;
+    double* e = lam + al256((size_t)op->g.N * l_s * sizeof(double)) / sizeof(double);
+    double* partial =
+        e + al256((size_t)std::max<int64_t>(op->n_vrows, 1) * sizeof(double)) / sizeof(double);
+    hipLaunchKernelGGL(lambda_kernel, dim3((unsigned)((op->g.N + 255) / 256)), dim3(256),
+                       (size_t)l_s * l_d * sizeof(double), s, op->g.N, l_s, l_d, Z_dev, Rs_dev,
+                       lam);
+    DOT_LAUNCH_CHECK();
+    if (op->n_vrows > 0) {
+      hipLaunchKernelGGL(grad_vrow_kernel, dim3((unsigned)((op->n_vrows + 255) / 256)), dim3(256),
+                         0, s, op->g.N, op->n_vrows, l_s, op->vrow_cell, op->vrow_nbr, op->vrow_w,
+                         U_dev, lam, e);
+      DOT_LAUNCH_CHECK();
+    }
+    if (op->n_vchunks > 0) {
+      hipLaunchKernelGGL(grad_chunk_kernel, dim3((unsigned)op->n_vchunks), dim3(256), 0, s, na,
+                         op->vpair_band, op->vpair_g, op->vchunk_begin, e, partial);
+      DOT_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(grad_reduce_kernel, dim3((m0 * na + 255) / 256), dim3(256), 0, s, m0,
+                       op->vrbf_chunk0, na, partial, g_dev);
+    DOT_LAUNCH_CHECK();
+    return DOT_OK;
+  }
   double* partial = sc + ((op->g.N + 31) / 32) * 32;
   if (l_s <= 32)
     hipLaunchKernelGGL(grad_cell_small_kernel<32>, dim3((unsigned)((op->g.N + 255) / 256)), dim3(256),
@@ -1220,6 +1633,46 @@ int dot_grad_misfit(dot_op* op, int l_s, const double* U_dev, int l_d, const dou
                      op->rbf_chunk0, na, partial, g_dev);
   DOT_LAUNCH_CHECK();
   return DOT_OK;
+}
+
+}  // namespace dot
+
+extern "C" {
+
+int dot_dadp_apply(dot_op* op, int k, const double* Theta_dev, const double* X_dev, double* Y_dev,
+                 void* stream) {
+  clear_error();
+  if (!op) DOT_FAIL(DOT_EINVAL, "op is NULL");
+  if (!op->have_pals) DOT_FAIL(DOT_EINVAL, "dot_pals_mua has not been called on this handle");
+  if (k < 1 || k > DOT_MAX_COLUMNS) DOT_FAIL(DOT_EINVAL, "k must be in [1, %d]", DOT_MAX_COLUMNS);
+  if (!Theta_dev || !X_dev || !Y_dev) DOT_FAIL(DOT_EINVAL, "NULL argument");
+  if (X_dev == Y_dev) DOT_FAIL(DOT_EINVAL, "X_dev and Y_dev must not overlap");
+  if (op->diff_mode)
+    DOT_FAIL(DOT_EINVAL, "dot_dadp_apply covers the absorption-only model (dot_pals_mua)");
+  const JacParams P = make_params(op);
+  const int n_p = op->pals.m0 * P.n_act;
+  const GridDims& g = op->g;
+  int64_t tiles;
+  if (g.dim == 3)
+    tiles = (int64_t)((g.nx + 7) / 8) * ((g.ny + 7) / 8) * ((g.nz + 3) / 4);
+  else
+    tiles = (int64_t)((g.nx + 15) / 16) * ((g.ny + 15) / 16);
+  hipLaunchKernelGGL(dA_dir_kernel, dim3((unsigned)tiles), dim3(256), 0, as_stream(stream), g, P,
+                     op->theta, op->phi, op->pals.m0, k, Theta_dev, n_p, X_dev, Y_dev);
+  DOT_LAUNCH_CHECK();
+  return DOT_OK;
+}
+
+int dot_grad_misfit(dot_op* op, int l_s, const double* U_dev, int l_d, const double* Z_dev,
+                    const double* Rs_dev, double* g_dev, void* work_dev, size_t work_bytes,
+                    void* stream) {
+  clear_error();
+  DOT_TRY_J(grad_check_args(op, l_s, l_d, U_dev, Z_dev, Rs_dev, g_dev));
+  const size_t need = jac_bytes(op, l_s, l_d);
+  if (!work_dev || work_bytes < need)
+    DOT_FAIL(DOT_ENOMEM, "workspace too small: need %zu bytes, got %zu", need, work_bytes);
+  return grad_run(op, l_s, U_dev, l_d, Z_dev, Rs_dev, g_dev, (double*)work_dev,
+                  as_stream(stream));
 }
 
 }  // extern "C"

@@ -298,10 +298,18 @@ __device__ __forceinline__ int bj_index(int I, int J, int i) {
   return i < BJ_B ? I * BJ_B + i : J * BJ_B + (i - BJ_B);
 }
 
-__global__ __launch_bounds__(64) void bj_eig_kernel(int ld, int nbk, int round,
-                                                    const double* __restrict__ G,
-                                                    double* __restrict__ Qbuf, int max_inner,
-                                                    double floor, int* __restrict__ flag) {
+// One block of BJT threads per pair of index blocks: the 16 disjoint
+// rotations of a step are applied by 32 threads each (one matrix index per
+// thread), so a step is two LDS phases of one load and one store per value.
+constexpr int BJT = 512;
+constexpr int BJ_PG = BJT / BJ_S;         // rotation pairs applied at once
+constexpr int BJ_PM = (BJ_S / 2) / BJ_PG; // rotation pairs per thread
+constexpr int BJ_EM = BJ_S * BJ_S / BJT;  // matrix entries per thread
+
+__global__ __launch_bounds__(BJT) void bj_eig_kernel(int ld, int nbk, int round,
+                                                     const double* __restrict__ G,
+                                                     double* __restrict__ Qbuf, int max_inner,
+                                                     double floor, int* __restrict__ flag) {
   __shared__ double a[BJ_S][BJ_S + 1];
   __shared__ double v[BJ_S][BJ_S + 1];
   __shared__ double cs[BJ_S / 2][2];
@@ -310,7 +318,7 @@ __global__ __launch_bounds__(64) void bj_eig_kernel(int ld, int nbk, int round,
   const int t = threadIdx.x;
   int I, J;
   tournament(nbk, round, blockIdx.x, &I, &J);
-  for (int e = t; e < BJ_S * BJ_S; e += 64) {
+  for (int e = t; e < BJ_S * BJ_S; e += BJT) {
     const int i = e % BJ_S, j = e / BJ_S;
     a[i][j] = G[bj_index(I, J, i) + (int64_t)ld * bj_index(I, J, j)];
     v[i][j] = i == j ? 1.0 : 0.0;
@@ -335,31 +343,31 @@ __global__ __launch_bounds__(64) void bj_eig_kernel(int ld, int nbk, int round,
         cs[t][1] = s;
       }
       __syncthreads();
-      // lane t owns index x = t % BJ_S of the pairs k = t / BJ_S + 2 m: all
-      // LDS loads of a phase are issued before its stores (the elements of
-      // distinct pairs are disjoint), so each phase waits on LDS once
+      // thread t owns index x = t % BJ_S of the pairs k = t / BJ_S + BJ_PG m;
+      // all LDS loads of a phase are issued before its stores (the elements
+      // of distinct pairs are disjoint)
       const int x = t % BJ_S, kb = t / BJ_S;
-      int pp[8], qq[8];
-      double cc[8], ss[8];
+      int pp[BJ_PM], qq[BJ_PM];
+      double cc[BJ_PM], ss[BJ_PM];
 #pragma unroll
-      for (int m = 0; m < 8; ++m) {
-        const int k = kb + 2 * m;
+      for (int m = 0; m < BJ_PM; ++m) {
+        const int k = kb + BJ_PG * m;
         pp[m] = pq[k][0];
         qq[m] = pq[k][1];
         cc[m] = cs[k][0];
         ss[m] = cs[k][1];
       }
       {
-        double axp[8], axq[8], vxp[8], vxq[8];
+        double axp[BJ_PM], axq[BJ_PM], vxp[BJ_PM], vxq[BJ_PM];
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
+        for (int m = 0; m < BJ_PM; ++m) {
           axp[m] = a[x][pp[m]];
           axq[m] = a[x][qq[m]];
           vxp[m] = v[x][pp[m]];
           vxq[m] = v[x][qq[m]];
         }
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
+        for (int m = 0; m < BJ_PM; ++m) {
           a[x][pp[m]] = cc[m] * axp[m] - ss[m] * axq[m];
           a[x][qq[m]] = ss[m] * axp[m] + cc[m] * axq[m];
           v[x][pp[m]] = cc[m] * vxp[m] - ss[m] * vxq[m];
@@ -368,9 +376,9 @@ __global__ __launch_bounds__(64) void bj_eig_kernel(int ld, int nbk, int round,
       }
       __syncthreads();
       {
-        double apx[8], aqx[8];
+        double apx[BJ_PM], aqx[BJ_PM];
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
+        for (int m = 0; m < BJ_PM; ++m) {
           apx[m] = a[pp[m]][x];
           aqx[m] = a[qq[m]][x];
         }
@@ -378,7 +386,7 @@ __global__ __launch_bounds__(64) void bj_eig_kernel(int ld, int nbk, int round,
         // rounding residue, which would otherwise keep the threshold test
         // above firing when a_pp and a_qq differ greatly in size
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
+        for (int m = 0; m < BJ_PM; ++m) {
           const bool rot = ss[m] != 0.0;
           a[pp[m]][x] = (rot && x == qq[m]) ? 0.0 : cc[m] * apx[m] - ss[m] * aqx[m];
           a[qq[m]][x] = (rot && x == pp[m]) ? 0.0 : ss[m] * apx[m] + cc[m] * aqx[m];
@@ -396,37 +404,37 @@ __global__ __launch_bounds__(64) void bj_eig_kernel(int ld, int nbk, int round,
   // diagonal tile is then recomputed as Q^T S Q like every other tile: the
   // rotated submatrix itself carries the rounding of every inner rotation.
   if (rotated) {
-    double acc[16];
+    double acc[BJ_EM];
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      const int e = t + 64 * m, i = e % BJ_S, j = e / BJ_S;
+    for (int m = 0; m < BJ_EM; ++m) {
+      const int e = t + BJT * m, i = e % BJ_S, j = e / BJ_S;
       double g = 0.0;
       for (int k = 0; k < BJ_S; ++k) g = fma(v[k][i], v[k][j], g);
       acc[m] = (i == j ? 1.0 : 0.0) - g;
     }
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      const int e = t + 64 * m;
+    for (int m = 0; m < BJ_EM; ++m) {
+      const int e = t + BJT * m;
       a[e % BJ_S][e / BJ_S] = acc[m];
     }
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      const int e = t + 64 * m, i = e % BJ_S, j = e / BJ_S;
+    for (int m = 0; m < BJ_EM; ++m) {
+      const int e = t + BJT * m, i = e % BJ_S, j = e / BJ_S;
       double g = 0.0;
       for (int k = 0; k < BJ_S; ++k) g = fma(v[i][k], a[k][j], g);
       acc[m] = fma(0.5, g, v[i][j]);
     }
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      const int e = t + 64 * m;
+    for (int m = 0; m < BJ_EM; ++m) {
+      const int e = t + BJT * m;
       v[e % BJ_S][e / BJ_S] = acc[m];
     }
     __syncthreads();
   }
   double* Q = Qbuf + (int64_t)blockIdx.x * BJ_S * BJ_S;
-  for (int e = t; e < BJ_S * BJ_S; e += 64) Q[e] = v[e % BJ_S][e / BJ_S];
+  for (int e = t; e < BJ_S * BJ_S; e += BJT) Q[e] = v[e % BJ_S][e / BJ_S];
   if (t == 0 && rotated) atomicOr(flag, 1);
 }
 
@@ -717,7 +725,7 @@ static int symeig(int n, const double* A, int lda, double* w, double* V, int ldv
     hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, s, flag, 0);
     DOT_LAUNCH_CHECK();
     for (int round = 0; round < nbk - 1; ++round) {
-      hipLaunchKernelGGL(bj_eig_kernel, dim3(npairs), dim3(64), 0, s, ld, nbk, round, Gw, Qb,
+      hipLaunchKernelGGL(bj_eig_kernel, dim3(npairs), dim3(BJT), 0, s, ld, nbk, round, Gw, Qb,
                          BJ_INNER_SWEEPS, floor, flag);
       DOT_LAUNCH_CHECK();
       hipLaunchKernelGGL(bj_update_kernel, dim3(ntiles), dim3(256), 0, s, ld, nbk, round, Gw, Vw,

@@ -1,10 +1,12 @@
 // Geometric multigrid V-cycle: the preconditioner of the multi-right-hand-side
-// CG on 3D grids that halve (the forward and adjoint solves of Section 3.3).
+// CG (the forward and adjoint solves of Section 3.3), on 3D and 2D grids.
 //
 // The CG runs on the symmetrically scaled system A^ = S^-1 A S^-1 (S =
 // sqrt(diag A)); its preconditioner is z = S V(S r), V one V-cycle for A.
-// Every level is kept in scaled form (unit diagonal), so with P the 2 x 2 x 2
-// piecewise-constant prolongation the transfers between level l (scaling S_l)
+// Every level is kept in scaled form (unit diagonal), so with P the
+// piecewise-constant prolongation (a coarse value copied to the 2 x 2 x 2
+// children of its aggregate; 2 x 2 in 2D, fewer in the last aggregate of an
+// odd side) the transfers between level l (scaling S_l)
 // and level l + 1 (S_{l+1}) are
 //     prolongation  x^_l += S_l P S_{l+1}^-1 x^_{l+1}   (weight q = sd / sd_parent)
 //     restriction   b^_{l+1} = S_{l+1}^-1 P^T S_l r^_l   (its transpose)
@@ -284,14 +286,16 @@ __global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T> a) {
       const T Av = vc[r] - cW * vW - cE * vE - cS * vS - cN * vN - cD * vm[r] - cU * vp[r];
       const T bv = bcur[r];
       if constexpr (MODE == MG_DOWN) {
-        // restriction: S_l (b - A^ x) summed over the 2 x 2 x 2 aggregate
+        // restriction: S_l (b - A^ x) summed over the aggregate (cells
+        // outside the grid contribute zero)
         const T e = in ? sdv * (bv - Av) : T(0);
         T s2 = e + __shfl_xor(e, 1, 64);
         s2 += __shfl_xor(s2, 32, 64);
-        if ((z & 1) == 0) {
-          zacc[r] = s2;
-        } else {
-          zacc[r] += s2;
+        // the aggregate is complete after its odd plane, or after an even
+        // plane that is the last of an odd n_z (also the one plane in 2D)
+        if ((z & 1) == 0) zacc[r] = s2;
+        else zacc[r] += s2;
+        if ((z & 1) == 1 || z + 1 == G.nz) {
           if (in && (lane & 33) == 0) {
             const int64_t C = (x >> 1) + (int64_t)G.cnx * (y >> 1) + G.cnxy * (z >> 1);
             a.bc[C + a.cld * col[r]] = zacc[r] / sdc_next;
@@ -494,10 +498,11 @@ __global__ __launch_bounds__(MG_TAIL_THREADS) void mg_tail_kernel(MgTailArgs<T> 
     for (int cc = t; cc < C.N; cc += MG_TAIL_THREADS) {
       const int X = cc % C.nx, Y = (cc / C.nx) % C.ny, Z = cc / (C.nx * C.ny);
       const int f0 = 2 * X + L.nx * (2 * Y) + nxy * (2 * Z);
+      const int ex = min(2, L.nx - 2 * X), ey = min(2, L.ny - 2 * Y), ez = min(2, L.nz - 2 * Z);
       T s = T(0);
-      for (int dz = 0; dz < 2; ++dz)
-        for (int dy = 0; dy < 2; ++dy)
-          for (int dx = 0; dx < 2; ++dx) s += r[f0 + dx + L.nx * dy + nxy * dz];
+      for (int dz = 0; dz < ez; ++dz)
+        for (int dy = 0; dy < ey; ++dy)
+          for (int dx = 0; dx < ex; ++dx) s += r[f0 + dx + L.nx * dy + nxy * dz];
       bc[cc] = s / (T)C.sd[cc];
     }
     __syncthreads();

@@ -111,24 +111,6 @@ __device__ __forceinline__ double heaviside_eps(double s, double eps) {
   return 0.5 * (1.0 + s / eps + sin(M_PI * s / eps) / M_PI);
 }
 
-// Block-wide exclusive prefix sum of a 0/1 flag over 256 threads; returns the
-// position and sets *total.  Order follows threadIdx.x, so compaction is
-// deterministic.
-__device__ __forceinline__ int block_scan_flag256(int flag, int* s_wave, int* total) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const unsigned long long bal = __ballot(flag);
-  const int before = __popcll(bal & ((1ull << lane) - 1ull));
-  if (lane == 0) s_wave[wave] = __popcll(bal);
-  __syncthreads();
-  int off = 0, tot = 0;
-  for (int w = 0; w < 4; ++w) {
-    if (w < wave) off += s_wave[w];
-    tot += s_wave[w];
-  }
-  *total = tot;
-  return off + before;
-}
-
 // One block of 256 threads per cell tile (8x8x4 in 3D, 16x16 in 2D).  RBFs are
 // culled against the tile's bounding box in chunks of 256, compacted in RBF
 // order, and summed in that order at each cell centre.
@@ -314,8 +296,41 @@ __global__ void scale_kernel(GridDims g, const double* __restrict__ cx, const do
 
 static unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// D = 1 / (3 (mu + mu_s)) with both optical properties from the level set:
+// mu = mu_out + (mu_in - mu_out) H, mu_s = mus_out + (mus_in - mus_out) H,
+// H = H_eps(phi - cutoff).
+__global__ void diff_from_phi_kernel(GridDims g, PalsK p, double mus_in, double mus_out,
+                                     const double* __restrict__ phi, double* __restrict__ D) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= g.N) return;
+  const double H = heaviside_eps(phi[c] - p.cutoff, p.eps);
+  const double mu = p.mu_in * H + p.mu_out * (1.0 - H);
+  const double ms = mus_in * H + mus_out * (1.0 - H);
+  D[c] = 1.0 / (3.0 * (mu + ms));
+}
+
+// face coefficients and boundary diagonal from the diffusion field in D0
+static int rebuild_coefficients(dot_op* op, hipStream_t s) {
+  BC6 bc;
+  for (int f = 0; f < 6; ++f) bc.f[f] = op->bc[f];
+  hipLaunchKernelGGL(build_coef_kernel, dim3(nblk(op->g.N, 256)), dim3(256), 0, s, op->g, bc,
+                     op->D0, op->cx, op->cy, op->cz, op->b0);
+  DOT_LAUNCH_CHECK();
+  return DOT_OK;
+}
+
+// back to the diffusion given at build time (absorption-only calls)
+static int leave_diffusion_mode(dot_op* op, hipStream_t s) {
+  if (!op->diff_mode) return DOT_OK;
+  DOT_HIP(hipMemcpyAsync(op->D0, op->Dbuild, (size_t)op->g.N * sizeof(double),
+                         hipMemcpyDeviceToDevice, s));
+  op->diff_mode = false;
+  return rebuild_coefficients(op, s);
+}
+
 // ------------------------------------------------------------------ multigrid setup
-// coarse D and mu: means over the 2 x 2 x 2 children
+// coarse D and mu: means over the children of the aggregate (2 x 2 x 2, or
+// 2 x 2 in 2D; fewer in the last aggregate of an odd side)
 __global__ void mg_coarsen_kernel(GridDims gf, GridDims gc, const double* __restrict__ Df,
                                   const double* __restrict__ muf, double* __restrict__ Dc,
                                   double* __restrict__ muc) {
@@ -325,15 +340,19 @@ __global__ void mg_coarsen_kernel(GridDims gf, GridDims gc, const double* __rest
   const int Y = (int)((C / gc.nx) % gc.ny);
   const int Z = (int)(C / gc.nxy);
   double sD = 0.0, sm = 0.0;
+  int cnt = 0;
   for (int dz = 0; dz < 2; ++dz)
     for (int dy = 0; dy < 2; ++dy)
       for (int dx = 0; dx < 2; ++dx) {
-        const int64_t c = (2 * X + dx) + gf.nx * ((int64_t)(2 * Y + dy) + gf.ny * (int64_t)(2 * Z + dz));
+        const int x = 2 * X + dx, y = 2 * Y + dy, z = 2 * Z + dz;
+        if (x >= gf.nx || y >= gf.ny || z >= gf.nz) continue;
+        const int64_t c = x + gf.nx * ((int64_t)y + gf.ny * (int64_t)z);
         sD += Df[c];
         sm += muf[c];
+        ++cnt;
       }
-  Dc[C] = 0.125 * sD;
-  muc[C] = 0.125 * sm;
+  Dc[C] = sD / cnt;
+  muc[C] = sm / cnt;
 }
 
 // prolongation weight sd(c) / sd_coarse(parent(c))
@@ -365,21 +384,30 @@ __global__ void mg_check_kernel(int64_t N, const double* __restrict__ diag, int*
 
 __global__ void mg_flag_clear_kernel(int* __restrict__ flag) { flag[0] = 0; }
 
+// Level l + 1 halves every side of level l, rounding up (the last aggregate
+// of an odd side has one cell along it; 2D grids keep n_z = 1), while every
+// coarse side keeps at least MG_MIN_SIDE cells.  A coarse level is the same
+// discretization with h = 1 / n_x, like the finest.
+constexpr int MG_MIN_SIDE = 3;
+
 int mg_levels_for(const GridDims& g, GridDims* lv) {
-  if (g.dim != 3) return 0;
+  if (g.dim != 2 && g.dim != 3) return 0;
+  auto coarse_ok = [&](const GridDims& c) {
+    return (c.nx + 1) / 2 >= MG_MIN_SIDE && (c.ny + 1) / 2 >= MG_MIN_SIDE &&
+           (c.dim == 2 || (c.nz + 1) / 2 >= MG_MIN_SIDE);
+  };
   int n = 0;
   GridDims cur = g;
   lv[n++] = cur;
-  while (n < DOT_MG_MAXLEV && cur.nx % 2 == 0 && cur.ny % 2 == 0 && cur.nz % 2 == 0 &&
-         std::min(cur.nx, std::min(cur.ny, cur.nz)) >= 8) {
+  while (n < DOT_MG_MAXLEV && coarse_ok(cur)) {
     GridDims c = cur;
-    c.nx /= 2;
-    c.ny /= 2;
-    c.nz /= 2;
+    c.nx = (cur.nx + 1) / 2;
+    c.ny = (cur.ny + 1) / 2;
+    c.nz = cur.dim == 3 ? (cur.nz + 1) / 2 : 1;
     c.nxy = (int64_t)c.nx * c.ny;
     c.N = c.nxy * c.nz;
-    c.h = 2.0 * cur.h;
-    c.hd = c.h * c.h * c.h;
+    c.h = 1.0 / c.nx;
+    c.hd = cur.dim == 3 ? c.h * c.h * c.h : c.h * c.h;
     lv[n++] = c;
     cur = c;
   }
@@ -696,7 +724,9 @@ int dot_destroy_operator(dot_op* op) {
                   op->sy32,      op->sz32,       op->phi,         op->theta,     op->pair_cell,
                   op->rbf_start, op->chunk_rbf,  op->chunk_begin, op->rbf_chunk0, op->cells_dev,  op->small_dev,
                   op->pair_g,    op->pair_g32,   op->pair_band,   op->band_idx,   op->band_cells,
-                  op->band_part, op->D0,         op->mu0,         op->rbf_sub};
+                  op->band_part, op->D0,         op->mu0,         op->rbf_sub,
+                  op->Dbuild,    op->vrow_cell,  op->vrow_nbr,    op->vrow_w,    op->vpair_band,
+                  op->vpair_g,   op->vpair_g32,  op->vchunk_begin, op->vrbf_chunk0};
   mg_free(op);
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -719,8 +749,18 @@ int dot_set_mua(dot_op* op, const double* mua_dev, void* stream) {
   if (!op) DOT_FAIL(DOT_EINVAL, "op is NULL");
   if (!mua_dev) DOT_FAIL(DOT_EINVAL, "mua_dev is NULL");
   op->have_pals = false;
+  const int rc = leave_diffusion_mode(op, as_stream(stream));
+  if (rc) return rc;
   return refresh_diag(op, mua_dev, as_stream(stream));
 }
+
+}  // extern "C"
+
+static int pals_state(dot_op* op, const dot_pals* pals, const double* theta_dev, double* mua_dev,
+                      bool diffusion, double mus_in, double mus_out, double* diff_dev,
+                      hipStream_t s);
+
+extern "C" {
 
 int dot_pals_mua(dot_op* op, const dot_pals* pals, const double* theta_dev, double* mua_dev,
                  void* stream) {
@@ -729,7 +769,33 @@ int dot_pals_mua(dot_op* op, const dot_pals* pals, const double* theta_dev, doub
   int rc = validate_pals(pals, op->g.dim);
   if (rc) return rc;
   if (!theta_dev) DOT_FAIL(DOT_EINVAL, "theta_dev is NULL");
-  hipStream_t s = as_stream(stream);
+  return pals_state(op, pals, theta_dev, mua_dev, false, 0.0, 0.0, nullptr, as_stream(stream));
+}
+
+int dot_pals_mua_diffusion(dot_op* op, const dot_pals* pals, double mus_in, double mus_out,
+                           const double* theta_dev, double* mua_dev, double* diff_dev,
+                           void* stream) {
+  clear_error();
+  if (!op) DOT_FAIL(DOT_EINVAL, "op is NULL");
+  int rc = validate_pals(pals, op->g.dim);
+  if (rc) return rc;
+  if (!theta_dev) DOT_FAIL(DOT_EINVAL, "theta_dev is NULL");
+  if (!(pals->mu_in != pals->mu_out))
+    DOT_FAIL(DOT_EINVAL, "diffusion mode needs an absorption contrast (mu_in != mu_out)");
+  if (!std::isfinite(mus_in) || !std::isfinite(mus_out) || mus_in < 0.0 || mus_out < 0.0)
+    DOT_FAIL(DOT_EINVAL, "mus_in and mus_out must be finite and >= 0");
+  if (!(pals->mu_in + mus_in > 0.0) || !(pals->mu_out + mus_out > 0.0))
+    DOT_FAIL(DOT_EINVAL, "mu + mu_s must be positive inside and outside");
+  return pals_state(op, pals, theta_dev, mua_dev, true, mus_in, mus_out, diff_dev,
+                    as_stream(stream));
+}
+
+}  // extern "C"
+
+static int pals_state(dot_op* op, const dot_pals* pals, const double* theta_dev, double* mua_dev,
+                      bool diffusion, double mus_in, double mus_out, double* diff_dev,
+                      hipStream_t s) {
+  int rc = DOT_OK;
   const GridDims& g = op->g;
   const int m0 = pals->m0, stride = 2 + g.dim;
   // keep a copy of theta
@@ -742,11 +808,37 @@ int dot_pals_mua(dot_op* op, const dot_pals* pals, const double* theta_dev, doub
   }
   DOT_HIP(hipMemcpyAsync(op->theta, theta_dev, (size_t)m0 * stride * sizeof(double),
                          hipMemcpyDeviceToDevice, s));
-  // mu and phi, then the diagonal.  Without a caller buffer, mu is written
-  // into the handle's absorption array (kept for the multigrid levels).
+  // mu and phi, then (diffusion mode) D(theta) and the face coefficients,
+  // then the diagonal.  Without a caller buffer, mu is written into the
+  // handle's absorption array (kept for the multigrid levels).
   double* tmp_mu = mua_dev ? mua_dev : op->mu0;
   rc = launch_pals(g, pals, op->theta, 0.0, tmp_mu, nullptr, op->phi, s);
   if (rc) return rc;
+  if (diffusion) {
+    if (!op->Dbuild) {
+      DOT_HIP(hipMalloc(&op->Dbuild, (size_t)g.N * sizeof(double)));
+      DOT_HIP(hipMemcpyAsync(op->Dbuild, op->D0, (size_t)g.N * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+    } else if (!op->diff_mode) {
+      DOT_HIP(hipMemcpyAsync(op->Dbuild, op->D0, (size_t)g.N * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+    }
+    PalsK pk{pals->mu_in, pals->mu_out, pals->cutoff, pals->eps, pals->gamma, m0, g.dim, stride};
+    hipLaunchKernelGGL(diff_from_phi_kernel, dim3(nblk(g.N, 256)), dim3(256), 0, s, g, pk, mus_in,
+                       mus_out, op->phi, op->D0);
+    DOT_LAUNCH_CHECK();
+    op->diff_mode = true;
+    op->mus_in = mus_in;
+    op->mus_out = mus_out;
+    rc = rebuild_coefficients(op, s);
+    if (rc) return rc;
+    if (diff_dev)
+      DOT_HIP(hipMemcpyAsync(diff_dev, op->D0, (size_t)g.N * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+  } else {
+    rc = leave_diffusion_mode(op, s);
+    if (rc) return rc;
+  }
   rc = refresh_diag(op, tmp_mu, s);
   if (rc) return rc;
   // per-RBF cell lists
@@ -843,8 +935,10 @@ int dot_pals_mua(dot_op* op, const dot_pals* pals, const double* theta_dev, doub
   op->pals = *pals;
   rc = jac_prepare(op, s);
   if (rc) return rc;
+  if (op->diff_mode) {
+    rc = jac_prepare_faces(op, s);
+    if (rc) return rc;
+  }
   op->have_pals = true;
   return DOT_OK;
 }
-
-}  // extern "C"

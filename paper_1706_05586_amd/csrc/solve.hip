@@ -14,7 +14,7 @@
 // alpha, beta, norms and the convergence mask live on the device; the host
 // polls the number of active columns every few iterations.
 //
-// Preconditioner: on 3D grids whose sides halve, a geometric multigrid
+// Preconditioner: wherever the grid coarsens (every side >= 5), a geometric multigrid
 // V-cycle on the scaled system (mg.hip) by default: pass 1 then forms
 // p = z + beta p_old from z = M^-1 r, the V-cycle runs after pass 2 and its
 // last kernel forms r.z, so an iteration is the two sweeps plus one V-cycle.
@@ -1323,7 +1323,7 @@ int dot_solve_multi_rhs(dot_op* op, int trans, int k, const double* rhs_dev, dou
       opts->precond != DOT_PRECOND_MG)
     DOT_FAIL(DOT_EINVAL, "opts.precond must be DOT_PRECOND_AUTO, _JACOBI or _MG");
   if (opts->precond == DOT_PRECOND_MG && op->mg_nlev < 2)
-    DOT_FAIL(DOT_EINVAL, "no multigrid hierarchy for this grid (3D, sides that halve to >= 4)");
+    DOT_FAIL(DOT_EINVAL, "no multigrid hierarchy for this grid (every side must be >= 5)");
   if (opts->precond == DOT_PRECOND_MG && !op->mg_ok)
     DOT_FAIL(DOT_EINVAL, "multigrid hierarchy has a non-positive diagonal on some level");
   const bool mg = op->mg_nlev >= 2 && op->mg_ok && opts->precond != DOT_PRECOND_JACOBI;

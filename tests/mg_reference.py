@@ -12,15 +12,17 @@ error against its direct solve.
 
 The design, written out:
 
-  * levels: level l + 1 aggregates the 2 x 2 x 2 cells of level l, while
-    all three sides are even and the smallest is at least 8; every level is
-    the finite-volume operator of `oracle.discretization.assemble` on its own
-    grid, with D and mu the means over the children (so the coarse mass is
-    the sum of the fine masses);
+  * levels: level l + 1 aggregates the 2 x 2 x 2 cells of level l (2 x 2
+    in 2D; the last aggregate of an odd side is one cell thick along it),
+    every side halved rounding up while each coarse side keeps at least 3
+    cells; every level is the finite-volume operator of
+    `oracle.discretization.assemble` on its own grid (h = 1 / n_x), with D
+    and mu the means over the children (so a full aggregate's mass is the
+    sum of its children's masses);
   * each level in the symmetrically scaled form A^_l = S_l^-1 A_l S_l^-1,
     S_l = diag(A_l)^(1/2);
   * transfers with the piecewise-constant prolongation P (a coarse value
-    copied to its 8 children), in scaled variables
+    copied to its children), in scaled variables
         prolongation  x^_l += S_l P S_{l+1}^-1 x^_{l+1}
         restriction   b^_{l+1} = S_{l+1}^-1 P^T S_l r^_l
   * one cycle on level l with right-hand side b, J(v) = v + w (b - A^ v)
@@ -53,34 +55,49 @@ NU2 = 5
 NU_C = 8
 
 
+MIN_SIDE = 3
+
+
 def level_shapes(n) -> list:
-    """Cells per axis (n_x, n_y, n_z) of each level; a single level in 2D or
-    when the grid does not halve."""
+    """Cells per axis of each level: every side halved, rounding up, while
+    every coarse side keeps at least MIN_SIDE cells (2D grids stay 2D)."""
     n = tuple(int(v) for v in n)
     out = [n]
-    if len(n) != 3:
-        return out
-    while all(v % 2 == 0 for v in n) and min(n) >= 8:
-        n = tuple(v // 2 for v in n)
+    while all((v + 1) // 2 >= MIN_SIDE for v in n):
+        n = tuple((v + 1) // 2 for v in n)
         out.append(n)
     return out
 
 
-def _coarsen_mean(a: np.ndarray) -> np.ndarray:
-    z, y, x = a.shape
-    return a.reshape(z // 2, 2, y // 2, 2, x // 2, 2).mean(axis=(1, 3, 5))
+def _parents(n) -> np.ndarray:
+    """Coarse index of every fine cell (cell order i + n_x (j + n_y k))."""
+    nc = [(v + 1) // 2 for v in n]
+    idx = np.indices(tuple(reversed(n)))[::-1]        # x, y, (z) index arrays
+    P = np.zeros(idx[0].shape, dtype=np.int64)
+    stride = 1
+    for a in range(len(n)):
+        P += (idx[a] // 2) * stride
+        stride *= nc[a]
+    return P.ravel()
+
+
+def _coarsen_mean(a: np.ndarray, n) -> np.ndarray:
+    """Means over the children of each aggregate (fewer at an odd side's end)."""
+    P = _parents(n)
+    Nc = int(np.prod([(v + 1) // 2 for v in n]))
+    return np.bincount(P, weights=a.ravel(), minlength=Nc) / np.bincount(P, minlength=Nc)
 
 
 def hierarchy(n, bc, D: np.ndarray, mua: np.ndarray) -> list:
     """Per level: cells per axis, the scaled operator A^ (CSR) and S = sqrt(diag A)."""
     shapes = level_shapes(n)
-    Dl = np.asarray(D, dtype=np.float64).reshape(shapes[0][::-1])
-    ml = np.asarray(mua, dtype=np.float64).reshape(shapes[0][::-1])
+    Dl = np.asarray(D, dtype=np.float64).ravel()
+    ml = np.asarray(mua, dtype=np.float64).ravel()
     levels = []
     for li, nl in enumerate(shapes):
         if li > 0:
-            Dl, ml = _coarsen_mean(Dl), _coarsen_mean(ml)
-        A = disc.assemble(nl, bc, Dl.ravel(), ml.ravel())
+            Dl, ml = _coarsen_mean(Dl, shapes[li - 1]), _coarsen_mean(ml, shapes[li - 1])
+        A = disc.assemble(nl, bc, Dl, ml)
         sd = np.sqrt(A.diagonal())
         Ah = sp.diags(1.0 / sd) @ A @ sp.diags(1.0 / sd)
         levels.append(dict(n=nl, A=A, Ah=sp.csr_matrix(Ah), sd=sd))
@@ -88,14 +105,12 @@ def hierarchy(n, bc, D: np.ndarray, mua: np.ndarray) -> list:
 
 
 def _sum_children(v: np.ndarray, n) -> np.ndarray:
-    nx, ny, nz = n
-    return v.reshape(nz // 2, 2, ny // 2, 2, nx // 2, 2).sum(axis=(1, 3, 5)).ravel()
+    Nc = int(np.prod([(a + 1) // 2 for a in n]))
+    return np.bincount(_parents(n), weights=v, minlength=Nc)
 
 
 def _copy_to_children(vc: np.ndarray, n) -> np.ndarray:
-    nx, ny, nz = n
-    c = vc.reshape(nz // 2, ny // 2, nx // 2)
-    return np.repeat(np.repeat(np.repeat(c, 2, axis=0), 2, axis=1), 2, axis=2).ravel()
+    return vc[_parents(n)]
 
 
 def vcycle_scaled(levels: list, b: np.ndarray, level: int = 0) -> np.ndarray:

@@ -132,7 +132,9 @@ def test_solve_fp64_matches_oracle(dotlib, dev, name, precond):
         res = op.solve(torch.tensor(rhs, device=dev), rtol=1e-12, precision=dotlib.DOT_FP64,
                        precond=pc)
         X = res.x.cpu().numpy()
-    assert levels == (3 if name == "t3d_b" else 0)
+    import mg_reference as omg
+    # every test grid coarsens: odd sides end in a ragged aggregate, 2D in 2 x 2
+    assert levels == len(omg.level_shapes(prob.n))
     assert res.converged
     true_rel = osol.relative_residuals(ref["A"], X, rhs)
     assert np.all(true_rel <= 1.5e-12), true_rel.max()
@@ -144,7 +146,8 @@ def test_solve_fp64_matches_oracle(dotlib, dev, name, precond):
         # iteration counts follow the oracle's Jacobi-PCG
         assert np.all(np.abs(res.iters - its) <= np.maximum(2, 0.03 * its)), (res.iters, its)
     else:
-        assert np.all(2 * res.iters < its), (res.iters, its)
+        # the V-cycle takes at most a fifth of Jacobi-PCG's iterations
+        assert np.all(5 * res.iters <= its), (res.iters, its)
 
 
 @pytest.mark.parametrize("precond", ["auto", "jacobi"])
@@ -207,12 +210,13 @@ def test_solve_edge_cases(dotlib, dev):
         assert ei.value.code == -5
 
 
-@pytest.mark.parametrize("shape", ["t3d_b", (32, 16, 8), (64, 64, 64)])
+@pytest.mark.parametrize("shape", ["t3d_b", (32, 16, 8), (64, 64, 64), "t3d", "t3d_c", "t2d", "C1"])
 def test_multigrid_vcycle_matches_reference_model(dotlib, dev, shape):
     """One binary64 V-cycle (as an approximate inverse of A) against the
     scipy model of the V-cycle on random right-hand sides, 5 columns (a ragged column
     group); grids cubic with mixed boundary faces, flat (one tile across x,
-    two coarse levels) and 64^3."""
+    two coarse levels), 64^3, odd sides in every direction (ragged last
+    aggregates, an odd number of planes per level) and 2D."""
     import mg_reference as omg
     if isinstance(shape, str):
         wl = synthetic.make_workload(synthetic.get_config(shape))
@@ -235,15 +239,17 @@ def test_multigrid_vcycle_matches_reference_model(dotlib, dev, shape):
 
 
 def test_multigrid_availability(dotlib, dev):
-    """No hierarchy on grids that do not halve (odd sides) or in 2D: the
-    solver falls back to Jacobi and an explicit request is refused."""
-    for name in ("t3d", "t2d"):
-        wl, prob, W, V, data, ref = case(name)
+    """No hierarchy where a side has fewer than 5 cells (a coarse side would
+    fall below 3): the solver falls back to Jacobi and an explicit request
+    is refused."""
+    for name, n in (("t3d", (19, 13, 4)), ("t2d", (37, 4))):
+        wl = synthetic.make_workload(synthetic.get_config(name, n=n))
         op, grid, pals, th = gpu_operator(dotlib, dev, wl)
         with op:
             op.pals_mua(pals, th)
             assert op.multigrid_levels == 0
-            b = torch.tensor(ref["BW"][:, :1].copy(), device=dev)
+            b = torch.zeros((int(np.prod(n)), 1), dtype=torch.float64, device=dev)
+            b[0, 0] = 1.0
             with pytest.raises(dotlib.DotError) as ei:
                 op.solve(b, rtol=1e-8, precond=dotlib.DOT_PRECOND_MG)
             assert ei.value.code == -1
@@ -306,11 +312,11 @@ def test_jacobian_fp64_matches_oracle(dotlib, dev, name):
 
 @pytest.mark.parametrize("ls,ld", [(64, 64), (3, 70), (9, 64)])
 def test_jacobian_large_sample_counts(dotlib, dev, ls, ld):
-    """Sample counts at and beyond the matrix-core tilings, against the
-    oracle's loop nest on random fields (the contraction is linear in them):
-    64 x 64 (the plain binary64 kernel when the tiles exceed 64; the split
-    forms at their largest tiling), l_d = 70 (ragged l_s + l_d = 73; the split
-    forms refuse l_d > 64) and 9 x 64 (one row tile, four detector tiles)."""
+    """Sample counts at and beyond one pass of the matrix-core kernels, against
+    the oracle's loop nest on random fields (the contraction is linear in
+    them): 64 x 64 (binary64 in detector tiles of 51, the split forms at their
+    largest tiling), l_d = 70 (ragged l_s + l_d = 73; the split forms in two
+    detector tiles) and 9 x 64 (one row tile, four detector tiles)."""
     wl = synthetic.make_workload(synthetic.get_config("t3d"))
     prob = oprob.build(wl)
     rng = np.random.default_rng(ls * 100 + ld)
@@ -323,22 +329,17 @@ def test_jacobian_large_sample_counts(dotlib, dev, ls, ld):
         Ut, Zt = torch.tensor(U, device=dev), torch.tensor(Z, device=dev)
         Js = op.jacobian(Ut, Zt, dotlib.DOT_JAC_FP64).cpu().numpy()
         assert np.linalg.norm(Js - Jr) <= 1e-12 * np.linalg.norm(Jr)
-        if ld > 64:
-            with pytest.raises(dotlib.DotError) as ei:
-                op.jacobian(Ut, Zt, dotlib.DOT_JAC_SPLIT_BF16)
-            assert ei.value.code == -1
-        else:
-            # three parts (the product form): binary32-level operands, within
-            # the 1e-6 bound; two parts (the faster option): each product is
-            # exact to about 2^-16 relative (dropped lo lo term and lo
-            # rounding), within its stated 2e-5 bound
-            J2 = op.jacobian(Ut, Zt, dotlib.DOT_JAC_SPLIT_BF16).cpu().numpy()
-            J3 = op.jacobian(Ut, Zt, dotlib.DOT_JAC_SPLIT_BF16X3).cpu().numpy()
-            e2 = np.linalg.norm(J2 - Jr) / np.linalg.norm(Jr)
-            e3 = np.linalg.norm(J3 - Jr) / np.linalg.norm(Jr)
-            print(f"[jac {ls}x{ld}] 3-part {e3:.2e}, 2-part option {e2:.2e}", flush=True)
-            assert e3 <= 1e-6
-            assert e2 <= 2e-5
+        # three parts (the product form): binary32-level operands, within
+        # the 1e-6 bound; two parts (the faster option): each product is
+        # exact to about 2^-16 relative (dropped lo lo term and lo
+        # rounding), within its stated 2e-5 bound
+        J2 = op.jacobian(Ut, Zt, dotlib.DOT_JAC_SPLIT_BF16).cpu().numpy()
+        J3 = op.jacobian(Ut, Zt, dotlib.DOT_JAC_SPLIT_BF16X3).cpu().numpy()
+        e2 = np.linalg.norm(J2 - Jr) / np.linalg.norm(Jr)
+        e3 = np.linalg.norm(J3 - Jr) / np.linalg.norm(Jr)
+        print(f"[jac {ls}x{ld}] 3-part {e3:.2e}, 2-part option {e2:.2e}", flush=True)
+        assert e3 <= 1e-6
+        assert e2 <= 2e-5
 
 
 @pytest.mark.parametrize("name", NAMES)
@@ -409,7 +410,7 @@ def test_mixed_multigrid_iteration_cap(dotlib, dev, check_every):
     op, grid, pals, th = gpu_operator(dotlib, dev, wl)
     with op:
         op.pals_mua(pals, th)
-        assert op.multigrid_levels == 3
+        assert op.multigrid_levels == 4   # 24^3 down to 3^3
         rhs = np.hstack([ref["BW"], ref["CV"]])
         with pytest.warns(dotlib.NotConverged):
             capped = op.solve(torch.tensor(rhs, device=dev), rtol=1e-14, max_iter=3,

@@ -20,7 +20,7 @@ def smooth_fields(n, seed):
     mu = np.full(x.shape[0], 0.01)
     D = np.full(x.shape[0], 1.0 / 3.0)
     for _ in range(3):
-        c = rng.uniform(0.2, 0.8, size=3) * np.array(n) / n[0]
+        c = rng.uniform(0.2, 0.8, size=len(n)) * np.array(n) / n[0]
         r2 = np.sum((x - c) ** 2, axis=1)
         mu += 0.04 * np.exp(-r2 / 0.02)
         D *= 1.0 - 0.2 * np.exp(-r2 / 0.05)
@@ -30,10 +30,30 @@ def smooth_fields(n, seed):
 def test_level_shapes():
     assert omg.level_shapes((128, 128, 128)) == [(128,) * 3, (64,) * 3, (32,) * 3, (16,) * 3,
                                                  (8,) * 3, (4,) * 3]
-    assert omg.level_shapes((96, 96, 96))[-1] == (6, 6, 6)
+    assert omg.level_shapes((96, 96, 96))[-1] == (3, 3, 3)
     assert omg.level_shapes((32, 16, 8)) == [(32, 16, 8), (16, 8, 4)]
-    assert omg.level_shapes((19, 13, 11)) == [(19, 13, 11)]
-    assert omg.level_shapes((32, 32)) == [(32, 32)]
+    assert omg.level_shapes((19, 13, 11)) == [(19, 13, 11), (10, 7, 6), (5, 4, 3)]
+    assert omg.level_shapes((70, 33, 17)) == [(70, 33, 17), (35, 17, 9), (18, 9, 5), (9, 5, 3)]
+    assert omg.level_shapes((32, 32)) == [(32, 32), (16, 16), (8, 8), (4, 4)]
+    assert omg.level_shapes((37, 29)) == [(37, 29), (19, 15), (10, 8), (5, 4)]
+    assert omg.level_shapes((4, 40, 40)) == [(4, 40, 40)]
+
+
+def test_transfers_ragged_aggregates():
+    """P^T sums the children and P copies the parent, also where the last
+    aggregate of an odd side holds fewer cells: P^T 1 counts the children."""
+    for n, counts in (((5, 3), [4, 2, 2, 1]), ((3, 2, 3), [8, 4, 8, 4])):
+        N = int(np.prod(n))
+        cnt = omg._sum_children(np.ones(N), n)
+        assert cnt.sum() == N
+        # the corner aggregates at (0, 0, 0), (last x), (last y) and (last x, y)
+        nc = [(v + 1) // 2 for v in n]
+        corners = [0, nc[0] - 1, nc[0] * (nc[1] - 1), nc[0] * nc[1] - 1]
+        assert list(cnt[corners]) == counts
+        rng = np.random.default_rng(1)
+        u, vc = rng.standard_normal(N), rng.standard_normal(cnt.size)
+        # adjoint pair: <P^T u, vc> = <u, P vc>
+        assert abs(omg._sum_children(u, n) @ vc - u @ omg._copy_to_children(vc, n)) <= 1e-13 * N
 
 
 @pytest.fixture(scope="module")
@@ -123,3 +143,37 @@ def test_four_level_cycle_symmetric_positive():
     Mu, Mv = omg.apply(lv, u), omg.apply(lv, v)
     assert abs(u @ Mv - v @ Mu) <= 1e-13 * abs(u @ Mv)
     assert v @ Mv > 0.0 and u @ Mu > 0.0
+
+
+@pytest.mark.parametrize("n", [(9, 7, 5), (11, 9)])
+def test_ragged_and_2d_cycles_symmetric_positive_definite(n):
+    """Odd sides (ragged last aggregates) and a 2D grid: the dense M is
+    symmetric positive definite and M A has no eigenvalue beyond 2."""
+    bc = (ROBIN, DIRICHLET, ROBIN, ROBIN, DIRICHLET, ROBIN)[:2 * len(n)]
+    D, mu = smooth_fields(n, 4)
+    A = disc.assemble(n, bc, D, mu).toarray()
+    lv = omg.hierarchy(n, bc, D, mu)
+    assert len(lv) >= 2
+    M = omg.apply(lv, np.eye(A.shape[0]))
+    assert np.linalg.norm(M - M.T) <= 1e-13 * np.linalg.norm(M)
+    L = np.linalg.cholesky(0.5 * (M + M.T))
+    ev = np.linalg.eigvalsh(L.T @ A @ L)
+    assert ev.min() > 0.0 and ev.max() < 2.0
+
+
+@pytest.mark.parametrize("n,factor", [((70, 33, 17), 8), ((37, 29), 8), ((101, 77), 16)])
+def test_pcg_iterations_odd_and_2d_grids(n, factor):
+    """On grids with odd sides, and in 2D, the cycle still takes CG to the
+    tolerance in a fraction of Jacobi-PCG's iterations."""
+    bc = (ROBIN, ROBIN, DIRICHLET, ROBIN, ROBIN, ROBIN)[:2 * len(n)]
+    D, mu = smooth_fields(n, 6)
+    A = disc.assemble(n, bc, D, mu)
+    lv = omg.hierarchy(n, bc, D, mu)
+    rng = np.random.default_rng(7)
+    b = np.zeros(A.shape[0])
+    b[rng.integers(0, A.shape[0], 12)] = rng.choice([-1.0, 1.0], 12)
+    dg = A.diagonal()
+    _, itj = pcg(A, b, lambda r: r / dg, 1e-10)
+    xm, itm = pcg(A, b, lambda r: omg.apply(lv, r), 1e-10)
+    assert np.linalg.norm(b - A @ xm) <= 1e-10 * np.linalg.norm(b)
+    assert itm * factor <= itj, (itm, itj)
