@@ -184,8 +184,8 @@ int dot_pals_mua(dot_op* op, const dot_pals* pals, const double* theta_dev, doub
  * h^d d mu / d p_k), with the same parameters and band lists.  Needs
  * mu_in != mu_out.  mua_dev and diff_dev (may be NULL) receive mu and D.
  * dot_pals_mua and dot_set_mua return to the diffusion given at build time;
- * dot_dadp_apply covers the absorption-only model and returns DOT_EINVAL in
- * this mode.  Synchronizes the stream.
+ * dot_dadp_apply and dot_grad_misfit_noalloc cover the absorption-only model
+ * and return DOT_EINVAL in this mode.  Synchronizes the stream.
  */
 int dot_pals_mua_diffusion(dot_op* op, const dot_pals* pals, double mus_in, double mus_out,
                            const double* theta_dev, double* mua_dev, double* diff_dev,
@@ -356,6 +356,24 @@ int dot_grad_misfit(dot_op* op, int l_s, const double* U_dev, int l_d, const dou
                     const double* Rs_dev, double* g_dev, void* work_dev, size_t work_bytes,
                     void* stream);
 
+/*
+ * dot_grad_misfit for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and the same result, bit for bit, with the scratch (the
+ * per-cell sums and the per-chunk partials) in a fixed device array of
+ * DOT_NOALLOC_SCRATCH_DOUBLES binary64 values (32 MiB) that the library
+ * holds on every GPU it runs on until the process ends.  The call allocates
+ * nothing and does not synchronize; the caller passes the inputs and g_dev.
+ * The scratch needed is N rounded up to 32 plus (band chunks) x (active
+ * parameters per RBF) values: grids up to about 4.1 million cells (128^3 with
+ * 1000 RBFs fits); larger ones return DOT_EINVAL.  Every call on one GPU
+ * shares that GPU's array, so calls that overlap on one GPU (on different
+ * streams or host threads) race and must be serialized by the caller.
+ */
+#define DOT_NOALLOC_SCRATCH_DOUBLES (1u << 22)
+int dot_grad_misfit_noalloc(dot_op* op, int l_s, const double* U_dev, int l_d,
+                            const double* Z_dev, const double* Rs_dev, double* g_dev,
+                            void* stream);
 
 /*
  * Kernel timing with HIP events on the caller's stream (off by default).

@@ -34,6 +34,7 @@ DOT_ACT_ALPHA = 1
 DOT_ACT_BETA = 2
 DOT_ACT_CHI = 4
 DOT_MAX_COLUMNS = 4096
+DOT_NOALLOC_SCRATCH_DOUBLES = 1 << 22
 DOT_PROF_PCG1_FP64 = 0
 DOT_PROF_PCG2_FP64 = 1
 DOT_PROF_PCG1_FP32 = 2
@@ -103,6 +104,7 @@ SIGNATURES = {
     "dot_jacobian": (_i, [_vp, _i, _vp, _i, _vp, _i, _vp, _vp, _sz, _vp]),
     "dot_dadp_apply": (_i, [_vp, _i, _vp, _vp, _vp, _vp]),
     "dot_grad_misfit": (_i, [_vp, _i, _vp, _i, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "dot_grad_misfit_noalloc": (_i, [_vp, _i, _vp, _i, _vp, _vp, _vp, _vp]),
     "dot_gemm": (_i, [_i, _i, _i, _i, _i, _d, _vp, _i, _vp, _i, _d, _vp, _i, _vp]),
     "dot_mode_gram_workspace_bytes": (_sz, [_i, _i, _i, _i]),
     "dot_mode_gram": (_i, [_i, _i, _i, _vp, _i, _vp, _vp, _sz, _vp]),

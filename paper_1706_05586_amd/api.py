@@ -574,3 +574,22 @@ class Operator:
                                   _ptr(work), work.numel(), _stream()), "dot_grad_misfit")
         return g
 
+    def grad_misfit_noalloc(self, U: torch.Tensor, Z: torch.Tensor, Rs: torch.Tensor,
+                            out: torch.Tensor) -> torch.Tensor:
+        """grad_misfit through the library's allocation-free entry point: the
+        caller supplies ``out`` (n_p float64 values), U, Z and Rs already
+        column-major (as the solver returns them), and the library uses its
+        fixed per-GPU scratch array."""
+        if self.pals is None:
+            raise RuntimeError("call pals_mua before grad_misfit_noalloc")
+        l_s, l_d = U.shape[1], Z.shape[1]
+        n_p = self.pals.m0 * self.pals.n_act(self.grid.dim)
+        for t, name, rows, cols in ((U, "U", self.N, l_s), (Z, "Z", self.N, l_d),
+                                    (Rs, "Rs", l_d, l_s)):
+            check_field_block(t, rows, cols, name)
+        if (not isinstance(out, torch.Tensor) or out.dtype != torch.float64 or not out.is_cuda
+                or out.numel() != n_p or not out.is_contiguous()):
+            raise ValueError(f"out must be a contiguous float64 CUDA tensor of {n_p} values")
+        check(lib.dot_grad_misfit_noalloc(self._handle, l_s, _ptr(U), l_d, _ptr(Z), _ptr(Rs),
+                                          _ptr(out), _stream()), "dot_grad_misfit_noalloc")
+        return out

@@ -14,6 +14,7 @@
 // Gradient (eq. UnbiasedGrad, sampled): g = Js^T vec(Rs) evaluated as
 // g_k = - sum_c G[c,k] s_c with s_c = sum_i U[c,i] (Z Rs)[c,i].
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "dot_internal.h"
@@ -1582,8 +1583,14 @@ static int grad_check_args(const dot_op* op, int l_s, int l_d, const double* U_d
   return DOT_OK;
 }
 
-// The gradient's launches on scratch memory sc: per-cell sums s_c (N values,
-// padded to 32), then one partial per (chunk, active parameter).
+// doubles of gradient scratch: per-cell sums s_c (N, padded to 32), then one
+// partial per (chunk, active parameter)
+static int64_t grad_scratch_doubles(const dot_op* op) {
+  const int na = n_active_bits(op->pals.active, op->g.dim);
+  return ((op->g.N + 31) / 32) * 32 + std::max<int64_t>(op->n_chunks, 1) * na;
+}
+
+// The gradient's launches on scratch memory sc of at least grad_scratch_doubles.
 static int grad_run(dot_op* op, int l_s, const double* U_dev, int l_d, const double* Z_dev,
                     const double* Rs_dev, double* g_dev, double* sc, hipStream_t s) {
   const JacParams P = make_params(op);
@@ -1635,6 +1642,35 @@ static int grad_run(dot_op* op, int l_s, const double* U_dev, int l_d, const dou
   return DOT_OK;
 }
 
+// Fixed scratch of dot_grad_misfit_noalloc, one copy per GPU for the life of
+// the process.  In host code `scratch` names a host-side stand-in; kernels
+// get the device address that hipGetSymbolAddress returns for the current
+// device, looked up once per device and kept in scratch_dev.
+static __device__ __align__(256) double scratch[DOT_NOALLOC_SCRATCH_DOUBLES];
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static double* scratch_dev[SCRATCH_MAX_DEVICES];
+static std::mutex scratch_mu;
+
+static int scratch_address(double** out) {
+  int dev = -1;
+  DOT_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES)
+    DOT_FAIL(DOT_EINVAL, "device %d beyond the %d devices the fixed scratch supports", dev,
+             SCRATCH_MAX_DEVICES);
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      DOT_FAIL(DOT_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+               hipGetErrorString(e));
+    scratch_dev[dev] = (double*)p;
+  }
+  *out = scratch_dev[dev];
+  return DOT_OK;
+}
+
 }  // namespace dot
 
 extern "C" {
@@ -1673,6 +1709,26 @@ int dot_grad_misfit(dot_op* op, int l_s, const double* U_dev, int l_d, const dou
     DOT_FAIL(DOT_ENOMEM, "workspace too small: need %zu bytes, got %zu", need, work_bytes);
   return grad_run(op, l_s, U_dev, l_d, Z_dev, Rs_dev, g_dev, (double*)work_dev,
                   as_stream(stream));
+}
+
+int dot_grad_misfit_noalloc(dot_op* op, int l_s, const double* U_dev, int l_d,
+                            const double* Z_dev, const double* Rs_dev, double* g_dev,
+                            void* stream) {
+  clear_error();
+  DOT_TRY_J(grad_check_args(op, l_s, l_d, U_dev, Z_dev, Rs_dev, g_dev));
+  if (op->diff_mode)
+    DOT_FAIL(DOT_EINVAL, "the fixed-scratch gradient covers the absorption-only model "
+                         "(dot_pals_mua), not diffusion mode");
+  const int64_t need = grad_scratch_doubles(op);
+  if (need > (int64_t)DOT_NOALLOC_SCRATCH_DOUBLES)
+    DOT_FAIL(DOT_EINVAL,
+             "grid too large for the fixed gradient scratch: needs %lld doubles (N = %lld cells "
+             "plus %lld chunk partials), the maximum is %lld",
+             (long long)need, (long long)op->g.N, (long long)(need - ((op->g.N + 31) / 32) * 32),
+             (long long)DOT_NOALLOC_SCRATCH_DOUBLES);
+  double* sc = nullptr;
+  DOT_TRY_J(scratch_address(&sc));
+  return grad_run(op, l_s, U_dev, l_d, Z_dev, Rs_dev, g_dev, sc, as_stream(stream));
 }
 
 }  // extern "C"
