@@ -69,6 +69,8 @@ extern "C" {
 #define DOT_PRECOND_AUTO 0    /* multigrid where the grid has a hierarchy, else Jacobi */
 #define DOT_PRECOND_JACOBI 1  /* Jacobi (the symmetric diagonal scaling alone) */
 #define DOT_PRECOND_MG 2      /* geometric multigrid V-cycle (DOT_EINVAL without a hierarchy) */
+#define DOT_PRECOND_MG_F32 3  /* the same; with DOT_MIXED its work vectors are kept in binary32
+                                 instead of bfloat16 (AUTO and MG), for comparison */
 
 /* Jacobian precision */
 #define DOT_JAC_FP64 0        /* binary64 products and sums */
@@ -107,7 +109,7 @@ typedef struct dot_solve_opts {
                          drop before its correction is folded into x in binary64 and its
                          residual is replaced by the binary64 b - A x (e.g. 0.1) */
   int check_every;    /* iterations between host polls of the column flags (>= 1) */
-  int precond;        /* DOT_PRECOND_AUTO, DOT_PRECOND_JACOBI or DOT_PRECOND_MG */
+  int precond;        /* DOT_PRECOND_AUTO, _JACOBI, _MG or _MG_F32 */
 } dot_solve_opts;
 
 typedef struct dot_solve_info {
@@ -235,7 +237,12 @@ size_t dot_solve_workspace_bytes(const dot_op* op, int k, int precision);
  * correction is folded into x in binary64, and the residual b - A x is
  * recomputed in binary64 and replaces the binary32 one whenever the latter
  * has dropped by inner_rtol (the search direction is kept); convergence is
- * decided on the binary64 residual; the V-cycle then runs in binary32.
+ * decided on the binary64 residual; the V-cycle then runs in binary32
+ * arithmetic with its work vectors (every level's iterates, the coarse
+ * right-hand sides and corrections) stored in bfloat16, rounded to nearest
+ * even (DOT_PRECOND_MG_F32: stored in binary32); its input r and output z
+ * stay binary32.  The preconditioner only steers CG: the accuracy is that
+ * of the binary64 residual test.
  * The host reads the column flags every check_every iterations, one such
  * poll late: iterations launched after the last column converged run with
  * every column masked off.
@@ -278,7 +285,8 @@ int dot_multigrid_levels(const dot_op* op);
 
 /* Algorithmic HBM bytes per column of one V-cycle of the solver's
  * preconditioner in the given precision (DOT_FP64: binary64 vectors,
- * DOT_MIXED: binary32): every vector each level's kernels must read or write
+ * DOT_MIXED: binary32 input and output, bfloat16 work vectors): every vector
+ * each level's kernels must read or write
  * once (right-hand sides, iterates, coarse values, results), the operator's
  * coefficients not counted; 0 without a hierarchy.  For roofline figures. */
 double dot_multigrid_cycle_bytes(const dot_op* op, int precision);

@@ -6,7 +6,7 @@ declared in include/dotpath.h.  The HIP library libdotpath.so is required.
 
 from ._lib import (DOT_ACT_ALPHA, DOT_ACT_BETA, DOT_ACT_CHI, DOT_BC_DIRICHLET, DOT_BC_ROBIN,
                    DOT_FP64, DOT_JAC_FP64, DOT_JAC_SPLIT_BF16, DOT_JAC_SPLIT_BF16X3, DOT_MIXED,
-                   DOT_PRECOND_AUTO, DOT_PRECOND_JACOBI, DOT_PRECOND_MG, DotError, NotConverged,
+                   DOT_PRECOND_AUTO, DOT_PRECOND_JACOBI, DOT_PRECOND_MG, DOT_PRECOND_MG_F32, DotError, NotConverged,
                    LIB_PATH)
 from .api import (Grid, Operator, Pals, SolveResult, colmajor, empty_colmajor, gemm, hooi,
                   mode_gram, optimized_design, pals_field, qr_complete, svd_thin, symeig,
@@ -16,7 +16,7 @@ from . import inversion  # noqa: E402  (outer Gauss-Newton driver on the ABI cal
 
 __all__ = [
     "DOT_ACT_ALPHA", "DOT_ACT_BETA", "DOT_ACT_CHI", "DOT_BC_DIRICHLET", "DOT_BC_ROBIN",
-    "DOT_FP64", "DOT_MIXED", "DOT_PRECOND_AUTO", "DOT_PRECOND_JACOBI", "DOT_PRECOND_MG", "DOT_JAC_FP64", "DOT_JAC_SPLIT_BF16", "DOT_JAC_SPLIT_BF16X3", "DotError", "NotConverged",
+    "DOT_FP64", "DOT_MIXED", "DOT_PRECOND_AUTO", "DOT_PRECOND_JACOBI", "DOT_PRECOND_MG", "DOT_PRECOND_MG_F32", "DOT_JAC_FP64", "DOT_JAC_SPLIT_BF16", "DOT_JAC_SPLIT_BF16X3", "DotError", "NotConverged",
     "LIB_PATH", "Grid", "Operator", "Pals", "SolveResult", "colmajor", "empty_colmajor",
     "gemm", "pals_field", "MisfitFn", "MisfitProblem", "misfit", "mode_gram", "symeig",
     "qr_complete", "hooi", "svd_thin", "tsvd_step", "optimized_design", "inversion",

@@ -27,6 +27,7 @@ DOT_MIXED = 1
 DOT_PRECOND_AUTO = 0
 DOT_PRECOND_JACOBI = 1
 DOT_PRECOND_MG = 2
+DOT_PRECOND_MG_F32 = 3
 DOT_JAC_FP64 = 0
 DOT_JAC_SPLIT_BF16 = 1
 DOT_JAC_SPLIT_BF16X3 = 2

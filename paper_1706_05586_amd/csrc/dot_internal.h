@@ -217,8 +217,16 @@ int mg_levels_for(const GridDims& g, GridDims* levels);
 int mg_refresh(dot_op* op, hipStream_t s);
 void mg_free(dot_op* op);
 
+// bfloat16 storage of V-cycle vectors whose arithmetic is binary32: the
+// upper half of the binary32 pattern, rounded to nearest even when stored
+struct bf16s {
+  unsigned short u;
+};
+
 // Work vectors of one V-cycle: per level l >= 1 a right-hand side, an
-// iterate and a result (N_l columns apart).
+// iterate and a result (N_l columns apart); on level 0 one iterate, or two
+// when the vectors are stored in a narrower type than the arithmetic (the
+// right-hand side and the result are the caller's).
 template <typename T>
 struct MgWork {
   int nlev = 0;
@@ -229,18 +237,22 @@ struct MgWork {
 };
 // bytes of MgWork<T> for k columns on op's hierarchy (0 without one);
 // carve the vectors from base (256-aligned); ld0: the level-0 stride
-size_t mg_work_bytes(const dot_op* op, int k, int64_t ld0, size_t elem);
+// (level0_iterates: 1, or 2 for narrower storage)
+size_t mg_work_bytes(const dot_op* op, int k, int64_t ld0, size_t elem, int level0_iterates = 1);
 template <typename T>
-void mg_work_layout(const dot_op* op, int k, int64_t ld0, char* base, MgWork<T>* w);
-// algorithmic bytes per column of one V-cycle with elements of elem bytes
-double mg_cycle_stream_bytes(const dot_op* op, size_t elem);
+void mg_work_layout(const dot_op* op, int k, int64_t ld0, char* base, MgWork<T>* w,
+                    int level0_iterates = 1);
+// algorithmic bytes per column of one V-cycle: the level-0 right-hand side
+// and result in elements of elem0 bytes, every other vector of elem bytes
+double mg_cycle_stream_bytes(const dot_op* op, size_t elem0, size_t elem);
 // partial slots per column of the level-0 smoothing kernel (the dot (r, z))
 int mg_partial_slots(const dot_op* op, int k);
 // z0 = V-cycle applied to r0 (both k columns ld0 apart; columns outside
 // `active` are skipped); partial[0][j][slot] receives r0_j . z0_j
 // (prof_cols: optional, receives the number of active columns)
-template <typename T>
-int mg_vcycle(dot_op* op, const MgWork<T>& w, int k, const T* r0, int64_t ld0, T* z0,
+// (T: the arithmetic and r0, z0; S: the stored work vectors, T or bf16s)
+template <typename T, typename S>
+int mg_vcycle(dot_op* op, const MgWork<S>& w, int k, const T* r0, int64_t ld0, T* z0,
               const int* active, double* partial, hipStream_t s,
               unsigned long long* prof_cols = nullptr);
 

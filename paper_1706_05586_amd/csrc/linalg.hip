@@ -196,6 +196,7 @@ __global__ __launch_bounds__(256) void symeig_small_kernel(int n, const double* 
   }
   __syncthreads();
   int sweep = 0;
+  const int hp = np / 2;
   for (; sweep < max_sweeps; ++sweep) {
     double off = 0.0, tot = 0.0;
     for (int e = threadIdx.x; e < n * n; e += 256) {
@@ -204,25 +205,22 @@ __global__ __launch_bounds__(256) void symeig_small_kernel(int n, const double* 
       tot += x;
       if (i != j) off += x;
     }
-    red[threadIdx.x] = off;
-    __syncthreads();
-    for (int s = 128; s >= 1; s >>= 1) {
-      if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-      __syncthreads();
+    // both sums: wave shuffles, then the four wave partials in order
+    for (int o = 32; o >= 1; o >>= 1) {
+      off += __shfl_xor(off, o, 64);
+      tot += __shfl_xor(tot, o, 64);
     }
-    const double offs = red[0];
-    __syncthreads();
-    red[threadIdx.x] = tot;
-    __syncthreads();
-    for (int s = 128; s >= 1; s >>= 1) {
-      if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-      __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+      red[threadIdx.x >> 6] = off;
+      red[4 + (threadIdx.x >> 6)] = tot;
     }
-    const double tots = red[0];
+    __syncthreads();
+    const double offs = (red[0] + red[1]) + (red[2] + red[3]);
+    const double tots = (red[4] + red[5]) + (red[6] + red[7]);
     __syncthreads();
     if (!(offs > 1e-30 * tots) || offs == 0.0) break;
     for (int round = 0; round < np - 1; ++round) {
-      if ((int)threadIdx.x < np / 2) {
+      if ((int)threadIdx.x < hp) {
         int p, q;
         tournament(np, round, threadIdx.x, &p, &q);
         double c = 1.0, s = 0.0;
@@ -233,27 +231,27 @@ __global__ __launch_bounds__(256) void symeig_small_kernel(int n, const double* 
         cs[threadIdx.x][1] = s;
       }
       __syncthreads();
-      // columns: A <- A J, V <- V J
-      for (int e = threadIdx.x; e < (np / 2) * np; e += 256) {
+      // A <- J^T A J by 2 x 2 blocks on the pairs (columns, then rows) and
+      // V <- V J by entry pairs: the blocks and pairs are disjoint
+      for (int e = threadIdx.x; e < hp * np; e += 256) {
         const int k = e / np, r = e % np;
         const int p = pq[k][0], q = pq[k][1];
         const double c = cs[k][0], s = cs[k][1];
-        const double arp = a[r][p], arq = a[r][q];
-        a[r][p] = c * arp - s * arq;
-        a[r][q] = s * arp + c * arq;
         const double vrp = v[r][p], vrq = v[r][q];
         v[r][p] = c * vrp - s * vrq;
         v[r][q] = s * vrp + c * vrq;
       }
-      __syncthreads();
-      // rows: A <- J^T A
-      for (int e = threadIdx.x; e < (np / 2) * np; e += 256) {
-        const int k = e / np, r = e % np;
-        const int p = pq[k][0], q = pq[k][1];
-        const double c = cs[k][0], s = cs[k][1];
-        const double apr = a[p][r], aqr = a[q][r];
-        a[p][r] = c * apr - s * aqr;
-        a[q][r] = s * apr + c * aqr;
+      for (int e = threadIdx.x; e < hp * hp; e += 256) {
+        const int k = e % hp, m = e / hp;
+        const int pk = pq[k][0], qk = pq[k][1], pm = pq[m][0], qm = pq[m][1];
+        const double ck = cs[k][0], sk = cs[k][1], cm = cs[m][0], sm = cs[m][1];
+        const double x00 = a[pk][pm], x01 = a[pk][qm], x10 = a[qk][pm], x11 = a[qk][qm];
+        const double y00 = cm * x00 - sm * x01, y01 = sm * x00 + cm * x01;
+        const double y10 = cm * x10 - sm * x11, y11 = sm * x10 + cm * x11;
+        a[pk][pm] = ck * y00 - sk * y10;
+        a[qk][pm] = sk * y00 + ck * y10;
+        a[pk][qm] = ck * y01 - sk * y11;
+        a[qk][qm] = sk * y01 + ck * y11;
       }
       __syncthreads();
     }
@@ -298,12 +296,17 @@ __device__ __forceinline__ int bj_index(int I, int J, int i) {
   return i < BJ_B ? I * BJ_B + i : J * BJ_B + (i - BJ_B);
 }
 
-// One block of BJT threads per pair of index blocks: the 16 disjoint
-// rotations of a step are applied by 32 threads each (one matrix index per
-// thread), so a step is two LDS phases of one load and one store per value.
+// One block of BJT threads per pair of index blocks.  A step of the inner
+// sweep rotates the 16 disjoint pairs (p_k, q_k) at once: A <- J^T A J and
+// V <- V J.  Entry (i, j) of J^T A J depends only on the 2 x 2 block of A on
+// the pairs of i and j, so after 16 threads have formed the rotation
+// parameters each of 256 threads transforms one block {p_k, q_k} x
+// {p_m, q_m} (columns first, then rows, as two separate passes would) and
+// each of the 512 threads one pair of entries of V: a step is one parameter
+// phase and one LDS phase.
 constexpr int BJT = 512;
-constexpr int BJ_PG = BJT / BJ_S;         // rotation pairs applied at once
-constexpr int BJ_PM = (BJ_S / 2) / BJ_PG; // rotation pairs per thread
+constexpr int BJ_NP = BJ_S / 2;            // rotation pairs per step
+static_assert(BJ_NP * BJ_NP <= BJT && BJ_NP * BJ_S == BJT, "one block / V pair per thread");
 constexpr int BJ_EM = BJ_S * BJ_S / BJT;  // matrix entries per thread
 
 __global__ __launch_bounds__(BJT) void bj_eig_kernel(int ld, int nbk, int round,
@@ -323,12 +326,17 @@ __global__ __launch_bounds__(BJT) void bj_eig_kernel(int ld, int nbk, int round,
     a[i][j] = G[bj_index(I, J, i) + (int64_t)ld * bj_index(I, J, j)];
     v[i][j] = i == j ? 1.0 : 0.0;
   }
+  // this thread's block of A (pairs km = t % 16 of rows, mm = t / 16 of
+  // columns; threads >= 256 have none) and entry pair of V (row vx, pair vk)
+  const int km = t % BJ_NP, mm = t / BJ_NP;
+  const bool has_a = t < BJ_NP * BJ_NP;
+  const int vx = t % BJ_S, vk = t / BJ_S;
   int rotated = 0;
   for (int sw = 0; sw < max_inner; ++sw) {
     if (t == 0) any = 0;
     __syncthreads();
     for (int r = 0; r < BJ_S - 1; ++r) {
-      if (t < BJ_S / 2) {
+      if (t < BJ_NP) {
         int p, q;
         tournament(BJ_S, r, t, &p, &q);
         const double app = a[p][p], aqq = a[q][q], apq = a[p][q];
@@ -343,54 +351,31 @@ __global__ __launch_bounds__(BJT) void bj_eig_kernel(int ld, int nbk, int round,
         cs[t][1] = s;
       }
       __syncthreads();
-      // thread t owns index x = t % BJ_S of the pairs k = t / BJ_S + BJ_PG m;
-      // all LDS loads of a phase are issued before its stores (the elements
-      // of distinct pairs are disjoint)
-      const int x = t % BJ_S, kb = t / BJ_S;
-      int pp[BJ_PM], qq[BJ_PM];
-      double cc[BJ_PM], ss[BJ_PM];
-#pragma unroll
-      for (int m = 0; m < BJ_PM; ++m) {
-        const int k = kb + BJ_PG * m;
-        pp[m] = pq[k][0];
-        qq[m] = pq[k][1];
-        cc[m] = cs[k][0];
-        ss[m] = cs[k][1];
-      }
+      // V <- V J on the entry pair (vx, p_vk), (vx, q_vk)
       {
-        double axp[BJ_PM], axq[BJ_PM], vxp[BJ_PM], vxq[BJ_PM];
-#pragma unroll
-        for (int m = 0; m < BJ_PM; ++m) {
-          axp[m] = a[x][pp[m]];
-          axq[m] = a[x][qq[m]];
-          vxp[m] = v[x][pp[m]];
-          vxq[m] = v[x][qq[m]];
-        }
-#pragma unroll
-        for (int m = 0; m < BJ_PM; ++m) {
-          a[x][pp[m]] = cc[m] * axp[m] - ss[m] * axq[m];
-          a[x][qq[m]] = ss[m] * axp[m] + cc[m] * axq[m];
-          v[x][pp[m]] = cc[m] * vxp[m] - ss[m] * vxq[m];
-          v[x][qq[m]] = ss[m] * vxp[m] + cc[m] * vxq[m];
-        }
+        const int pv = pq[vk][0], qv = pq[vk][1];
+        const double c = cs[vk][0], s = cs[vk][1];
+        const double xp = v[vx][pv], xq = v[vx][qv];
+        v[vx][pv] = c * xp - s * xq;
+        v[vx][qv] = s * xp + c * xq;
       }
-      __syncthreads();
-      {
-        double apx[BJ_PM], aqx[BJ_PM];
-#pragma unroll
-        for (int m = 0; m < BJ_PM; ++m) {
-          apx[m] = a[pp[m]][x];
-          aqx[m] = a[qq[m]][x];
-        }
+      if (has_a) {
+        const int pk = pq[km][0], qk = pq[km][1], pm = pq[mm][0], qm = pq[mm][1];
+        const double ck = cs[km][0], sk = cs[km][1], cm = cs[mm][0], sm = cs[mm][1];
+        const double x00 = a[pk][pm], x01 = a[pk][qm], x10 = a[qk][pm], x11 = a[qk][qm];
+        // columns (p_m, q_m), then rows (p_k, q_k)
+        const double y00 = cm * x00 - sm * x01, y01 = sm * x00 + cm * x01;
+        const double y10 = cm * x10 - sm * x11, y11 = sm * x10 + cm * x11;
+        double z00 = ck * y00 - sk * y10, z10 = sk * y00 + ck * y10;
+        double z01 = ck * y01 - sk * y11, z11 = sk * y01 + ck * y11;
         // the annihilated pair (p, q) is set to zero rather than to its
         // rounding residue, which would otherwise keep the threshold test
         // above firing when a_pp and a_qq differ greatly in size
-#pragma unroll
-        for (int m = 0; m < BJ_PM; ++m) {
-          const bool rot = ss[m] != 0.0;
-          a[pp[m]][x] = (rot && x == qq[m]) ? 0.0 : cc[m] * apx[m] - ss[m] * aqx[m];
-          a[qq[m]][x] = (rot && x == pp[m]) ? 0.0 : ss[m] * apx[m] + cc[m] * aqx[m];
-        }
+        if (km == mm && sk != 0.0) z01 = z10 = 0.0;
+        a[pk][pm] = z00;
+        a[pk][qm] = z01;
+        a[qk][pm] = z10;
+        a[qk][qm] = z11;
       }
       __syncthreads();
     }
@@ -403,34 +388,36 @@ __global__ __launch_bounds__(BJT) void bj_eig_kernel(int ld, int nbk, int round,
   // orthogonality that the accumulated rotations lose to rounding.  The
   // diagonal tile is then recomputed as Q^T S Q like every other tile: the
   // rotated submatrix itself carries the rounding of every inner rotation.
+  // (lane t holds the entries (i, j_m) = (t % 32, t / 32 + 2 m) of both
+  // products, so each k loads one value of its row or column once)
+  static_assert(BJT % BJ_S == 0, "one row index per lane");
   if (rotated) {
+    __syncthreads();
+    const int i = t % BJ_S, j0 = t / BJ_S;
+    constexpr int JS = BJT / BJ_S;
     double acc[BJ_EM];
 #pragma unroll
-    for (int m = 0; m < BJ_EM; ++m) {
-      const int e = t + BJT * m, i = e % BJ_S, j = e / BJ_S;
-      double g = 0.0;
-      for (int k = 0; k < BJ_S; ++k) g = fma(v[k][i], v[k][j], g);
-      acc[m] = (i == j ? 1.0 : 0.0) - g;
+    for (int m = 0; m < BJ_EM; ++m) acc[m] = 0.0;
+    for (int k = 0; k < BJ_S; ++k) {
+      const double vki = v[k][i];
+#pragma unroll
+      for (int m = 0; m < BJ_EM; ++m) acc[m] = fma(vki, v[k][j0 + JS * m], acc[m]);
     }
 #pragma unroll
-    for (int m = 0; m < BJ_EM; ++m) {
-      const int e = t + BJT * m;
-      a[e % BJ_S][e / BJ_S] = acc[m];
-    }
+    for (int m = 0; m < BJ_EM; ++m) a[i][j0 + JS * m] = (i == j0 + JS * m ? 1.0 : 0.0) - acc[m];
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < BJ_EM; ++m) {
-      const int e = t + BJT * m, i = e % BJ_S, j = e / BJ_S;
-      double g = 0.0;
-      for (int k = 0; k < BJ_S; ++k) g = fma(v[i][k], a[k][j], g);
-      acc[m] = fma(0.5, g, v[i][j]);
+    for (int m = 0; m < BJ_EM; ++m) acc[m] = 0.0;
+    for (int k = 0; k < BJ_S; ++k) {
+      const double vik = v[i][k];
+#pragma unroll
+      for (int m = 0; m < BJ_EM; ++m) acc[m] = fma(vik, a[k][j0 + JS * m], acc[m]);
     }
+#pragma unroll
+    for (int m = 0; m < BJ_EM; ++m) acc[m] = fma(0.5, acc[m], v[i][j0 + JS * m]);
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < BJ_EM; ++m) {
-      const int e = t + BJT * m;
-      v[e % BJ_S][e / BJ_S] = acc[m];
-    }
+    for (int m = 0; m < BJ_EM; ++m) v[i][j0 + JS * m] = acc[m];
     __syncthreads();
   }
   double* Q = Qbuf + (int64_t)blockIdx.x * BJ_S * BJ_S;
@@ -589,16 +576,27 @@ __global__ void copy_matrix_kernel(int m, int n, const double* __restrict__ X, i
 
 // descending order of the first n diagonal entries of G (ld): the rank of
 // entry i counts the larger entries and the equal ones with a smaller index
-__global__ void eig_rank_kernel(int n, int ld, const double* __restrict__ G, int* __restrict__ order,
-                                double* __restrict__ w, double wscale) {
+// (the diagonal is staged through LDS in chunks; 256 threads per block)
+constexpr int EIG_RANK_CHUNK = 2048;
+
+__global__ __launch_bounds__(256) void eig_rank_kernel(int n, int ld, const double* __restrict__ G,
+                                                       int* __restrict__ order,
+                                                       double* __restrict__ w, double wscale) {
+  __shared__ double dg[EIG_RANK_CHUNK];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double di = G[i + (int64_t)ld * i];
+  const double di = i < n ? G[i + (int64_t)ld * i] : 0.0;
   int rank = 0;
-  for (int j = 0; j < n; ++j) {
-    const double dj = G[j + (int64_t)ld * j];
-    rank += (dj > di || (dj == di && j < i)) ? 1 : 0;
+  for (int j0 = 0; j0 < n; j0 += EIG_RANK_CHUNK) {
+    const int cnt = min(EIG_RANK_CHUNK, n - j0);
+    __syncthreads();
+    for (int j = threadIdx.x; j < cnt; j += blockDim.x) dg[j] = G[(j0 + j) + (int64_t)ld * (j0 + j)];
+    __syncthreads();
+    for (int j = 0; j < cnt; ++j) {
+      const double dj = dg[j];
+      rank += (dj > di || (dj == di && j0 + j < i)) ? 1 : 0;
+    }
   }
+  if (i >= n) return;
   order[rank] = i;
   w[rank] = di * wscale;
 }
@@ -973,24 +971,34 @@ static int qr_complete(int n, int q, const double* X, int ldx, double* Q, int ld
 
 // ------------------------------------------- pivoted QR for the thin SVD
 // Householder QR with column pivoting of a wide X (m x n, m <= QP_MAXM,
-// ld m): X P = Q R, one kernel launch per step k.  Columns are never moved:
-// phys maps logical column positions to columns of X (ping-pong buffers
-// between steps, like the squared norms of rows k.. of every column).  Step
-// k takes the remaining position of largest norm (the lowest position among
-// equal ones), swaps it into position k, forms the reflector
-// H_k = I - tau_k v_k v_k^T (v_k(k) = 1) from rows k.. of that column into
-// V(:, k) with R(k, k) = beta_k, and applies it to every later position,
-// recomputing their norms exactly.  Every block finds the pivot and forms the
-// reflector itself from the same data in the same order, so all agree; each
-// wave then updates its own positions.  Once the largest remaining norm is
-// at most `floor` the step reduces nothing (tau_k = 0, done[k] = 0): the
-// rest of X is left as it is, a block below the eps ||A||_F level the
-// eigen-solver does not rotate.
-constexpr int QP_THREADS = 256;
+// ld m): X P = Q R.  Columns are never moved: phys maps logical column
+// positions to columns of X.  Step k takes the remaining position of largest
+// norm (the squared norm of rows k..; the lowest position among equal ones),
+// swaps it into position k, forms the reflector H_k = I - tau_k v_k v_k^T
+// (v_k(k) = 1) from rows k.. of that column into V(:, k) with R(k, k) =
+// beta_k, and applies it to every later position, recomputing their norms
+// exactly.  Once the largest remaining norm is at most `floor` the step
+// reduces nothing (tau_k = 0, done[k] = 0): the rest of X is left as it is,
+// a block below the eps ||A||_F level the eigen-solver does not rotate.
+//
+// All m steps run in one launch: block b keeps the columns c = b + nb j in
+// LDS.  In a step every block posts its best remaining column (norm,
+// position, rows k..) to its slot, tagged with the step; every block waits
+// for all tags of the step, reduces the slots to the same pivot, reads the
+// pivot column from its owner's slot, forms the same reflector and updates
+// its own columns, one wave per column.  Each wave's arithmetic (rows
+// lane + 64 r, wave sums) is the same for every block, so every block agrees
+// on every pivot.  Two slot sets alternate between steps: a block can post
+// step k + 2 only after every block has posted step k + 1, i.e. has read
+// everything of step k.
+constexpr int QP_THREADS = 1024;
 constexpr int QP_WAVES = QP_THREADS / 64;
 constexpr int QP_MAXM = 512;
 constexpr int QP_RPL = QP_MAXM / 64;  // rows per lane
 constexpr int QP_MAXN = 4096;
+constexpr int QP_MAXB = 256;          // blocks of the launch
+// every block's columns fit the lanes of one wave (its candidate search)
+static_assert((QP_MAXN + QP_MAXB - 1) / QP_MAXB <= 64, "columns per block");
 
 __device__ __forceinline__ double qp_wave_sum(double v) {
 #pragma unroll
@@ -998,122 +1006,313 @@ __device__ __forceinline__ double qp_wave_sum(double v) {
   return v;
 }
 
-__global__ __launch_bounds__(QP_THREADS) void qrcp_step_kernel(
-    int k, int m, int n, double* __restrict__ X, const double* __restrict__ nrm_in,
-    double* __restrict__ nrm_out, const int* __restrict__ phys_in, int* __restrict__ phys_out,
-    double* __restrict__ V, double* __restrict__ tau, double* __restrict__ beta,
-    int* __restrict__ done, const double* __restrict__ floor2) {
+// Wave-wide reductions on DPP lane moves instead of LDS permutes: within
+// each row of 16 lanes the pairings xor 1, xor 2 (quad permutations), then
+// the mirrored halves of 8 and of 16 leave the row's result in all of its
+// lanes; the four row results are then read from lanes 15, 31, 47 and 63
+// and combined in that order, so every lane ends with the same value.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, true);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = dpp_i32<CTRL>((int)b), hi = dpp_i32<CTRL>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double readlane_f64(double x, int lane) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+constexpr int DPP_XOR1 = 0xB1;        // quad_perm [1, 0, 3, 2]
+constexpr int DPP_XOR2 = 0x4E;        // quad_perm [2, 3, 0, 1]
+constexpr int DPP_HALF_MIRROR = 0x141;
+constexpr int DPP_MIRROR = 0x140;
+
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_f64<DPP_XOR1>(v);
+  v += dpp_f64<DPP_XOR2>(v);
+  v += dpp_f64<DPP_HALF_MIRROR>(v);
+  v += dpp_f64<DPP_MIRROR>(v);
+  return (readlane_f64(v, 15) + readlane_f64(v, 31)) + (readlane_f64(v, 47) + readlane_f64(v, 63));
+}
+
+// Error flag of the pivoted QR's waits: a block that waits for another
+// block's slot longer than GB_SPIN_LIMIT polls sets it and leaves, and so
+// does every block that sees it set, so the kernel always ends; the host
+// reports it.  The launch has at most QP_MAXB blocks of one per compute
+// unit's worth of LDS, all resident at once.
+constexpr unsigned GB_SPIN_LIMIT = 1u << 22;
+
+__global__ void qp_err_init_kernel(int* err) { err[0] = 0; }
+
+// a block's candidate pivot: squared norm, position, column, and the step
+// (k + 1) it was posted for, written last with release order
+struct QpSlot {
+  double nrm;
+  int pos;
+  int col;
+  unsigned tag;
+  unsigned pad;
+};
+
+__global__ void qp_slot_init_kernel(int count, QpSlot* __restrict__ slots) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) slots[i].tag = 0u;
+}
+
+__device__ __forceinline__ bool qp_better(double an, int ap, double bn, int bp) {
+  return an > bn || (an == bn && ap < bp);
+}
+
+// a candidate in the reductions: squared norm, position, column, owner
+struct QpCand {
+  double n;
+  int p, c, o;
+};
+template <int CTRL>
+__device__ __forceinline__ QpCand dpp_cand(const QpCand& x) {
+  return QpCand{dpp_f64<CTRL>(x.n), dpp_i32<CTRL>(x.p), dpp_i32<CTRL>(x.c), dpp_i32<CTRL>(x.o)};
+}
+__device__ __forceinline__ QpCand readlane_cand(const QpCand& x, int lane) {
+  return QpCand{readlane_f64(x.n, lane), __builtin_amdgcn_readlane(x.p, lane),
+                __builtin_amdgcn_readlane(x.c, lane), __builtin_amdgcn_readlane(x.o, lane)};
+}
+// the wave's best candidate (largest norm, then lowest position), in every lane
+__device__ __forceinline__ QpCand qp_wave_best(QpCand x) {
+  auto take = [](QpCand& a, const QpCand& b) {
+    if (qp_better(b.n, b.p, a.n, a.p)) a = b;
+  };
+  take(x, dpp_cand<DPP_XOR1>(x));
+  take(x, dpp_cand<DPP_XOR2>(x));
+  take(x, dpp_cand<DPP_HALF_MIRROR>(x));
+  take(x, dpp_cand<DPP_MIRROR>(x));
+  QpCand r = readlane_cand(x, 15);
+  take(r, readlane_cand(x, 31));
+  take(r, readlane_cand(x, 47));
+  take(r, readlane_cand(x, 63));
+  return r;
+}
+
+__global__ __launch_bounds__(QP_THREADS) void qrcp_kernel(
+    int m, int n, double* __restrict__ X, const double* __restrict__ nrm0,
+    const double* __restrict__ floor2, double* __restrict__ V, double* __restrict__ tau,
+    double* __restrict__ beta, int* __restrict__ done, int* __restrict__ phys_out,
+    QpSlot* __restrict__ slots, double* __restrict__ colslot, int* __restrict__ err) {
+  extern __shared__ __align__(16) unsigned char qp_smem[];
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int cpb = (n + nb - 1) / nb;
+  double* cols = reinterpret_cast<double*>(qp_smem);            // cpb x m
+  double* piv = cols + (size_t)cpb * m;                          // m
+  double* lnrm = piv + m;                                        // cpb
+  int* lpos = reinterpret_cast<int*>(lnrm + cpb);                // cpb
+  int* lact = lpos + cpb;                                        // cpb
   __shared__ double wv[QP_WAVES];
-  __shared__ int wi[QP_WAVES];
+  __shared__ int wp[QP_WAVES], wc[QP_WAVES], wo[QP_WAVES];
+  __shared__ int qp_abort;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  // pivot over positions k..n-1
-  double bv = -1.0;
-  int bi = k;
-  for (int j = k + t; j < n; j += QP_THREADS) {
-    const double v = nrm_in[phys_in[j]];
-    if (v > bv) {
-      bv = v;
-      bi = j;
-    }
+  if (t == 0) qp_abort = 0;
+  const int ncols = b < n ? (n - 1 - b) / nb + 1 : 0;            // own columns
+  for (int e = t; e < ncols * m; e += QP_THREADS) {
+    const int j = e / m, i = e % m;
+    cols[(size_t)j * m + i] = X[i + (int64_t)m * (b + nb * j)];
   }
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    const double ov = __shfl_xor(bv, off, 64);
-    const int oi = __shfl_xor(bi, off, 64);
-    if (ov > bv || (ov == bv && oi < bi)) {
-      bv = ov;
-      bi = oi;
-    }
-  }
-  if (lane == 0) {
-    wv[wave] = bv;
-    wi[wave] = bi;
+  for (int j = t; j < ncols; j += QP_THREADS) {
+    lnrm[j] = nrm0[b + nb * j];
+    lpos[j] = b + nb * j;
+    lact[j] = 1;
   }
   __syncthreads();
-  double best = wv[0];
-  int p = wi[0];
-#pragma unroll
-  for (int w = 1; w < QP_WAVES; ++w) {
-    if (wv[w] > best || (wv[w] == best && wi[w] < p)) {
-      best = wv[w];
-      p = wi[w];
+  const double fl = floor2[0];
+  for (int k = 0; k < m; ++k) {
+    const int par = k & 1;
+    // this block's candidate: largest norm, then lowest position
+    if (wave == 0) {
+      QpCand x{-1.0, n, -1, 0};
+      if (lane < ncols && lact[lane]) x = QpCand{lnrm[lane], lpos[lane], lane, 0};
+      x = qp_wave_best(x);
+      if (lane == 0) {
+        wv[0] = x.n;
+        wp[0] = x.p;
+        wc[0] = x.c;
+      }
     }
-  }
-  auto pos = [&](int j) { return j == k ? phys_in[p] : (j == p ? phys_in[k] : phys_in[j]); };
-  if (blockIdx.x == 0) {
-    for (int j = t; j < n; j += QP_THREADS) phys_out[j] = pos(j);
-  }
-  const int ck = pos(k);
-  const double* xk = X + (int64_t)m * ck;
-  const bool reduce = best > floor2[0];  // uniform
-  // the reflector's rows k + 1.. (lane + 64 r), unscaled, in every wave
-  double v[QP_RPL];
-  double s = 0.0;
+    __syncthreads();
+    const unsigned tag = (unsigned)k + 1u;
+    // wave 0 posts the candidate: its column's rows k.., then the fields,
+    // then the tag (its release covers the wave's own stores)
+    if (wave == 0) {
+      const int bj = wc[0];
+      if (bj >= 0) {
+        double* cs = colslot + ((size_t)par * nb + b) * m;
+        for (int i = k + lane; i < m; i += 64) cs[i] = cols[(size_t)bj * m + i];
+      }
+      if (lane == 0) {
+        QpSlot* sl = slots + (size_t)par * nb + b;
+        sl->nrm = wv[0];
+        sl->pos = wp[0];
+        sl->col = bj >= 0 ? b + nb * bj : -1;
+        __hip_atomic_store(&sl->tag, tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    // the pivot: the best of all slots of this step (every block waits for
+    // every slot's tag, then reads it; a wait beyond GB_SPIN_LIMIT polls
+    // sets the error flag and ends the kernel)
+    {
+      QpCand x{-1.0, n, -1, 0};
+      for (int q = t; q < nb; q += QP_THREADS) {
+        QpSlot* sq = slots + (size_t)par * nb + q;
+        unsigned spins = 0;
+        while (__hip_atomic_load(&sq->tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != tag) {
+          if (++spins > GB_SPIN_LIMIT ||
+              __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            qp_abort = 1;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const QpSlot sl = *sq;
+        if (sl.col >= 0 && qp_better(sl.nrm, sl.pos, x.n, x.p)) x = QpCand{sl.nrm, sl.pos, sl.col, q};
+      }
+      x = qp_wave_best(x);
+      if (lane == 0) {
+        wv[wave] = x.n;
+        wp[wave] = x.p;
+        wc[wave] = x.c;
+        wo[wave] = x.o;
+      }
+    }
+    __syncthreads();
+    if (qp_abort) break;  // uniform
+    double best = wv[0];
+    int ppos = wp[0], pcol = wc[0], powner = wo[0];
 #pragma unroll
-  for (int r = 0; r < QP_RPL; ++r) {
-    const int i = k + 1 + lane + 64 * r;
-    v[r] = i < m ? xk[i] : 0.0;
-    s += v[r] * v[r];
-  }
-  s = qp_wave_sum(s);
-  const double alpha = xk[k];
-  double tk = 0.0, bk = alpha, sc = 0.0;
-  if (reduce && s != 0.0) {
-    const double nr = sqrt(alpha * alpha + s);
-    bk = alpha >= 0.0 ? -nr : nr;
-    tk = (bk - alpha) / bk;
-    sc = 1.0 / (alpha - bk);
-  }
-#pragma unroll
-  for (int r = 0; r < QP_RPL; ++r) v[r] *= sc;
-  if (blockIdx.x == 0 && wave == 0) {
-    double* vk = V + (int64_t)m * k;
+    for (int w = 1; w < QP_WAVES; ++w) {
+      if (qp_better(wv[w], wp[w], best, ppos)) {
+        best = wv[w];
+        ppos = wp[w];
+        pcol = wc[w];
+        powner = wo[w];
+      }
+    }
+    {
+      const double* cs = colslot + ((size_t)par * nb + powner) * m;
+      for (int i = k + t; i < m; i += QP_THREADS) piv[i] = cs[i];
+    }
+    // positions: the pivot moves to k, the column at k to the pivot's place
+    for (int j = t; j < ncols; j += QP_THREADS) {
+      if (b + nb * j == pcol) {
+        lpos[j] = k;
+        lact[j] = 0;
+      } else if (lpos[j] == k) {
+        lpos[j] = ppos;
+      }
+    }
+    __syncthreads();
+    const bool reduce = best > fl;  // uniform
+    if (!reduce) {
+      // every later step reduces nothing either (the norms no longer
+      // change): identity reflectors for positions k..m-1; the remaining
+      // columns keep their positions (R R^T does not depend on their order)
+      if (b == 0) {
+        for (int e = t; e < (m - k) * m; e += QP_THREADS) {
+          const int j = k + e / m, i = e % m;
+          V[i + (int64_t)m * j] = i == j ? 1.0 : 0.0;
+        }
+        for (int j = k + t; j < m; j += QP_THREADS) {
+          tau[j] = 0.0;
+          beta[j] = 0.0;
+          done[j] = 0;
+        }
+      }
+      break;
+    }
+    double v[QP_RPL];
+    double sq = 0.0;
 #pragma unroll
     for (int r = 0; r < QP_RPL; ++r) {
       const int i = k + 1 + lane + 64 * r;
-      if (i < m) vk[i] = v[r];
+      v[r] = i < m ? piv[i] : 0.0;
+      sq += v[r] * v[r];
     }
-    if (lane == 0) {
-      vk[k] = 1.0;
-      tau[k] = tk;
-      beta[k] = bk;
-      done[k] = reduce ? 1 : 0;
+    sq = wave_sum_dpp(sq);
+    const double alpha = piv[k];
+    double tk = 0.0, bk = alpha, sc = 0.0;
+    if (sq != 0.0) {
+      const double nr = sqrt(alpha * alpha + sq);
+      bk = alpha >= 0.0 ? -nr : nr;
+      tk = (bk - alpha) / bk;
+      sc = 1.0 / (alpha - bk);
     }
-  }
-  if (!reduce) {  // uniform: nothing to apply, the norms carry over
-    for (int j = k + 1 + blockIdx.x * QP_THREADS + t; j < n; j += gridDim.x * QP_THREADS) {
-      const int c = pos(j);
-      nrm_out[c] = nrm_in[c];
-    }
-    return;
-  }
-  // positions k + 1.. : one per wave of the grid at a time
-  const int gw = blockIdx.x * QP_WAVES + wave, nw = gridDim.x * QP_WAVES;
-  for (int j = k + 1 + gw; j < n; j += nw) {
-    const int c = pos(j);
-    double* xj = X + (int64_t)m * c;
-    double xv[QP_RPL];
-    double d = lane == 0 ? xj[k] : 0.0;
 #pragma unroll
-    for (int r = 0; r < QP_RPL; ++r) {
-      const int i = k + 1 + lane + 64 * r;
-      xv[r] = i < m ? xj[i] : 0.0;
-      d += v[r] * xv[r];
-    }
-    d = qp_wave_sum(d);
-    const double f = tk * d;
-    double s2 = 0.0;
+    for (int r = 0; r < QP_RPL; ++r) v[r] *= sc;
+    if (b == 0 && wave == 0) {
+      double* vk = V + (int64_t)m * k;
 #pragma unroll
-    for (int r = 0; r < QP_RPL; ++r) {
-      const int i = k + 1 + lane + 64 * r;
-      const double nv = xv[r] - f * v[r];
-      if (i < m) xj[i] = nv;
-      s2 += nv * nv;
+      for (int r = 0; r < QP_RPL; ++r) {
+        const int i = k + 1 + lane + 64 * r;
+        if (i < m) vk[i] = v[r];
+      }
+      if (lane == 0) {
+        vk[k] = 1.0;
+        tau[k] = tk;
+        beta[k] = bk;
+        done[k] = 1;
+      }
     }
-    if (lane == 0) xj[k] -= f;
-    s2 = qp_wave_sum(s2);
-    if (lane == 0) nrm_out[c] = s2;
+    {
+      for (int j = wave; j < ncols; j += QP_WAVES) {
+        if (!lact[j]) continue;  // uniform over the wave
+        double* xj = cols + (size_t)j * m;
+        double xv[QP_RPL];
+        double d = lane == 0 ? xj[k] : 0.0;
+#pragma unroll
+        for (int r = 0; r < QP_RPL; ++r) {
+          const int i = k + 1 + lane + 64 * r;
+          xv[r] = i < m ? xj[i] : 0.0;
+          d += v[r] * xv[r];
+        }
+        d = wave_sum_dpp(d);
+        const double f = tk * d;
+        double s2 = 0.0;
+#pragma unroll
+        for (int r = 0; r < QP_RPL; ++r) {
+          const int i = k + 1 + lane + 64 * r;
+          const double nv = xv[r] - f * v[r];
+          if (i < m) xj[i] = nv;
+          s2 += nv * nv;
+        }
+        if (lane == 0) xj[k] -= f;
+        s2 = wave_sum_dpp(s2);
+        if (lane == 0) lnrm[j] = s2;
+      }
+    }
+    __syncthreads();
   }
+  for (int e = t; e < ncols * m; e += QP_THREADS) {
+    const int j = e / m, i = e % m;
+    X[i + (int64_t)m * (b + nb * j)] = cols[(size_t)j * m + i];
+  }
+  for (int j = t; j < ncols; j += QP_THREADS) phys_out[lpos[j]] = b + nb * j;
+}
+
+// blocks of the pivoted QR launch and its dynamic LDS bytes
+// Few blocks keep the grid barrier short (eight, one per XCD, when the
+// columns fit): each block holds at most 64 columns and at most
+// QP_LDS_COLS_BYTES of them in LDS.
+constexpr size_t QP_LDS_COLS_BYTES = 144 * 1024;
+static int qrcp_blocks(int m, int n) {
+  const int fit = (int)std::max<size_t>(1, std::min<size_t>(64, QP_LDS_COLS_BYTES / ((size_t)m * 8)));
+  return std::min(QP_MAXB, std::max(std::min(8, n), (n + fit - 1) / fit));
+}
+static size_t qrcp_lds_bytes(int m, int n) {
+  const int cpb = (n + qrcp_blocks(m, n) - 1) / qrcp_blocks(m, n);
+  return ((size_t)cpb * m + m + cpb) * sizeof(double) + 2 * (size_t)cpb * sizeof(int);
 }
 
 // Initial squared norms (one wave per column) and the identity mapping
@@ -1178,22 +1377,36 @@ __global__ __launch_bounds__(256) void qrcp_apply_q_kernel(int m, const double* 
     const int i = lane + 64 * r;
     u[r] = i < m ? uj[i] : 0.0;
   }
-  for (int k = m - 1; k >= 0; --k) {
-    const double tk = tau[k];
-    if (tk == 0.0) continue;  // uniform
+  // the next reflector's rows are loaded while this one is applied
+  auto load = [&](int k, double* vv) {
     const double* vk = V + (int64_t)m * k;
-    double vv[QP_RPL];
-    double d = 0.0;
 #pragma unroll
     for (int r = 0; r < QP_RPL; ++r) {
       const int i = lane + 64 * r;
       vv[r] = (i >= k && i < m) ? vk[i] : 0.0;
-      d += vv[r] * u[r];
     }
-    d = qp_wave_sum(d);
-    const double f = tk * d;
+  };
+  double cur[QP_RPL], nxt[QP_RPL];
+  load(m - 1, cur);
+  double tk = tau[m - 1];
+  for (int k = m - 1; k >= 0; --k) {
+    double tn = 0.0;
+    if (k > 0) {
+      load(k - 1, nxt);
+      tn = tau[k - 1];
+    }
+    if (tk != 0.0) {  // uniform
+      double d = 0.0;
 #pragma unroll
-    for (int r = 0; r < QP_RPL; ++r) u[r] -= f * vv[r];
+      for (int r = 0; r < QP_RPL; ++r) d += cur[r] * u[r];
+      d = wave_sum_dpp(d);
+      const double f = tk * d;
+#pragma unroll
+      for (int r = 0; r < QP_RPL; ++r) u[r] -= f * cur[r];
+    }
+#pragma unroll
+    for (int r = 0; r < QP_RPL; ++r) cur[r] = nxt[r];
+    tk = tn;
   }
 #pragma unroll
   for (int r = 0; r < QP_RPL; ++r) {
@@ -1463,11 +1676,14 @@ static bool svd_preconditioned(int m, int n) {
   return m > EIG_SMALL && m <= QP_MAXM && m <= n && n <= QP_MAXN;
 }
 
-// X, R (m x n), V (m x m), tau, beta (m), two norm and two mapping buffers
-// (n), done flags (m), the floor
+// X, R (m x n), V (m x m), tau, beta (m), norms and the final mapping (n),
+// done flags (m), the floor, the two sets of pivot slots and candidate
+// columns, the grid barrier
 static size_t qrcp_work_bytes(int m, int n) {
+  const size_t nb = (size_t)qrcp_blocks(m, n);
   return 2 * al256((size_t)m * n * 8) + al256((size_t)m * m * 8) + 2 * al256((size_t)m * 8) +
-         2 * al256((size_t)n * 8) + 2 * al256((size_t)n * 4) + al256((size_t)m * 4) + 256;
+         al256((size_t)n * 8) + al256((size_t)n * 4) + al256((size_t)m * 4) + 256 +
+         al256(2 * nb * sizeof(QpSlot)) + al256(2 * nb * (size_t)m * 8) + al256(sizeof(int));
 }
 
 size_t dot_svd_workspace_bytes(int m, int n) {
@@ -1506,6 +1722,7 @@ int dot_svd_thin(int m, int n, const double* A_dev, int lda, double* s_dev, doub
   char* rest = wb + 2 * al256((size_t)m * m * 8) + al256((size_t)m * 8);
   if (lda != m) DOT_FAIL(DOT_EINVAL, "lda must equal m");
   GramDesc d{m, n, 1, 1, m, (int64_t)m * n};
+  const int* bar_err = nullptr;  // the pivoted QR's barrier error flag (device)
   if (svd_preconditioned(m, n)) {
     GramDesc dd = d;
     int nc;
@@ -1522,26 +1739,36 @@ int dot_svd_thin(int m, int n, const double* A_dev, int lda, double* s_dev, doub
     double* V = (double*)take((size_t)m * m * 8);
     double* tau = (double*)take((size_t)m * 8);
     double* beta = (double*)take((size_t)m * 8);
-    double* nrm[2] = {(double*)take((size_t)n * 8), (double*)take((size_t)n * 8)};
-    int* phys[2] = {(int*)take((size_t)n * 4), (int*)take((size_t)n * 4)};
+    double* nrm = (double*)take((size_t)n * 8);
+    int* phys = (int*)take((size_t)n * 4);
     int* done = (int*)take((size_t)m * 4);
     double* floor2 = (double*)take(8);
+    const int nb = qrcp_blocks(m, n);
+    QpSlot* slots = (QpSlot*)take(2 * (size_t)nb * sizeof(QpSlot));
+    double* colslot = (double*)take(2 * (size_t)nb * m * 8);
+    int* qerr = (int*)take(sizeof(int));
     const unsigned b = (unsigned)(((int64_t)m * n + 255) / 256);
     hipLaunchKernelGGL(copy_matrix_kernel, dim3(b), dim3(256), 0, s, m, n, A_dev, lda, X, m);
     DOT_LAUNCH_CHECK();
-    hipLaunchKernelGGL(qrcp_init_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, m, n, X, nrm[0],
-                       phys[0]);
+    hipLaunchKernelGGL(qrcp_init_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, m, n, X, nrm,
+                       phys);
     DOT_LAUNCH_CHECK();
-    hipLaunchKernelGGL(qrcp_floor_kernel, dim3(1), dim3(256), 0, s, n, nrm[0], floor2);
+    hipLaunchKernelGGL(qrcp_floor_kernel, dim3(1), dim3(256), 0, s, n, nrm, floor2);
     DOT_LAUNCH_CHECK();
-    const unsigned qb = (unsigned)((n + QP_WAVES - 1) / QP_WAVES);
-    for (int k = 0; k < m; ++k) {
-      hipLaunchKernelGGL(qrcp_step_kernel, dim3(qb), dim3(QP_THREADS), 0, s, k, m, n, X, nrm[k & 1],
-                         nrm[(k + 1) & 1], phys[k & 1], phys[(k + 1) & 1], V, tau, beta, done, floor2);
-      DOT_LAUNCH_CHECK();
-    }
-    hipLaunchKernelGGL(qrcp_extract_r_kernel, dim3(b), dim3(256), 0, s, m, n, X, phys[m & 1], beta,
-                       done, R);
+    hipLaunchKernelGGL(qp_err_init_kernel, dim3(1), dim3(1), 0, s, qerr);
+    DOT_LAUNCH_CHECK();
+    hipLaunchKernelGGL(qp_slot_init_kernel, dim3((unsigned)((2 * nb + 255) / 256)), dim3(256), 0, s,
+                       2 * nb, slots);
+    DOT_LAUNCH_CHECK();
+    const size_t lds = qrcp_lds_bytes(m, n);
+    if (lds > 65536)
+      DOT_HIP(hipFuncSetAttribute((const void*)qrcp_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds));
+    hipLaunchKernelGGL(qrcp_kernel, dim3(nb), dim3(QP_THREADS), lds, s, m, n, X, nrm, floor2, V, tau,
+                       beta, done, phys, slots, colslot, qerr);
+    DOT_LAUNCH_CHECK();
+    bar_err = qerr;
+    hipLaunchKernelGGL(qrcp_extract_r_kernel, dim3(b), dim3(256), 0, s, m, n, X, phys, beta, done, R);
     DOT_LAUNCH_CHECK();
     DOT_TRY_L(gram(d, R, G, (double*)rest, s));
     DOT_TRY_L(symeig(m, G, m, lam, U_dev, ldu, rest, s, 60, nullptr));
@@ -1556,8 +1783,11 @@ int dot_svd_thin(int m, int n, const double* A_dev, int lda, double* s_dev, doub
   DOT_LAUNCH_CHECK();
   // Y = A^T U diag(1/s) for s > rcut s_max
   std::vector<double> l0(1);
+  int berr = 0;
   DOT_HIP(hipMemcpyAsync(l0.data(), lam, sizeof(double), hipMemcpyDeviceToHost, s));
+  if (bar_err) DOT_HIP(hipMemcpyAsync(&berr, bar_err, sizeof(int), hipMemcpyDeviceToHost, s));
   DOT_HIP(hipStreamSynchronize(s));
+  if (berr) DOT_FAIL(DOT_EHIP, "pivoted QR: a wait for another block timed out (blocks not co-resident)");
   const double cut = (rcut * rcut) * std::max(l0[0], 0.0);
   const unsigned b = (unsigned)(((int64_t)m * m + 255) / 256);
   hipLaunchKernelGGL(scale_cols_inv_sqrt_kernel, dim3(b), dim3(256), 0, s, m, m, U_dev, ldu, lam,

@@ -33,6 +33,7 @@
 // deterministic: the coarse sums are formed in a fixed order and the dot
 // products reduce through wave shuffles and per-block partial slots.
 #include <algorithm>
+#include <type_traits>
 
 #include "dot_internal.h"
 
@@ -67,7 +68,9 @@ struct MgGeom {
   int64_t cnxy;
 };
 
-template <typename T>
+// T: arithmetic and coefficients; TB: the right-hand side b; TS: the
+// stored iterates and coarse vectors; TO: the smoothing result
+template <typename T, typename TB, typename TS, typename TO>
 struct MgArgs {
   MgGeom G;
   int k;
@@ -78,11 +81,11 @@ struct MgArgs {
   const T* sdc;        // down: sqrt(diag) of the coarse level
   const T* q;          // prolongation: sd / sd_coarse(parent)
   const int* active;   // columns to process (NULL = all)
-  const T* b;          // right-hand side of this level (ld)
-  const T* x;          // staged iterate (ld; the kernels without it form w b)
-  const T* xc;         // coarse correction added to it (cld)
-  T* out;              // smoothing: result (ld)
-  T* bc;               // down: coarse right-hand side (cld)
+  const TB* b;         // right-hand side of this level (ld)
+  const TS* x;         // staged iterate (ld; the kernels without it form w b)
+  const TS* xc;        // coarse correction added to it (cld)
+  TO* out;             // smoothing: result (ld)
+  TS* bc;              // down: coarse right-hand side (cld)
   int64_t ld, cld;
   double* partial;     // smoothing: [2][k][nblk] slots of b . out (or NULL)
   unsigned long long* prof_cols;  // optional: += active columns of the launch
@@ -117,12 +120,32 @@ template <typename T>
 __device__ __forceinline__ T mg_ld(const T* p, int64_t i) {
   return p[i];
 }
+// loads and stores of the work vectors in their storage type
+template <typename T>
+__device__ __forceinline__ T mg_ldv(const float* p, int64_t i) {
+  return (T)p[i];
+}
+template <typename T>
+__device__ __forceinline__ T mg_ldv(const double* p, int64_t i) {
+  return (T)p[i];
+}
+template <typename T>
+__device__ __forceinline__ T mg_ldv(const bf16s* p, int64_t i) {
+  return (T)__uint_as_float((unsigned)p[i].u << 16);
+}
+__device__ __forceinline__ void mg_stv(float* p, int64_t i, float v) { p[i] = v; }
+__device__ __forceinline__ void mg_stv(double* p, int64_t i, double v) { p[i] = v; }
+__device__ __forceinline__ void mg_stv(bf16s* p, int64_t i, float v) {
+  unsigned u = __float_as_uint(v);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even (finite values)
+  p[i].u = (unsigned short)(u >> 16);
+}
 
 // The staged iterate v of a level kernel is x (HX) or w b, plus q xc(parent)
 // with the prolongation (HC).  MG_DOWN writes the restriction of b - A^ v,
 // MG_SMOOTH writes v + w (b - A^ v).
-template <int MODE, bool HX, bool HC, typename T>
-__global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T> a) {
+template <int MODE, bool HX, bool HC, typename T, typename TB, typename TS, typename TO>
+__global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T, TB, TS, TO> a) {
   const MgGeom& G = a.G;
   const int groups = (a.k + MRG - 1) / MRG;
   // column groups fastest, then tiles: the blocks of one tile and its x
@@ -200,10 +223,10 @@ __global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T> a) {
   auto load_raw = [&](int64_t c, int64_t p, Raw& o, bool with_xc) {
 #pragma unroll
     for (int r = 0; r < MRG; ++r) {
-      o.v[r] = mg_ld(a.b, c + a.ld * col[r]);
-      if constexpr (HX) o.x[r] = mg_ld(a.x, c + a.ld * col[r]);
+      o.v[r] = mg_ldv<T>(a.b, c + a.ld * col[r]);
+      if constexpr (HX) o.x[r] = mg_ldv<T>(a.x, c + a.ld * col[r]);
       if constexpr (HC) {
-        if (with_xc) o.xc[r] = mg_ld(a.xc, p + a.cld * col[r]);
+        if (with_xc) o.xc[r] = mg_ldv<T>(a.xc, p + a.cld * col[r]);
       }
     }
     if constexpr (HC) o.q = mg_ld(a.q, c);
@@ -298,13 +321,13 @@ __global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T> a) {
         if ((z & 1) == 1 || z + 1 == G.nz) {
           if (in && (lane & 33) == 0) {
             const int64_t C = (x >> 1) + (int64_t)G.cnx * (y >> 1) + G.cnxy * (z >> 1);
-            a.bc[C + a.cld * col[r]] = zacc[r] / sdc_next;
+            mg_stv(a.bc, C + a.cld * col[r], zacc[r] / sdc_next);
           }
         }
       } else {
         const T zv = vc[r] + w * (bv - Av);
         if (in) {
-          a.out[c + a.ld * col[r]] = zv;
+          mg_stv(a.out, c + a.ld * col[r], zv);
           acc[r] += (double)bv * (double)zv;
         }
       }
@@ -344,36 +367,37 @@ __global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T> a) {
 
 // One damped Jacobi step on the coarsest level, one thread per cell and
 // column: out = in + w (b - A^ in), or out = w b when in is NULL.
-template <typename T>
+template <typename T, typename TS>
 __global__ __launch_bounds__(256) void mg_jacobi_kernel(GridDims g, int k, const T* __restrict__ sx,
                                                         const T* __restrict__ sy,
                                                         const T* __restrict__ sz,
                                                         const int* __restrict__ active,
-                                                        const T* __restrict__ b,
-                                                        const T* __restrict__ xin, T* __restrict__ out,
-                                                        int64_t ld) {
+                                                        const TS* __restrict__ b,
+                                                        const TS* __restrict__ xin,
+                                                        TS* __restrict__ out, int64_t ld) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= g.N * k) return;
   const int j = (int)(t / g.N);
   const int64_t c = t - (int64_t)j * g.N;
   if (active && active[j] == 0) return;
   const T w = (T)MG_OMEGA;
-  const T* bj = b + ld * j;
-  T* oj = out + ld * j;
+  const TS* bj = b + ld * j;
+  TS* oj = out + ld * j;
   if (!xin) {
-    oj[c] = w * bj[c];
+    mg_stv(oj, c, w * mg_ldv<T>(bj, c));
     return;
   }
-  const T* xj = xin + ld * j;
+  const TS* xj = xin + ld * j;
   const int x = (int)(c % g.nx);
   const int y = (int)((c / g.nx) % g.ny);
   const int z = (int)(c / g.nxy);
-  T Av = xj[c] - sx[c] * (x + 1 < g.nx ? xj[c + 1] : T(0)) - sy[c] * (y + 1 < g.ny ? xj[c + g.nx] : T(0)) -
-         sz[c] * (z + 1 < g.nz ? xj[c + g.nxy] : T(0));
-  if (x > 0) Av -= sx[c - 1] * xj[c - 1];
-  if (y > 0) Av -= sy[c - g.nx] * xj[c - g.nx];
-  if (z > 0) Av -= sz[c - g.nxy] * xj[c - g.nxy];
-  oj[c] = xj[c] + w * (bj[c] - Av);
+  auto X = [&](int64_t i) { return mg_ldv<T>(xj, i); };
+  T Av = X(c) - sx[c] * (x + 1 < g.nx ? X(c + 1) : T(0)) - sy[c] * (y + 1 < g.ny ? X(c + g.nx) : T(0)) -
+         sz[c] * (z + 1 < g.nz ? X(c + g.nxy) : T(0));
+  if (x > 0) Av -= sx[c - 1] * X(c - 1);
+  if (y > 0) Av -= sy[c - g.nx] * X(c - g.nx);
+  if (z > 0) Av -= sz[c - g.nxy] * X(c - g.nxy);
+  mg_stv(oj, c, X(c) + w * (mg_ldv<T>(bj, c) - Av));
 }
 
 // The coarse tail of the V-cycle in one launch: the levels from the first
@@ -400,19 +424,19 @@ struct MgTailLevel {
   int nu;            // smoothing steps each way
 };
 
-template <typename T>
+template <typename T, typename TS>
 struct MgTailArgs {
   int nl;  // tail levels; L[nl - 1] is the coarsest
   MgTailLevel<T> L[DOT_MG_MAXLEV];
   int k;
   const int* active;
-  const T* b;  // right-hand side of L[0] (global, ldb)
-  T* z;        // result of L[0] (global, ldz)
+  const TS* b;  // right-hand side of L[0] (global, ldb)
+  TS* z;        // result of L[0] (global, ldz)
   int64_t ldb, ldz;
 };
 
-template <typename T>
-__global__ __launch_bounds__(MG_TAIL_THREADS) void mg_tail_kernel(MgTailArgs<T> a) {
+template <typename T, typename TS>
+__global__ __launch_bounds__(MG_TAIL_THREADS) void mg_tail_kernel(MgTailArgs<T, TS> a) {
   extern __shared__ __align__(16) unsigned char mg_tail_smem[];
   T* S = reinterpret_cast<T*>(mg_tail_smem);
   const int j = blockIdx.x;
@@ -469,7 +493,7 @@ __global__ __launch_bounds__(MG_TAIL_THREADS) void mg_tail_kernel(MgTailArgs<T> 
   };
 
   const MgTailLevel<T>& L0 = a.L[0];
-  for (int c = t; c < L0.N; c += MG_TAIL_THREADS) S[L0.off + c] = a.b[c + a.ldb * j];
+  for (int c = t; c < L0.N; c += MG_TAIL_THREADS) S[L0.off + c] = mg_ldv<T>(a.b, c + a.ldb * j);
   __syncthreads();
   const T* pre[DOT_MG_MAXLEV];
   // down: x = J^(nu - 1)(w b), restriction of b - A^ x
@@ -546,7 +570,7 @@ __global__ __launch_bounds__(MG_TAIL_THREADS) void mg_tail_kernel(MgTailArgs<T> 
     }
     zc = buf[cur];
   }
-  for (int c = t; c < L0.N; c += MG_TAIL_THREADS) a.z[c + a.ldz * j] = zc[c];
+  for (int c = t; c < L0.N; c += MG_TAIL_THREADS) mg_stv(a.z, c + a.ldz * j, zc[c]);
 }
 
 static size_t mg_al(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -556,23 +580,29 @@ static size_t mg_al(size_t v) { return (v + 255) & ~(size_t)255; }
 // apart.
 static int64_t mg_ld_of(int64_t N) { return N >= 8192 ? N + 1088 : N; }
 
-size_t mg_work_bytes(const dot_op* op, int k, int64_t ld0, size_t elem) {
+size_t mg_work_bytes(const dot_op* op, int k, int64_t ld0, size_t elem, int level0_iterates) {
   if (op->mg_nlev < 2) return 0;
-  size_t off = MG_NU0 >= 2 ? mg_al((size_t)ld0 * k * elem) : 0;
+  size_t off = MG_NU0 >= 2 ? (size_t)level0_iterates * mg_al((size_t)ld0 * k * elem) : 0;
   for (int l = 1; l < op->mg_nlev; ++l) off += 3 * mg_al((size_t)mg_ld_of(op->mg[l].g.N) * k * elem);
   return off;
 }
 
 template <typename T>
-void mg_work_layout(const dot_op* op, int k, int64_t ld0, char* base, MgWork<T>* w) {
+void mg_work_layout(const dot_op* op, int k, int64_t ld0, char* base, MgWork<T>* w,
+                    int level0_iterates) {
   *w = MgWork<T>{};
   if (op->mg_nlev < 2) return;
   w->nlev = op->mg_nlev;
   w->ld[0] = ld0;
   size_t off = 0;
   if (MG_NU0 >= 2) {
+    const size_t bytes = mg_al((size_t)ld0 * k * sizeof(T));
     w->x[0] = reinterpret_cast<T*>(base);
-    off += mg_al((size_t)ld0 * k * sizeof(T));
+    off += bytes;
+    if (level0_iterates > 1) {
+      w->z[0] = reinterpret_cast<T*>(base + off);
+      off += bytes;
+    }
   }
   for (int l = 1; l < op->mg_nlev; ++l) {
     w->ld[l] = mg_ld_of(op->mg[l].g.N);
@@ -585,8 +615,9 @@ void mg_work_layout(const dot_op* op, int k, int64_t ld0, char* base, MgWork<T>*
     off += bytes;
   }
 }
-template void mg_work_layout<float>(const dot_op*, int, int64_t, char*, MgWork<float>*);
-template void mg_work_layout<double>(const dot_op*, int, int64_t, char*, MgWork<double>*);
+template void mg_work_layout<float>(const dot_op*, int, int64_t, char*, MgWork<float>*, int);
+template void mg_work_layout<double>(const dot_op*, int, int64_t, char*, MgWork<double>*, int);
+template void mg_work_layout<bf16s>(const dot_op*, int, int64_t, char*, MgWork<bf16s>*, int);
 
 int mg_partial_slots(const dot_op* op, int k) {
   if (op->mg_nlev < 2) return 0;
@@ -613,10 +644,10 @@ struct MgCoef<float> {
   static const float* sd(const MgLevel& L) { return L.sd32; }
 };
 
-template <int MODE, bool HX, bool HC, typename T>
-static void mg_launch(const MgArgs<T>& a, int groups, hipStream_t s) {
+template <int MODE, bool HX, bool HC, typename T, typename TB, typename TS, typename TO>
+static void mg_launch(const MgArgs<T, TB, TS, TO>& a, int groups, hipStream_t s) {
   const int blocks = a.G.ntiles * a.G.nzc * groups;
-  hipLaunchKernelGGL((mg_level_kernel<MODE, HX, HC, T>), dim3(blocks), dim3(MNT), 0, s, a);
+  hipLaunchKernelGGL((mg_level_kernel<MODE, HX, HC, T, TB, TS, TO>), dim3(blocks), dim3(MNT), 0, s, a);
 }
 
 // The coarse tail run by mg_tail_kernel: levels t0 .. nl - 1 (t0 >= 1), the
@@ -637,75 +668,93 @@ static int mg_tail_start(const dot_op* op, size_t elem, size_t* tail_bytes) {
   return t0;
 }
 
-template <typename T>
-int mg_vcycle(dot_op* op, const MgWork<T>& w, int k, const T* r0, int64_t ld0, T* z0,
+// Level 0's smoothing outputs: with S = T they alternate between z0 and
+// w.x[0], the first and the last in z0 (2 nu - 1 of them); with a narrower
+// S they alternate between w.z[0] and w.x[0] and the last one is z0.  Every
+// coarser level alternates between w.z[l] and w.x[l], the last in w.z[l],
+// where the level above reads the correction.
+template <typename T, typename S>
+int mg_vcycle(dot_op* op, const MgWork<S>& w, int k, const T* r0, int64_t ld0, T* z0,
               const int* active, double* partial, hipStream_t s, unsigned long long* prof_cols) {
+  constexpr bool same = std::is_same<T, S>::value;
   const int nl = op->mg_nlev;
   if (nl < 2 || w.nlev != nl) DOT_FAIL(DOT_EINVAL, "multigrid hierarchy not available");
-  if (MG_NU0 >= 2 && !w.x[0]) DOT_FAIL(DOT_EINVAL, "multigrid work vectors missing");
+  if (MG_NU0 >= 2 && (!w.x[0] || (!same && !w.z[0])))
+    DOT_FAIL(DOT_EINVAL, "multigrid work vectors missing");
   const int groups = (k + MRG - 1) / MRG;
-  // right-hand side of level l; its smoothing results alternate between
-  // res(l) and alt(l), the first and the last (an odd count, 2 nu - 1) in
-  // res(l), where the level above reads the correction
-  auto bl = [&](int l) -> const T* { return l == 0 ? r0 : w.b[l]; };
-  auto res = [&](int l) -> T* { return l == 0 ? z0 : w.z[l]; };
-  auto alt = [&](int l) -> T* { return w.x[l]; };
-  auto args = [&](int l) {
+  auto geom = [&](int l) { return mg_geom(op->mg[l].g, l + 1 < nl ? &op->mg[l + 1].g : nullptr, k); };
+  // common fields of a level's launch
+  auto fill = [&](auto& a, int l) {
     const MgLevel& L = op->mg[l];
-    MgArgs<T> a{};
-    a.G = mg_geom(L.g, l + 1 < nl ? &op->mg[l + 1].g : nullptr, k);
+    a.G = geom(l);
     a.k = k;
     a.sx = MgCoef<T>::sx(L);
     a.sy = MgCoef<T>::sy(L);
     a.sz = MgCoef<T>::sz(L);
+    a.q = MgCoef<T>::q(L);
     a.active = active;
-    a.b = bl(l);
     a.ld = l == 0 ? ld0 : w.ld[l];
     if (l + 1 < nl) a.cld = w.ld[l + 1];
-    return a;
+    a.nblk = a.G.ntiles * a.G.nzc;
   };
-  size_t tail_bytes = 0;
-  const int t0 = mg_tail_start(op, sizeof(T), &tail_bytes);
-  const int ndown = t0 < nl ? t0 : nl - 1;  // levels with a down and an up pass
-  // one smoothing step on level l from x (NULL: w b) plus, with xc, the
-  // prolongation of xc; returns the buffer written
-  int outputs[DOT_MG_MAXLEV] = {};
-  auto smooth = [&](int l, const T* x, const T* xc, double* part) -> T* {
-    MgArgs<T> a = args(l);
-    T* o = (outputs[l]++ & 1) ? alt(l) : res(l);
+  // one smoothing step of level l with right-hand side b, staged iterate x
+  // (NULL: w b) and coarse correction xc (NULL: none), result to out
+  auto launch_smooth = [&](auto* b, const S* x, const S* xc, auto* out, int l, double* part) {
+    using TB = std::remove_const_t<std::remove_pointer_t<decltype(b)>>;
+    using TO = std::remove_pointer_t<decltype(out)>;
+    MgArgs<T, TB, S, TO> a{};
+    fill(a, l);
+    a.b = b;
     a.x = x;
     a.xc = xc;
-    a.q = MgCoef<T>::q(op->mg[l]);
-    a.out = o;
+    a.out = out;
     a.partial = part;
     a.prof_cols = part ? prof_cols : nullptr;
-    a.nblk = a.G.ntiles * a.G.nzc;
     if (x && xc) mg_launch<MG_SMOOTH, true, true>(a, groups, s);
     else if (x) mg_launch<MG_SMOOTH, true, false>(a, groups, s);
     else if (xc) mg_launch<MG_SMOOTH, false, true>(a, groups, s);
     else mg_launch<MG_SMOOTH, false, false>(a, groups, s);
-    return o;
   };
-  // down the hierarchy: nu - 1 steps after x = w b, then the restriction
-  const T* pre[DOT_MG_MAXLEV] = {};
-  for (int l = 0; l < ndown; ++l) {
-    const T* x = nullptr;
-    for (int i = 1; i < mg_nu(l); ++i) {
-      x = smooth(l, x, nullptr, nullptr);
-      DOT_LAUNCH_CHECK();
-    }
-    pre[l] = x;
-    MgArgs<T> a = args(l);
+  auto launch_down = [&](auto* b, const S* x, int l) {
+    using TB = std::remove_const_t<std::remove_pointer_t<decltype(b)>>;
+    MgArgs<T, TB, S, S> a{};
+    fill(a, l);
     a.sd = MgCoef<T>::sd(op->mg[l]);
     a.sdc = MgCoef<T>::sd(op->mg[l + 1]);
+    a.b = b;
     a.x = x;
     a.bc = w.b[l + 1];
     if (x) mg_launch<MG_DOWN, true, false>(a, groups, s);
     else mg_launch<MG_DOWN, false, false>(a, groups, s);
+  };
+  size_t tail_bytes = 0;
+  const int t0 = mg_tail_start(op, sizeof(T), &tail_bytes);
+  const int ndown = t0 < nl ? t0 : nl - 1;  // levels with a down and an up pass
+  int outputs[DOT_MG_MAXLEV] = {};
+  // the S buffer of level l's next non-final output
+  auto next_buf = [&](int l) -> S* {
+    const bool first_kind = (outputs[l]++ & 1) == 0;
+    if (l == 0 && same) return first_kind ? reinterpret_cast<S*>(z0) : w.x[0];
+    return first_kind ? w.z[l] : w.x[l];
+  };
+  // down the hierarchy: nu - 1 steps after x = w b, then the restriction
+  const S* pre[DOT_MG_MAXLEV] = {};
+  for (int l = 0; l < ndown; ++l) {
+    const S* x = nullptr;
+    for (int i = 1; i < mg_nu(l); ++i) {
+      S* o = next_buf(l);
+      if (l == 0) launch_smooth(r0, x, nullptr, o, 0, nullptr);
+      else launch_smooth(static_cast<const S*>(w.b[l]), x, nullptr, o, l, nullptr);
+      DOT_LAUNCH_CHECK();
+      x = o;
+    }
+    pre[l] = x;
+    if (l == 0) launch_down(r0, x, 0);
+    else launch_down(static_cast<const S*>(w.b[l]), x, l);
     DOT_LAUNCH_CHECK();
   }
   if (t0 < nl) {
-    MgTailArgs<T> ta{};
+    MgTailArgs<T, S> ta{};
     ta.nl = nl - t0;
     int off = 0;
     for (int i = 0; i < ta.nl; ++i) {
@@ -731,21 +780,21 @@ int mg_vcycle(dot_op* op, const MgWork<T>& w, int k, const T* r0, int64_t ld0, T
     ta.z = w.z[t0];
     ta.ldz = w.ld[t0];
     if (tail_bytes > 65536)
-      DOT_HIP(hipFuncSetAttribute((const void*)mg_tail_kernel<T>,
+      DOT_HIP(hipFuncSetAttribute((const void*)mg_tail_kernel<T, S>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)tail_bytes));
-    hipLaunchKernelGGL((mg_tail_kernel<T>), dim3(k), dim3(MG_TAIL_THREADS), tail_bytes, s, ta);
+    hipLaunchKernelGGL((mg_tail_kernel<T, S>), dim3(k), dim3(MG_TAIL_THREADS), tail_bytes, s, ta);
     DOT_LAUNCH_CHECK();
   } else {
     // coarsest level: MG_NU_C Jacobi steps from zero, ending in z
     const int l = nl - 1;
     const MgLevel& L = op->mg[l];
     const unsigned blocks = (unsigned)((L.g.N * k + 255) / 256);
-    T* bufs[2] = {w.x[l], w.z[l]};
+    S* bufs[2] = {w.x[l], w.z[l]};
     // step i writes bufs[(MG_NU_C - 1 - i) & 1], so the last one lands in z
-    const T* prev = nullptr;
+    const S* prev = nullptr;
     for (int i = 0; i < MG_NU_C; ++i) {
-      T* o = bufs[(MG_NU_C - 1 - i) & 1 ? 0 : 1];
-      hipLaunchKernelGGL((mg_jacobi_kernel<T>), dim3(blocks), dim3(256), 0, s, L.g, k,
+      S* o = bufs[(MG_NU_C - 1 - i) & 1 ? 0 : 1];
+      hipLaunchKernelGGL((mg_jacobi_kernel<T, S>), dim3(blocks), dim3(256), 0, s, L.g, k,
                          MgCoef<T>::sx(L), MgCoef<T>::sy(L), MgCoef<T>::sz(L), active, w.b[l], prev,
                          o, w.ld[l]);
       DOT_LAUNCH_CHECK();
@@ -753,13 +802,22 @@ int mg_vcycle(dot_op* op, const MgWork<T>& w, int k, const T* r0, int64_t ld0, T
     }
   }
   // up the hierarchy: the prolongation with the first of nu steps; on level
-  // 0 the last step also forms r0 . z0
+  // 0 the last step writes z0 and forms r0 . z0
   for (int l = ndown - 1; l >= 0; --l) {
-    const T* x = pre[l];
+    const S* x = pre[l];
     const int nu = mg_nu(l);
     for (int i = 0; i < nu; ++i) {
-      x = smooth(l, x, i == 0 ? w.z[l + 1] : nullptr, (l == 0 && i == nu - 1) ? partial : nullptr);
+      const S* xc = i == 0 ? w.z[l + 1] : nullptr;
+      if (l == 0 && i == nu - 1) {
+        launch_smooth(r0, x, xc, z0, 0, partial);
+        DOT_LAUNCH_CHECK();
+        break;
+      }
+      S* o = next_buf(l);
+      if (l == 0) launch_smooth(r0, x, xc, o, 0, nullptr);
+      else launch_smooth(static_cast<const S*>(w.b[l]), x, xc, o, l, nullptr);
       DOT_LAUNCH_CHECK();
+      x = o;
     }
   }
   return DOT_OK;
@@ -772,40 +830,47 @@ int mg_vcycle(dot_op* op, const MgWork<T>& w, int k, const T* r0, int64_t ld0, T
 // b and the iterate and writes the coarse right-hand side; the tail kernel
 // reads its top level's right-hand side and writes its result (the deeper
 // levels live in LDS); the Jacobi steps of a coarsest level without a tail
-// read b and the previous iterate and write.
-double mg_cycle_stream_bytes(const dot_op* op, size_t elem) {
+// read b and the previous iterate and write.  Level 0's right-hand side and
+// its last result take elem0 bytes, every other vector elem.
+double mg_cycle_stream_bytes(const dot_op* op, size_t elem0, size_t elem) {
   const int nl = op->mg_nlev;
   if (nl < 2) return 0.0;
   size_t tail_bytes = 0;
-  const int t0 = mg_tail_start(op, elem, &tail_bytes);
+  const int t0 = mg_tail_start(op, elem0, &tail_bytes);
   const int ndown = t0 < nl ? t0 : nl - 1;
-  double v = 0.0;   // vector streams, in cells
+  const double e0 = (double)elem0, e = (double)elem;
+  double v = 0.0;   // bytes
   for (int l = 0; l < ndown; ++l) {
     const double n = (double)op->mg[l].g.N, nc = (double)op->mg[l + 1].g.N;
+    const double eb = l == 0 ? e0 : e;   // this level's right-hand side
     const int nu = mg_nu(l);
     bool have_x = false;
     for (int i = 1; i < nu; ++i) {
-      v += (have_x ? 3.0 : 2.0) * n;
+      v += n * (eb + (have_x ? e : 0.0) + e);
       have_x = true;
     }
-    v += (have_x ? 2.0 : 1.0) * n + nc;            // restriction
+    v += n * (eb + (have_x ? e : 0.0)) + nc * e;            // restriction
     for (int i = 0; i < nu; ++i) {
-      v += (have_x ? 3.0 : 2.0) * n + (i == 0 ? nc : 0.0);
+      const double eo = (l == 0 && i == nu - 1) ? e0 : e;
+      v += n * (eb + (have_x ? e : 0.0) + eo) + (i == 0 ? nc * e : 0.0);
       have_x = true;
     }
   }
   if (t0 < nl) {
-    v += 2.0 * (double)op->mg[t0].g.N;
+    v += 2.0 * (double)op->mg[t0].g.N * e;
   } else {
     const double n = (double)op->mg[nl - 1].g.N;
-    v += 2.0 * n + (MG_NU_C - 1) * 3.0 * n;
+    v += (2.0 * n + (MG_NU_C - 1) * 3.0 * n) * e;
   }
-  return v * (double)elem;
+  return v;
 }
 
-template int mg_vcycle<float>(dot_op*, const MgWork<float>&, int, const float*, int64_t, float*,
-                              const int*, double*, hipStream_t, unsigned long long*);
-template int mg_vcycle<double>(dot_op*, const MgWork<double>&, int, const double*, int64_t,
-                               double*, const int*, double*, hipStream_t, unsigned long long*);
+template int mg_vcycle<float, float>(dot_op*, const MgWork<float>&, int, const float*, int64_t,
+                                     float*, const int*, double*, hipStream_t, unsigned long long*);
+template int mg_vcycle<float, bf16s>(dot_op*, const MgWork<bf16s>&, int, const float*, int64_t,
+                                     float*, const int*, double*, hipStream_t, unsigned long long*);
+template int mg_vcycle<double, double>(dot_op*, const MgWork<double>&, int, const double*, int64_t,
+                                       double*, const int*, double*, hipStream_t,
+                                       unsigned long long*);
 
 }  // namespace dot

@@ -747,7 +747,9 @@ struct Workspace {
   double* z64;
   float* z32;
   MgWork<double> mg64;
-  MgWork<float> mg32;
+  MgWork<float> mg32;   // DOT_MIXED with binary32 V-cycle vectors
+  MgWork<bf16s> mgh;    // DOT_MIXED with bfloat16 V-cycle vectors (the default)
+  bool mg_half;
   int mg_slots;      // partial slots per column of the V-cycle's r.z
   double* partial;
   size_t partial_stride;  // elements; the second set starts there
@@ -756,7 +758,7 @@ struct Workspace {
 };
 
 static size_t layout_workspace(const dot_op* op, const Geom& G, int precision, char* base,
-                               Workspace* w) {
+                               Workspace* w, bool mg_half = true) {
   const size_t Nk = (size_t)G.ldw * G.k;
   const bool mg = op->mg_nlev >= 2;
   size_t off = 0;
@@ -783,8 +785,12 @@ static size_t layout_workspace(const dot_op* op, const Geom& G, int precision, c
     ws.d32 = (float*)take(Nk * 4);
     if (mg) {
       ws.z32 = (float*)take(Nk * 4);
-      char* m = take(mg_work_bytes(op, G.k, G.ldw, 4));
-      if (base) mg_work_layout<float>(op, G.k, G.ldw, m, &ws.mg32);
+      // room for either storage of the V-cycle's vectors
+      char* m = take(std::max(mg_work_bytes(op, G.k, G.ldw, 4),
+                              mg_work_bytes(op, G.k, G.ldw, sizeof(bf16s), 2)));
+      ws.mg_half = mg_half;
+      if (base && mg_half) mg_work_layout<bf16s>(op, G.k, G.ldw, m, &ws.mgh, 2);
+      else if (base) mg_work_layout<float>(op, G.k, G.ldw, m, &ws.mg32);
     }
   }
   ws.mg_slots = mg ? mg_partial_slots(op, G.k) : 0;
@@ -1115,8 +1121,12 @@ static int solve_mixed(dot_op* op, const Geom& G, const Workspace& ws, const dou
     hipEvent_t e0, e1;
     unsigned long long* cols;
     DOT_TRY(prof_begin(op, DOT_PROF_VCYCLE_FP32, s, &e0, &e1, &cols));
-    DOT_TRY(mg_vcycle<float>(op, ws.mg32, G.k, ws.r32, G.ldw, ws.z32, ws.st.active, ws.partial, s,
-                             cols));
+    if (ws.mg_half)
+      DOT_TRY(mg_vcycle<float>(op, ws.mgh, G.k, ws.r32, G.ldw, ws.z32, ws.st.active, ws.partial, s,
+                               cols));
+    else
+      DOT_TRY(mg_vcycle<float>(op, ws.mg32, G.k, ws.r32, G.ldw, ws.z32, ws.st.active, ws.partial, s,
+                               cols));
     DOT_TRY(prof_end(op, DOT_PROF_VCYCLE_FP32, s, e0, e1, true));
     return launch_fin(F_RHO_MG, G, ws, ws.st.active, o.rtol, delta, s, first);
   };
@@ -1236,7 +1246,8 @@ int dot_multigrid_levels(const dot_op* op) {
 double dot_multigrid_cycle_bytes(const dot_op* op, int precision) {
   if (dot_multigrid_levels(op) == 0 || (precision != DOT_FP64 && precision != DOT_MIXED))
     return 0.0;
-  return mg_cycle_stream_bytes(op, precision == DOT_FP64 ? sizeof(double) : sizeof(float));
+  return precision == DOT_FP64 ? mg_cycle_stream_bytes(op, sizeof(double), sizeof(double))
+                                : mg_cycle_stream_bytes(op, sizeof(float), sizeof(bf16s));
 }
 
 // scaled vectors, r^ and z^, then the V-cycle's work vectors and dot slots
@@ -1320,11 +1331,12 @@ int dot_solve_multi_rhs(dot_op* op, int trans, int k, const double* rhs_dev, dou
   const char* xa = (const char*)x_dev;
   if (ra < xa + bytes && xa < ra + bytes) DOT_FAIL(DOT_EINVAL, "rhs_dev and x_dev overlap");
   if (opts->precond != DOT_PRECOND_AUTO && opts->precond != DOT_PRECOND_JACOBI &&
-      opts->precond != DOT_PRECOND_MG)
-    DOT_FAIL(DOT_EINVAL, "opts.precond must be DOT_PRECOND_AUTO, _JACOBI or _MG");
-  if (opts->precond == DOT_PRECOND_MG && op->mg_nlev < 2)
+      opts->precond != DOT_PRECOND_MG && opts->precond != DOT_PRECOND_MG_F32)
+    DOT_FAIL(DOT_EINVAL, "opts.precond must be DOT_PRECOND_AUTO, _JACOBI, _MG or _MG_F32");
+  const bool mg_req = opts->precond == DOT_PRECOND_MG || opts->precond == DOT_PRECOND_MG_F32;
+  if (mg_req && op->mg_nlev < 2)
     DOT_FAIL(DOT_EINVAL, "no multigrid hierarchy for this grid (every side must be >= 5)");
-  if (opts->precond == DOT_PRECOND_MG && !op->mg_ok)
+  if (mg_req && !op->mg_ok)
     DOT_FAIL(DOT_EINVAL, "multigrid hierarchy has a non-positive diagonal on some level");
   const bool mg = op->mg_nlev >= 2 && op->mg_ok && opts->precond != DOT_PRECOND_JACOBI;
   Geom G = make_geom(op->g, k);
@@ -1336,7 +1348,8 @@ int dot_solve_multi_rhs(dot_op* op, int trans, int k, const double* rhs_dev, dou
   if ((wa < xa + bytes && xa < wa + need) || (wa < ra + bytes && ra < wa + need))
     DOT_FAIL(DOT_EINVAL, "workspace overlaps rhs_dev or x_dev");
   Workspace ws;
-  layout_workspace(op, G, opts->precision, (char*)work_dev, &ws);
+  layout_workspace(op, G, opts->precision, (char*)work_dev, &ws,
+                   opts->precond != DOT_PRECOND_MG_F32);
   hipStream_t s = as_stream(stream);
   int iters = 0, outer = 0;
   int rc = opts->precision == DOT_FP64
