@@ -174,10 +174,12 @@ __global__ __launch_bounds__(256) void pair_g_kernel(GridDims g, JacParams P,
                                                      const int32_t* __restrict__ pair_cell,
                                                      double* __restrict__ pair_g,
                                                      float* __restrict__ pair_g32) {
+  // blocks (m, y): RBF m's pairs, split over gridDim.y blocks
   const int m = blockIdx.x;
   const double* th = theta + (int64_t)m * P.stride;
   const int na = P.n_act;
-  for (int64_t p = rbf_start[m] + threadIdx.x; p < rbf_start[m + 1]; p += 256) {
+  for (int64_t p = rbf_start[m] + blockIdx.y * 256 + threadIdx.x; p < rbf_start[m + 1];
+       p += 256 * (int64_t)gridDim.y) {
     const int64_t c = pair_cell[p];
     double x0, x1, x2, d[5];
     cell_xyz(g, c, &x0, &x1, &x2);
@@ -1293,7 +1295,9 @@ int jac_prepare(dot_op* op, hipStream_t s) {
   if (rc) return rc;
   int64_t* cnt = op->band_part + (nb + 1);
   if (np > 0) {
-    hipLaunchKernelGGL(pair_g_kernel, dim3(m0), dim3(256), 0, s, op->g, P, op->theta, op->phi,
+    // about four blocks per compute unit over all RBFs
+    const unsigned split = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, 1024 / std::max(m0, 1)));
+    hipLaunchKernelGGL(pair_g_kernel, dim3(m0, split), dim3(256), 0, s, op->g, P, op->theta, op->phi,
                        op->rbf_start, op->pair_cell, op->pair_g, op->pair_g32);
     DOT_LAUNCH_CHECK();
   }

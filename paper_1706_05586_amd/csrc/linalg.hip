@@ -308,32 +308,24 @@ constexpr int BJT = 512;
 constexpr int BJ_NP = BJ_S / 2;            // rotation pairs per step
 static_assert(BJ_NP * BJ_NP <= BJT && BJ_NP * BJ_S == BJT, "one block / V pair per thread");
 constexpr int BJ_EM = BJ_S * BJ_S / BJT;  // matrix entries per thread
+typedef double BjTile[BJ_S + 1];          // a row of a 32 x 32 LDS tile (padded)
 
-__global__ __launch_bounds__(BJT) void bj_eig_kernel(int ld, int nbk, int round,
-                                                     const double* __restrict__ G,
-                                                     double* __restrict__ Qbuf, int max_inner,
-                                                     double floor, int* __restrict__ flag) {
-  __shared__ double a[BJ_S][BJ_S + 1];
-  __shared__ double v[BJ_S][BJ_S + 1];
-  __shared__ double cs[BJ_S / 2][2];
-  __shared__ int pq[BJ_S / 2][2];
-  __shared__ int any;
+// The subproblem in `a` (loaded, the block synchronized): one threshold
+// Jacobi sweep (at most max_inner) accumulating the rotations in `v`, a
+// Newton-Schulz step, Q (32 x 32) to Qout; sets *flag if anything rotated.
+__device__ __forceinline__ void bj_solve_sub(BjTile* a, BjTile* v, double (*cs)[2], int (*pq)[2],
+                                             int* any, double* __restrict__ Qout, int max_inner,
+                                             double floor, int* __restrict__ flag) {
   const int t = threadIdx.x;
-  int I, J;
-  tournament(nbk, round, blockIdx.x, &I, &J);
-  for (int e = t; e < BJ_S * BJ_S; e += BJT) {
-    const int i = e % BJ_S, j = e / BJ_S;
-    a[i][j] = G[bj_index(I, J, i) + (int64_t)ld * bj_index(I, J, j)];
-    v[i][j] = i == j ? 1.0 : 0.0;
-  }
   // this thread's block of A (pairs km = t % 16 of rows, mm = t / 16 of
   // columns; threads >= 256 have none) and entry pair of V (row vx, pair vk)
   const int km = t % BJ_NP, mm = t / BJ_NP;
   const bool has_a = t < BJ_NP * BJ_NP;
   const int vx = t % BJ_S, vk = t / BJ_S;
+  for (int e = t; e < BJ_S * BJ_S; e += BJT) v[e % BJ_S][e / BJ_S] = (e % BJ_S) == (e / BJ_S) ? 1.0 : 0.0;
   int rotated = 0;
   for (int sw = 0; sw < max_inner; ++sw) {
-    if (t == 0) any = 0;
+    if (t == 0) *any = 0;
     __syncthreads();
     for (int r = 0; r < BJ_S - 1; ++r) {
       if (t < BJ_NP) {
@@ -343,7 +335,7 @@ __global__ __launch_bounds__(BJT) void bj_eig_kernel(int ld, int nbk, int round,
         double c = 1.0, s = 0.0;
         if (apq * apq > fmax(BJ_TOL * BJ_TOL * fabs(app * aqq), floor * floor)) {
           jacobi_angle_1div(app, aqq, apq, &c, &s);
-          any = 1;
+          *any = 1;
         }
         pq[t][0] = p;
         pq[t][1] = q;
@@ -379,7 +371,7 @@ __global__ __launch_bounds__(BJT) void bj_eig_kernel(int ld, int nbk, int round,
       }
       __syncthreads();
     }
-    const int did = any;
+    const int did = *any;
     __syncthreads();
     if (!did) break;
     rotated = 1;
@@ -388,11 +380,9 @@ __global__ __launch_bounds__(BJT) void bj_eig_kernel(int ld, int nbk, int round,
   // orthogonality that the accumulated rotations lose to rounding.  The
   // diagonal tile is then recomputed as Q^T S Q like every other tile: the
   // rotated submatrix itself carries the rounding of every inner rotation.
-  // (lane t holds the entries (i, j_m) = (t % 32, t / 32 + 2 m) of both
+  // (thread t holds the entries (i, j_m) = (t % 32, t / 32 + 16 m) of both
   // products, so each k loads one value of its row or column once)
-  static_assert(BJT % BJ_S == 0, "one row index per lane");
   if (rotated) {
-    __syncthreads();
     const int i = t % BJ_S, j0 = t / BJ_S;
     constexpr int JS = BJT / BJ_S;
     double acc[BJ_EM];
@@ -420,25 +410,67 @@ __global__ __launch_bounds__(BJT) void bj_eig_kernel(int ld, int nbk, int round,
     for (int m = 0; m < BJ_EM; ++m) v[i][j0 + JS * m] = acc[m];
     __syncthreads();
   }
-  double* Q = Qbuf + (int64_t)blockIdx.x * BJ_S * BJ_S;
-  for (int e = t; e < BJ_S * BJ_S; e += BJT) Q[e] = v[e % BJ_S][e / BJ_S];
+  for (int e = t; e < BJ_S * BJ_S; e += BJT) Qout[e] = v[e % BJ_S][e / BJ_S];
   if (t == 0 && rotated) atomicOr(flag, 1);
 }
 
-// Tiles of one round: blocks [0, ntri) are the upper tiles (P1 <= P2) of G,
-// the rest are (row block of BJ_S rows, pair P) tiles of V.
-__global__ __launch_bounds__(256) void bj_update_kernel(int ld, int nbk, int round,
-                                                        double* __restrict__ G,
-                                                        double* __restrict__ V,
-                                                        const double* __restrict__ Qbuf) {
-  __shared__ double x[BJ_S][BJ_S + 1];
-  __shared__ double q1[BJ_S][BJ_S + 1];
-  __shared__ double q2[BJ_S][BJ_S + 1];
+// The pair of the tournament's round that block index blk belongs to, and
+// its half (0: the pair's first block, 1: its second).
+__device__ __forceinline__ void tournament_inverse(int np, int round, int blk, int* pair, int* half) {
+  int k = 0;
+  if (blk != 0) k = (((blk - 1 - round) % (np - 1)) + (np - 1)) % (np - 1) + 1;
+  const int i = k < np / 2 ? k : np - 1 - k;
+  int p, q;
+  tournament(np, round, i, &p, &q);
+  *pair = i;
+  *half = blk == p ? 0 : 1;
+}
+
+// LDS of a block-Jacobi launch: the subproblem (a, v) and the staging of a
+// fused round (three tiles of G and two rotations; a and v reuse the first
+// two G tiles), or the tile update (x, q1, q2)
+constexpr int BJ_TILE = BJ_S * (BJ_S + 1);
+constexpr int BJ_SMEM = 5 * BJ_TILE + 3 * BJ_S * (BJ_NP + 1);
+
+// One block per pair of round `round`: the subproblem read from G.
+__global__ __launch_bounds__(BJT) void bj_eig_kernel(int ld, int nbk, int round,
+                                                     const double* __restrict__ G,
+                                                     double* __restrict__ Qbuf, int max_inner,
+                                                     double floor, int* __restrict__ flag) {
+  __shared__ double sm[2 * BJ_TILE];
+  __shared__ double cs[BJ_S / 2][2];
+  __shared__ int pq[BJ_S / 2][2];
+  __shared__ int any;
+  BjTile* a = reinterpret_cast<BjTile*>(sm);
+  BjTile* v = reinterpret_cast<BjTile*>(sm + BJ_TILE);
+  const int t = threadIdx.x;
+  int I, J;
+  tournament(nbk, round, blockIdx.x, &I, &J);
+  for (int e = t; e < BJ_S * BJ_S; e += BJT) {
+    const int i = e % BJ_S, j = e / BJ_S;
+    a[i][j] = G[bj_index(I, J, i) + (int64_t)ld * bj_index(I, J, j)];
+  }
+  __syncthreads();
+  bj_solve_sub(a, v, cs, pq, &any, Qbuf + (int64_t)blockIdx.x * BJ_S * BJ_S, max_inner, floor,
+               flag);
+}
+
+// One tile of round `round`'s update by NT threads, tile index b: b < ntri
+// are the upper tiles (P1 <= P2) of G, read from Gin and written (with the
+// mirror) to Gout; the rest are (row block of BJ_S rows, pair P) tiles of V,
+// updated in place.
+template <int NT>
+__device__ __forceinline__ void bj_update_tile(int ld, int nbk, int round, int b,
+                                               const double* __restrict__ Gin,
+                                               double* __restrict__ Gout, double* __restrict__ V,
+                                               const double* __restrict__ Qbuf, BjTile* x,
+                                               BjTile* q1, BjTile* q2) {
+  constexpr int OJ = BJ_S * BJ_S / NT;     // outputs per thread
+  constexpr int JS = NT / BJ_S;
   const int npairs = nbk / 2;
   const int ntri = npairs * (npairs + 1) / 2;
   const int t = threadIdx.x;
-  const int i = t % BJ_S, j0 = t / BJ_S;   // outputs (i, j0 + 8 m), m < 4
-  int b = blockIdx.x;
+  const int i = t % BJ_S, j0 = t / BJ_S;   // outputs (i, j0 + JS m), m < OJ
   if (b < ntri) {
     int P1 = 0;
     while (b >= npairs - P1) {
@@ -451,40 +483,42 @@ __global__ __launch_bounds__(256) void bj_update_kernel(int ld, int nbk, int rou
     tournament(nbk, round, P2, &I2, &J2);
     const double* Q1 = Qbuf + (int64_t)P1 * BJ_S * BJ_S;
     const double* Q2 = Qbuf + (int64_t)P2 * BJ_S * BJ_S;
-    for (int e = t; e < BJ_S * BJ_S; e += 256) {
+    for (int e = t; e < BJ_S * BJ_S; e += NT) {
       const int r = e % BJ_S, c = e / BJ_S;
-      x[r][c] = G[bj_index(I1, J1, r) + (int64_t)ld * bj_index(I2, J2, c)];
+      x[r][c] = Gin[bj_index(I1, J1, r) + (int64_t)ld * bj_index(I2, J2, c)];
       q1[r][c] = Q1[e];
       q2[r][c] = Q2[e];
     }
     __syncthreads();
-    double y[4] = {0.0, 0.0, 0.0, 0.0};
+    double y[OJ];
+#pragma unroll
+    for (int m = 0; m < OJ; ++m) y[m] = 0.0;
     for (int k = 0; k < BJ_S; ++k) {
       const double xik = x[i][k];
 #pragma unroll
-      for (int m = 0; m < 4; ++m) y[m] = fma(xik, q2[k][j0 + 8 * m], y[m]);
+      for (int m = 0; m < OJ; ++m) y[m] = fma(xik, q2[k][j0 + JS * m], y[m]);
     }
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < 4; ++m) x[i][j0 + 8 * m] = y[m];
+    for (int m = 0; m < OJ; ++m) x[i][j0 + JS * m] = y[m];
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < 4; ++m) y[m] = 0.0;
+    for (int m = 0; m < OJ; ++m) y[m] = 0.0;
     for (int k = 0; k < BJ_S; ++k) {
       const double qki = q1[k][i];
 #pragma unroll
-      for (int m = 0; m < 4; ++m) y[m] = fma(qki, x[k][j0 + 8 * m], y[m]);
+      for (int m = 0; m < OJ; ++m) y[m] = fma(qki, x[k][j0 + JS * m], y[m]);
     }
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < 4; ++m) x[i][j0 + 8 * m] = y[m];
+    for (int m = 0; m < OJ; ++m) x[i][j0 + JS * m] = y[m];
     __syncthreads();
-    for (int e = t; e < BJ_S * BJ_S; e += 256) {
+    for (int e = t; e < BJ_S * BJ_S; e += NT) {
       const int r = e % BJ_S, c = e / BJ_S;
       // a diagonal tile is symmetrized from its upper triangle
       const double val = (P1 == P2 && r > c) ? x[c][r] : x[r][c];
-      G[bj_index(I1, J1, r) + (int64_t)ld * bj_index(I2, J2, c)] = val;
-      if (P1 != P2) G[bj_index(I2, J2, c) + (int64_t)ld * bj_index(I1, J1, r)] = val;
+      Gout[bj_index(I1, J1, r) + (int64_t)ld * bj_index(I2, J2, c)] = val;
+      if (P1 != P2) Gout[bj_index(I2, J2, c) + (int64_t)ld * bj_index(I1, J1, r)] = val;
     }
   } else {
     b -= ntri;
@@ -493,21 +527,138 @@ __global__ __launch_bounds__(256) void bj_update_kernel(int ld, int nbk, int rou
     tournament(nbk, round, P, &I, &J);
     const double* Q = Qbuf + (int64_t)P * BJ_S * BJ_S;
     const int64_t row0 = (int64_t)R * BJ_S;
-    for (int e = t; e < BJ_S * BJ_S; e += 256) {
+    for (int e = t; e < BJ_S * BJ_S; e += NT) {
       const int r = e % BJ_S, c = e / BJ_S;
       x[r][c] = V[row0 + r + (int64_t)ld * bj_index(I, J, c)];
       q2[r][c] = Q[e];
     }
     __syncthreads();
-    double y[4] = {0.0, 0.0, 0.0, 0.0};
+    double y[OJ];
+#pragma unroll
+    for (int m = 0; m < OJ; ++m) y[m] = 0.0;
     for (int k = 0; k < BJ_S; ++k) {
       const double xik = x[i][k];
 #pragma unroll
-      for (int m = 0; m < 4; ++m) y[m] = fma(xik, q2[k][j0 + 8 * m], y[m]);
+      for (int m = 0; m < OJ; ++m) y[m] = fma(xik, q2[k][j0 + JS * m], y[m]);
     }
 #pragma unroll
-    for (int m = 0; m < 4; ++m) V[row0 + i + (int64_t)ld * bj_index(I, J, j0 + 8 * m)] = y[m];
+    for (int m = 0; m < OJ; ++m) V[row0 + i + (int64_t)ld * bj_index(I, J, j0 + JS * m)] = y[m];
   }
+}
+
+// The update of round `round` alone (the last round of a sweep).
+__global__ __launch_bounds__(256) void bj_update_kernel(int ld, int nbk, int round,
+                                                        const double* __restrict__ Gin,
+                                                        double* __restrict__ Gout,
+                                                        double* __restrict__ V,
+                                                        const double* __restrict__ Qbuf) {
+  __shared__ double sm[3 * BJ_TILE];
+  bj_update_tile<256>(ld, nbk, round, blockIdx.x, Gin, Gout, V, Qbuf,
+                      reinterpret_cast<BjTile*>(sm), reinterpret_cast<BjTile*>(sm + BJ_TILE),
+                      reinterpret_cast<BjTile*>(sm + 2 * BJ_TILE));
+}
+
+// A fused round: blocks [0, npairs) solve the subproblems of round + 1, each
+// formed from round `round`'s G (Gin) and rotations (Qin) as the tile update
+// would form it (G' = Q^T G Q on the two pairs holding the new pair's
+// blocks, (G Q) first, the diagonal tiles from their upper triangles); the
+// other blocks run round `round`'s update (Gin -> Gout, V).  So the update
+// leaves the critical path of a round: one launch per round.
+__global__ __launch_bounds__(BJT) void bj_round_kernel(int ld, int nbk, int round,
+                                                       const double* __restrict__ Gin,
+                                                       double* __restrict__ Gout,
+                                                       double* __restrict__ V,
+                                                       const double* __restrict__ Qin,
+                                                       double* __restrict__ Qout, int max_inner,
+                                                       double floor, int* __restrict__ flag) {
+  __shared__ double sm[BJ_SMEM];
+  __shared__ double cs[BJ_S / 2][2];
+  __shared__ int pq[BJ_S / 2][2];
+  __shared__ int any;
+  const int npairs = nbk / 2;
+  const int t = threadIdx.x;
+  if ((int)blockIdx.x >= npairs) {
+    bj_update_tile<BJT>(ld, nbk, round, blockIdx.x - npairs, Gin, Gout, V, Qin,
+                        reinterpret_cast<BjTile*>(sm), reinterpret_cast<BjTile*>(sm + BJ_TILE),
+                        reinterpret_cast<BjTile*>(sm + 2 * BJ_TILE));
+    return;
+  }
+  // pair P' = blockIdx.x of round + 1: blocks (I', J'), held in round
+  // `round` by pairs pa (half ha) and pb (half hb)
+  int Ip, Jp, pa, ha, pb, hb;
+  tournament(nbk, round + 1, blockIdx.x, &Ip, &Jp);
+  tournament_inverse(nbk, round, Ip, &pa, &ha);
+  tournament_inverse(nbk, round, Jp, &pb, &hb);
+  int Ia, Ja, Ib, Jb;
+  tournament(nbk, round, pa, &Ia, &Ja);
+  tournament(nbk, round, pb, &Ib, &Jb);
+  BjTile* g3 = reinterpret_cast<BjTile*>(sm);                 // [3]: aa, ab, bb
+  BjTile* q2 = reinterpret_cast<BjTile*>(sm + 3 * BJ_TILE);   // [2]: Q_pa, Q_pb
+  double (*tt)[BJ_S][BJ_NP + 1] =
+      reinterpret_cast<double (*)[BJ_S][BJ_NP + 1]>(sm + 5 * BJ_TILE);  // [3]: G Q halves
+  const double* Qa = Qin + (int64_t)pa * BJ_S * BJ_S;
+  const double* Qb = Qin + (int64_t)pb * BJ_S * BJ_S;
+  for (int e = t; e < BJ_S * BJ_S; e += BJT) {
+    const int r = e % BJ_S, c = e / BJ_S;
+    const int64_t ra = bj_index(Ia, Ja, r), rb = bj_index(Ib, Jb, r);
+    const int64_t ca = (int64_t)ld * bj_index(Ia, Ja, c), cb = (int64_t)ld * bj_index(Ib, Jb, c);
+    g3[r][c] = Gin[ra + ca];
+    g3[BJ_S + r][c] = Gin[ra + cb];
+    g3[2 * BJ_S + r][c] = Gin[rb + cb];
+    q2[r][c] = Qa[e];
+    q2[BJ_S + r][c] = Qb[e];
+  }
+  __syncthreads();
+  // tt[0] = G_aa Q_a[:, ha], tt[1] = G_ab Q_b[:, hb], tt[2] = G_bb Q_b[:, hb]
+  for (int e = t; e < 3 * BJ_S * BJ_NP; e += BJT) {
+    const int w = e / (BJ_S * BJ_NP), r = e % BJ_S, c = (e / BJ_S) % BJ_NP;
+    const BjTile* gw = g3 + w * BJ_S;
+    const BjTile* qw = q2 + (w == 0 ? 0 : BJ_S);
+    const int qc = (w == 0 ? ha : hb) * BJ_NP + c;
+    double y = 0.0;
+    for (int k = 0; k < BJ_S; ++k) y = fma(gw[r][k], qw[k][qc], y);
+    tt[w][r][c] = y;
+  }
+  __syncthreads();
+  // the subproblem: [Q_a^T tt0, Q_a^T tt1; ., Q_b^T tt2] on the halves,
+  // upper triangles of the diagonal blocks, lower parts by symmetry
+  double sub[2];
+  int si[2], sj[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int e = t + BJT * u;   // 3 x 256 entries: blocks 00, 01, 11
+    sub[u] = 0.0;
+    si[u] = -1;
+    sj[u] = -1;
+    if (e < 3 * BJ_NP * BJ_NP) {
+      const int w = e / (BJ_NP * BJ_NP), r = e % BJ_NP, c = (e / BJ_NP) % BJ_NP;
+      const BjTile* qw = q2 + (w == 2 ? BJ_S : 0);
+      const int qr = (w == 2 ? hb : ha) * BJ_NP + r;
+      double y = 0.0;
+      for (int k = 0; k < BJ_S; ++k) y = fma(qw[k][qr], tt[w][k][c], y);
+      sub[u] = y;
+      si[u] = (w == 2 ? BJ_NP : 0) + r;
+      sj[u] = (w == 0 ? 0 : BJ_NP) + c;
+    }
+  }
+  __syncthreads();
+  BjTile* a = g3;            // the G tiles are no longer needed
+  BjTile* v = g3 + BJ_S;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    if (si[u] < 0) continue;
+    const int r = si[u], c = sj[u];
+    const bool diag = (r < BJ_NP) == (c < BJ_NP);
+    if (!diag) {
+      a[r][c] = sub[u];
+      a[c][r] = sub[u];
+    } else if (r <= c) {
+      a[r][c] = sub[u];
+      a[c][r] = sub[u];
+    }
+  }
+  __syncthreads();
+  bj_solve_sub(a, v, cs, pq, &any, Qout + (int64_t)blockIdx.x * BJ_S * BJ_S, max_inner, floor, flag);
 }
 
 __global__ void bj_pad_kernel(int n, int ld, const double* __restrict__ A, int lda,
@@ -629,7 +780,7 @@ static size_t symeig_work_bytes(int n) {
   if (n <= EIG_SMALL) return 256;
   const int nbk = bj_blocks(n);
   const size_t ld = (size_t)nbk * BJ_B;
-  return 4 * al256(ld * ld * 8) + al256((size_t)(nbk / 2) * BJ_S * BJ_S * 8) +
+  return 4 * al256(ld * ld * 8) + 2 * al256((size_t)(nbk / 2) * BJ_S * BJ_S * 8) +
          al256(512 * 2 * sizeof(double)) + al256((size_t)n * sizeof(int)) +
          al256((size_t)n * sizeof(double)) + 256;
 }
@@ -656,7 +807,10 @@ static int symeig(int n, const double* A, int lda, double* w, double* V, int ldv
   off += al256(ll * 8);
   double* Vt = (double*)(work + off);
   off += al256(ll * 8);
-  double* Qb = (double*)(work + off);
+  double* Qb[2];   // the rotations of alternate rounds
+  Qb[0] = (double*)(work + off);
+  off += al256((size_t)npairs * BJ_S * BJ_S * 8);
+  Qb[1] = (double*)(work + off);
   off += al256((size_t)npairs * BJ_S * BJ_S * 8);
   double* part = (double*)(work + off);
   off += al256(512 * 2 * sizeof(double));
@@ -722,14 +876,23 @@ static int symeig(int n, const double* A, int lda, double* w, double* V, int ldv
     std::swap(Vw, Vt);
     hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, s, flag, 0);
     DOT_LAUNCH_CHECK();
-    for (int round = 0; round < nbk - 1; ++round) {
-      hipLaunchKernelGGL(bj_eig_kernel, dim3(npairs), dim3(BJT), 0, s, ld, nbk, round, Gw, Qb,
-                         BJ_INNER_SWEEPS, floor, flag);
+    // round 0's subproblems, then per round its update beside the next
+    // round's subproblems (G alternates between Gw and Gt), then the last
+    // round's update
+    const int R = nbk - 1;
+    hipLaunchKernelGGL(bj_eig_kernel, dim3(npairs), dim3(BJT), 0, s, ld, nbk, 0, Gw, Qb[0],
+                       BJ_INNER_SWEEPS, floor, flag);
+    DOT_LAUNCH_CHECK();
+    for (int round = 0; round + 1 < R; ++round) {
+      hipLaunchKernelGGL(bj_round_kernel, dim3(npairs + ntiles), dim3(BJT), 0, s, ld, nbk, round, Gw,
+                         Gt, Vw, Qb[round & 1], Qb[(round + 1) & 1], BJ_INNER_SWEEPS, floor, flag);
       DOT_LAUNCH_CHECK();
-      hipLaunchKernelGGL(bj_update_kernel, dim3(ntiles), dim3(256), 0, s, ld, nbk, round, Gw, Vw,
-                         Qb);
-      DOT_LAUNCH_CHECK();
+      std::swap(Gw, Gt);
     }
+    hipLaunchKernelGGL(bj_update_kernel, dim3(ntiles), dim3(256), 0, s, ld, nbk, R - 1, Gw, Gt, Vw,
+                       Qb[(R - 1) & 1]);
+    DOT_LAUNCH_CHECK();
+    std::swap(Gw, Gt);
   }
   if (sweeps) *sweeps = sweep;
   hipLaunchKernelGGL(eig_rank_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, ld, Gw, order, w,
