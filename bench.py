@@ -228,6 +228,7 @@ def main():
         if not res.converged:
             raise RuntimeError(f"solve did not converge: {res.relres.max():.3e}")
         state["res"] = res
+        marks = [time.perf_counter()]
         if full_path:
             U, Z = x[:, :ls], x[:, ls:]
             Rs, f = op.sampled_misfit(wl.det_cells, U, V, DW)
@@ -241,6 +242,7 @@ def main():
             if cfg.q_s > 0:
                 side.wait_stream(main)
                 fut = pool.submit(design_on_side, Js, main)
+            marks.append(time.perf_counter())
             # Gauss-Newton model: thin SVD of J_s (of J_s^T when J_s is tall)
             # and the truncated-SVD step for min ||J_s d + vec(R_s)||, kept to
             # the singular values above 1e-4 s_max
@@ -251,20 +253,33 @@ def main():
             t = int((sv > 1e-4 * sv[0]).sum().item())
             d = dl.tsvd_step(Lv, sv, Rv, Rs.t().reshape(-1), t)
             state.update(f=f, Js=Js, g=g, sv=sv, gn_step=d, gn_rank=t)
+            marks.append(time.perf_counter())
             if cfg.q_s > 0:
                 Wn, Vn, info = fut.result()
                 main.wait_stream(side)
                 state.update(W_next=Wn, V_next=Vn, hooi_iters=info["hooi_iters"])
+            marks.append(time.perf_counter())
+        state.setdefault("marks", []).append(marks)
 
     for _ in range(args.warmup):
         step(th_ref)
     torch.cuda.synchronize()
     op.profile_enable(True)
     t0 = time.perf_counter()
+    state["marks"] = []
+    starts = []
     for _ in range(args.steps):
+        starts.append(time.perf_counter())
         step(th_ref)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    # host time of each step's phases: the solve (it returns once every
+    # column has converged), misfit, Jacobian and gradient (launches only),
+    # thin SVD and Gauss-Newton step, the wait for the design
+    step_phases = [[round((b - a) * 1e3, 2) for a, b in zip([s0] + m[:-1], m)]
+                   for s0, m in zip(starts, state["marks"])]
+    log(f"[bench] step phases (solve; misfit, Jacobian, gradient; thin SVD and "
+        f"Gauss-Newton step; design wait) ms: {step_phases}")
     ms2, n2, cols2 = op.profile_read(L.DOT_PROF_PCG2_FP32)
     ms1, n1, cols1 = op.profile_read(L.DOT_PROF_PCG1_FP32)
     msj, nj, _ = op.profile_read(L.DOT_PROF_JACOBIAN)
@@ -398,6 +413,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "step_phases_ms": step_phases,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
