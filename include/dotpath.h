@@ -208,8 +208,12 @@ int dot_apply(dot_op* op, int k, const double* X_dev, double* Y_dev, void* strea
 /*
  * Simultaneous sources (Section 3.1, eq. Rw; Section 3.3): rhs_dev (N x k) =
  * B W, i.e. column l is sum_i weights_dev[i + n_pts l] e_{cells_host[i]}.
- * cells_host: n_pts cell indices in [0, N) (host array; repeated cells add).
- * Used for C V with the detector cells and V.
+ * cells_host: n_pts cell indices in [0, N) (host array, read before the
+ * call returns; repeated cells add, in the order given).  The handle keeps
+ * device copies of the last few distinct cell lists, so a list seen before
+ * costs no copy and the call returns without waiting for the GPU; a new list
+ * is copied after the stream's pending work.  Used for C V with the detector
+ * cells and V.
  */
 int dot_form_rhs(dot_op* op, int n_pts, const int32_t* cells_host, int k,
                  const double* weights_dev, double* rhs_dev, void* stream);

@@ -178,12 +178,32 @@ struct dot_op {
   int32_t* band_idx = nullptr;   // N: band row of a cell, -1 elsewhere
   int32_t* band_cells = nullptr; // cell of each band row
   int64_t band_cap = 0;
-  int64_t n_band = 0;
+  int64_t n_band = 0;            // valid once band_pending is false (band_count)
+  bool band_pending = false;     // n_band is still on its way to pinned_band
+  hipEvent_t band_ev = nullptr;  // recorded after that copy
+  int64_t* pinned_band = nullptr;
+  // pinned staging of the per-RBF list tables, reused once lists_ev (the
+  // previous upload) has completed
+  char* stage = nullptr;
+  size_t stage_cap = 0;
+  hipEvent_t lists_ev = nullptr;
+  bool lists_pending = false;
   int64_t* band_part = nullptr;  // per 2048-cell block: band cells before it
   int64_t band_part_cap = 0;
+  // optode cell lists on the device, keyed by the host list's content (the
+  // same sources and detectors come back every step, so a repeated list
+  // costs no copy): the cells in the caller's order, the points sorted
+  // stably by cell, the distinct cells and each one's run of points
+  struct CellList {
+    std::vector<int32_t> key;     // the host list
+    int32_t* dev = nullptr;       // [n] cells, [n] sorted points, [n_u] cells, [n_u + 1] runs
+    int64_t cap = 0;              // int32 slots of dev
+    int n = 0, n_u = 0;
+    uint64_t used = 0;            // last use, for replacement
+  };
+  CellList cell_lists[4];
+  uint64_t cell_clock = 0;
   // small device/pinned staging
-  int32_t* cells_dev = nullptr;   // optode cells staging
-  int64_t cells_cap = 0;
   double* small_dev = nullptr;    // small device scratch (scalars)
   void* prof = nullptr;           // kernel timing state (solve.hip)
   int32_t* pinned = nullptr;      // pinned host mailbox (counters/flags)
@@ -206,9 +226,14 @@ int profile_begin(dot_op* op, int kind, hipStream_t s, hipEvent_t* e0, hipEvent_
                   unsigned long long** cols);
 int profile_end(dot_op* op, int kind, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 constexpr int kPinnedInts = 4 * DOT_MAX_COLUMNS + 64;
-int ensure_cells_dev(dot_op* op, int n, const int32_t* cells_host, hipStream_t s);
+// the device copy of an optode cell list (host, n entries, each in [0, N));
+// *out is valid until the next call with a different list
+int cells_on_device(dot_op* op, int n, const int32_t* cells_host, hipStream_t s,
+                    const dot_op::CellList** out);
 // after the pair lists of dot_pals_mua: per-pair d mu / d p and band rows
 int jac_prepare(dot_op* op, hipStream_t s);
+// rows of the band lists (waits for the count of the last jac_prepare)
+int64_t band_count(dot_op* op);
 // the face rows and pairs of diffusion mode (after jac_prepare)
 int jac_prepare_faces(dot_op* op, hipStream_t s);
 // multigrid: levels of the grid (0 or 1: none), hierarchy (re)build after

@@ -1160,7 +1160,7 @@ static JacTables jac_tables(const dot_op* op) {
   JacTables t;
   t.face = op->diff_mode;
   if (!t.face) {
-    t.n_rows = op->n_band;
+    t.n_rows = band_count(const_cast<dot_op*>(op));
     t.row_cell = op->band_cells;
     t.row_nbr = nullptr;
     t.row_w = nullptr;
@@ -1313,10 +1313,16 @@ int jac_prepare(dot_op* op, hipStream_t s) {
   DOT_LAUNCH_CHECK();
   hipLaunchKernelGGL(band_scan_kernel, dim3(1), dim3(1024), 0, s, (int)nb, cnt, op->band_part);
   DOT_LAUNCH_CHECK();
-  int64_t n_band = 0;
-  DOT_HIP(hipMemcpyAsync(&n_band, op->band_part + nb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  DOT_HIP(hipStreamSynchronize(s));
-  rc = grow(&op->band_cells, &op->band_cap, std::max<int64_t>(n_band, 1));
+  // the band holds at most min(N, pairs) cells: band_cells is sized by that
+  // bound, and the count itself comes back through pinned memory, read
+  // when it is first needed (band_count), so nothing here waits for the GPU
+  if (op->band_pending) DOT_HIP(hipEventSynchronize(op->band_ev));
+  DOT_HIP(hipMemcpyAsync(op->pinned_band, op->band_part + nb, sizeof(int64_t),
+                         hipMemcpyDeviceToHost, s));
+  DOT_HIP(hipEventRecord(op->band_ev, s));
+  op->band_pending = true;
+  op->n_band = -1;
+  rc = grow(&op->band_cells, &op->band_cap, std::max<int64_t>(std::min<int64_t>(N, np), 1));
   if (rc) return rc;
   hipLaunchKernelGGL(band_fill_kernel, dim3((unsigned)nb), dim3(256), 0, s, N, op->band_part,
                      op->band_idx, op->band_cells);
@@ -1326,8 +1332,16 @@ int jac_prepare(dot_op* op, hipStream_t s) {
                        op->pair_cell, op->band_idx, op->pair_band);
     DOT_LAUNCH_CHECK();
   }
-  op->n_band = n_band;
   return DOT_OK;
+}
+
+int64_t band_count(dot_op* op) {
+  if (op->band_pending) {
+    if (hipEventSynchronize(op->band_ev) != hipSuccess) return -1;
+    op->n_band = *op->pinned_band;
+    op->band_pending = false;
+  }
+  return op->n_band;
 }
 
 int jac_prepare_faces(dot_op* op, hipStream_t s) {
@@ -1335,7 +1349,7 @@ int jac_prepare_faces(dot_op* op, hipStream_t s) {
   const int R = 1 + 2 * g.dim;
   const int na = n_active_bits(op->pals.active, g.dim);
   const int m0 = op->pals.m0;
-  const int64_t nr = op->n_band * R, nv = op->n_pairs * R;
+  const int64_t nr = band_count(op) * R, nv = op->n_pairs * R;
   // the three row arrays share one capacity
   const int64_t old_cap = op->vrow_cap;
   int rc = grow(&op->vrow_cell, &op->vrow_cap, std::max<int64_t>(nr, 1));
@@ -1353,7 +1367,7 @@ int jac_prepare_faces(dot_op* op, hipStream_t s) {
   const double ratio = 1.0 + (op->mus_in - op->mus_out) / (op->pals.mu_in - op->pals.mu_out);
   if (nr > 0) {
     hipLaunchKernelGGL(vrow_kernel, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s, g, fb,
-                       op->n_band, op->band_cells, op->D0, ratio, R, op->vrow_cell, op->vrow_nbr,
+                       band_count(op), op->band_cells, op->D0, ratio, R, op->vrow_cell, op->vrow_nbr,
                        op->vrow_w);
     DOT_LAUNCH_CHECK();
   }

@@ -16,11 +16,19 @@ __global__ void fill_zero_kernel(double* __restrict__ y, int64_t n) {
 
 // One thread per column; the points of a column are added in order, so
 // repeated cells accumulate deterministically.
-__global__ void scatter_rhs_kernel(int64_t N, int n_pts, const int32_t* __restrict__ cells, int k,
+// One thread per (distinct cell, column): the weights of the points at that
+// cell summed in the points' order (the sum a sequential scatter would
+// form), written into the zeroed block.
+__global__ void scatter_rhs_kernel(int64_t N, int n_pts, int n_u, const int32_t* __restrict__ perm,
+                                   const int32_t* __restrict__ ucell,
+                                   const int32_t* __restrict__ ustart, int k,
                                    const double* __restrict__ w, double* __restrict__ rhs) {
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= k) return;
-  for (int i = 0; i < n_pts; ++i) rhs[cells[i] + N * l] += w[i + (int64_t)n_pts * l];
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n_u * k) return;
+  const int u = (int)(e % n_u), l = (int)(e / n_u);
+  double s = 0.0;
+  for (int i = ustart[u]; i < ustart[u + 1]; ++i) s += w[perm[i] + (int64_t)n_pts * l];
+  rhs[ucell[u] + N * l] = s;
 }
 
 // Rs[j, i] = sum_a V[a, j] (U[det[a], i] - DW[a, i]);  f = 1/2 sum Rs^2.
@@ -124,13 +132,16 @@ int dot_form_rhs(dot_op* op, int n_pts, const int32_t* cells_host, int k,
   hipLaunchKernelGGL(fill_zero_kernel, dim3(blocks), dim3(256), 0, s, rhs_dev, n);
   DOT_LAUNCH_CHECK();
   if (n_pts == 0) return DOT_OK;
-  int rc = ensure_cells_dev(op, n_pts, cells_host, s);
+  const dot_op::CellList* cl = nullptr;
+  int rc = cells_on_device(op, n_pts, cells_host, s, &cl);
   if (rc) return rc;
-  hipLaunchKernelGGL(scatter_rhs_kernel, dim3((k + 63) / 64), dim3(64), 0, s, op->g.N, n_pts,
-                     op->cells_dev, k, weights_dev, rhs_dev);
+  const int32_t* perm = cl->dev + n_pts;
+  const int32_t* ucell = perm + n_pts;
+  const int32_t* ustart = ucell + cl->n_u;
+  const int64_t work = (int64_t)cl->n_u * k;
+  hipLaunchKernelGGL(scatter_rhs_kernel, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, op->g.N,
+                     n_pts, cl->n_u, perm, ucell, ustart, k, weights_dev, rhs_dev);
   DOT_LAUNCH_CHECK();
-  // the staging copy reads cells_host asynchronously: finish before returning
-  DOT_HIP(hipStreamSynchronize(s));
   return DOT_OK;
 }
 
@@ -146,9 +157,10 @@ int dot_sampled_misfit(dot_op* op, int n_d, const int32_t* det_host, int l_s, co
     if (det_host[a] < 0 || det_host[a] >= op->g.N)
       DOT_FAIL(DOT_EINVAL, "detector cell %d outside the grid", det_host[a]);
   hipStream_t s = as_stream(stream);
-  int rc = ensure_cells_dev(op, n_d, det_host, s);
+  const dot_op::CellList* cl = nullptr;
+  int rc = cells_on_device(op, n_d, det_host, s, &cl);
   if (rc) return rc;
-  hipLaunchKernelGGL(misfit_kernel, dim3(1), dim3(256), 0, s, op->g.N, n_d, op->cells_dev, l_s,
+  hipLaunchKernelGGL(misfit_kernel, dim3(1), dim3(256), 0, s, op->g.N, n_d, cl->dev, l_s,
                      U_dev, l_d, V_dev, DW_dev, Rs_dev, op->small_dev);
   DOT_LAUNCH_CHECK();
   DOT_HIP(hipMemcpyAsync(op->pinned_d, op->small_dev, sizeof(double), hipMemcpyDeviceToHost, s));

@@ -79,16 +79,57 @@ static int validate_pals(const dot_pals* p, int dim) {
   return DOT_OK;
 }
 
-int ensure_cells_dev(dot_op* op, int n, const int32_t* cells_host, hipStream_t s) {
-  if (n > op->cells_cap) {
-    if (op->cells_dev) DOT_HIP(hipFree(op->cells_dev));
-    op->cells_dev = nullptr;
-    int64_t cap = std::max<int64_t>(n, 1024);
-    DOT_HIP(hipMalloc(&op->cells_dev, cap * sizeof(int32_t)));
-    op->cells_cap = cap;
+int cells_on_device(dot_op* op, int n, const int32_t* cells_host, hipStream_t s,
+                    const dot_op::CellList** out) {
+  ++op->cell_clock;
+  dot_op::CellList* hit = nullptr;
+  dot_op::CellList* lru = &op->cell_lists[0];
+  for (auto& e : op->cell_lists) {
+    if (e.dev && e.n == n && std::equal(cells_host, cells_host + n, e.key.begin())) hit = &e;
+    if (e.used < lru->used) lru = &e;
   }
-  DOT_HIP(hipMemcpyAsync(op->cells_dev, cells_host, (size_t)n * sizeof(int32_t),
-                         hipMemcpyHostToDevice, s));
+  if (!hit) {
+    // replace the least recently used list; kernels still queued on this
+    // stream may read it
+    hit = lru;
+    DOT_HIP(hipStreamSynchronize(s));
+    std::vector<int32_t> perm(n);
+    for (int i = 0; i < n; ++i) perm[i] = i;
+    std::stable_sort(perm.begin(), perm.end(),
+                     [&](int a, int b) { return cells_host[a] < cells_host[b]; });
+    std::vector<int32_t> ucell, ustart;
+    for (int i = 0; i < n; ++i) {
+      if (i == 0 || cells_host[perm[i]] != cells_host[perm[i - 1]]) {
+        ucell.push_back(cells_host[perm[i]]);
+        ustart.push_back(i);
+      }
+    }
+    ustart.push_back(n);
+    const int n_u = (int)ucell.size();
+    std::vector<int32_t> buf;
+    buf.reserve((size_t)2 * n + 2 * n_u + 1);
+    buf.insert(buf.end(), cells_host, cells_host + n);
+    buf.insert(buf.end(), perm.begin(), perm.end());
+    buf.insert(buf.end(), ucell.begin(), ucell.end());
+    buf.insert(buf.end(), ustart.begin(), ustart.end());
+    if ((int64_t)buf.size() > hit->cap) {
+      if (hit->dev) DOT_HIP(hipFree(hit->dev));
+      hit->dev = nullptr;
+      hit->cap = 0;
+      const int64_t cap = std::max<int64_t>((int64_t)buf.size(), 1024);
+      DOT_HIP(hipMalloc(&hit->dev, (size_t)cap * sizeof(int32_t)));
+      hit->cap = cap;
+    }
+    DOT_HIP(hipMemcpyAsync(hit->dev, buf.data(), buf.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, s));
+    // the copy reads buf asynchronously
+    DOT_HIP(hipStreamSynchronize(s));
+    hit->key.assign(cells_host, cells_host + n);
+    hit->n = n;
+    hit->n_u = n_u;
+  }
+  hit->used = op->cell_clock;
+  *out = hit;
   return DOT_OK;
 }
 
@@ -693,6 +734,10 @@ int dot_build_operator(const dot_grid* grid, const double* D_dev, void* stream, 
     e = hipHostMalloc(&op->pinned_d, 64 * sizeof(double), hipHostMallocDefault);
   for (int i = 0; i < 2; ++i)
     if (e == hipSuccess) e = hipEventCreateWithFlags(&op->poll_ev[i], hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&op->band_ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&op->lists_ev, hipEventDisableTiming);
+  if (e == hipSuccess)
+    e = hipHostMalloc((void**)&op->pinned_band, sizeof(int64_t), hipHostMallocDefault);
   if (e != hipSuccess) {
     set_error("device allocation failed: %s", hipGetErrorString(e));
     dot_destroy_operator(op);
@@ -722,15 +767,21 @@ int dot_destroy_operator(dot_op* op) {
   void* ptrs[] = {op->cx,        op->cy,         op->cz,          op->b0,        op->diag,
                   op->sd,        op->sx,         op->sy,          op->sz,        op->sx32,
                   op->sy32,      op->sz32,       op->phi,         op->theta,     op->pair_cell,
-                  op->rbf_start, op->chunk_rbf,  op->chunk_begin, op->rbf_chunk0, op->cells_dev,  op->small_dev,
+                  op->rbf_start, op->chunk_rbf,  op->chunk_begin, op->rbf_chunk0, op->small_dev,
                   op->pair_g,    op->pair_g32,   op->pair_band,   op->band_idx,   op->band_cells,
                   op->band_part, op->D0,         op->mu0,         op->rbf_sub,
                   op->Dbuild,    op->vrow_cell,  op->vrow_nbr,    op->vrow_w,    op->vpair_band,
                   op->vpair_g,   op->vpair_g32,  op->vchunk_begin, op->vrbf_chunk0};
+  for (auto& e : op->cell_lists)
+    if (e.dev) (void)hipFree(e.dev);
   mg_free(op);
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (op->pinned) (void)hipHostFree(op->pinned);
+  if (op->pinned_band) (void)hipHostFree(op->pinned_band);
+  if (op->stage) (void)hipHostFree(op->stage);
+  if (op->band_ev) (void)hipEventDestroy(op->band_ev);
+  if (op->lists_ev) (void)hipEventDestroy(op->lists_ev);
   if (op->pinned_d) (void)hipHostFree(op->pinned_d);
   for (hipEvent_t ev : op->poll_ev)
     if (ev) (void)hipEventDestroy(ev);
@@ -742,7 +793,9 @@ int64_t dot_operator_cells(const dot_op* op) { return op ? op->g.N : -1; }
 
 int64_t dot_pals_pairs(const dot_op* op) { return (op && op->have_pals) ? op->n_pairs : -1; }
 
-int64_t dot_pals_band_cells(const dot_op* op) { return (op && op->have_pals) ? op->n_band : -1; }
+int64_t dot_pals_band_cells(const dot_op* op) {
+  return (op && op->have_pals) ? band_count(const_cast<dot_op*>(op)) : -1;
+}
 
 int dot_set_mua(dot_op* op, const double* mua_dev, void* stream) {
   clear_error();
@@ -913,23 +966,39 @@ static int pals_state(dot_op* op, const dot_pals* pals, const double* theta_dev,
     op->chunk_cap = cap;
   }
   chunk_begin.push_back(total);
-  DOT_HIP(hipMemcpyAsync(op->rbf_start, start.data(), (size_t)(m0 + 1) * sizeof(int64_t),
-                         hipMemcpyHostToDevice, s));
-  DOT_HIP(hipMemcpyAsync(op->rbf_chunk0, rbf_chunk0.data(), (size_t)(m0 + 1) * sizeof(int32_t),
-                         hipMemcpyHostToDevice, s));
-  if (nch > 0) {
-    DOT_HIP(hipMemcpyAsync(op->chunk_rbf, chunk_rbf.data(), (size_t)nch * sizeof(int32_t),
-                           hipMemcpyHostToDevice, s));
+  // the tables go up through the pinned staging buffer: the copies do not
+  // wait for the host, and the call returns without waiting for them
+  if (op->lists_pending) DOT_HIP(hipEventSynchronize(op->lists_ev));
+  op->lists_pending = false;
+  size_t sz[5] = {(size_t)(m0 + 1) * sizeof(int64_t), (size_t)(m0 + 1) * sizeof(int32_t),
+                  (size_t)nch * sizeof(int32_t), (size_t)(nch + 1) * sizeof(int64_t),
+                  (size_t)nsub * sizeof(int64_t)};
+  const void* src[5] = {start.data(), rbf_chunk0.data(), chunk_rbf.data(), chunk_begin.data(),
+                        sub_start.data()};
+  void* dst[5] = {op->rbf_start, op->rbf_chunk0, op->chunk_rbf, op->chunk_begin, op->rbf_sub};
+  size_t at[5], need = 0;
+  for (int i = 0; i < 5; ++i) {
+    at[i] = need;
+    need += (sz[i] + 255) & ~(size_t)255;
   }
-  DOT_HIP(hipMemcpyAsync(op->chunk_begin, chunk_begin.data(), (size_t)(nch + 1) * sizeof(int64_t),
-                         hipMemcpyHostToDevice, s));
-  DOT_HIP(hipMemcpyAsync(op->rbf_sub, sub_start.data(), (size_t)nsub * sizeof(int64_t),
-                         hipMemcpyHostToDevice, s));
+  if (need > op->stage_cap) {
+    if (op->stage) DOT_HIP(hipHostFree(op->stage));
+    op->stage = nullptr;
+    op->stage_cap = 0;
+    const size_t cap = std::max<size_t>(need + need / 4, (size_t)1 << 16);
+    DOT_HIP(hipHostMalloc((void**)&op->stage, cap, hipHostMallocDefault));
+    op->stage_cap = cap;
+  }
+  for (int i = 0; i < 5; ++i) {
+    if (sz[i] == 0) continue;
+    std::memcpy(op->stage + at[i], src[i], sz[i]);
+    DOT_HIP(hipMemcpyAsync(dst[i], op->stage + at[i], sz[i], hipMemcpyHostToDevice, s));
+  }
+  DOT_HIP(hipEventRecord(op->lists_ev, s));
+  op->lists_pending = true;
   hipLaunchKernelGGL(rbf_cells_kernel<true>, dim3((unsigned)nsub), dim3(256), 0, s, g, p, op->theta,
                      op->phi, nullptr, op->rbf_sub, op->pair_cell);
   DOT_LAUNCH_CHECK();
-  // the host vectors above are read by the asynchronous copies: wait for them
-  DOT_HIP(hipStreamSynchronize(s));
   op->n_pairs = total;
   op->n_chunks = nch;
   op->pals = *pals;

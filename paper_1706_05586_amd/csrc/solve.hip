@@ -443,7 +443,7 @@ struct EltArgs {
   const double* scale;  // per column scale
   const double* b;      // INIT: rhs
   double* xh;           // x^ (binary64)
-  double* r64;          // binary64 residual
+  double* r64;          // INIT: binary64 residual b^ (or NULL: not kept)
   float* r32;           // inner residual
   float* d32;           // inner correction
   double* p64z;         // INIT: binary64 direction buffer to clear (or NULL)
@@ -492,14 +492,16 @@ __global__ __launch_bounds__(NT) void elt_kernel(EltArgs a) {
           const double bv = a.b[o];
           const double rv = bv / a.sd[c];
           a.xh[o] = 0.0;
-          a.r64[w] = rv;
+          if (a.r64) a.r64[w] = rv;
           if (a.d32) a.d32[w] = 0.0f;
           if (a.p64z) a.p64z[w] = 0.0;
           if (a.p32z) a.p32z[w] = 0.0f;
           acc[r][0] += rv * rv;
           acc[r][1] += bv * bv;
         } else if constexpr (MODE == E_REPLACE) {
-          const float rv = (float)(a.r64[w] / sc[r]);
+          // the first binary32 residual (b^ / scale, x = 0), formed from b
+          // as E_INIT forms b^
+          const float rv = (float)((a.b[o] / a.sd[c]) / sc[r]);
           a.r32[w] = rv;
           const double rd = (double)rv;
           acc[r][0] += rd * rd;
@@ -778,7 +780,6 @@ static size_t layout_workspace(const dot_op* op, const Geom& G, int precision, c
       if (base) mg_work_layout<double>(op, G.k, G.ldw, m, &ws.mg64);
     }
   } else {
-    ws.r64 = (double*)take(Nk * 8);
     ws.r32 = (float*)take(Nk * 4);
     ws.p32[0] = (float*)take(Nk * 4);
     ws.p32[1] = (float*)take(Nk * 4);
@@ -1104,7 +1105,6 @@ static int solve_mixed(dot_op* op, const Geom& G, const Workspace& ws, const dou
   e.sd = op->sd;
   e.b = rhs;
   e.xh = x;
-  e.r64 = ws.r64;
   e.r32 = ws.r32;
   e.d32 = ws.d32;
   e.scale = ws.st.scale;

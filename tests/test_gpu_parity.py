@@ -117,6 +117,24 @@ def test_form_rhs_exact(dotlib, dev, name):
         w = np.array([[1.0, 2.0], [0.5, -1.0], [4.0, 0.0]])
         R = op.form_rhs(cells, torch.tensor(w, device=dev)).cpu().numpy()
         assert R[3, 0] == 1.5 and R[3, 1] == 1.0 and R[5, 0] == 4.0 and np.count_nonzero(R) == 3
+        # in the order given: 1 is lost to 1e16 before -1e16 cancels it
+        cells = np.array([7, 2, 7, 7], dtype=np.int32)
+        w = np.array([[1e16], [2.0], [1.0], [-1e16]])
+        R = op.form_rhs(cells, torch.tensor(w, device=dev)).cpu().numpy()
+        assert R[7, 0] == 0.0 and R[2, 0] == 2.0 and np.count_nonzero(R) == 1
+        # lists seen before, new ones and ones pushed out of the handle's
+        # device copies all give the sequential sum
+        rng = np.random.default_rng(3)
+        lists = [rng.integers(0, op.N, size=n).astype(np.int32) for n in (5, 9, 5, 12, 7, 3)]
+        lists.append(lists[0][[0, 0, 1, 2, 0]])
+        for _ in range(2):
+            for c in lists + lists[:2]:
+                w = rng.standard_normal((len(c), 3))
+                R = op.form_rhs(c, torch.tensor(w, device=dev)).cpu().numpy()
+                E = np.zeros((op.N, 3))
+                for i, cell in enumerate(c):
+                    E[cell] += w[i]
+                assert np.array_equal(R, E)
 
 
 @pytest.mark.parametrize("precond", ["auto", "jacobi"])
