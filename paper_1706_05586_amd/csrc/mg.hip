@@ -25,13 +25,16 @@
 // little, take more of them.  The last step on level 0 also forms r . z per
 // column.
 //
-// Kernel layout: a block is a 32 x 8 (x, y) tile (each wave two rows of 32,
-// so the 2 x 2 aggregates of a plane are pairs of lanes l, l ^ 1 and l, l ^ 32)
-// marching through an even chunk of z planes with the z neighbours in
-// registers and the x/y neighbours from a double-buffered LDS plane; a block
-// handles MRG columns so coefficients are read once per group.  Results are
-// deterministic: the coarse sums are formed in a fixed order and the dot
-// products reduce through wave shuffles and per-block partial slots.
+// Kernel layout: a block is a 64 x 4 (x, y) tile, one wave per row of 64
+// cells (a bfloat16 row is one full 128-byte line), marching through an even
+// chunk of z planes with the z neighbours in registers and the x/y
+// neighbours from a double-buffered LDS plane; a block handles MRG columns
+// so coefficients are read once per group.  A 2 x 2 aggregate of a plane is
+// lanes l, l ^ 1 of two waves: the x pair is a wave shuffle, the z pair is
+// summed in registers, and the odd row hands its sum to the even row through
+// LDS at the next barrier.  Results are deterministic: the coarse sums are
+// formed in a fixed order and the dot products reduce through wave shuffles
+// and per-block partial slots.
 #include <algorithm>
 #include <type_traits>
 
@@ -39,8 +42,8 @@
 
 namespace dot {
 
-constexpr int MTX = 32;                 // tile width: half a wave
-constexpr int MTY = 8;                  // tile rows: two per wave
+constexpr int MTX = 64;                 // tile width: one wave
+constexpr int MTY = 4;                  // tile rows: one per wave
 constexpr int MNT = MTX * MTY;          // 256 threads
 constexpr int MNH = 2 * MTX + 2 * MTY;  // halo cells of a tile
 static_assert(MNT >= MNH, "every halo cell needs a thread");
@@ -157,12 +160,14 @@ __global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T, TB, TS, TO> a) 
   const int slot = tile + G.ntiles * zci;
   const int x0 = (tile % G.tiles_x) * MTX, y0 = (tile / G.tiles_x) * MTY;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int tx = lane & 31, ty = 2 * wave + (lane >> 5);
+  const int tx = lane, ty = wave;
   const int x = x0 + tx, y = y0 + ty;
   const bool in = x < G.nx && y < G.ny;
   const int z0 = zci * G.zc, z1 = min(G.nz, z0 + G.zc);
   const T w = (T)MG_OMEGA;
   __shared__ T sm[2][MRG][MTY + 2][MTX + 2];
+  // restriction: the odd rows' sums over a completed aggregate (even lanes)
+  __shared__ T xr[MODE == MG_DOWN ? MRG : 1][MTY / 2][MTX / 2];
 
   bool act[MRG];
   int64_t col[MRG];
@@ -267,6 +272,24 @@ __global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T, TB, TS, TO> a) 
     zacc[r] = T(0);
     acc[r] = 0.0;
   }
+  // restriction: an aggregate completed on the previous plane (its coarse
+  // plane and sqrt(diag)) is written by the even row once the barrier has
+  // made the odd row's sum visible
+  bool pend = false;
+  int pzc = 0;
+  T psdc = T(1);
+  auto write_coarse = [&]() {
+    if constexpr (MODE == MG_DOWN) {
+      if ((ty & 1) == 0 && in && (lane & 1) == 0) {
+        const int64_t C = (x >> 1) + (int64_t)G.cnx * (y >> 1) + G.cnxy * pzc;
+#pragma unroll
+        for (int r = 0; r < MRG; ++r) {
+          if (!act[r]) continue;
+          mg_stv(a.bc, C + a.cld * col[r], (zacc[r] + xr[r][ty >> 1][lane >> 1]) / psdc);
+        }
+      }
+    }
+  };
 
   for (int z = z0; z < z1; ++z) {
     const int buf = (z - z0) & 1;
@@ -296,6 +319,10 @@ __global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T, TB, TS, TO> a) 
       sdc_next = mg_ld(a.sdc, in ? (x >> 1) + (int64_t)G.cnx * (y >> 1) + G.cnxy * (z >> 1) : 0);
     load_raw(hbase + zu * G.nxy, phbase + (zu >> 1) * G.cnxy, hr, new_parent);
     __syncthreads();
+    if constexpr (MODE == MG_DOWN) {
+      if (pend) write_coarse();  // block-uniform
+      pend = false;
+    }
     const T cW = has_w ? cWl : T(0);
     const T cS = has_s ? cSl : T(0);
     T vp[MRG];
@@ -310,20 +337,16 @@ __global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T, TB, TS, TO> a) 
       const T bv = bcur[r];
       if constexpr (MODE == MG_DOWN) {
         // restriction: S_l (b - A^ x) summed over the aggregate (cells
-        // outside the grid contribute zero)
+        // outside the grid contribute zero): the x pair here, the z pair
+        // in registers, the y pair at the coarse write
         const T e = in ? sdv * (bv - Av) : T(0);
-        T s2 = e + __shfl_xor(e, 1, 64);
-        s2 += __shfl_xor(s2, 32, 64);
-        // the aggregate is complete after its odd plane, or after an even
-        // plane that is the last of an odd n_z (also the one plane in 2D)
+        const T s2 = e + __shfl_xor(e, 1, 64);
         if ((z & 1) == 0) zacc[r] = s2;
         else zacc[r] += s2;
-        if ((z & 1) == 1 || z + 1 == G.nz) {
-          if (in && (lane & 33) == 0) {
-            const int64_t C = (x >> 1) + (int64_t)G.cnx * (y >> 1) + G.cnxy * (z >> 1);
-            mg_stv(a.bc, C + a.cld * col[r], zacc[r] / sdc_next);
-          }
-        }
+        // the aggregate is complete after its odd plane, or after an even
+        // plane that is the last of an odd n_z (also the one plane in 2D)
+        if (((z & 1) == 1 || z + 1 == G.nz) && (ty & 1) == 1 && (lane & 1) == 0)
+          xr[r][ty >> 1][lane >> 1] = zacc[r];
       } else {
         const T zv = vc[r] + w * (bv - Av);
         if (in) {
@@ -332,12 +355,25 @@ __global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T, TB, TS, TO> a) 
         }
       }
     }
+    if constexpr (MODE == MG_DOWN) {
+      if ((z & 1) == 1 || z + 1 == G.nz) {
+        pend = true;
+        pzc = z >> 1;
+        psdc = sdc_next;
+      }
+    }
     cD = cU;
 #pragma unroll
     for (int r = 0; r < MRG; ++r) {
       vm[r] = vc[r];
       vc[r] = vp[r];
       bcur[r] = pr.v[r];
+    }
+  }
+  if constexpr (MODE == MG_DOWN) {
+    if (pend) {  // the chunk's last aggregate
+      __syncthreads();
+      write_coarse();
     }
   }
   if constexpr (MODE == MG_SMOOTH) {
