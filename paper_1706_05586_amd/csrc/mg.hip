@@ -223,16 +223,16 @@ __global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T, TB, TS, TO> a) 
     T xc[MRG];
     T q;
   };
-  // with_xc false: the plane has the parent plane of the previous one, whose
-  // coarse values o.xc still holds (block-uniform)
-  auto load_raw = [&](int64_t c, int64_t p, Raw& o, bool with_xc) {
+  // Every load is unconditional: the odd plane reloads its aggregate's
+  // parent (a cache hit) rather than keep the even plane's, because a load
+  // issued on one path only makes the compiler wait for every load in
+  // flight (the counter retires in order) where the paths join.
+  auto load_raw = [&](int64_t c, int64_t p, Raw& o) {
 #pragma unroll
     for (int r = 0; r < MRG; ++r) {
       o.v[r] = mg_ldv<T>(a.b, c + a.ld * col[r]);
       if constexpr (HX) o.x[r] = mg_ldv<T>(a.x, c + a.ld * col[r]);
-      if constexpr (HC) {
-        if (with_xc) o.xc[r] = mg_ldv<T>(a.xc, p + a.cld * col[r]);
-      }
+      if constexpr (HC) o.xc[r] = mg_ldv<T>(a.xc, p + a.cld * col[r]);
     }
     if constexpr (HC) o.q = mg_ld(a.q, c);
   };
@@ -252,8 +252,8 @@ __global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T, TB, TS, TO> a) 
   {
     Raw om;
     const int zm = z0 > 0 ? z0 - 1 : z0;
-    load_raw(base + zm * G.nxy, pbase + (zm >> 1) * G.cnxy, om, true);
-    load_raw(base + z0 * G.nxy, pbase + (z0 >> 1) * G.cnxy, pr, true);
+    load_raw(base + zm * G.nxy, pbase + (zm >> 1) * G.cnxy, om);
+    load_raw(base + z0 * G.nxy, pbase + (z0 >> 1) * G.cnxy, pr);
 #pragma unroll
     for (int r = 0; r < MRG; ++r) {
       vm[r] = (z0 > 0 && in) ? staged(om, r) : T(0);
@@ -262,7 +262,7 @@ __global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T, TB, TS, TO> a) 
     }
   }
   Raw hr;  // halo cell, plane z
-  load_raw(hbase + z0 * G.nxy, phbase + (z0 >> 1) * G.cnxy, hr, true);
+  load_raw(hbase + z0 * G.nxy, phbase + (z0 >> 1) * G.cnxy, hr);
   T cD = z0 > 0 ? mg_ld(a.sz, base + (z0 - 1) * G.nxy) : T(0);
   T sdc_next = T(1);
   T zacc[MRG];
@@ -304,8 +304,7 @@ __global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T, TB, TS, TO> a) 
     }
     // loads for after the barrier: own cell of plane z + 1, this plane's
     // right-hand side and coefficients; then the halo of plane z + 1
-    const bool new_parent = (zu >> 1) != (z >> 1);
-    load_raw(base + zu * G.nxy, pbase + (zu >> 1) * G.cnxy, pr, new_parent);
+    load_raw(base + zu * G.nxy, pbase + (zu >> 1) * G.cnxy, pr);
     const bool has_w = in && x > 0, has_s = in && y > 0;
     const T cE = mg_ld(a.sx, c);
     const T cWl = mg_ld(a.sx, has_w ? c - 1 : c);
@@ -317,7 +316,7 @@ __global__ __launch_bounds__(MNT) void mg_level_kernel(MgArgs<T, TB, TS, TO> a) 
     // odd plane's write
     if (MODE == MG_DOWN && (z & 1) == 0)
       sdc_next = mg_ld(a.sdc, in ? (x >> 1) + (int64_t)G.cnx * (y >> 1) + G.cnxy * (z >> 1) : 0);
-    load_raw(hbase + zu * G.nxy, phbase + (zu >> 1) * G.cnxy, hr, new_parent);
+    load_raw(hbase + zu * G.nxy, phbase + (zu >> 1) * G.cnxy, hr);
     __syncthreads();
     if constexpr (MODE == MG_DOWN) {
       if (pend) write_coarse();  // block-uniform
