@@ -407,6 +407,13 @@ int dot_grad_misfit_noalloc(dot_op* op, int l_s, const double* U_dev, int l_d,
 #define DOT_PROF_VCYCLE_FP32 7 /* multigrid V-cycle (all levels), binary32 */
 #define DOT_PROF_KINDS 8
 int dot_profile_enable(dot_op* op, int enable);
+/* Time only the kinds whose bit (1u << DOT_PROF_*) is set in mask (after
+ * dot_profile_enable, which selects every kind).  Each timed launch is
+ * bracketed by two event records, which keep the next kernel from starting
+ * early (about 5 us per boundary on MI355X), so a caller timing a whole
+ * workload selects only the kinds it reports.  DOT_EINVAL before the first
+ * dot_profile_enable. */
+int dot_profile_kinds(dot_op* op, unsigned mask);
 int dot_profile_read(dot_op* op, int kind, double* ms_total, int64_t* launches,
                      int64_t* column_sweeps);
 

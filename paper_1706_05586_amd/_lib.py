@@ -121,6 +121,7 @@ SIGNATURES = {
     "dot_tsvd_step_workspace_bytes": (_sz, [_i]),
     "dot_tsvd_step": (_i, [_i, _i, _i, _vp, _i, _vp, _vp, _i, _i, _vp, _vp, _vp, _sz, _vp]),
     "dot_profile_enable": (_i, [_vp, _i]),
+    "dot_profile_kinds": (_i, [_vp, C.c_uint]),
     "dot_profile_read": (_i, [_vp, _i, C.POINTER(C.c_double), C.POINTER(_i64),
                               C.POINTER(_i64)]),
 }

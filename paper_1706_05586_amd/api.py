@@ -502,6 +502,13 @@ class Operator:
     def profile_enable(self, on: bool = True):
         check(lib.dot_profile_enable(self._handle, int(on)), "dot_profile_enable")
 
+    def profile_kinds(self, *kinds: int):
+        """Time only these DOT_PROF_* kinds (profile_enable selects all)."""
+        mask = 0
+        for k in kinds:
+            mask |= 1 << int(k)
+        check(lib.dot_profile_kinds(self._handle, mask), "dot_profile_kinds")
+
     def profile_read(self, kind: int):
         """(summed event ms, launches, sum over launches of active columns)."""
         ms, n, cols = C.c_double(), C.c_int64(), C.c_int64()

@@ -825,6 +825,7 @@ static size_t layout_workspace(const dot_op* op, const Geom& G, int precision, c
 constexpr int kProfSlots = 2048;
 struct ProfState {
   bool on = false;
+  unsigned mask = ~0u;  // kinds timed (bit 1 << kind)
   std::vector<hipEvent_t> pool;
   struct Pending {
     int kind;
@@ -870,7 +871,7 @@ static int prof_begin(dot_op* op, int kind, hipStream_t s, hipEvent_t* e0, hipEv
   *e0 = *e1 = nullptr;
   *cols = nullptr;
   ProfState* p = prof_of(op);
-  if (!p || !p->on || kind < 0) return DOT_OK;
+  if (!p || !p->on || kind < 0 || !((p->mask >> kind) & 1u)) return DOT_OK;
   if (p->pending.size() >= (size_t)kProfSlots) DOT_TRY(prof_drain(op));
   for (hipEvent_t* e : {e0, e1}) {
     if (p->pool.empty()) {
@@ -1401,11 +1402,21 @@ int dot_profile_enable(dot_op* op, int enable) {
   }
   DOT_TRY(prof_drain(op));
   p->on = enable != 0;
+  p->mask = ~0u;
   for (int i = 0; i < DOT_PROF_KINDS; ++i) {
     p->ms[i] = 0.0;
     p->launches[i] = 0;
     p->cols[i] = 0;
   }
+  return DOT_OK;
+}
+
+int dot_profile_kinds(dot_op* op, unsigned mask) {
+  clear_error();
+  if (!op) DOT_FAIL(DOT_EINVAL, "op is NULL");
+  ProfState* p = prof_of(op);
+  if (!p) DOT_FAIL(DOT_EINVAL, "profiling was never enabled on this handle");
+  p->mask = mask;
   return DOT_OK;
 }
 

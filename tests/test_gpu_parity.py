@@ -534,3 +534,34 @@ def test_mixed_vcycle_storage_bf16_vs_binary32(dotlib, dev, name):
           f"binary32 {out[dotlib.DOT_PRECOND_MG_F32]}", flush=True)
     it_h, it_s = out[dotlib.DOT_PRECOND_MG], out[dotlib.DOT_PRECOND_MG_F32]
     assert it_h.max() <= it_s.max() + 1 and it_h.mean() <= it_s.mean() + 1
+
+
+def test_profile_kinds_select_timed_launches(dotlib, dev):
+    """dot_profile_kinds: only the selected kinds are timed, profile_enable
+    selects every kind again, and the solve itself is unchanged."""
+    wl, prob, W, V, data, ref = case("t3d_b")
+    op, grid, pals, th = gpu_operator(dotlib, dev, wl)
+    rhs = torch.tensor(np.hstack([ref["BW"], ref["CV"]]), device=dev)
+    with op:
+        with pytest.raises(dotlib.DotError):
+            op.profile_kinds(dotlib.DOT_PROF_PCG2_FP32)
+        op.pals_mua(pals, th)
+        assert op.multigrid_levels >= 2
+
+        def solve():
+            return op.solve(rhs, rtol=1e-10, precision=dotlib.DOT_MIXED, inner_rtol=0.01)
+
+        op.profile_enable(True)
+        op.profile_kinds(dotlib.DOT_PROF_PCG2_FP32)
+        r1 = solve()
+        ms2, n2, c2 = op.profile_read(dotlib.DOT_PROF_PCG2_FP32)
+        assert n2 >= r1.iters_max and ms2 > 0.0 and c2 >= n2
+        for kind in (dotlib.DOT_PROF_PCG1_FP32, dotlib.DOT_PROF_VCYCLE_FP32, dotlib.DOT_PROF_RESID):
+            assert op.profile_read(kind) == (0.0, 0, 0)
+        op.profile_enable(True)
+        r2 = solve()
+        for kind in (dotlib.DOT_PROF_PCG1_FP32, dotlib.DOT_PROF_PCG2_FP32,
+                     dotlib.DOT_PROF_VCYCLE_FP32, dotlib.DOT_PROF_RESID):
+            assert op.profile_read(kind)[1] > 0
+        op.profile_enable(False)
+    assert torch.equal(r1.x, r2.x)
