@@ -554,10 +554,13 @@ KAPPA_100MHZ_PER_MM = 2.0 * np.pi * 100e6 / (3.0e11 / 1.4)
 
 def frequency_leg(dl, L, torch, dev, op, cfg, wl, W, V, reps=3):
     """The step's 40 right-hand sides solved at 100 MHz modulation:
-    (A + i kappa h^d I) X = [B W, C V] by COCG with the multigrid V-cycle
-    (binary64, relres 1e-8).  Algorithmic bytes per cell, complex column and
-    iteration: apply 32 (read p, write q), update 96 (read p, q, x, r; write
-    x, r), r^T z 32, direction 48, plus the binary64 V-cycle on both parts."""
+    (A + i kappa h^d I) X = [B W, C V] by binary64 COCG with the multigrid
+    V-cycle on both parts (relres 1e-8), the V-cycle in binary64 or in
+    binary32 with bfloat16 vectors.  Algorithmic bytes per cell, complex
+    column and iteration: apply 32 (read p, write q), update 96 (read p, q,
+    x, r; write x, r), r^T z 32, direction 48, plus the V-cycle on both
+    parts; with the binary32 V-cycle the update also writes r / ||b|| in
+    binary32 (+8) and r^T z and the direction read z in binary32 (-8 each)."""
     ls, ld = cfg.l_s, cfg.l_d
     k = ls + ld
     N = op.N
@@ -565,22 +568,29 @@ def frequency_leg(dl, L, torch, dev, op, cfg, wl, W, V, reps=3):
     rhs[:, :ls] = op.form_rhs(wl.src_cells, W)
     rhs[:, ls:] = op.form_rhs(wl.det_cells, V)
     kappa = KAPPA_100MHZ_PER_MM
-    res = op.solve_complex(rhs, kappa, rtol=1e-8)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        res = op.solve_complex(rhs, kappa, rtol=1e-8)
-    torch.cuda.synchronize()
-    t = (time.perf_counter() - t0) / reps
-    it = int(res.iters_max)
-    per = 32 + 96 + 32 + 48 + 2 * op.multigrid_cycle_bytes(L.DOT_FP64) / N
-    gbs = per * N * k * it / t / 1e9
-    return {"kappa": kappa, "columns_complex": k, "ms_per_solve": round(t * 1e3, 2),
-            "rhs_per_s": round(k / t, 2), "iters": it, "relres_max": float(res.relres.max()),
-            "bytes_per_cell_column_iteration": round(per, 1),
-            "achieved_gbs_algorithmic": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-            "preconditioner": f"multigrid V-cycle on real and imaginary parts, "
-                              f"{op.multigrid_levels} levels"}
+    out = {"kappa": kappa, "columns_complex": k,
+           "preconditioner": f"multigrid V-cycle on real and imaginary parts, "
+                             f"{op.multigrid_levels} levels"}
+    for name, prec, per in (
+            ("fp64_vcycle", L.DOT_FP64,
+             32 + 96 + 32 + 48 + 2 * op.multigrid_cycle_bytes(L.DOT_FP64) / N),
+            ("mixed_vcycle", L.DOT_MIXED,
+             32 + 104 + 24 + 40 + 2 * op.multigrid_cycle_bytes(L.DOT_MIXED) / N)):
+        res = op.solve_complex(rhs, kappa, rtol=1e-8, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            res = op.solve_complex(rhs, kappa, rtol=1e-8, precision=prec)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / reps
+        it = int(res.iters_max)
+        gbs = per * N * k * it / t / 1e9
+        out[name] = {"ms_per_solve": round(t * 1e3, 2), "rhs_per_s": round(k / t, 2),
+                     "iters": it, "relres_max": float(res.relres.max()),
+                     "bytes_per_cell_column_iteration": round(per, 1),
+                     "achieved_gbs_algorithmic": round(gbs, 1),
+                     "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
 
 
 def diffusion_leg(dl, L, torch, dev, op, cfg, wl, pals, W, V):

@@ -271,8 +271,12 @@ int dot_solve_multi_rhs(dot_op* op, int trans, int k, const double* rhs_dev, dou
  * the Jacobi scaling alone), per column until ||b - A_w x||_2 <= rtol
  * ||b||_2 (conjugated norms).  Complex N x k blocks are N x 2k binary64
  * arrays: real parts in columns 0 .. k-1, imaginary parts in k .. 2k-1.
- * opts: rtol, max_iter, check_every and precond as for dot_solve_multi_rhs,
- * precision must be DOT_FP64.  info.relres_host (k values) receives the true
+ * opts: rtol, max_iter, check_every and precond as for dot_solve_multi_rhs.
+ * opts.precision: DOT_FP64, or DOT_MIXED, which runs the V-cycle in
+ * binary32 (binary32 work vectors) on a binary32 copy of r / ||b||; COCG
+ * itself and the convergence test stay binary64 either way, and with Jacobi
+ * preconditioning the two are the same.
+ * The workspace size covers both.  info.relres_host (k values) receives the true
  * relative residual recomputed in binary64; DOT_NOT_CONVERGED when one
  * exceeds 1.01 rtol.  kappa = 0 solves the real system.  k <= 2048.
  * Synchronizes the stream.

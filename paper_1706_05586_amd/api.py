@@ -466,9 +466,11 @@ class Operator:
 
     def solve_complex(self, rhs: torch.Tensor, kappa: float, rtol: float = 1e-10,
                       max_iter: int = 20000, check_every: int = 8,
-                      precond: int = L.DOT_PRECOND_AUTO, warn: bool = True) -> SolveResult:
+                      precond: int = L.DOT_PRECOND_AUTO, warn: bool = True,
+                      precision: int = L.DOT_FP64) -> SolveResult:
         """(A + i kappa h^d I) X = rhs for a complex128 (N, k) block (COCG).
-        The result's x is complex128 (N, k)."""
+        precision DOT_MIXED runs the V-cycle preconditioner in binary32 (COCG
+        stays binary64).  The result's x is complex128 (N, k)."""
         if not isinstance(rhs, torch.Tensor) or rhs.dtype != torch.complex128 or not rhs.is_cuda:
             raise TypeError("rhs must be a complex128 CUDA tensor")
         R2 = rhs.reshape(-1, 1) if rhs.dim() == 1 else rhs
@@ -482,7 +484,7 @@ class Operator:
         X = empty_colmajor(self.N, 2 * k, self.device)
         nbytes = int(lib.dot_solve_complex_workspace_bytes(self._handle, k, precond))
         work = _workspace(nbytes, self.device)
-        opts = L.DotSolveOpts(rtol, max_iter, L.DOT_FP64, 0.1, check_every, precond)
+        opts = L.DotSolveOpts(rtol, max_iter, precision, 0.1, check_every, precond)
         iters = np.zeros(k, dtype=np.int32)
         rel = np.zeros(k, dtype=np.float64)
         info = L.DotSolveInfo(0, 0, iters.ctypes.data_as(C.POINTER(C.c_int32)),

@@ -21,7 +21,14 @@
 //   dir    : p = z + beta p, beta = rho / rho_old
 // Per-column scalars (complex alpha, beta, rho) live on the device and are
 // formed by one block per column from the per-block partials in fixed order
-// (deterministic).  An N x k complex block is stored as an N x 2k real block:
+// (deterministic).  With DOT_MIXED the V-cycle runs in binary32 (binary32
+// work vectors: with bfloat16 ones, as in the real mixed solve, COCG lost
+// its short-recurrence orthogonality and stalled) on a binary32 copy of
+// r^ / ||b|| (per column) that the update pass writes beside r^; z comes
+// back in binary32 and is scaled by ||b|| where the r^T z and direction
+// passes read it.  Every recurrence and the convergence test stay binary64:
+// the preconditioner only steers the iteration.
+// An N x k complex block is stored as an N x 2k real block:
 // the real parts in columns 0 .. k-1, the imaginary parts in columns
 // k .. 2k-1 (so either half is an ordinary real field block).
 #include <algorithm>
@@ -60,7 +67,15 @@ struct CzArgs {
   double* partial;       // [4][k][nblk]
   int jacobi;            // update also forms rho = r^T r
   int first;             // dir: the first direction p = z
+  float* r32;            // update: also r^ / ||b|| in binary32 (or NULL)
+  const float* z32;      // rz, dir: z in binary32, times ||b|| (or NULL: in1 / in0)
+  const double* bnorm;   // ||b|| per complex column (with r32 / z32)
 };
+
+__device__ __forceinline__ double cz_bscale(const CzArgs& a, int j) {
+  const double b = a.bnorm[j];
+  return b > 0.0 ? b : 1.0;
+}
 
 __device__ __forceinline__ double cz_wave_sum(double v) {
 #pragma unroll
@@ -162,6 +177,11 @@ __global__ __launch_bounds__(CZ_T) void cz_update_kernel(CzArgs a) {
     a.out0[oi] = xi;
     a.out1[o] = rr;
     a.out1[oi] = ri;
+    if (a.r32) {  // block-uniform
+      const double inv = 1.0 / cz_bscale(a, j);
+      a.r32[o] = (float)(rr * inv);
+      a.r32[oi] = (float)(ri * inv);
+    }
     acc[r][0] = s * s * (rr * rr + ri * ri);
     if (a.jacobi) {
       acc[r][1] = rr * rr - ri * ri;
@@ -185,7 +205,15 @@ __global__ __launch_bounds__(CZ_T) void cz_rz_kernel(CzArgs a) {
     const int64_t o = (int64_t)j * a.ld + c;
     const int64_t oi = o + (int64_t)a.k * a.ld;
     const double rr = a.in0[o], ri = a.in0[oi];
-    const double zr = a.in1[o], zi = a.in1[oi];
+    double zr, zi;
+    if (a.z32) {  // block-uniform
+      const double bs = cz_bscale(a, j);
+      zr = bs * (double)a.z32[o];
+      zi = bs * (double)a.z32[oi];
+    } else {
+      zr = a.in1[o];
+      zi = a.in1[oi];
+    }
     acc[r][0] = rr * zr - ri * zi;
     acc[r][1] = rr * zi + ri * zr;
   }
@@ -203,15 +231,41 @@ __global__ __launch_bounds__(CZ_T) void cz_dir_kernel(CzArgs a) {
     if (j >= a.k || !a.active[j]) continue;
     const int64_t o = (int64_t)j * a.ld + c;
     const int64_t oi = o + (int64_t)a.k * a.ld;
+    double zr, zi;
+    if (a.z32) {  // block-uniform
+      const double bs = cz_bscale(a, j);
+      zr = bs * (double)a.z32[o];
+      zi = bs * (double)a.z32[oi];
+    } else {
+      zr = a.in0[o];
+      zi = a.in0[oi];
+    }
     if (a.first) {
-      a.out0[o] = a.in0[o];
-      a.out0[oi] = a.in0[oi];
+      a.out0[o] = zr;
+      a.out0[oi] = zi;
       continue;
     }
     const double br = a.coef[2 * j], bi = a.coef[2 * j + 1];
     const double pr = a.out0[o], pi = a.out0[oi];
-    a.out0[o] = a.in0[o] + (br * pr - bi * pi);
-    a.out0[oi] = a.in0[oi] + (br * pi + bi * pr);
+    a.out0[o] = zr + (br * pr - bi * pi);
+    a.out0[oi] = zi + (br * pi + bi * pr);
+  }
+}
+
+// r32 = r^ / ||b|| for the first V-cycle (the update pass writes it after
+// that); in0 = r^.
+__global__ __launch_bounds__(CZ_T) void cz_r32_kernel(CzArgs a) {
+  const int64_t c = blockIdx.x * (int64_t)CZ_T + threadIdx.x;
+  if (c >= a.g.N) return;
+#pragma unroll
+  for (int r = 0; r < CZ_RG; ++r) {
+    const int j = blockIdx.y * CZ_RG + r;
+    if (j >= a.k || !a.active[j]) continue;
+    const double inv = 1.0 / cz_bscale(a, j);
+    const int64_t o = (int64_t)j * a.ld + c;
+    const int64_t oi = o + (int64_t)a.k * a.ld;
+    a.r32[o] = (float)(a.in0[o] * inv);
+    a.r32[oi] = (float)(a.in0[oi] * inv);
   }
 }
 
@@ -426,11 +480,15 @@ struct CzWork {
   double* mgpart;
   MgWork<double> mg;
   bool use_mg;
+  bool mixed;        // binary32 V-cycle: r32 / z32 and mg32 instead of z and mg
+  float *r32, *z32;
+  MgWork<float> mg32;
 };
 
 static size_t al256z(size_t v) { return (v + 255) & ~(size_t)255; }
 
-static size_t cz_layout(const dot_op* op, int k, bool use_mg, char* base, CzWork* w) {
+static size_t cz_layout(const dot_op* op, int k, bool use_mg, bool mixed, char* base, CzWork* w) {
+  mixed = mixed && use_mg;
   const int64_t N = op->g.N;
   const int64_t ld = N + CZ_PAD;
   const int nblk = (int)((N + CZ_T - 1) / CZ_T);
@@ -445,7 +503,9 @@ static size_t cz_layout(const dot_op* op, int k, bool use_mg, char* base, CzWork
   double* r = (double*)take(vec);
   double* p = (double*)take(vec);
   double* q = (double*)take(vec);
-  double* z = use_mg ? (double*)take(vec) : nullptr;
+  double* z = (use_mg && !mixed) ? (double*)take(vec) : nullptr;
+  float* r32 = mixed ? (float*)take(vec / 2) : nullptr;
+  float* z32 = mixed ? (float*)take(vec / 2) : nullptr;
   double* partial = (double*)take((size_t)4 * k * nblk * sizeof(double));
   double* sc = (double*)take((size_t)8 * k * sizeof(double));
   int* iv = (int*)take((size_t)(6 * k + 8) * sizeof(int));
@@ -453,7 +513,8 @@ static size_t cz_layout(const dot_op* op, int k, bool use_mg, char* base, CzWork
   char* mgbase = nullptr;
   if (use_mg) {
     mgpart = (double*)take((size_t)2 * (2 * k) * mg_partial_slots(op, 2 * k) * sizeof(double));
-    mgbase = take(mg_work_bytes(op, 2 * k, ld, sizeof(double)));
+    mgbase = take(mixed ? mg_work_bytes(op, 2 * k, ld, sizeof(float))
+                        : mg_work_bytes(op, 2 * k, ld, sizeof(double)));
   }
   if (w) {
     w->ld = ld;
@@ -465,7 +526,11 @@ static size_t cz_layout(const dot_op* op, int k, bool use_mg, char* base, CzWork
     w->n_active = iv + 5 * k;
     w->mgpart = mgpart;
     w->use_mg = use_mg;
-    if (use_mg) mg_work_layout<double>(op, 2 * k, ld, mgbase, &w->mg);
+    w->mixed = mixed;
+    w->r32 = r32;
+    w->z32 = z32;
+    if (mixed) mg_work_layout<float>(op, 2 * k, ld, mgbase, &w->mg32, 1);
+    else if (use_mg) mg_work_layout<double>(op, 2 * k, ld, mgbase, &w->mg);
   }
   return off + 256;
 }
@@ -484,6 +549,7 @@ static CzArgs cz_args(const dot_op* op, int k, double wk, const CzWork& w) {
   a.wk = wk;
   a.active = w.active;
   a.partial = w.partial;
+  a.bnorm = w.bnorm;
   return a;
 }
 
@@ -496,7 +562,8 @@ extern "C" {
 size_t dot_solve_complex_workspace_bytes(const dot_op* op, int k, int precond) {
   if (!op || k < 1 || k > DOT_MAX_COLUMNS / 2) return 0;
   const bool mg = precond != DOT_PRECOND_JACOBI && dot_multigrid_levels(op) > 0;
-  return cz_layout(op, k, mg, nullptr, nullptr);
+  return std::max(cz_layout(op, k, mg, false, nullptr, nullptr),
+                  cz_layout(op, k, mg, true, nullptr, nullptr));
 }
 
 int dot_solve_complex(dot_op* op, double kappa, int k, const double* rhs_dev, double* x_dev,
@@ -511,8 +578,8 @@ int dot_solve_complex(dot_op* op, double kappa, int k, const double* rhs_dev, do
   if (!(kappa >= 0.0) || !std::isfinite(kappa)) DOT_FAIL(DOT_EINVAL, "kappa must be finite, >= 0");
   if (!(opts->rtol > 0.0) || opts->max_iter < 1 || opts->check_every < 1)
     DOT_FAIL(DOT_EINVAL, "rtol > 0, max_iter >= 1 and check_every >= 1 are required");
-  if (opts->precision != DOT_FP64)
-    DOT_FAIL(DOT_EINVAL, "the frequency-domain solve runs in binary64 only (DOT_FP64)");
+  if (opts->precision != DOT_FP64 && opts->precision != DOT_MIXED)
+    DOT_FAIL(DOT_EINVAL, "precision must be DOT_FP64 or DOT_MIXED");
   if (opts->precond != DOT_PRECOND_AUTO && opts->precond != DOT_PRECOND_JACOBI &&
       opts->precond != DOT_PRECOND_MG)
     DOT_FAIL(DOT_EINVAL, "unknown preconditioner");
@@ -520,7 +587,8 @@ int dot_solve_complex(dot_op* op, double kappa, int k, const double* rhs_dev, do
   if (opts->precond == DOT_PRECOND_MG && levels == 0)
     DOT_FAIL(DOT_EINVAL, "no multigrid hierarchy for this operator");
   const bool use_mg = opts->precond != DOT_PRECOND_JACOBI && levels > 0;
-  const size_t need = cz_layout(op, k, use_mg, nullptr, nullptr);
+  const bool mixed = opts->precision == DOT_MIXED;
+  const size_t need = cz_layout(op, k, use_mg, mixed, nullptr, nullptr);
   if (!work_dev || work_bytes < need)
     DOT_FAIL(DOT_ENOMEM, "workspace too small: need %zu bytes, got %zu", need, work_bytes);
   if (((uintptr_t)work_dev & 255) != 0) DOT_FAIL(DOT_EINVAL, "work_dev must be 256-byte aligned");
@@ -531,7 +599,7 @@ int dot_solve_complex(dot_op* op, double kappa, int k, const double* rhs_dev, do
 
   hipStream_t s = as_stream(stream);
   CzWork w;
-  cz_layout(op, k, use_mg, (char*)work_dev, &w);
+  cz_layout(op, k, use_mg, mixed, (char*)work_dev, &w);
   const double wk = kappa * op->g.hd;
   const CzArgs a = cz_args(op, k, wk, w);
   const CzState st{w.rho, w.alpha, w.beta, w.bnorm, w.relres, w.active, w.active2, w.iters,
@@ -548,10 +616,15 @@ int dot_solve_complex(dot_op* op, double kappa, int k, const double* rhs_dev, do
   // Jacobi the update pass forms rho = r^T r in the same slots)
   auto precondition = [&]() -> int {
     if (!use_mg) return DOT_OK;
-    DOT_TRY_C(mg_vcycle<double>(op, w.mg, 2 * k, w.r, w.ld, w.z, w.active2, w.mgpart, s));
+    if (w.mixed)
+      DOT_TRY_C(mg_vcycle<float, float>(op, w.mg32, 2 * k, w.r32, w.ld, w.z32, w.active2,
+                                        w.mgpart, s));
+    else
+      DOT_TRY_C(mg_vcycle<double>(op, w.mg, 2 * k, w.r, w.ld, w.z, w.active2, w.mgpart, s));
     CzArgs b = a;
     b.in0 = w.r;
     b.in1 = w.z;
+    b.z32 = w.z32;
     hipLaunchKernelGGL(cz_rz_kernel, grid, dim3(CZ_T), 0, s, b);
     DOT_LAUNCH_CHECK();
     return DOT_OK;
@@ -559,6 +632,7 @@ int dot_solve_complex(dot_op* op, double kappa, int k, const double* rhs_dev, do
   auto direction = [&](bool first) -> int {
     CzArgs b = a;
     b.in0 = use_mg ? w.z : w.r;
+    b.z32 = use_mg ? w.z32 : nullptr;
     b.out0 = w.p;
     b.coef = w.beta;
     b.first = first ? 1 : 0;
@@ -579,6 +653,13 @@ int dot_solve_complex(dot_op* op, double kappa, int k, const double* rhs_dev, do
     DOT_LAUNCH_CHECK();
   }
   DOT_TRY_C(fin(CZ_F_INIT));
+  if (w.mixed) {  // the first binary32 residual, now that ||b|| is known
+    CzArgs b = a;
+    b.in0 = w.r;
+    b.r32 = w.r32;
+    hipLaunchKernelGGL(cz_r32_kernel, grid, dim3(CZ_T), 0, s, b);
+    DOT_LAUNCH_CHECK();
+  }
   DOT_TRY_C(precondition());
   if (use_mg) DOT_TRY_C(fin(CZ_F_RHO0));
   DOT_TRY_C(direction(true));
@@ -598,6 +679,7 @@ int dot_solve_complex(dot_op* op, double kappa, int k, const double* rhs_dev, do
     b.out1 = w.r;
     b.coef = w.alpha;
     b.jacobi = use_mg ? 0 : 1;
+    b.r32 = w.r32;
     hipLaunchKernelGGL(cz_update_kernel, grid, dim3(CZ_T), 0, s, b);
     DOT_LAUNCH_CHECK();
     DOT_TRY_C(fin(CZ_F_RES));

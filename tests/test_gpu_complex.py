@@ -56,6 +56,28 @@ def test_complex_solve_matches_direct(dl, dev, name, kappa):
             assert np.all(rel <= 1.5e-12)
             assert np.allclose(rel, res.relres, rtol=1e-2, atol=1e-15)
             assert fwd.max() <= 1e-8
+            if precond == dl.DOT_PRECOND_AUTO:
+                fp64_its, fp64_x = res.iters_max, X
+            else:
+                jac_x = X
+        # the binary32 V-cycle (bfloat16 vectors) as preconditioner of the
+        # binary64 COCG: the same accuracy; at this tight tolerance the
+        # rounded preconditioner costs a few more iterations
+        res_m = op.solve_complex(torch.tensor(Bc, device=dev), kappa, rtol=1e-12,
+                                 precision=dl.DOT_MIXED)
+        Xm = res_m.x.cpu().numpy()
+        rel_m = ofreq.relative_residuals(Aw, Xm, Bc)
+        print(f"[complex {name} kappa={kappa} mixed V-cycle] iters {res_m.iters_max} "
+              f"(binary64 V-cycle {fp64_its}) relres {rel_m.max():.2e}", flush=True)
+        assert res_m.converged and np.all(rel_m <= 1.5e-12)
+        assert np.linalg.norm(Xm - Xr) <= 1e-8 * np.linalg.norm(Xr)
+        if op.multigrid_levels >= 2:
+            assert res_m.iters_max <= 1.5 * fp64_its + 2
+        else:  # no V-cycle: nothing runs in binary32
+            assert np.array_equal(Xm, fp64_x)
+        res_j = op.solve_complex(torch.tensor(Bc, device=dev), kappa, rtol=1e-12,
+                                 precond=dl.DOT_PRECOND_JACOBI, precision=dl.DOT_MIXED)
+        assert np.array_equal(res_j.x.cpu().numpy(), jac_x)
         if kappa == 0.0:
             # the real solve of the same right-hand sides
             Rr = op.solve(torch.tensor(Bc.real, device=dev), rtol=1e-12).x.cpu().numpy()
