@@ -565,3 +565,32 @@ def test_profile_kinds_select_timed_launches(dotlib, dev):
             assert op.profile_read(kind)[1] > 0
         op.profile_enable(False)
     assert torch.equal(r1.x, r2.x)
+
+
+def test_mixed_solve_scales_with_the_right_hand_side(dotlib, dev):
+    """The binary32 residual is kept at scale |b^| per column: right-hand
+    sides scaled by 1e-20 and 1e20 (and a block mixing both) converge and
+    give the scaled solutions."""
+    wl, prob, W, V, data, ref = case("t3d_b")
+    op, grid, pals, th = gpu_operator(dotlib, dev, wl)
+    rhs = np.hstack([ref["BW"], ref["CV"]])
+    with op:
+        op.pals_mua(pals, th)
+
+        def solve(b):
+            res = op.solve(torch.tensor(b, device=dev), rtol=1e-10, precision=dotlib.DOT_MIXED,
+                           inner_rtol=0.01)
+            assert res.converged
+            X = res.x.cpu().numpy()
+            assert np.all(osol.relative_residuals(ref["A"], X, b) <= 1e-10)
+            return X
+
+        X1 = solve(rhs)
+        for f in (1e-20, 1e20):
+            Xf = solve(rhs * f)
+            assert np.linalg.norm(Xf / f - X1) <= 1e-7 * np.linalg.norm(X1)
+        mixed = rhs.copy()
+        mixed[:, 0] *= 1e-20
+        mixed[:, 1] *= 1e20
+        Xm = solve(mixed)
+        assert np.linalg.norm(Xm[:, 2:] - X1[:, 2:]) <= 1e-7 * np.linalg.norm(X1[:, 2:])
