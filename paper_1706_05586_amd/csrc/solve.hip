@@ -65,7 +65,7 @@ struct ColsPerBlock<float> {
 };
 
 enum SweepMode { M_APPLY = 0, M_TRUE = 1, M_PCG1 = 2, M_PCG2 = 3, M_RESID = 4 };
-enum EltMode { E_INIT = 0, E_REPLACE = 1, E_FOLD = 2, E_UNSCALE = 3 };
+enum EltMode { E_INIT = 0, E_REPLACE = 1, E_FOLD = 2, E_UNSCALE = 3, E_FINISH = 4 };
 enum FinMode {
   F_INIT = 0,      // bnorm, rho, scale = |b^|, activity
   F_ALPHA = 1,     // alpha = rho / p.q
@@ -111,6 +111,10 @@ struct ColState {
   int* upd;          // reliable update due
   int* iters;        // iterations per column
   int* flags;        // FLAG_* per column
+  // binary32 CG: x^ (xnew) or the correction d (dnew) holds no value of
+  // this solve yet and reads as zero, so the set-up writes no zeros
+  int* xnew;
+  int* dnew;
 };
 
 template <typename T>
@@ -127,10 +131,11 @@ struct SweepArgs {
   int64_t ld_in0, ld_in1, ld_out0, ld_out1;
   bool norm_s;         // PCG2: also accumulate |S r|^2 (reads sqrt(diag))
   const T* in0;        // APPLY/TRUE: x; PCG1: r; PCG2: p; RESID: x^
-  const T* in1;        // PCG1: p_old (zero before the first iteration)
+  const T* in1;        // PCG1: p_old (not read for a column whose beta is 0)
   const double* b;     // TRUE/RESID: right-hand side
   T* out0;             // APPLY: y; PCG1: p_new; PCG2: x (in place); RESID: r64
   T* out1;             // PCG2: r (in place)
+  const int* dnew;     // PCG2: columns whose out0 holds no value yet (read as 0)
   double* partial;     // [2][k][nblk_col]
   unsigned long long* prof_cols;  // optional: sum of active columns over launches
   // RESID with out2: instead of r64, the binary32 residual r / scale[j] (column
@@ -197,6 +202,17 @@ __device__ __forceinline__ void st(T* base, uint32_t c, T v) {
   *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + c * (uint32_t)sizeof(T)) = v;
 }
 
+// v, or +0 when keep is false, without a branch: the load stays
+// unconditional and a stale NaN or Inf pattern is cleared exactly
+template <typename T>
+__device__ __forceinline__ T zero_unless(T v, bool keep) {
+  if constexpr (sizeof(T) == 4) {
+    return __uint_as_float(__float_as_uint(v) & (keep ? 0xffffffffu : 0u));
+  } else {
+    return __longlong_as_double(__double_as_longlong(v) & (keep ? ~0ll : 0ll));
+  }
+}
+
 template <int MODE, typename T>
 __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs<T> a) {
   constexpr int RG = ColsPerBlock<T>::value;
@@ -231,6 +247,7 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs<T> a) {
   const double* bcol[RG];
   float* out2c[RG];
   double scl[RG];
+  bool keep0[RG];
   bool any = false;
 #pragma unroll
   for (int r = 0; r < RG; ++r) {
@@ -239,7 +256,10 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs<T> a) {
     cf[r] = (act[r] && a.coef) ? (T)a.coef[j] : T(0);
     const int64_t jj = j < G.k ? j : 0;
     in0[r] = a.in0 + (a.ld_in0 ? a.ld_in0 : G.N) * jj;
-    in1[r] = TWO ? a.in1 + (a.ld_in1 ? a.ld_in1 : G.N) * jj : nullptr;
+    // beta = 0 (the first direction): p_old may hold anything, so the term
+    // cf * p_old reads the first operand instead (0 * finite = 0)
+    in1[r] = TWO ? (cf[r] == T(0) ? in0[r] : a.in1 + (a.ld_in1 ? a.ld_in1 : G.N) * jj) : nullptr;
+    keep0[r] = !(MODE == M_PCG2 && a.dnew && j < G.k && a.dnew[j] != 0);
     out0[r] = a.out0 ? a.out0 + (a.ld_out0 ? a.ld_out0 : G.N) * jj : nullptr;
     out1[r] = a.out1 ? a.out1 + (a.ld_out1 ? a.ld_out1 : G.N) * jj : nullptr;
     bcol[r] = a.b ? a.b + G.N * jj : nullptr;
@@ -349,7 +369,7 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs<T> a) {
 #pragma unroll
     for (int r = 0; r < RG; ++r) {
       if constexpr (MODE == M_PCG2) {
-        o0[r] = ld((const T*)out0[r], c);
+        o0[r] = zero_unless(ld((const T*)out0[r], c), keep0[r]);
         o1[r] = ld((const T*)out1[r], c);
       }
       if constexpr (MODE == M_RESID || MODE == M_TRUE) bo[r] = ld(bcol[r], c);
@@ -442,12 +462,15 @@ struct EltArgs {
   const int* mask;      // columns to process (NULL = all)
   const double* scale;  // per column scale
   const double* b;      // INIT: rhs
-  double* xh;           // x^ (binary64)
+  double* xh;           // x^ (binary64; INIT: cleared unless NULL)
   double* r64;          // INIT: binary64 residual b^ (or NULL: not kept)
   float* r32;           // inner residual
   float* d32;           // inner correction
   double* p64z;         // INIT: binary64 direction buffer to clear (or NULL)
   float* p32z;          // INIT: binary32 direction buffer to clear (or NULL)
+  const int* xnew;      // FOLD / FINISH: columns whose x^ reads as 0 (or NULL)
+  const int* dnew;      // FOLD / FINISH: columns whose d reads as 0 (or NULL)
+  const int* fold;      // FINISH: columns whose d is folded (the others only unscaled)
   double* partial;
 };
 
@@ -463,7 +486,7 @@ __global__ __launch_bounds__(NT) void elt_kernel(EltArgs a) {
   const int y = (tile / G.tiles_x) * TY + (threadIdx.x >> 6);
   const bool in = x < G.nx && y < G.ny;
   const int z0 = zci * G.zc, z1 = min(G.nz, z0 + G.zc);
-  bool act[RG];
+  bool act[RG], hx[RG], hd[RG];
   int col[RG];
   double sc[RG];
   bool any = false;
@@ -473,6 +496,11 @@ __global__ __launch_bounds__(NT) void elt_kernel(EltArgs a) {
     col[r] = j;
     act[r] = j < G.k && (a.mask == nullptr || a.mask[j] != 0);
     sc[r] = (act[r] && a.scale) ? a.scale[j] : 0.0;
+    // x^ and d hold values (block-uniform); FINISH folds d only where asked
+    hx[r] = act[r] && !(a.xnew && a.xnew[j] != 0);
+    hd[r] = act[r] && !(a.dnew && a.dnew[j] != 0) && (MODE != E_FINISH || (a.fold && a.fold[j] != 0));
+    // FOLD: nothing to add to a valid x^
+    if (MODE == E_FOLD && hx[r] && !hd[r]) act[r] = false;
     any |= act[r];
   }
   if (!any) return;
@@ -491,7 +519,7 @@ __global__ __launch_bounds__(NT) void elt_kernel(EltArgs a) {
         if constexpr (MODE == E_INIT) {
           const double bv = a.b[o];
           const double rv = bv / a.sd[c];
-          a.xh[o] = 0.0;
+          if (a.xh) a.xh[o] = 0.0;
           if (a.r64) a.r64[w] = rv;
           if (a.d32) a.d32[w] = 0.0f;
           if (a.p64z) a.p64z[w] = 0.0;
@@ -508,10 +536,18 @@ __global__ __launch_bounds__(NT) void elt_kernel(EltArgs a) {
           const double t = a.sd[c] * rd;
           acc[r][1] += t * t;
         } else if constexpr (MODE == E_FOLD) {
-          a.xh[o] += sc[r] * (double)a.d32[w];
-          a.d32[w] = 0.0f;
+          // d is not cleared: the columns folded here are marked as holding
+          // no correction, which the next CG pass 2 reads as zero
+          const double xv = hx[r] ? a.xh[o] : 0.0;
+          a.xh[o] = hd[r] ? xv + sc[r] * (double)a.d32[w] : xv;
         } else if constexpr (MODE == E_UNSCALE) {
           a.xh[o] = a.xh[o] / a.sd[c];
+        } else if constexpr (MODE == E_FINISH) {
+          // pending correction folded (columns stopped by the iteration cap)
+          // and x = x^ / sqrt(diag) in one pass
+          double xv = hx[r] ? a.xh[o] : 0.0;
+          if (hd[r]) xv += sc[r] * (double)a.d32[w];
+          a.xh[o] = xv / a.sd[c];
         }
       }
     }
@@ -566,6 +602,8 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
       st.iters[j] = 0;
       st.flags[j] = 0;
       st.upd[j] = 0;
+      st.xnew[j] = 1;
+      st.dnew[j] = 1;
       if (!fin) {
         st.flags[j] |= FLAG_NONFINITE;
         st.active[j] = 0;
@@ -603,6 +641,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
     }
     case F_BETA_RU: {  // binary32 CG: schedule a reliable update when due
       st.iters[j] += 1;
+      st.dnew[j] = 0;  // CG pass 2 has written d
       if (!fin) {
         st.flags[j] |= FLAG_NONFINITE;
         st.active[j] = 0;
@@ -625,6 +664,8 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
       break;
     }
     case F_RESID: {  // true binary64 residual after folding the correction
+      st.xnew[j] = 0;
+      st.dnew[j] = 1;
       const double rel = sqrt(s1) / st.bnorm[j];
       st.relres[j] = rel;
       if (!fin) {
@@ -679,6 +720,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
     }
     case F_RU_MG: {
       st.iters[j] += 1;
+      st.dnew[j] = 0;  // CG pass 2 has written d
       if (!fin) {
         st.flags[j] |= FLAG_NONFINITE;
         st.active[j] = 0;
@@ -812,6 +854,8 @@ static size_t layout_workspace(const dot_op* op, const Geom& G, int precision, c
   ws.st.upd = (int*)take(k * 4);
   ws.st.iters = (int*)take(k * 4);
   ws.st.flags = (int*)take(k * 4);
+  ws.st.xnew = (int*)take(k * 4);
+  ws.st.dnew = (int*)take(k * 4);
   ws.bytes = off;
   if (w) *w = ws;
   return off;
@@ -1004,13 +1048,16 @@ static SweepArgs<float> base_args32(dot_op* op, const Geom& G) {
   return a;
 }
 
+// x = x^ / sqrt(diag) (or the binary32 CG's finishing pass `fin`), then the
+// true residual of x in binary64
 static int finish_true(dot_op* op, const Geom& G, const Workspace& ws, const double* rhs,
-                       double* x, hipStream_t s) {
+                       double* x, hipStream_t s, const EltArgs* fin = nullptr) {
   EltArgs e{};
   e.G = G;
   e.sd = op->sd;
   e.xh = x;
-  DOT_TRY(launch_elt<E_UNSCALE>(e, s));
+  if (fin) DOT_TRY(launch_elt<E_FINISH>(*fin, s));
+  else DOT_TRY(launch_elt<E_UNSCALE>(e, s));
   SweepArgs<double> t{};
   t.G = G;
   t.cx = op->cx;
@@ -1110,8 +1157,14 @@ static int solve_mixed(dot_op* op, const Geom& G, const Workspace& ws, const dou
   e.d32 = ws.d32;
   e.scale = ws.st.scale;
   e.partial = ws.partial;
+  e.xnew = ws.st.xnew;
+  e.dnew = ws.st.dnew;
+  // norms of b^ and b only: x^, d and the first direction are not cleared
+  // (F_INIT marks x^ and d as holding no value; the first CG pass 1 does not
+  // read p_old, its beta being 0)
   EltArgs e0 = e;
-  e0.p32z = ws.p32[0];
+  e0.xh = nullptr;
+  e0.d32 = nullptr;
   DOT_TRY(launch_elt<E_INIT>(e0, s));
   DOT_TRY(launch_fin(F_INIT, G, ws, nullptr, o.rtol, delta, s));
   EltArgs er = e;
@@ -1161,6 +1214,7 @@ static int solve_mixed(dot_op* op, const Geom& G, const Workspace& ws, const dou
     p2.out0 = ws.d32;
     p2.out1 = ws.r32;
     p2.ld_in0 = p2.ld_out0 = p2.ld_out1 = G.ldw;
+    p2.dnew = ws.st.dnew;
     p2.partial = ws.partial;
     const bool polled = (it + 1) % o.check_every == 0 || it + 1 == o.max_iter;
     p2.norm_s = polled;
@@ -1194,16 +1248,13 @@ static int solve_mixed(dot_op* op, const Geom& G, const Workspace& ws, const dou
     if (polled) DOT_TRY(count(true));
   }
   DOT_TRY(count(false));
-  // columns stopped by the iteration cap: fold their pending correction
-  // (masked by the activity flags: a no-op where every column converged)
-  {
-    EltArgs ef = e;
-    ef.mask = ws.st.active;
-    DOT_TRY(launch_elt<E_FOLD>(ef, s));
-  }
+  // columns stopped by the iteration cap fold their pending correction in
+  // the pass that unscales x
+  EltArgs ef = e;
+  ef.fold = ws.st.active;
   *iters_done = it;
   *outer_done = updates;
-  return finish_true(op, G, ws, rhs, x, s);
+  return finish_true(op, G, ws, rhs, x, s, &ef);
 }
 
 }  // namespace dot
