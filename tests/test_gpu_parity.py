@@ -594,3 +594,42 @@ def test_mixed_solve_scales_with_the_right_hand_side(dotlib, dev):
         mixed[:, 1] *= 1e20
         Xm = solve(mixed)
         assert np.linalg.norm(Xm[:, 2:] - X1[:, 2:]) <= 1e-7 * np.linalg.norm(X1[:, 2:])
+
+
+@pytest.mark.parametrize("precond", ["mg", "jacobi"])
+def test_mixed_solve_ignores_stale_workspace_and_output(dotlib, dev, precond):
+    """The binary32 CG does not clear x^, its correction or the first
+    direction at set-up (per-column flags mark them as unset): a workspace
+    and an output block full of NaN bit patterns give bit-identical
+    solutions, iteration counts and residuals to zero-filled ones, for
+    converged columns, a zero right-hand side and columns stopped by the
+    iteration cap."""
+    wl, prob, W, V, data, ref = case("t3d_b")
+    op, grid, pals, th = gpu_operator(dotlib, dev, wl)
+    rhs = np.hstack([ref["BW"], ref["CV"]])
+    rhs[:, 1] = 0.0
+    pc = dotlib.DOT_PRECOND_MG if precond == "mg" else dotlib.DOT_PRECOND_JACOBI
+    B = torch.tensor(rhs, device=dev).t().contiguous().t()
+    with op:
+        op.pals_mua(pals, th)
+        nbytes = op.solve_workspace_bytes(B.shape[1], dotlib.DOT_MIXED)
+
+        def run(fill, **kw):
+            work = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+            work = work[(-work.data_ptr()) % 256:]
+            work.fill_(fill)
+            out = torch.empty_like(B).t().contiguous().t()
+            out.t().view(torch.uint8).fill_(fill)
+            res = op.solve(B, precision=dotlib.DOT_MIXED, precond=pc, out=out, work=work,
+                           inner_rtol=0.01, warn=False, **kw)
+            torch.cuda.synchronize()
+            return res
+
+        for kw in ({"rtol": 1e-10}, {"rtol": 1e-14, "max_iter": 3}):
+            clean, stale = run(0, **kw), run(255, **kw)
+            assert torch.isfinite(stale.x).all()
+            assert torch.equal(clean.x, stale.x), kw
+            assert np.array_equal(clean.iters, stale.iters)
+            assert np.array_equal(clean.relres, stale.relres)
+            assert torch.count_nonzero(stale.x[:, 1]) == 0
+        assert clean.iters_max == 3 and not clean.converged
