@@ -474,6 +474,8 @@ struct EltArgs {
   double* partial;
 };
 
+constexpr int EU = 4;  // planes per step of the elementwise passes
+
 template <int MODE>
 __global__ __launch_bounds__(NT) void elt_kernel(EltArgs a) {
   const Geom& G = a.G;
@@ -509,45 +511,74 @@ __global__ __launch_bounds__(NT) void elt_kernel(EltArgs a) {
   for (int r = 0; r < RG; ++r) acc[r][0] = acc[r][1] = 0.0;
   if (in) {
     const int64_t base = x + (int64_t)G.nx * y;
-    for (int z = z0; z < z1; ++z) {
-      const int64_t c = base + (int64_t)z * G.nxy;
+    // EU planes per step: every load of the step's planes and columns is
+    // issued before any of them is used (the last step's surplus planes
+    // load the chunk's last plane again and are dropped); sqrt(diag) is
+    // loaded once per plane for the block's columns
+    constexpr bool LB = MODE == E_INIT || MODE == E_REPLACE;
+    constexpr bool LS = MODE != E_FOLD;
+    bool lx[RG], lddd[RG];
 #pragma unroll
-      for (int r = 0; r < RG; ++r) {
-        if (!act[r]) continue;
-        const int64_t o = c + G.N * (int64_t)col[r];     // caller's arrays
-        const int64_t w = c + G.ldw * (int64_t)col[r];   // work vectors
-        if constexpr (MODE == E_INIT) {
-          const double bv = a.b[o];
-          const double rv = bv / a.sd[c];
-          if (a.xh) a.xh[o] = 0.0;
-          if (a.r64) a.r64[w] = rv;
-          if (a.d32) a.d32[w] = 0.0f;
-          if (a.p64z) a.p64z[w] = 0.0;
-          if (a.p32z) a.p32z[w] = 0.0f;
-          acc[r][0] += rv * rv;
-          acc[r][1] += bv * bv;
-        } else if constexpr (MODE == E_REPLACE) {
-          // the first binary32 residual (b^ / scale, x = 0), formed from b
-          // as E_INIT forms b^
-          const float rv = (float)((a.b[o] / a.sd[c]) / sc[r]);
-          a.r32[w] = rv;
-          const double rd = (double)rv;
-          acc[r][0] += rd * rd;
-          const double t = a.sd[c] * rd;
-          acc[r][1] += t * t;
-        } else if constexpr (MODE == E_FOLD) {
-          // d is not cleared: the columns folded here are marked as holding
-          // no correction, which the next CG pass 2 reads as zero
-          const double xv = hx[r] ? a.xh[o] : 0.0;
-          a.xh[o] = hd[r] ? xv + sc[r] * (double)a.d32[w] : xv;
-        } else if constexpr (MODE == E_UNSCALE) {
-          a.xh[o] = a.xh[o] / a.sd[c];
-        } else if constexpr (MODE == E_FINISH) {
-          // pending correction folded (columns stopped by the iteration cap)
-          // and x = x^ / sqrt(diag) in one pass
-          double xv = hx[r] ? a.xh[o] : 0.0;
-          if (hd[r]) xv += sc[r] * (double)a.d32[w];
-          a.xh[o] = xv / a.sd[c];
+    for (int r = 0; r < RG; ++r) {
+      lx[r] = act[r] && (MODE == E_UNSCALE || ((MODE == E_FOLD || MODE == E_FINISH) && hx[r]));
+      lddd[r] = act[r] && (MODE == E_FOLD || MODE == E_FINISH) && hd[r];
+    }
+    for (int z = z0; z < z1; z += EU) {
+      double vb[RG][EU], vs[EU], vx[RG][EU];
+      float vd[RG][EU];
+#pragma unroll
+      for (int u = 0; u < EU; ++u) {
+        const int64_t c = base + (int64_t)min(z + u, z1 - 1) * G.nxy;
+        vs[u] = LS ? a.sd[c] : 1.0;
+#pragma unroll
+        for (int r = 0; r < RG; ++r) {
+          const int64_t o = c + G.N * (int64_t)col[r], w = c + G.ldw * (int64_t)col[r];
+          vb[r][u] = (LB && act[r]) ? a.b[o] : 0.0;
+          vx[r][u] = lx[r] ? a.xh[o] : 0.0;
+          vd[r][u] = lddd[r] ? a.d32[w] : 0.0f;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < EU; ++u) {
+        if (z + u >= z1) break;
+        const int64_t c = base + (int64_t)(z + u) * G.nxy;
+#pragma unroll
+        for (int r = 0; r < RG; ++r) {
+          if (!act[r]) continue;  // block-uniform
+          const int64_t o = c + G.N * (int64_t)col[r];     // caller's arrays
+          const int64_t w = c + G.ldw * (int64_t)col[r];   // work vectors
+          if constexpr (MODE == E_INIT) {
+            const double bv = vb[r][u];
+            const double rv = bv / vs[u];
+            if (a.xh) a.xh[o] = 0.0;
+            if (a.r64) a.r64[w] = rv;
+            if (a.d32) a.d32[w] = 0.0f;
+            if (a.p64z) a.p64z[w] = 0.0;
+            if (a.p32z) a.p32z[w] = 0.0f;
+            acc[r][0] += rv * rv;
+            acc[r][1] += bv * bv;
+          } else if constexpr (MODE == E_REPLACE) {
+            // the first binary32 residual (b^ / scale, x = 0), formed from b
+            // as E_INIT forms b^
+            const float rv = (float)((vb[r][u] / vs[u]) / sc[r]);
+            a.r32[w] = rv;
+            const double rd = (double)rv;
+            acc[r][0] += rd * rd;
+            const double t = vs[u] * rd;
+            acc[r][1] += t * t;
+          } else if constexpr (MODE == E_FOLD) {
+            // d is not cleared: the columns folded here are marked as
+            // holding no correction, which the next CG pass 2 reads as zero
+            a.xh[o] = hd[r] ? vx[r][u] + sc[r] * (double)vd[r][u] : vx[r][u];
+          } else if constexpr (MODE == E_UNSCALE) {
+            a.xh[o] = vx[r][u] / vs[u];
+          } else if constexpr (MODE == E_FINISH) {
+            // pending correction folded (columns stopped by the iteration
+            // cap) and x = x^ / sqrt(diag) in one pass
+            double xv = vx[r][u];
+            if (hd[r]) xv += sc[r] * (double)vd[r][u];
+            a.xh[o] = xv / vs[u];
+          }
         }
       }
     }
